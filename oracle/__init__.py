@@ -1,0 +1,270 @@
+"""FP64 CPU oracle for the fluctuating ideal-gas D2Q9 lattice Boltzmann method.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py`` may import this package.  It shares
+no code with the GPU library (``paper_1010_1233_amd``) and never imports it.
+
+The arithmetic lives in ``oracle.c`` (plain C, FP64, libm); this module only
+marshals numpy arrays through ctypes.  Each function names the passage of
+Kaehler & Wagner (Sec. 2-3, Eqs. 1-12) that it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (-O2, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+             "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Cfg(ctypes.Structure):
+    """Mirror of ``oracle_cfg`` in oracle.c."""
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("tau", ctypes.c_double * 9),
+        ("theta", ctypes.c_double), ("rho0", ctypes.c_double),
+        ("u0x", ctypes.c_double), ("u0y", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32),
+        ("ladd", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        L.oracle_tables.argtypes = [_dp, _dp, _dp, _ip]
+        L.oracle_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.oracle_noise_words.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                         ctypes.c_uint32, ctypes.c_uint32, _u32p]
+        L.oracle_normals_from_words.argtypes = [_u32p, _dp]
+        L.oracle_equilibrium.argtypes = [ctypes.c_double] * 3 + [_dp]
+        L.oracle_moments.argtypes = [_dp, _dp]
+        L.oracle_equilibrium_moments.argtypes = [ctypes.c_double] * 3 + [_dp]
+        L.oracle_noise_amplitudes.argtypes = [_dp, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_int, _dp]
+        L.oracle_collide_site.argtypes = [_dp, _dp, _dp, _dp, _dp]
+        cp = ctypes.POINTER(Cfg)
+        L.oracle_init.argtypes = [cp, _dp]
+        L.oracle_step.argtypes = [cp, _dp, _dp, ctypes.c_uint32]
+        L.oracle_conservation.argtypes = [cp, _dp, _dp]
+        L.oracle_thermalize.argtypes = [cp, _dp]
+        L.oracle_dft2.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int]
+        L.oracle_nkx.argtypes = [ctypes.c_int]
+        L.oracle_nkx.restype = ctypes.c_int
+        L.oracle_sample.argtypes = [cp, _dp, _dp]
+        L.oracle_run.argtypes = [cp, _dp, _dp, ctypes.c_uint32, ctypes.c_int64,
+                                 ctypes.c_int, _dp]
+        L.oracle_run.restype = ctypes.c_int64
+        _lib = L
+    return _lib
+
+
+def _p(a, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+NKINDS = 15
+KINDS = ("rho_rho", "jx_jx", "jy_jy", "ux_ux", "uy_uy",
+         "re_ux_uy", "im_ux_uy", "re_rho_jx", "im_rho_jx", "re_rho_jy", "im_rho_jy",
+         "re_rho_ux", "im_rho_ux", "re_rho_uy", "im_rho_uy")
+
+
+def tables():
+    """(m[a][i], n[i][a], w[i], v[i][2]) of Eq. (9) and the text after it."""
+    m = np.zeros(81); n = np.zeros(81); w = np.zeros(9); v = np.zeros(18, dtype=np.int32)
+    lib().oracle_tables(_p(m), _p(n), _p(w), _p(v, _ip))
+    return m.reshape(9, 9), n.reshape(9, 9), w, v.reshape(9, 2)
+
+
+def philox(ctr, key):
+    """Philox4x32-10 of one 128-bit counter under one 64-bit key."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32_10(_p(c, _u32p), _p(k, _u32p), _p(o, _u32p))
+    return o
+
+
+def noise_words(seed, stream_id, t, site, d=0):
+    o = np.zeros(4, dtype=np.uint32)
+    lib().oracle_noise_words(seed, stream_id, t, site, d, _p(o, _u32p))
+    return o
+
+
+def normals_from_words(w):
+    w = np.ascontiguousarray(w, dtype=np.uint32)
+    z = np.zeros(6)
+    lib().oracle_normals_from_words(_p(w, _u32p), _p(z))
+    return z
+
+
+def equilibrium(rho, ux, uy):
+    """Eq. (2), c = 1."""
+    f = np.zeros(9)
+    lib().oracle_equilibrium(rho, ux, uy, _p(f))
+    return f
+
+
+def moments(f):
+    """Eq. (3)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    M = np.zeros(9)
+    lib().oracle_moments(_p(f), _p(M))
+    return M
+
+
+def equilibrium_moments(rho, ux, uy):
+    """Eq. (10)."""
+    M = np.zeros(9)
+    lib().oracle_equilibrium_moments(rho, ux, uy, _p(M))
+    return M
+
+
+def noise_amplitudes(tau, theta, rho0, ladd=False):
+    """Eq. (8) with variance scale mu = 3 theta."""
+    t = np.ascontiguousarray(tau, dtype=np.float64)
+    s = np.zeros(9)
+    lib().oracle_noise_amplitudes(_p(t), theta, rho0, int(bool(ladd)), _p(s))
+    return s
+
+
+def collide_site(f, tau, sigma, z):
+    """Eq. (5) at one site: post-collision populations."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    t = np.ascontiguousarray(tau, dtype=np.float64)
+    s = np.ascontiguousarray(sigma, dtype=np.float64)
+    zz = np.ascontiguousarray(z, dtype=np.float64)
+    o = np.zeros(9)
+    lib().oracle_collide_site(_p(f), _p(t), _p(s), _p(zz), _p(o))
+    return o
+
+
+def dft2(x):
+    """2-D discrete transform X(k) = sum_x x(x) exp(-i k.x) of an (ny, nx) array."""
+    x = np.asarray(x, dtype=np.complex128)
+    ny, nx = x.shape
+    re = np.ascontiguousarray(x.real)
+    im = np.ascontiguousarray(x.imag)
+    lib().oracle_dft2(_p(re), _p(im), nx, ny)
+    return re + 1j * im
+
+
+def nkx(nx):
+    return lib().oracle_nkx(nx)
+
+
+class Lattice:
+    """A periodic nx x ny lattice evolved by the oracle in FP64.
+
+    ``f`` is the pre-collision state f[i][y][x]; ``t`` the number of steps
+    taken (the noise counter of the next step).
+    """
+
+    def __init__(self, nx, ny, tau, theta, rho0=1.0, u0=(0.0, 0.0), seed=1,
+                 stream_id=0, ladd=False, thermalize=False):
+        self.cfg = Cfg()
+        self.cfg.nx, self.cfg.ny = int(nx), int(ny)
+        for a in range(9):
+            self.cfg.tau[a] = float(tau[a])
+        self.cfg.theta, self.cfg.rho0 = float(theta), float(rho0)
+        self.cfg.u0x, self.cfg.u0y = float(u0[0]), float(u0[1])
+        self.cfg.seed, self.cfg.stream_id = int(seed), int(stream_id)
+        self.cfg.ladd = int(bool(ladd))
+        self.nx, self.ny = int(nx), int(ny)
+        self.f = np.zeros((9, self.ny, self.nx))
+        self._tmp = np.zeros_like(self.f)
+        lib().oracle_init(ctypes.byref(self.cfg), _p(self.f))
+        if thermalize:
+            lib().oracle_thermalize(ctypes.byref(self.cfg), _p(self.f))
+        self.t = 0
+        self.acc = np.zeros((NKINDS, self.ny, nkx(self.nx)))
+        self.nsamples = 0
+
+    @property
+    def V(self):
+        return self.nx * self.ny
+
+    def set_populations(self, f):
+        f = np.asarray(f, dtype=np.float64)
+        assert f.shape == (9, self.ny, self.nx)
+        self.f[...] = f
+
+    def step(self, n=1):
+        for _ in range(n):
+            lib().oracle_step(ctypes.byref(self.cfg), _p(self.f), _p(self._tmp), self.t)
+            self.f, self._tmp = self._tmp, self.f
+            self.t += 1
+
+    def run(self, nsteps, sample_every=0):
+        """nsteps steps, sampling at every t with t % sample_every == 0."""
+        ns = lib().oracle_run(ctypes.byref(self.cfg), _p(self.f), _p(self._tmp), self.t,
+                              int(nsteps), int(sample_every),
+                              _p(self.acc) if sample_every > 0 else None)
+        self.t += int(nsteps)
+        self.nsamples += int(ns)
+        return int(ns)
+
+    def sample(self):
+        lib().oracle_sample(ctypes.byref(self.cfg), _p(self.f), _p(self.acc))
+        self.nsamples += 1
+
+    def conservation(self):
+        o = np.zeros(5)
+        lib().oracle_conservation(ctypes.byref(self.cfg), _p(self.f), _p(o))
+        return o
+
+    def thermalize(self):
+        lib().oracle_thermalize(ctypes.byref(self.cfg), _p(self.f))
+
+
+def normalized(acc, nsamples, nx, ny, theta, rho0):
+    """Normalised correlators from raw sums, in the oracle's own arithmetic.
+
+    S(rho)  = <|rho_k|^2> / (V mu rho0)        (Eq. 11 with N^rho; mu = 3 theta)
+    S(j_a)  = <|j_a,k|^2> / (V rho0 theta)
+    S(u_a)  = rho0 <|u_a,k|^2> / (V theta)     (N^{u_a} = 1/(rho0 V kT))
+    R(ux,uy) = rho0 <ux uy*> / (V theta)       (Eq. 12)
+    R(rho,j_a) = <rho j_a*> / (V mu rho0 c_s),  R(rho,u_a) = <rho u_a*> / (V mu c_s)
+    """
+    V = nx * ny
+    mu = 3.0 * theta
+    cs = 1.0 / np.sqrt(3.0)
+    m = acc / max(nsamples, 1)
+    out = {
+        "S_rho": m[0] / (V * mu * rho0),
+        "S_jx": m[1] / (V * rho0 * theta),
+        "S_jy": m[2] / (V * rho0 * theta),
+        "S_ux": rho0 * m[3] / (V * theta),
+        "S_uy": rho0 * m[4] / (V * theta),
+        "R_uxuy": rho0 * (m[5] + 1j * m[6]) / (V * theta),
+        "R_rhojx": (m[7] + 1j * m[8]) / (V * mu * rho0 * cs),
+        "R_rhojy": (m[9] + 1j * m[10]) / (V * mu * rho0 * cs),
+        "R_rhoux": (m[11] + 1j * m[12]) / (V * mu * cs),
+        "R_rhouy": (m[13] + 1j * m[14]) / (V * mu * cs),
+    }
+    return out
