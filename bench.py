@@ -1,0 +1,233 @@
+"""Throughput of the noisy D2Q9 hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5_4096]
+                    [--storage f32|bf16|f16] [--no-cpu-baseline] [--no-forms]
+
+One benchmark step is one pass of the whole path on the workload: ten fused
+collide+noise+stream updates of every site, one correlator sample (field
+extraction, 2-D transforms, FP64 accumulation of the fifteen products) and one
+FP64 conservation check.  W untimed steps, then K timed steps bracketed by
+device synchronisation.  `value` is site updates per second (GLUPS) over the
+timed region, inputs resident in HBM.
+
+The JSON line also carries
+  roofline      the step kernel (dominant): algorithmic bytes per launch
+                (9 reads + 9 writes per site) over its average duration,
+                measured with HIP events on the stream it runs on, within
+                the timed region; HBM traffic from rocprofv3 counters when a
+                summary for the current kernel source is committed;
+  cpu_baseline  the FP64 oracle, single thread, on a bounded sample of the
+                same workload;
+  forms         step-kernel rates of the other storage formats and of the
+                noise-free step (the paper's ghost-noise overhead).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "noisy D2Q9 GLUPS and % of HBM peak, FP32/batched vs plain, at matched S(k)"
+HBM_PEAK_GBS = 8000.0
+SAMPLE_EVERY = 10
+STEP_KERNEL = "step_kernel"
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("flb_step.hip", "flb_device.h", "flb_internal.h"):
+        with open(os.path.join(ROOT, "paper_1010_1233_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, storage):
+    """HBM bytes per step-kernel launch from the committed counter summary,
+    or None when it is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    key = f"{workload}/{storage}"
+    e = d.get(key)
+    if not e or e.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def make_lattice(flb, workloads, name, storage):
+    c = workloads.CONFIGS[name]
+    g = flb.Lattice(c["nx"], c["ny"], c["tau"], c["theta"], rho0=c["rho0"], u0=c["u0"],
+                    seed=c["seed"], storage=storage)
+    return g, c
+
+
+def time_step_kernel(torch, g, stream, n):
+    """Average duration (ms) of n back-to-back step launches on `stream`."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.step(n)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def cpu_baseline(workloads, name, max_side=2048):
+    """The oracle (FP64, one thread) on a bounded sample of the same workload:
+    the same parameters on a lattice of at most max_side^2 sites, ten steps
+    and one correlator sample (one benchmark step), timed as a whole."""
+    import oracle
+    c = workloads.CONFIGS[name]
+    nx, ny = min(c["nx"], max_side), min(c["ny"], max_side)
+    L = oracle.Lattice(nx, ny, c["tau"], c["theta"], rho0=c["rho0"], u0=c["u0"], seed=c["seed"])
+    t0 = time.perf_counter()
+    L.step(SAMPLE_EVERY)
+    L.sample()
+    dt = time.perf_counter() - t0
+    V = nx * ny
+    return {"value": SAMPLE_EVERY * V / dt / 1e9, "unit": "GLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{SAMPLE_EVERY} steps + 1 correlator sample of a {nx}x{ny} lattice with "
+                      f"the workload's parameters ({dt:.1f} s, FP64, one thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c5_4096")
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the method's lattices are "
+              "independent; sharding across GPUs is described, not built). Use --gpus 1.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1010_1233_amd as flb
+    from paper_1010_1233_amd import workloads
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    stream = torch.cuda.Stream()
+    g, c = make_lattice(flb, workloads, args.workload, args.storage)
+    g.set_stream(stream)
+    V = c["nx"] * c["ny"]
+    print(f"bench: {args.workload} {c['nx']}x{c['ny']} storage={args.storage} "
+          f"step config={g.step_config()}", file=sys.stderr, flush=True)
+    g.thermalize()
+    cons = torch.zeros((args.steps + args.warmup, 5), dtype=torch.float64, device="cuda")
+
+    def bench_step(i, ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        g.step(SAMPLE_EVERY)
+        if ev is not None:
+            ev[1].record(stream)
+        g.accumulate()
+        g.conservation_dev(cons[i].data_ptr())
+
+    with torch.cuda.stream(stream):
+        for i in range(args.warmup):
+            bench_step(i)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            bench_step(args.warmup + i, evs[i])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+
+    step_ms = sum(a.elapsed_time(b) for a, b in evs) / (args.steps * SAMPLE_EVERY)
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = args.steps * SAMPLE_EVERY * V / elapsed / 1e9
+    bytes_per_value = g.storage_info()[1]
+    algo_bytes = 18 * bytes_per_value * V  # 9 loads + 9 stores per site
+    achieved = algo_bytes / (step_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, args.storage)
+    c_np = cons.cpu().numpy()
+    drift = float(abs(c_np[-1, 0] - c_np[0, 0]))
+
+    # correlator sanity (matched S(k)): k-averaged S(rho) over the run
+    acc, ns = g.read_correlators()
+    S = flb.normalize(acc, ns, c["nx"], c["ny"], c["theta"], c["rho0"])
+    s_rho_mean = float(S["S_rho"][1:, 1:].mean())
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": f"D2Q9 {c['nx']}x{c['ny']} periodic, {args.storage} storage, "
+                               f"rho0={c['rho0']}, u0={tuple(c['u0'])}, tau_shear={c['tau'][3]}, "
+                               f"kT={c['theta']}, thermal start, correlators every "
+                               f"{SAMPLE_EVERY} steps",
+                   "sites": V, "lb_steps_per_bench_step": SAMPLE_EVERY,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "kernel": STEP_KERNEL,
+                     "algorithmic_bytes_per_launch": algo_bytes,
+                     "avg_launch_ms": step_ms},
+        "step_kernel_glups": V / (step_ms * 1e-3) / 1e9,
+        "sample_ms": max(ms_per_step - SAMPLE_EVERY * step_ms, 0.0),
+        "mass_drift": drift,
+        "S_rho_kmean": s_rho_mean,
+    }
+
+    if not args.no_forms:
+        forms = {}
+        with torch.cuda.stream(stream):
+            for st in ("f32", "bf16", "f16"):
+                if st == args.storage:
+                    continue
+                h, _ = make_lattice(flb, workloads, args.workload, st)
+                h.set_stream(stream)
+                h.thermalize()
+                time_step_kernel(torch, h, stream, 5)
+                ms = time_step_kernel(torch, h, stream, 50)
+                b = h.storage_info()[1]
+                forms[st] = {"step_glups": V / (ms * 1e-3) / 1e9,
+                             "achieved_GBs": 18 * b * V / (ms * 1e-3) / 1e9}
+                h.close()
+            cq = dict(workloads.CONFIGS[args.workload])
+            h = flb.Lattice(cq["nx"], cq["ny"], cq["tau"], 0.0, rho0=cq["rho0"], u0=cq["u0"],
+                            seed=cq["seed"], storage=args.storage)
+            h.set_stream(stream)
+            time_step_kernel(torch, h, stream, 5)
+            ms = time_step_kernel(torch, h, stream, 50)
+            forms["noise_off_" + args.storage] = {"step_glups": V / (ms * 1e-3) / 1e9}
+            out["noise_overhead"] = step_ms / ms - 1.0
+            h.close()
+        out["forms"] = forms
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(workloads, args.workload)
+    print(json.dumps(out), flush=True)
+    g.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,220 @@
+/*
+ * flb.h -- C interface of the MI355X (gfx950) fluctuating ideal-gas lattice
+ * Boltzmann library.
+ *
+ * The method is the D2Q9 scheme with noise on every non-conserved moment
+ * analysed by Kaehler & Wagner, "Cross Correlators and Galilean Invariance in
+ * Fluctuating Ideal Gas Lattice Boltzmann Simulations":
+ *   - one time step is Eq. (1) written in moment space, Eq. (5): moments
+ *     M^a = sum_i m_i^a f_i (Eq. 3, matrix Eq. 9), relaxation of every
+ *     non-conserved moment by its own 1/tau^a towards the equilibrium
+ *     moments of Eq. (10), Gaussian noise of amplitude Eq. (8) on the stress
+ *     and ghost moments a = 3..8 (Sec. 2, last paragraph), back transform
+ *     with n_i^a = w_i m_i^a (Eq. 4), then streaming on a periodic lattice;
+ *   - the measurement accumulates the static structure factors of Eq. (11)
+ *     and the cross correlators of Eq. (12) from spatial Fourier transforms
+ *     of the density, momentum and velocity fluctuations (Sec. 3).
+ *
+ * Conventions used by every call:
+ *   - Lattice sites x = 0..nx-1, y = 0..ny-1, periodic; site index
+ *     s = y*nx + x.  Velocities in the order of Sec. 3:
+ *     (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1).
+ *   - Moments a = 0..8: 0 density, 1-2 momentum (x sqrt 3), 3-4 shear
+ *     stress, 5 bulk stress, 6-8 ghost modes.  tau[a] for a = 0..2 is ignored
+ *     (those moments are conserved).
+ *   - theta is a noise temperature: the moment variance of Eq. (7) becomes
+ *     mu*rho0 with mu = theta / c_s^2 = 3 theta; theta = 1/3 reproduces the
+ *     paper's unit-mass noise exactly, theta = 0 switches noise off.  The
+ *     noise uses the constant rho0 (the u << 1 form of Eq. 7, as in the paper).
+ *   - Noise: Philox4x32-10 (Salmon et al., SC'11), key = (seed & 0xffffffff,
+ *     seed >> 32), counter = (site, t, stream_id, 0) for the collision of step
+ *     t -> t+1 at that site.  The four words give six unit normals: radius
+ *     uniforms r_p = (2(w_p >> 9) + 1) 2^-24 and angle uniforms
+ *     a_p = (2 alpha_p + 1) 2^-20, alpha_p = ((w_p & 0x1ff) << 10) |
+ *     ((w_3 >> 10p) & 0x3ff), p = 0,1,2; z_2p = sqrt(-2 ln r_p) cos(2 pi a_p),
+ *     z_2p+1 = sqrt(-2 ln r_p) sin(2 pi a_p); z_{a-3} drives moment a.
+ *   - Populations exchanged with the caller are full values f_i (not
+ *     deviations), FP64, laid out [9][ny][nx], and are the state just after
+ *     streaming (before the next collision) at the current time.
+ *
+ * Ownership: a handle owns all of its device memory.  Every pointer argument
+ * that is read or written by a call belongs to the caller and is a HOST
+ * pointer unless its name ends in _dev.  Calls that return data to the host
+ * synchronise the handle's stream; flb_step, flb_run and
+ * flb_accumulate_correlators only enqueue work.
+ *
+ * Errors: calls return FLB_OK (0) or a negative FLB_E* code and leave a
+ * message for flb_last_error() (per thread).  Creation calls return NULL on
+ * error.  A handle is not safe to use from two threads at once.
+ */
+#ifndef FLB_H
+#define FLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FLB_OK 0
+#define FLB_EINVAL (-1) /* invalid argument (value, range, NULL pointer) */
+#define FLB_ENOMEM (-2) /* device or host allocation failed */
+#define FLB_EHIP (-3)   /* a HIP runtime call failed */
+#define FLB_ESIZE (-4)  /* a buffer size or lattice size outside what is supported */
+#define FLB_ESTATE (-5) /* the call does not apply to this handle's state */
+
+/* Storage of the populations in device memory. */
+#define FLB_STORAGE_F32 0  /* FP32 deviation f_i - w_i rho0 */
+#define FLB_STORAGE_BF16 1 /* bfloat16 of (f_i - f_i^0(rho0,u0)) / sqrt(mu rho0 w_i) */
+#define FLB_STORAGE_F16 2  /* binary16 of the same scaled deviation */
+
+/* Creation flags. */
+#define FLB_FLAG_NO_GHOST_NOISE 1u /* zero noise on moments 6..8: the older
+                                      scheme Sec. 3 compares against */
+
+/* Correlator kinds, first index of the accumulator array. */
+#define FLB_NKINDS 15
+/*  0 |rho_k|^2   1 |jx_k|^2   2 |jy_k|^2   3 |ux_k|^2   4 |uy_k|^2
+ *  5,6  Re,Im ux_k uy_k*     7,8  Re,Im rho_k jx_k*    9,10 Re,Im rho_k jy_k*
+ *  11,12 Re,Im rho_k ux_k*   13,14 Re,Im rho_k uy_k*
+ * where X_k = sum_x (X(x) - <X>) exp(-i k.x), k = 2 pi (kx/nx, ky/ny)
+ * (Sec. 3, text after Eq. 11), u = j / rho at each site. */
+
+/* Largest side for which correlators are supported. */
+#define FLB_MAX_FFT_SIDE 4096
+
+typedef struct flb flb_t;
+
+/* One lattice of a batch. */
+typedef struct flb_lattice_spec {
+    int32_t nx, ny;    /* sides, >= 2 */
+    double tau[9];     /* relaxation times per moment; tau[3..8] > 1/2 */
+    double theta;      /* noise temperature, >= 0 */
+    double rho0;       /* mean density, > 0 */
+    double u0[2];      /* imposed mean velocity, |u0| < 1/sqrt(3) */
+    uint32_t stream_id; /* third Philox counter word of this lattice */
+    uint32_t reserved;  /* must be 0 */
+} flb_lattice_spec;
+
+/* Creates one lattice in the uniform equilibrium f_i^0(rho0, u0) of Eq. (2)
+ * (c = 1), time t = 0, FP32 storage, stream_id 0, noise on all of 3..8.
+ * tau: 9 doubles (host).  u0: 2 doubles (host).  Returns NULL on invalid
+ * input (nx or ny < 2, non-finite values, rho0 <= 0, theta < 0,
+ * tau[a] <= 1/2 for a >= 3, |u0| >= c_s) or on allocation failure. */
+flb_t *flb_create(int nx, int ny, const double tau[9], double theta, double rho0,
+                  const double u0[2], uint64_t seed);
+
+/* As flb_create, with a storage format (FLB_STORAGE_*), the Philox stream id
+ * of the lattice and creation flags (FLB_FLAG_*). */
+flb_t *flb_create_ex(int nx, int ny, const double tau[9], double theta, double rho0,
+                     const double u0[2], uint64_t seed, int storage, uint32_t stream_id,
+                     uint32_t flags);
+
+/* Creates n >= 1 independent lattices (any mix of sizes and parameters) that
+ * step together: one launch advances all of them.  specs: n entries (host).
+ * All share the seed, storage and flags; each has its own stream_id, which
+ * should differ between lattices for independent noise. */
+flb_t *flb_create_batch(int n, const flb_lattice_spec *specs, uint64_t seed, int storage,
+                        uint32_t flags);
+
+/* Frees the handle and its device memory (after draining its stream).
+ * NULL is accepted. */
+void flb_destroy(flb_t *h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *flb_last_error(void);
+
+/* Makes the handle enqueue all later work on the HIP stream `hip_stream`
+ * (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream; NULL = the
+ * handle's own stream).  The caller keeps ownership of the stream and must
+ * keep it alive while the handle uses it. */
+int flb_set_stream(flb_t *h, void *hip_stream);
+
+/* Blocks until all work enqueued by the handle has finished. */
+int flb_synchronize(flb_t *h);
+
+/* Advances every lattice of the handle by nsteps >= 0 steps of Eq. (5) with
+ * streaming (Eq. 1).  Enqueues only. */
+int flb_step(flb_t *h, int64_t nsteps);
+
+/* Advances by nsteps and, after every step that reaches a time t with
+ * t % sample_every == 0, adds a correlator sample (sample_every = 0: no
+ * samples).  Whole periods of sample_every steps plus their sample are
+ * replayed from a captured HIP graph.  Enqueues only. */
+int flb_run(flb_t *h, int64_t nsteps, int sample_every);
+
+/* Adds one sample of the current state of every lattice to its FP64
+ * correlator sums (Eqs. 11-12, the kinds listed above), on the half plane
+ * kx = 0..nx/2, ky = 0..ny-1; the k = 0 entry is left unchanged (the mean is
+ * removed, Sec. 3).  FLB_ESIZE if a side exceeds FLB_MAX_FFT_SIDE.
+ * Enqueues only. */
+int flb_accumulate_correlators(flb_t *h);
+
+/* Copies lattice `lattice`'s raw FP64 sums to out[kind][ky][kx] (host), with
+ * kind < FLB_NKINDS, ky < ny, kx < nx/2+1, and writes the number of samples
+ * taken to *nsamples (may be NULL).  n_doubles must be at least
+ * FLB_NKINDS*ny*(nx/2+1), else FLB_ESIZE.  Synchronises. */
+int flb_read_correlators(flb_t *h, int lattice, double *out, size_t n_doubles,
+                         int64_t *nsamples);
+
+/* Zeroes every lattice's correlator sums and the sample count. */
+int flb_reset_correlators(flb_t *h);
+
+/* Copies lattice `lattice`'s populations f_i(x, t) to out[9][ny][nx] (host,
+ * FP64).  n must be at least 9*nx*ny.  Synchronises. */
+int flb_get_populations(flb_t *h, int lattice, double *out, size_t n);
+
+/* Replaces lattice `lattice`'s populations by in[9][ny][nx] (host, FP64 full
+ * values).  Values are rounded to the storage format.  Synchronises. */
+int flb_set_populations(flb_t *h, int lattice, const double *in, size_t n);
+
+/* FP64 sums over lattice `lattice`: out[0] = sum (rho - rho0),
+ * out[1..2] = sum j, out[3] = sum (-1)^x j_x, out[4] = sum (-1)^y j_y.
+ * The first three are conserved by Eq. (5); for even sides the staggered
+ * sums change sign every step.  Any non-finite population makes the sums
+ * non-finite.  Synchronises. */
+int flb_conservation(flb_t *h, int lattice, double out[5]);
+
+/* As flb_conservation, but enqueue-only: the five sums are written to
+ * out_dev, 5 doubles of DEVICE memory (e.g. a torch tensor's data_ptr())
+ * owned by the caller. */
+int flb_conservation_dev(flb_t *h, int lattice, double *out_dev);
+
+/* Equilibrium-fluctuation start: adds sqrt(mu rho0 w_i) z_i(x) to every
+ * population, z_0..z_8 being the first nine normals of the counters
+ * (site, 0xffffffff, stream_id, d), d = 0, 1, then removes each
+ * population's spatial mean of what was added, so totals are unchanged. */
+int flb_thermalize(flb_t *h);
+
+/* Noise of lattice `lattice` at step t for sites site0 .. site0+nsites-1:
+ * words_out[4*nsites] (may be NULL) gets the Philox words, z_out[6*nsites]
+ * (may be NULL) the six normals as computed by the step kernel.
+ * Synchronises.  For testing. */
+int flb_debug_noise(flb_t *h, int lattice, uint32_t t, int64_t site0, int64_t nsites,
+                    uint32_t *words_out, float *z_out);
+
+/* Number of steps taken so far (the t of the next step). */
+int64_t flb_get_step(flb_t *h);
+
+/* Number of lattices in the handle (-1 on error). */
+int flb_num_lattices(flb_t *h);
+
+/* Sides of lattice `lattice` and the kx extent nx/2+1 of its correlators. */
+int flb_lattice_info(flb_t *h, int lattice, int32_t *nx, int32_t *ny, int32_t *nkx);
+
+/* Storage format and bytes per population value. */
+int flb_storage_info(flb_t *h, int32_t *storage, int32_t *bytes_per_value);
+
+/* Launch shape of the step kernel: tiles of tile_w sites along x (64, 128
+ * or 256) by 256/tile_w thread rows, each thread updating `rows` rows (1, 2
+ * or 4 depending on tile_w), and streaming (non-temporal) stores on or off.
+ * Results do not depend on it.  FLB_EINVAL for an unsupported shape. */
+int flb_set_step_config(flb_t *h, int tile_w, int rows, int nontemporal);
+int flb_get_step_config(flb_t *h, int *tile_w, int *rows, int *nontemporal);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLB_H */

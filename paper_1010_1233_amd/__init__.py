@@ -1,0 +1,310 @@
+"""MI355X (gfx950) fluctuating ideal-gas lattice Boltzmann library.
+
+Python binding of ``libflb.so`` (C interface in ``include/flb.h``): argument
+marshalling only; every step of the method runs in the library's HIP
+kernels.  PyTorch, when used, only supplies streams (``set_stream``).
+
+The library must have been built (``python -m paper_1010_1233_amd.build``);
+importing the package does not load it, the first use does, and a missing
+library raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libflb.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "flb.h")
+
+OK, EINVAL, ENOMEM, EHIP, ESIZE, ESTATE = 0, -1, -2, -3, -4, -5
+STORAGE = {"f32": 0, "bf16": 1, "f16": 2}
+FLAG_NO_GHOST_NOISE = 1
+NKINDS = 15
+KINDS = ("rho_rho", "jx_jx", "jy_jy", "ux_ux", "uy_uy",
+         "re_ux_uy", "im_ux_uy", "re_rho_jx", "im_rho_jx", "re_rho_jy", "im_rho_jy",
+         "re_rho_ux", "im_rho_ux", "re_rho_uy", "im_rho_uy")
+
+
+class FlbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"flb error {code}: {msg}")
+        self.code = code
+
+
+class LatticeSpec(ctypes.Structure):
+    """Mirror of ``flb_lattice_spec``."""
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("tau", ctypes.c_double * 9), ("theta", ctypes.c_double),
+                ("rho0", ctypes.c_double), ("u0", ctypes.c_double * 2),
+                ("stream_id", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_intp = ctypes.POINTER(ctypes.c_int)
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "flb_create": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double,
+                                     ctypes.c_double, _dp, ctypes.c_uint64]),
+    "flb_create_ex": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double,
+                                        ctypes.c_double, _dp, ctypes.c_uint64, ctypes.c_int,
+                                        ctypes.c_uint32, ctypes.c_uint32]),
+    "flb_create_batch": (ctypes.c_void_p, [ctypes.c_int, ctypes.POINTER(LatticeSpec),
+                                           ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32]),
+    "flb_destroy": (None, [ctypes.c_void_p]),
+    "flb_last_error": (ctypes.c_char_p, []),
+    "flb_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "flb_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
+    "flb_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "flb_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int]),
+    "flb_accumulate_correlators": (ctypes.c_int, [ctypes.c_void_p]),
+    "flb_read_correlators": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_size_t,
+                                            _i64p]),
+    "flb_reset_correlators": (ctypes.c_int, [ctypes.c_void_p]),
+    "flb_get_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_size_t]),
+    "flb_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_size_t]),
+    "flb_conservation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp]),
+    "flb_conservation_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "flb_thermalize": (ctypes.c_int, [ctypes.c_void_p]),
+    "flb_debug_noise": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32,
+                                       ctypes.c_int64, ctypes.c_int64, _u32p, _fp]),
+    "flb_get_step": (ctypes.c_int64, [ctypes.c_void_p]),
+    "flb_num_lattices": (ctypes.c_int, [ctypes.c_void_p]),
+    "flb_lattice_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _i32p, _i32p, _i32p]),
+    "flb_storage_info": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i32p]),
+    "flb_set_step_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int]),
+    "flb_get_step_config": (ctypes.c_int, [ctypes.c_void_p, _intp, _intp, _intp]),
+}
+
+
+def lib():
+    """Load libflb.so (raises if it has not been built).
+
+    PyTorch ships its own HIP runtime under the same soname as the system
+    one; whichever is loaded first serves the whole process.  torch is
+    therefore imported first (when installed) so that the library and torch
+    share torch's runtime, streams and events.
+    """
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1010_1233_amd.build`")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error():
+    return lib().flb_last_error().decode()
+
+
+def _check(rc):
+    if rc != OK:
+        raise FlbError(rc, last_error())
+    return rc
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def make_spec(nx, ny, tau, theta, rho0=1.0, u0=(0.0, 0.0), stream_id=0):
+    s = LatticeSpec()
+    s.nx, s.ny = int(nx), int(ny)
+    for a in range(9):
+        s.tau[a] = float(tau[a])
+    s.theta, s.rho0 = float(theta), float(rho0)
+    s.u0[0], s.u0[1] = float(u0[0]), float(u0[1])
+    s.stream_id = int(stream_id)
+    s.reserved = 0
+    return s
+
+
+class Lattice:
+    """One handle of the library: a single lattice or a batch of lattices.
+
+    ``Lattice(nx, ny, tau, theta, ...)`` creates one lattice;
+    ``Lattice.batch(specs, ...)`` many that step together.
+    """
+
+    def __init__(self, nx=None, ny=None, tau=None, theta=None, rho0=1.0, u0=(0.0, 0.0),
+                 seed=1, storage="f32", stream_id=0, ladd=False, _handle=None):
+        L = lib()
+        if _handle is None:
+            t = np.ascontiguousarray(tau, dtype=np.float64)
+            u = np.ascontiguousarray(u0, dtype=np.float64)
+            flags = FLAG_NO_GHOST_NOISE if ladd else 0
+            _handle = L.flb_create_ex(int(nx), int(ny), _dptr(t), float(theta), float(rho0),
+                                      _dptr(u), int(seed), STORAGE[storage], int(stream_id),
+                                      flags)
+            if not _handle:
+                raise FlbError(EINVAL, last_error())
+        self._h = _handle
+        self.nlattices = L.flb_num_lattices(self._h)
+        self._shapes = []
+        for i in range(self.nlattices):
+            nx_, ny_, nk_ = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            _check(L.flb_lattice_info(self._h, i, ctypes.byref(nx_), ctypes.byref(ny_),
+                                      ctypes.byref(nk_)))
+            self._shapes.append((nx_.value, ny_.value, nk_.value))
+        self.nx, self.ny, self.nkx = self._shapes[0]
+
+    @classmethod
+    def batch(cls, specs, seed=1, storage="f32", ladd=False):
+        """specs: list of dicts with nx, ny, tau, theta, rho0, u0, stream_id."""
+        arr = (LatticeSpec * len(specs))()
+        for i, s in enumerate(specs):
+            arr[i] = make_spec(s["nx"], s["ny"], s["tau"], s["theta"], s.get("rho0", 1.0),
+                               s.get("u0", (0.0, 0.0)), s.get("stream_id", i))
+        h = lib().flb_create_batch(len(specs), arr, int(seed), STORAGE[storage],
+                                   FLAG_NO_GHOST_NOISE if ladd else 0)
+        if not h:
+            raise FlbError(EINVAL, last_error())
+        return cls(_handle=h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().flb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def shape(self, lattice=0):
+        return self._shapes[lattice]
+
+    # --- stepping -------------------------------------------------------
+    def set_stream(self, stream):
+        """stream: a torch.cuda.Stream, a raw hipStream_t integer, or None."""
+        ptr = getattr(stream, "cuda_stream", stream)
+        _check(lib().flb_set_stream(self._h, ctypes.c_void_p(ptr) if ptr else None))
+
+    def synchronize(self):
+        _check(lib().flb_synchronize(self._h))
+
+    def step(self, n=1):
+        _check(lib().flb_step(self._h, int(n)))
+
+    def run(self, nsteps, sample_every=0):
+        _check(lib().flb_run(self._h, int(nsteps), int(sample_every)))
+
+    @property
+    def t(self):
+        return int(lib().flb_get_step(self._h))
+
+    def set_step_config(self, tile_w, rows, nontemporal):
+        _check(lib().flb_set_step_config(self._h, int(tile_w), int(rows), int(nontemporal)))
+
+    def step_config(self):
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().flb_get_step_config(self._h, ctypes.byref(a), ctypes.byref(b),
+                                         ctypes.byref(c)))
+        return a.value, b.value, bool(c.value)
+
+    def storage_info(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().flb_storage_info(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    # --- state ----------------------------------------------------------
+    def get_populations(self, lattice=0):
+        nx, ny, _ = self._shapes[lattice]
+        out = np.empty((9, ny, nx), dtype=np.float64)
+        _check(lib().flb_get_populations(self._h, lattice, _dptr(out), out.size))
+        return out
+
+    def set_populations(self, f, lattice=0):
+        nx, ny, _ = self._shapes[lattice]
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        if f.shape != (9, ny, nx):
+            raise ValueError(f"expected shape (9, {ny}, {nx}), got {f.shape}")
+        _check(lib().flb_set_populations(self._h, lattice, _dptr(f), f.size))
+
+    def conservation(self, lattice=0):
+        out = np.zeros(5)
+        _check(lib().flb_conservation(self._h, lattice, _dptr(out)))
+        return out
+
+    def conservation_dev(self, out_ptr, lattice=0):
+        """Enqueue the five FP64 sums into device memory at out_ptr."""
+        _check(lib().flb_conservation_dev(self._h, lattice, ctypes.c_void_p(int(out_ptr))))
+
+    def thermalize(self):
+        _check(lib().flb_thermalize(self._h))
+
+    def debug_noise(self, t, site0, nsites, lattice=0):
+        w = np.zeros((int(nsites), 4), dtype=np.uint32)
+        z = np.zeros((int(nsites), 6), dtype=np.float32)
+        _check(lib().flb_debug_noise(self._h, lattice, int(t), int(site0), int(nsites),
+                                     w.ctypes.data_as(_u32p), z.ctypes.data_as(_fp)))
+        return w, z
+
+    # --- correlators ----------------------------------------------------
+    def accumulate(self):
+        _check(lib().flb_accumulate_correlators(self._h))
+
+    def reset_correlators(self):
+        _check(lib().flb_reset_correlators(self._h))
+
+    def read_correlators(self, lattice=0):
+        """(raw FP64 sums [15][ny][nx//2+1], number of samples)."""
+        nx, ny, nk = self._shapes[lattice]
+        out = np.empty((NKINDS, ny, nk), dtype=np.float64)
+        ns = ctypes.c_int64()
+        _check(lib().flb_read_correlators(self._h, lattice, _dptr(out), out.size,
+                                          ctypes.byref(ns)))
+        return out, ns.value
+
+
+def normalize(acc, nsamples, nx, ny, theta, rho0):
+    """Normalised correlators from raw sums (host arithmetic of the library).
+
+    S(rho) = <|rho_k|^2> / (V mu rho0) with mu = 3 theta (Eq. 11, N^rho at the
+    noise temperature); S(j_a) = <|j_a|^2> / (V rho0 theta);
+    S(u_a) = rho0 <|u_a|^2> / (V theta) (N^{u_a} = 1/(rho0 V k_B T));
+    R(u_x, u_y) = rho0 <u_x u_y*> / (V theta) (Eq. 12);
+    R(rho, j_a) = <rho j_a*> / (V mu rho0 c_s); R(rho, u_a) = <rho u_a*> / (V mu c_s).
+    """
+    V = float(nx) * float(ny)
+    mu = 3.0 * theta
+    cs = 3.0 ** -0.5
+    m = np.asarray(acc) / max(int(nsamples), 1)
+    return {
+        "S_rho": m[0] / (V * mu * rho0),
+        "S_jx": m[1] / (V * rho0 * theta),
+        "S_jy": m[2] / (V * rho0 * theta),
+        "S_ux": rho0 * m[3] / (V * theta),
+        "S_uy": rho0 * m[4] / (V * theta),
+        "R_uxuy": rho0 * (m[5] + 1j * m[6]) / (V * theta),
+        "R_rhojx": (m[7] + 1j * m[8]) / (V * mu * rho0 * cs),
+        "R_rhojy": (m[9] + 1j * m[10]) / (V * mu * rho0 * cs),
+        "R_rhoux": (m[11] + 1j * m[12]) / (V * mu * cs),
+        "R_rhouy": (m[13] + 1j * m[14]) / (V * mu * cs),
+    }

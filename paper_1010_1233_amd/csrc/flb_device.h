@@ -1,0 +1,117 @@
+// flb_device.h -- device-side building blocks of the gfx950 kernels:
+// the Philox4x32-10 noise stream, the normals derived from it, and the
+// population storage codecs.
+#pragma once
+
+#include "flb_internal.h"
+
+namespace flbdev {
+
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, SC'11).  The key
+// is wave-uniform, so its schedule lives in scalar registers; each round is
+// two 32x32->64 multiplies and two three-way xors.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Six unit normals from one draw (the layout documented in flb.h).  The
+// uniforms are exact in FP32: (2k+1) 2^-24 with k < 2^23 and (2a+1) 2^-20
+// with a < 2^19.  The angle is passed to the hardware sine/cosine in
+// revolutions, so 2 pi a needs no range reduction.
+__device__ __forceinline__ void normals6(uint4 w, float z[6])
+{
+    const uint32_t wv[3] = {w.x, w.y, w.z};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const float r = fmaf((float)(wv[p] >> 9), 0x1p-23f, 0x1p-24f);
+        const uint32_t al = ((wv[p] & 0x1FFu) << 10) | ((w.w >> (10 * p)) & 0x3FFu);
+        const float a = fmaf((float)al, 0x1p-19f, 0x1p-20f);
+        const float R = __builtin_amdgcn_sqrtf(-2.0f * logf(r));
+        z[2 * p] = R * __builtin_amdgcn_cosf(a);
+        z[2 * p + 1] = R * __builtin_amdgcn_sinf(a);
+    }
+}
+
+// ---------------------------------------------------------------------
+// Storage codecs.  FP32 keeps the deviation d = f - w rho0 itself; the
+// 16-bit formats keep q = (d - feq) / scale, rounded to nearest even.
+// ---------------------------------------------------------------------
+template <int S> struct Codec;
+
+template <> struct Codec<kF32> {
+    using T = float;
+    static __device__ __forceinline__ float decode(T v, const LatticeParams &, int) { return v; }
+    static __device__ __forceinline__ T encode(float d, const LatticeParams &, int) { return d; }
+};
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h)
+{
+    return __uint_as_float((uint32_t)h << 16);
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u)           // inf / nan: keep, quiet nans
+        return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+    u += 0x7FFFu + ((u >> 16) & 1u);                // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+template <> struct Codec<kBF16> {
+    using T = uint16_t;
+    static __device__ __forceinline__ float decode(T v, const LatticeParams &P, int i)
+    {
+        return fmaf(bf16_to_f32(v), P.scale[i], P.feq[i]);
+    }
+    static __device__ __forceinline__ T encode(float d, const LatticeParams &P, int i)
+    {
+        return f32_to_bf16((d - P.feq[i]) * P.inv_scale[i]);
+    }
+};
+
+template <> struct Codec<kF16> {
+    using T = _Float16;
+    static __device__ __forceinline__ float decode(T v, const LatticeParams &P, int i)
+    {
+        return fmaf((float)v, P.scale[i], P.feq[i]);
+    }
+    static __device__ __forceinline__ T encode(float d, const LatticeParams &P, int i)
+    {
+        return (T)((d - P.feq[i]) * P.inv_scale[i]);
+    }
+};
+
+// Plain or streaming (non-temporal) global stores.
+template <bool NT, typename T> __device__ __forceinline__ void gstore(T *p, T v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+// D2Q9 velocities in the order of Sec. 3.
+__device__ constexpr int kVX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int kVY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+__device__ __forceinline__ int wrap_add(int x, int d, int n)
+{
+    int r = x + d;
+    r = (r < 0) ? r + n : r;
+    r = (r >= n) ? r - n : r;
+    return r;
+}
+
+}  // namespace flbdev

@@ -1,0 +1,123 @@
+// flb_internal.h -- data shared by the host runtime and the gfx950 kernels.
+//
+// Device layout of one handle (all lattices of a batch share each buffer):
+//   pops[2]  : two population buffers (ping-pong), per lattice 9 planes of
+//              nx*ny values in the storage format, plane i at base + i*plane.
+//              They hold the POST-collision state of the last step; the
+//              state at time t (just after streaming) is
+//              f_i(x) = stored_i(x - v_i): every kernel that needs f(x)
+//              gathers, the step kernel streams by gathering ("pull").
+//   step     : one uint32 on the device, the time t of the next step, so
+//              that captured graphs replay with advancing noise counters.
+//   spec     : complex64 scratch for the correlator transforms, per lattice
+//              5 fields x ny x nkx (the half spectra of the real fields).
+//   acc      : FP64 correlator sums, per lattice FLB_NKINDS x ny x nkx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace flbdev {
+
+constexpr int kThreads = 256;
+constexpr int kFields = 5;   // delta rho, delta jx, delta jy, delta ux, delta uy
+constexpr int kKinds = 15;
+
+// Per-lattice constants, read by every kernel through scalar loads.
+struct alignas(16) LatticeParams {
+    int32_t nx, ny;
+    int32_t nkx;              // nx/2 + 1
+    int32_t tiles_x;          // step tiles along x
+    int64_t base;             // element offset of population 0 in pops[]
+    int64_t plane;            // nx*ny
+    int64_t spec_base;        // complex offset of field 0 in spec
+    int64_t acc_base;         // double offset of kind 0 in acc
+    float omega[6];           // 1/tau^a, a = 3..8
+    float amp[6];             // noise amplitude per scaled moment, a = 3..8
+    float rho0, u0x, u0y;
+    float feq[9];             // f_i^0(rho0,u0) - w_i rho0 (16-bit reference state)
+    float scale[9];           // sqrt(mu rho0 w_i) (16-bit storage scale)
+    float inv_scale[9];
+    float therm_amp[9];       // sqrt(mu rho0 w_i) for the thermal start
+    uint32_t stream_id;
+    int32_t line_x;           // index of the x-direction line plan
+    int32_t line_y;           // index of the y-direction line plan
+    int32_t pad0;
+};
+
+// How to transform one line of length n in LDS.  Powers of two are done
+// directly; other lengths by Bluestein's chirp-z convolution of length m.
+struct alignas(16) LinePlan {
+    int32_t n;                // transform length
+    int32_t m;                // power-of-two work length (n itself, or >= 2n-1)
+    int32_t bluestein;        // 0 or 1
+    int32_t log2m;
+    int64_t chirp_off;        // float2 offset of exp(-i pi j^2 / n), j < n
+    int64_t kernel_off;       // float2 offset of the length-m FFT of the chirp kernel
+};
+
+// Twiddle table: exp(-2 pi i k / kTwN), k < kTwN/2, for every power-of-two
+// work length up to kTwN.
+constexpr int kTwLog = 13;
+constexpr int kTwN = 1 << kTwLog;
+
+// Work item of the step kernel: lattice and tile index (lattice -1 = idle).
+struct StepItem {
+    int32_t lattice;
+    int32_t tile;
+};
+
+// Work item of the row transform: lattice and row; of the column transform:
+// lattice, field and first column; of the accumulation: lattice and first k.
+struct CorrItem {
+    int32_t lattice;
+    int32_t a;
+    int32_t b;
+    int32_t c;
+};
+
+enum Storage : int { kF32 = 0, kBF16 = 1, kF16 = 2 };
+
+// ---------------------------------------------------------------------
+// Kernel launchers (implemented in the .hip files).
+// ---------------------------------------------------------------------
+struct DeviceView {
+    void *pops[2];
+    int cur;                          // index of the buffer holding the state
+    const LatticeParams *params;      // device
+    const uint32_t *step;             // device step counter
+    uint32_t *step_rw;
+    float2 *spec;
+    double *acc;
+    const LinePlan *plans;            // device
+    const float2 *tables;             // device: twiddles, chirps, kernels
+    uint64_t seed;
+    int storage;
+    int nlat;
+};
+
+hipError_t launch_step(const DeviceView &v, const StepItem *items, int nitems, int tile_w,
+                       int rows, uint32_t step_add, bool nontemporal, bool noise,
+                       hipStream_t s);
+bool step_tile_supported(int tw, int r);
+hipError_t launch_advance_step(uint32_t *step, uint32_t n, hipStream_t s);
+hipError_t launch_init(const DeviceView &v, int lattice, int64_t plane, hipStream_t s);
+hipError_t launch_get(const DeviceView &v, int lattice, int nx, int ny, double *out_dev,
+                      hipStream_t s);
+hipError_t launch_set(const DeviceView &v, int lattice, int nx, int ny, const double *in_dev,
+                      hipStream_t s);
+hipError_t launch_conservation(const DeviceView &v, int lattice, int nx, int ny, double *part,
+                               int nblocks, double *out_dev, hipStream_t s);
+hipError_t launch_thermalize(const DeviceView &v, int lattice, int nx, int ny, double *part,
+                             int nblocks, double *mean_dev, hipStream_t s);
+hipError_t launch_debug_noise(uint64_t seed, uint32_t stream_id, uint32_t t, int64_t site0,
+                              int64_t n, uint32_t *words_dev, float *z_dev, hipStream_t s);
+hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems,
+                            int lds_bytes, hipStream_t s);
+hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int cb,
+                            int lds_bytes, hipStream_t s);
+hipError_t launch_corr_accum(const DeviceView &v, const CorrItem *items, int nitems,
+                             hipStream_t s);
+hipError_t launch_fill(double *p, size_t n, hipStream_t s);
+
+}  // namespace flbdev

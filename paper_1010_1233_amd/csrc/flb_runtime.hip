@@ -1,0 +1,843 @@
+// flb_runtime.hip -- host runtime behind the C interface of flb.h.
+//
+// A handle owns: the two population buffers of all its lattices, the
+// per-lattice constant table, the step-kernel work list (one item per
+// (lattice, tile), ordered so that each XCD receives a contiguous run of
+// tiles), the correlator work lists, line plans and tables, the FP64
+// accumulators, a device step counter, and captured HIP graphs of one
+// sampling period.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/flb.h"
+#include "flb_internal.h"
+
+using namespace flbdev;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define FLB_HIP(call)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(FLB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));       \
+    } while (0)
+
+constexpr double kCs2 = 1.0 / 3.0;
+const double kW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+const int kVx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+const int kVy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+struct GraphKey {
+    int every, parity;
+    bool operator<(const GraphKey &o) const
+    {
+        return every < o.every || (every == o.every && parity < o.parity);
+    }
+};
+
+}  // namespace
+
+struct flb {
+    int device = 0;
+    int storage = kF32;
+    int elem_bytes = 4;
+    uint32_t flags = 0;
+    uint64_t seed = 0;
+    std::vector<flb_lattice_spec> specs;
+    std::vector<LatticeParams> params;
+    int64_t total_elems = 0;  // per population buffer
+    bool noise = false;
+
+    // device memory
+    void *pops[2] = {nullptr, nullptr};
+    int cur = 0;
+    LatticeParams *d_params = nullptr;
+    uint32_t *d_step = nullptr;
+    double *d_red = nullptr;  // reduction scratch
+    int red_blocks = 1024;
+
+    // stepping
+    int tile_w = 256, rows = 1;
+    bool nontemporal = false;
+    StepItem *d_items = nullptr;
+    int nitems = 0;
+    int64_t t = 0;
+
+    // correlators
+    bool corr_ready = false;
+    std::vector<LinePlan> plans;
+    LinePlan *d_plans = nullptr;
+    float2 *d_tables = nullptr;
+    float2 *d_spec = nullptr;
+    double *d_acc = nullptr;
+    int64_t spec_elems = 0, acc_elems = 0;
+    CorrItem *d_rows = nullptr, *d_cols = nullptr, *d_accum = nullptr;
+    int n_rows = 0, n_cols = 0, n_accum = 0;
+    int rows_lds = 0, cols_lds = 0, cols_cb = 1;
+    int64_t nsamples = 0;
+
+    // streams and graphs
+    hipStream_t own = nullptr;
+    hipStream_t stream = nullptr;  // where work is enqueued
+    hipEvent_t ev = nullptr;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+
+    DeviceView view() const
+    {
+        DeviceView v;
+        v.pops[0] = pops[0];
+        v.pops[1] = pops[1];
+        v.cur = cur;
+        v.params = d_params;
+        v.step = d_step;
+        v.step_rw = d_step;
+        v.spec = d_spec;
+        v.acc = d_acc;
+        v.plans = d_plans;
+        v.tables = d_tables;
+        v.seed = seed;
+        v.storage = storage;
+        v.nlat = (int)params.size();
+        return v;
+    }
+};
+
+namespace {
+
+bool finite(double v) { return std::isfinite(v); }
+
+int validate_spec(const flb_lattice_spec &s, int idx)
+{
+    char buf[256];
+    if (s.nx < 2 || s.ny < 2) {
+        snprintf(buf, sizeof buf, "lattice %d: nx and ny must be >= 2 (got %d x %d)", idx, s.nx,
+                 s.ny);
+        return fail(FLB_EINVAL, buf);
+    }
+    if ((int64_t)s.nx * s.ny * 9 >= (int64_t)1 << 31) {
+        snprintf(buf, sizeof buf, "lattice %d: 9*nx*ny must stay below 2^31", idx);
+        return fail(FLB_ESIZE, buf);
+    }
+    for (int a = 0; a < 9; ++a)
+        if (!finite(s.tau[a])) return fail(FLB_EINVAL, "tau must be finite");
+    for (int a = 3; a < 9; ++a)
+        if (!(s.tau[a] > 0.5)) {
+            snprintf(buf, sizeof buf, "lattice %d: tau[%d] = %g must exceed 1/2", idx, a, s.tau[a]);
+            return fail(FLB_EINVAL, buf);
+        }
+    if (!finite(s.theta) || s.theta < 0) return fail(FLB_EINVAL, "theta must be finite and >= 0");
+    if (!finite(s.rho0) || !(s.rho0 > 0)) return fail(FLB_EINVAL, "rho0 must be finite and > 0");
+    if (!finite(s.u0[0]) || !finite(s.u0[1])) return fail(FLB_EINVAL, "u0 must be finite");
+    if (s.u0[0] * s.u0[0] + s.u0[1] * s.u0[1] >= kCs2)
+        return fail(FLB_EINVAL, "|u0| must be below the sound speed 1/sqrt(3)");
+    if (s.reserved != 0) return fail(FLB_EINVAL, "reserved field must be 0");
+    return FLB_OK;
+}
+
+LatticeParams make_params(const flb_lattice_spec &s, uint32_t flags)
+{
+    LatticeParams P;
+    std::memset(&P, 0, sizeof P);
+    P.nx = s.nx;
+    P.ny = s.ny;
+    P.nkx = s.nx / 2 + 1;
+    P.plane = (int64_t)s.nx * s.ny;
+    const double mu = s.theta / kCs2;
+    // scale of each stored moment relative to M^a: s3 = 3/2 M3, s4 = 3 M4,
+    // s5 = M5, s6,7 = sqrt(3/2) M6,7, s8 = M8
+    const double mscale[6] = {1.5, 3.0, 1.0, std::sqrt(1.5), std::sqrt(1.5), 1.0};
+    for (int a = 3; a < 9; ++a) {
+        const double tau = s.tau[a];
+        P.omega[a - 3] = (float)(1.0 / tau);
+        double sigma = std::sqrt(mu * s.rho0 * (2.0 * tau - 1.0)) / tau;  // Eq. (8)
+        if ((flags & FLB_FLAG_NO_GHOST_NOISE) && a >= 6) sigma = 0.0;
+        P.amp[a - 3] = (float)(mscale[a - 3] * sigma);
+    }
+    P.rho0 = (float)s.rho0;
+    P.u0x = (float)s.u0[0];
+    P.u0y = (float)s.u0[1];
+    const double uu = s.u0[0] * s.u0[0] + s.u0[1] * s.u0[1];
+    const double mu_store = std::max(mu, 3e-4);  // 16-bit scale when theta is tiny or zero
+    for (int i = 0; i < 9; ++i) {
+        const double uv = s.u0[0] * kVx[i] + s.u0[1] * kVy[i];
+        // Eq. (2), c = 1, minus w_i rho0
+        P.feq[i] = (float)(s.rho0 * kW[i] * (3.0 * uv + 4.5 * uv * uv - 1.5 * uu));
+        P.scale[i] = (float)std::sqrt(mu_store * s.rho0 * kW[i]);
+        P.inv_scale[i] = 1.0f / P.scale[i];
+        P.therm_amp[i] = (float)std::sqrt(mu * s.rho0 * kW[i]);
+    }
+    P.stream_id = s.stream_id;
+    return P;
+}
+
+// XCD-aware order: blocks are dispatched round-robin over the 8 XCDs, so
+// block b runs on XCD b % 8.  Give each XCD a contiguous run of work items so
+// that neighbouring tiles (which share cache lines and halo rows) meet in the
+// same L2.
+template <typename T>
+std::vector<T> xcd_order(const std::vector<T> &in, const T &idle)
+{
+    const int nx = 8;
+    const size_t n = in.size();
+    const size_t per = (n + nx - 1) / nx;
+    std::vector<T> out(per * nx, idle);
+    for (size_t b = 0; b < out.size(); ++b) {
+        const size_t j = (b % nx) * per + b / nx;
+        if (j < n) out[b] = in[j];
+    }
+    return out;
+}
+
+template <typename T>
+int upload(T **dptr, const std::vector<T> &v)
+{
+    if (*dptr) {
+        (void)hipFree(*dptr);
+        *dptr = nullptr;
+    }
+    if (v.empty()) return FLB_OK;
+    FLB_HIP(hipMalloc((void **)dptr, v.size() * sizeof(T)));
+    FLB_HIP(hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return FLB_OK;
+}
+
+int build_step_items(flb_t *h)
+{
+    const int TH = kThreads / h->tile_w;
+    std::vector<StepItem> items;
+    for (size_t l = 0; l < h->params.size(); ++l) {
+        LatticeParams &P = h->params[l];
+        P.tiles_x = (P.nx + h->tile_w - 1) / h->tile_w;
+        const int tiles_y = (P.ny + TH * h->rows - 1) / (TH * h->rows);
+        for (int t = 0; t < P.tiles_x * tiles_y; ++t) items.push_back({(int32_t)l, t});
+    }
+    items = xcd_order(items, StepItem{-1, 0});
+    h->nitems = (int)items.size();
+    int rc = upload(&h->d_items, items);
+    if (rc) return rc;
+    return upload(&h->d_params, h->params);
+}
+
+void clear_graphs(flb_t *h)
+{
+    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+}
+
+int is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int log2i(int n)
+{
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+// In-place radix-2 transform on the host, FP64 (for the Bluestein kernel).
+void host_fft(std::vector<std::complex<double>> &a)
+{
+    const int n = (int)a.size();
+    for (int i = 1, j = 0; i < n; ++i) {
+        int bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(a[i], a[j]);
+    }
+    for (int len = 2; len <= n; len <<= 1) {
+        for (int k = 0; k < len / 2; ++k) {
+            const double ang = -2.0 * M_PI * k / len;
+            const std::complex<double> w(std::cos(ang), std::sin(ang));
+            for (int b = 0; b < n; b += len) {
+                const auto u = a[b + k], v = w * a[b + k + len / 2];
+                a[b + k] = u + v;
+                a[b + k + len / 2] = u - v;
+            }
+        }
+    }
+}
+
+int setup_correlators(flb_t *h)
+{
+    if (h->corr_ready) return FLB_OK;
+    // tables below replace device buffers that queued kernels may still read
+    FLB_HIP(hipStreamSynchronize(h->stream));
+    for (auto &P : h->params)
+        if (P.nx > FLB_MAX_FFT_SIDE || P.ny > FLB_MAX_FFT_SIDE)
+            return fail(FLB_ESIZE, "correlators support sides up to FLB_MAX_FFT_SIDE");
+
+    // tables: twiddles, then chirp and kernel of every Bluestein length
+    std::vector<float2> tables(kTwN / 2);
+    for (int k = 0; k < kTwN / 2; ++k) {
+        const double ang = -2.0 * M_PI * k / kTwN;
+        tables[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    std::map<int, int> plan_of;
+    h->plans.clear();
+    auto plan_for = [&](int n) {
+        auto it = plan_of.find(n);
+        if (it != plan_of.end()) return it->second;
+        LinePlan L;
+        std::memset(&L, 0, sizeof L);
+        L.n = n;
+        if (is_pow2(n)) {
+            L.m = n;
+            L.bluestein = 0;
+        } else {
+            L.m = 1 << log2i(2 * n - 1);
+            L.bluestein = 1;
+            L.chirp_off = (int64_t)tables.size();
+            std::vector<std::complex<double>> c(n);
+            for (int j = 0; j < n; ++j) {
+                const long long q = ((long long)j * j) % (2LL * n);  // exp(-i pi j^2 / n)
+                const double ang = -M_PI * (double)q / n;
+                c[j] = std::complex<double>(std::cos(ang), std::sin(ang));
+                tables.push_back(make_float2((float)c[j].real(), (float)c[j].imag()));
+            }
+            std::vector<std::complex<double>> b(L.m, 0.0);
+            for (int j = 0; j < n; ++j) {
+                b[j] = std::conj(c[j]);
+                if (j > 0) b[L.m - j] = std::conj(c[j]);
+            }
+            host_fft(b);
+            L.kernel_off = (int64_t)tables.size();
+            for (int j = 0; j < L.m; ++j) {
+                const auto v = b[j] / (double)L.m;  // inverse transform's 1/m folded in
+                tables.push_back(make_float2((float)v.real(), (float)v.imag()));
+            }
+        }
+        L.log2m = log2i(L.m);
+        const int id = (int)h->plans.size();
+        h->plans.push_back(L);
+        plan_of[n] = id;
+        return id;
+    };
+
+    int64_t spec = 0, acc = 0;
+    int max_mx = 1, max_my = 1;
+    for (auto &P : h->params) {
+        P.line_x = plan_for(P.nx);
+        P.line_y = plan_for(P.ny);
+        max_mx = std::max(max_mx, h->plans[P.line_x].m);
+        max_my = std::max(max_my, h->plans[P.line_y].m);
+        P.spec_base = spec;
+        P.acc_base = acc;
+        spec += (int64_t)kFields * P.ny * P.nkx;
+        acc += (int64_t)kKinds * P.ny * P.nkx;
+    }
+    h->spec_elems = spec;
+    h->acc_elems = acc;
+    h->rows_lds = max_mx * (int)sizeof(float2);
+    h->cols_cb = std::max(1, std::min(16, 8192 / max_my));
+    h->cols_lds = max_my * h->cols_cb * (int)sizeof(float2);
+
+    std::vector<CorrItem> rows, cols, accum;
+    for (size_t l = 0; l < h->params.size(); ++l) {
+        const LatticeParams &P = h->params[l];
+        for (int y = 0; y < P.ny; ++y) {
+            rows.push_back({(int32_t)l, y, 0, 0});
+            rows.push_back({(int32_t)l, y, 1, 0});
+            if ((y & 1) == 0) rows.push_back({(int32_t)l, y, 2, 0});
+        }
+        for (int f = 0; f < kFields; ++f)
+            for (int c0 = 0; c0 < P.nkx; c0 += h->cols_cb) cols.push_back({(int32_t)l, f, c0, 0});
+        const int64_t nk = (int64_t)P.ny * P.nkx;
+        for (int64_t k0 = 0; k0 < nk; k0 += kThreads) accum.push_back({(int32_t)l, (int32_t)k0, 0, 0});
+    }
+    const CorrItem idle{-1, 0, 0, 0};
+    rows = xcd_order(rows, idle);
+    cols = xcd_order(cols, idle);
+    h->n_rows = (int)rows.size();
+    h->n_cols = (int)cols.size();
+    h->n_accum = (int)accum.size();
+    int rc;
+    if ((rc = upload(&h->d_rows, rows)) || (rc = upload(&h->d_cols, cols)) ||
+        (rc = upload(&h->d_accum, accum)) || (rc = upload(&h->d_plans, h->plans)) ||
+        (rc = upload(&h->d_tables, tables)) || (rc = upload(&h->d_params, h->params)))
+        return rc;
+    FLB_HIP(hipMalloc((void **)&h->d_spec, spec * sizeof(float2)));
+    FLB_HIP(hipMalloc((void **)&h->d_acc, acc * sizeof(double)));
+    FLB_HIP(launch_fill(h->d_acc, (size_t)acc, h->stream));
+    h->nsamples = 0;
+    h->corr_ready = true;
+    clear_graphs(h);
+    return FLB_OK;
+}
+
+int enqueue_sample(flb_t *h, hipStream_t s)
+{
+    const DeviceView v = h->view();
+    FLB_HIP(launch_corr_rows(v, h->d_rows, h->n_rows, h->rows_lds, s));
+    FLB_HIP(launch_corr_cols(v, h->d_cols, h->n_cols, h->cols_cb, h->cols_lds, s));
+    FLB_HIP(launch_corr_accum(v, h->d_accum, h->n_accum, s));
+    return FLB_OK;
+}
+
+// n steps from the device counter value; the counter is advanced afterwards.
+int enqueue_steps(flb_t *h, int64_t n, hipStream_t s)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        FLB_HIP(launch_step(h->view(), h->d_items, h->nitems, h->tile_w, h->rows, (uint32_t)k,
+                            h->nontemporal, h->noise, s));
+        h->cur ^= 1;
+    }
+    if (n > 0) FLB_HIP(launch_advance_step(h->d_step, (uint32_t)n, s));
+    return FLB_OK;
+}
+
+int check_time(flb_t *h, int64_t n)
+{
+    if (n < 0) return fail(FLB_EINVAL, "nsteps must be >= 0");
+    if (h->t + n >= (int64_t)0xFFFFFFFF)
+        return fail(FLB_ESIZE, "the step counter is a 32-bit noise counter word; "
+                               "t must stay below 2^32 - 1");
+    return FLB_OK;
+}
+
+flb_t *create_impl(int n, const flb_lattice_spec *specs, uint64_t seed, int storage,
+                   uint32_t flags)
+{
+    if (n < 1 || !specs) {
+        fail(FLB_EINVAL, "need at least one lattice spec");
+        return nullptr;
+    }
+    if (storage != FLB_STORAGE_F32 && storage != FLB_STORAGE_BF16 && storage != FLB_STORAGE_F16) {
+        fail(FLB_EINVAL, "unknown storage format");
+        return nullptr;
+    }
+    if (flags & ~FLB_FLAG_NO_GHOST_NOISE) {
+        fail(FLB_EINVAL, "unknown flags");
+        return nullptr;
+    }
+    for (int l = 0; l < n; ++l)
+        if (validate_spec(specs[l], l) != FLB_OK) return nullptr;
+
+    flb_t *h = new flb_t();
+    h->storage = storage;
+    h->elem_bytes = storage == FLB_STORAGE_F32 ? 4 : 2;
+    h->flags = flags;
+    h->seed = seed;
+    h->specs.assign(specs, specs + n);
+    int64_t off = 0;
+    for (int l = 0; l < n; ++l) {
+        LatticeParams P = make_params(specs[l], flags);
+        P.base = off;
+        off += 9 * P.plane;
+        off = (off + 63) / 64 * 64;  // 256-byte aligned planes per lattice
+        for (int a = 0; a < 6; ++a) h->noise = h->noise || P.amp[a] != 0.0f;
+        h->params.push_back(P);
+    }
+    h->total_elems = off;
+    // streaming stores pay off once a buffer no longer fits the last-level cache
+    h->nontemporal = (double)off * h->elem_bytes > 256.0 * 1024 * 1024;
+
+    auto bail = [&](int rc) -> flb_t * {
+        (void)rc;
+        flb_destroy(h);
+        return nullptr;
+    };
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        fail(FLB_EHIP, "no HIP device");
+        return bail(0);
+    }
+    if (hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev, hipEventDisableTiming) != hipSuccess) {
+        fail(FLB_EHIP, "stream creation failed");
+        return bail(0);
+    }
+    h->stream = h->own;
+    const size_t bytes = (size_t)h->total_elems * h->elem_bytes;
+    for (int b = 0; b < 2; ++b)
+        if (hipMalloc(&h->pops[b], bytes) != hipSuccess) {
+            fail(FLB_ENOMEM, "population buffers: out of device memory");
+            return bail(0);
+        }
+    if (hipMalloc((void **)&h->d_step, sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&h->d_red, (size_t)(h->red_blocks * 9 + 16) * sizeof(double)) !=
+            hipSuccess) {
+        fail(FLB_ENOMEM, "scratch allocation failed");
+        return bail(0);
+    }
+    if (hipMemsetAsync(h->d_step, 0, sizeof(uint32_t), h->stream) != hipSuccess) {
+        fail(FLB_EHIP, "step counter reset failed");
+        return bail(0);
+    }
+    if (build_step_items(h) != FLB_OK) return bail(0);
+    for (int l = 0; l < n; ++l)
+        if (launch_init(h->view(), l, h->params[l].plane, h->stream) != hipSuccess) {
+            fail(FLB_EHIP, "init kernel launch failed");
+            return bail(0);
+        }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) {
+        fail(FLB_EHIP, "initialisation failed");
+        return bail(0);
+    }
+    return h;
+}
+
+int check_handle(flb_t *h)
+{
+    if (!h) return fail(FLB_EINVAL, "NULL handle");
+    return FLB_OK;
+}
+
+int check_lattice(flb_t *h, int lattice)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (lattice < 0 || lattice >= (int)h->params.size())
+        return fail(FLB_EINVAL, "lattice index out of range");
+    return FLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *flb_last_error(void) { return g_err.c_str(); }
+
+flb_t *flb_create_batch(int n, const flb_lattice_spec *specs, uint64_t seed, int storage,
+                        uint32_t flags)
+{
+    return create_impl(n, specs, seed, storage, flags);
+}
+
+flb_t *flb_create_ex(int nx, int ny, const double tau[9], double theta, double rho0,
+                     const double u0[2], uint64_t seed, int storage, uint32_t stream_id,
+                     uint32_t flags)
+{
+    if (!tau || !u0) {
+        fail(FLB_EINVAL, "tau and u0 must not be NULL");
+        return nullptr;
+    }
+    flb_lattice_spec s;
+    std::memset(&s, 0, sizeof s);
+    s.nx = nx;
+    s.ny = ny;
+    for (int a = 0; a < 9; ++a) s.tau[a] = tau[a];
+    s.theta = theta;
+    s.rho0 = rho0;
+    s.u0[0] = u0[0];
+    s.u0[1] = u0[1];
+    s.stream_id = stream_id;
+    return create_impl(1, &s, seed, storage, flags);
+}
+
+flb_t *flb_create(int nx, int ny, const double tau[9], double theta, double rho0,
+                  const double u0[2], uint64_t seed)
+{
+    return flb_create_ex(nx, ny, tau, theta, rho0, u0, seed, FLB_STORAGE_F32, 0, 0);
+}
+
+void flb_destroy(flb_t *h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->own) (void)hipStreamSynchronize(h->own);
+    clear_graphs(h);
+    void *ptrs[] = {h->pops[0], h->pops[1], h->d_params, h->d_step, h->d_red, h->d_items,
+                    h->d_plans, h->d_tables, h->d_spec, h->d_acc, h->d_rows, h->d_cols,
+                    h->d_accum};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (h->ev) (void)hipEventDestroy(h->ev);
+    if (h->own) (void)hipStreamDestroy(h->own);
+    delete h;
+}
+
+int flb_set_stream(flb_t *h, void *hip_stream)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : h->own;
+    if (s != h->stream) {
+        // order the new stream after everything already enqueued
+        FLB_HIP(hipEventRecord(h->ev, h->stream));
+        FLB_HIP(hipStreamWaitEvent(s, h->ev, 0));
+        h->stream = s;
+    }
+    return FLB_OK;
+}
+
+int flb_synchronize(flb_t *h)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    FLB_HIP(hipStreamSynchronize(h->stream));
+    return FLB_OK;
+}
+
+int flb_step(flb_t *h, int64_t nsteps)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    int rc = check_time(h, nsteps);
+    if (rc) return rc;
+    rc = enqueue_steps(h, nsteps, h->stream);
+    if (rc) return rc;
+    h->t += nsteps;
+    return FLB_OK;
+}
+
+int flb_accumulate_correlators(flb_t *h)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    int rc = setup_correlators(h);
+    if (rc) return rc;
+    rc = enqueue_sample(h, h->stream);
+    if (rc) return rc;
+    h->nsamples += 1;
+    return FLB_OK;
+}
+
+// One period of `every` steps followed by a sample, from a captured graph.
+static int run_period_graph(flb_t *h, int every)
+{
+    const GraphKey key{every, h->cur};
+    auto it = h->graphs.find(key);
+    if (it == h->graphs.end()) {
+        // capture on the handle's own stream (capturing the legacy default
+        // stream is not allowed), then launch on the current stream
+        const int cur0 = h->cur;
+        FLB_HIP(hipStreamBeginCapture(h->own, hipStreamCaptureModeRelaxed));
+        int rc = enqueue_steps(h, every, h->own);
+        if (!rc) rc = enqueue_sample(h, h->own);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(h->own, &g);
+        h->cur = cur0;
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(FLB_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess)
+            return fail(FLB_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        it = h->graphs.emplace(key, ex).first;
+    }
+    FLB_HIP(hipGraphLaunch(it->second, h->stream));
+    if (every & 1) h->cur ^= 1;
+    h->t += every;
+    h->nsamples += 1;
+    return FLB_OK;
+}
+
+int flb_run(flb_t *h, int64_t nsteps, int sample_every)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (sample_every < 0) return fail(FLB_EINVAL, "sample_every must be >= 0");
+    int rc = check_time(h, nsteps);
+    if (rc) return rc;
+    if (sample_every == 0) return flb_step(h, nsteps);
+    rc = setup_correlators(h);
+    if (rc) return rc;
+    while (nsteps > 0) {
+        const int64_t phase = h->t % sample_every;
+        if (phase == 0 && nsteps >= sample_every) {
+            rc = run_period_graph(h, sample_every);
+            if (rc) return rc;
+            nsteps -= sample_every;
+            continue;
+        }
+        const int64_t to_sample = sample_every - phase;
+        const int64_t n = std::min(nsteps, to_sample);
+        rc = flb_step(h, n);
+        if (rc) return rc;
+        nsteps -= n;
+        if (n == to_sample) {
+            rc = flb_accumulate_correlators(h);
+            if (rc) return rc;
+        }
+    }
+    return FLB_OK;
+}
+
+int flb_read_correlators(flb_t *h, int lattice, double *out, size_t n_doubles, int64_t *nsamples)
+{
+    if (check_lattice(h, lattice)) return FLB_EINVAL;
+    if (!out) return fail(FLB_EINVAL, "out must not be NULL");
+    int rc = setup_correlators(h);
+    if (rc) return rc;
+    const LatticeParams &P = h->params[lattice];
+    const size_t need = (size_t)kKinds * P.ny * P.nkx;
+    if (n_doubles < need) return fail(FLB_ESIZE, "output buffer too small for the correlators");
+    FLB_HIP(hipStreamSynchronize(h->stream));
+    FLB_HIP(hipMemcpy(out, h->d_acc + P.acc_base, need * sizeof(double), hipMemcpyDeviceToHost));
+    if (nsamples) *nsamples = h->nsamples;
+    return FLB_OK;
+}
+
+int flb_reset_correlators(flb_t *h)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    int rc = setup_correlators(h);
+    if (rc) return rc;
+    FLB_HIP(launch_fill(h->d_acc, (size_t)h->acc_elems, h->stream));
+    h->nsamples = 0;
+    return FLB_OK;
+}
+
+int flb_get_populations(flb_t *h, int lattice, double *out, size_t n)
+{
+    if (check_lattice(h, lattice)) return FLB_EINVAL;
+    if (!out) return fail(FLB_EINVAL, "out must not be NULL");
+    const LatticeParams &P = h->params[lattice];
+    const size_t need = 9 * (size_t)P.plane;
+    if (n < need) return fail(FLB_ESIZE, "output buffer smaller than 9*nx*ny");
+    double *d = nullptr;
+    FLB_HIP(hipMalloc((void **)&d, need * sizeof(double)));
+    hipError_t e = launch_get(h->view(), lattice, P.nx, P.ny, d, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMemcpy(out, d, need * sizeof(double), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(FLB_EHIP, std::string("get populations: ") + hipGetErrorString(e));
+    return FLB_OK;
+}
+
+int flb_set_populations(flb_t *h, int lattice, const double *in, size_t n)
+{
+    if (check_lattice(h, lattice)) return FLB_EINVAL;
+    if (!in) return fail(FLB_EINVAL, "in must not be NULL");
+    const LatticeParams &P = h->params[lattice];
+    const size_t need = 9 * (size_t)P.plane;
+    if (n < need) return fail(FLB_ESIZE, "input buffer smaller than 9*nx*ny");
+    double *d = nullptr;
+    FLB_HIP(hipMalloc((void **)&d, need * sizeof(double)));
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMemcpy(d, in, need * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_set(h->view(), lattice, P.nx, P.ny, d, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(FLB_EHIP, std::string("set populations: ") + hipGetErrorString(e));
+    return FLB_OK;
+}
+
+int flb_conservation(flb_t *h, int lattice, double out[5])
+{
+    if (check_lattice(h, lattice)) return FLB_EINVAL;
+    if (!out) return fail(FLB_EINVAL, "out must not be NULL");
+    const LatticeParams &P = h->params[lattice];
+    const int nb = (int)std::min<int64_t>(h->red_blocks, (P.plane + kThreads - 1) / kThreads);
+    double *res = h->d_red + (size_t)h->red_blocks * 9;
+    FLB_HIP(launch_conservation(h->view(), lattice, P.nx, P.ny, h->d_red, nb, res, h->stream));
+    FLB_HIP(hipStreamSynchronize(h->stream));
+    FLB_HIP(hipMemcpy(out, res, 5 * sizeof(double), hipMemcpyDeviceToHost));
+    return FLB_OK;
+}
+
+int flb_conservation_dev(flb_t *h, int lattice, double *out_dev)
+{
+    if (check_lattice(h, lattice)) return FLB_EINVAL;
+    if (!out_dev) return fail(FLB_EINVAL, "out_dev must not be NULL");
+    const LatticeParams &P = h->params[lattice];
+    const int nb = (int)std::min<int64_t>(h->red_blocks, (P.plane + kThreads - 1) / kThreads);
+    FLB_HIP(launch_conservation(h->view(), lattice, P.nx, P.ny, h->d_red, nb, out_dev, h->stream));
+    return FLB_OK;
+}
+
+int flb_thermalize(flb_t *h)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    for (size_t l = 0; l < h->params.size(); ++l) {
+        const LatticeParams &P = h->params[l];
+        const int nb = (int)std::min<int64_t>(h->red_blocks, (P.plane + kThreads - 1) / kThreads);
+        double *sums = h->d_red + (size_t)h->red_blocks * 9;
+        FLB_HIP(launch_thermalize(h->view(), (int)l, P.nx, P.ny, h->d_red, nb, sums, h->stream));
+    }
+    FLB_HIP(hipStreamSynchronize(h->stream));
+    return FLB_OK;
+}
+
+int flb_debug_noise(flb_t *h, int lattice, uint32_t t, int64_t site0, int64_t nsites,
+                    uint32_t *words_out, float *z_out)
+{
+    if (check_lattice(h, lattice)) return FLB_EINVAL;
+    if (site0 < 0 || nsites < 0 || site0 + nsites > ((int64_t)1 << 32))
+        return fail(FLB_EINVAL, "site range outside the 32-bit counter word");
+    if (nsites == 0) return FLB_OK;
+    uint32_t *dw = nullptr;
+    float *dz = nullptr;
+    FLB_HIP(hipMalloc((void **)&dw, (size_t)nsites * 4 * sizeof(uint32_t)));
+    hipError_t e = hipMalloc((void **)&dz, (size_t)nsites * 6 * sizeof(float));
+    if (e == hipSuccess)
+        e = launch_debug_noise(h->seed, h->params[lattice].stream_id, t, site0, nsites, dw, dz,
+                               h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess && words_out)
+        e = hipMemcpy(words_out, dw, (size_t)nsites * 4 * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && z_out)
+        e = hipMemcpy(z_out, dz, (size_t)nsites * 6 * sizeof(float), hipMemcpyDeviceToHost);
+    (void)hipFree(dw);
+    if (dz) (void)hipFree(dz);
+    if (e != hipSuccess) return fail(FLB_EHIP, std::string("debug noise: ") + hipGetErrorString(e));
+    return FLB_OK;
+}
+
+int64_t flb_get_step(flb_t *h)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    return h->t;
+}
+
+int flb_num_lattices(flb_t *h)
+{
+    if (check_handle(h)) return -1;
+    return (int)h->params.size();
+}
+
+int flb_lattice_info(flb_t *h, int lattice, int32_t *nx, int32_t *ny, int32_t *nkx)
+{
+    if (check_lattice(h, lattice)) return FLB_EINVAL;
+    const LatticeParams &P = h->params[lattice];
+    if (nx) *nx = P.nx;
+    if (ny) *ny = P.ny;
+    if (nkx) *nkx = P.nkx;
+    return FLB_OK;
+}
+
+int flb_storage_info(flb_t *h, int32_t *storage, int32_t *bytes_per_value)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (storage) *storage = h->storage;
+    if (bytes_per_value) *bytes_per_value = h->elem_bytes;
+    return FLB_OK;
+}
+
+int flb_set_step_config(flb_t *h, int tile_w, int rows, int nontemporal)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (!step_tile_supported(tile_w, rows)) return fail(FLB_EINVAL, "unsupported step tile");
+    FLB_HIP(hipStreamSynchronize(h->stream));
+    h->tile_w = tile_w;
+    h->rows = rows;
+    h->nontemporal = nontemporal != 0;
+    clear_graphs(h);
+    return build_step_items(h);
+}
+
+int flb_get_step_config(flb_t *h, int *tile_w, int *rows, int *nontemporal)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (tile_w) *tile_w = h->tile_w;
+    if (rows) *rows = h->rows;
+    if (nontemporal) *nontemporal = h->nontemporal ? 1 : 0;
+    return FLB_OK;
+}
+
+}  // extern "C"

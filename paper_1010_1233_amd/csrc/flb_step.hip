@@ -1,0 +1,552 @@
+// flb_step.hip -- the fused noisy D2Q9 step and the state utility kernels.
+//
+// One thread updates one site per row it owns: it gathers the nine
+// post-collision values of the previous step from the neighbours x - v_i
+// (streaming, Eq. 1, in pull form), forms the moments of Eq. (3), relaxes the
+// non-conserved ones towards Eq. (10) by their own 1/tau^a (Eq. 5), adds the
+// noise of Eq. (8) on moments 3..8, transforms back with n_i^a = w_i m_i^a
+// and stores the nine new values at x.  Population planes are SoA, so every
+// wave's loads and stores are contiguous 64-site runs of one plane.  There is
+// no dense contraction here: the 9x9 transforms are written out using the
+// sign structure of Eq. (9), about forty adds each way.
+#include "flb_device.h"
+
+namespace flbdev {
+
+// Eq. (5) for one site on deviations d_i = f_i - w_i rho0, in place.
+// Moments are kept in a scaled basis so the back transform has unit
+// coefficients: s3 = 3/2 M^3, s4 = 3 M^4, s5 = M^5, s6 = sqrt(3/2) M^6,
+// s7 = sqrt(3/2) M^7, s8 = M^8; M^1 = sqrt(3) jx, M^2 = sqrt(3) jy.  The
+// deviation from w_i rho0 shifts only M^0 (sum_i w_i m_i^a = 0 for a > 0).
+// Only the change of moments 3..8, -(M^a - M^{a,0})/tau^a + xi^a, is
+// transformed back and added to the gathered values: density and momentum
+// ride along untouched, so FP32 weights such as 1/9 (not exact in binary)
+// cannot bias them step after step; what remains is zero-mean rounding.
+template <bool NOISE>
+__device__ __forceinline__ void collide(float (&d)[9], const LatticeParams &P, const float (&z)[6])
+{
+    const float a = d[1] + d[3], b = d[2] + d[4];
+    const float c = d[5] + d[7], e = d[6] + d[8];
+    const float ab = a + b, ce = c + e;
+    const float drho = d[0] + ab + ce;
+    const float x13 = d[1] - d[3], y24 = d[2] - d[4];
+    const float p57 = d[5] - d[7], p68 = d[6] - d[8];
+    const float jx = x13 + p57 - p68;
+    const float jy = y24 + p57 + p68;
+
+    const float s3 = 2.25f * (a - b);
+    const float s4 = 9.0f * (c - e);
+    const float s5 = fmaf(0.5f, ab, fmaf(2.0f, ce, -d[0]));
+    const float s6 = 1.5f * fmaf(2.0f, p57 - p68, -x13);
+    const float s7 = 1.5f * fmaf(2.0f, p57 + p68, -y24);
+    const float s8 = fmaf(0.5f, d[0], fmaf(2.0f, ce, -ab));
+
+    // Eq. (10) in the scaled basis: 3/2 rho (ux^2 - uy^2) -> 9/4 (jx^2 - jy^2)/rho, ...
+    const float ir = __builtin_amdgcn_rcpf(P.rho0 + drho);
+    const float jxx = jx * jx, jyy = jy * jy;
+    const float e3 = 2.25f * (jxx - jyy) * ir;
+    const float e4 = 9.0f * (jx * jy) * ir;
+    const float e5 = 1.5f * (jxx + jyy) * ir;
+
+    // change of each scaled moment, Eq. (5) and Eq. (8)
+    float t3 = P.omega[0] * (e3 - s3);
+    float t4 = P.omega[1] * (e4 - s4);
+    float t5 = P.omega[2] * (e5 - s5);
+    float t6 = -P.omega[3] * s6;
+    float t7 = -P.omega[4] * s7;
+    float t8 = -P.omega[5] * s8;
+    if constexpr (NOISE) {
+        t3 = fmaf(P.amp[0], z[0], t3);
+        t4 = fmaf(P.amp[1], z[1], t4);
+        t5 = fmaf(P.amp[2], z[2], t5);
+        t6 = fmaf(P.amp[3], z[3], t6);
+        t7 = fmaf(P.amp[4], z[4], t7);
+        t8 = fmaf(P.amp[5], z[5], t8);
+    }
+
+    // d*_i = d_i + w_i sum_{a>=3} m_i^a dM^a
+    const float A = fmaf(0.5f, t5, -t8);
+    const float B = 2.0f * (t5 + t8);
+    const float P6 = 2.0f * t6, Q7 = 2.0f * t7;
+    constexpr float w0 = 4.0f / 9.0f, w1 = 1.0f / 9.0f, w5 = 1.0f / 36.0f;
+    d[0] = fmaf(w0, fmaf(0.5f, t8, -t5), d[0]);
+    d[1] = fmaf(w1, (A + t3) - t6, d[1]);
+    d[3] = fmaf(w1, (A + t3) + t6, d[3]);
+    d[2] = fmaf(w1, (A - t3) - t7, d[2]);
+    d[4] = fmaf(w1, (A - t3) + t7, d[4]);
+    d[5] = fmaf(w5, (B + t4) + (P6 + Q7), d[5]);
+    d[6] = fmaf(w5, (B - t4) - (P6 - Q7), d[6]);
+    d[7] = fmaf(w5, (B + t4) - (P6 + Q7), d[7]);
+    d[8] = fmaf(w5, (B - t4) + (P6 - Q7), d[8]);
+}
+
+struct StepArgs {
+    const void *src;
+    void *dst;
+    const LatticeParams *params;
+    const StepItem *items;
+    const uint32_t *step;
+    uint32_t step_add;
+    uint32_t key0, key1;
+};
+
+template <int S, bool NT, bool NOISE, int TW, int R>
+__global__ __launch_bounds__(kThreads) void step_kernel(StepArgs g)
+{
+    using T = typename Codec<S>::T;
+    constexpr int TH = kThreads / TW;
+    const StepItem it = g.items[blockIdx.x];
+    if (it.lattice < 0) return;
+    const LatticeParams &P = g.params[it.lattice];
+    const int nx = P.nx, ny = P.ny;
+    const int tx = it.tile % P.tiles_x, ty = it.tile / P.tiles_x;
+    const int x = tx * TW + (int)(threadIdx.x % TW);
+    if (x >= nx) return;  // no barriers below: a thread may leave early
+    const int y0 = ty * (TH * R) + (int)(threadIdx.x / TW);
+    const T *__restrict__ src = (const T *)g.src + P.base;
+    T *__restrict__ dst = (T *)g.dst + P.base;
+    const int plane = (int)P.plane;
+    const int xm = (x == 0) ? nx - 1 : x - 1;
+    const int xp = (x == nx - 1) ? 0 : x + 1;
+    const uint32_t t = *g.step + g.step_add;
+
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int y = y0 + r * TH;
+        if (y >= ny) break;
+        const int ym = (y == 0) ? ny - 1 : y - 1;
+        const int yp = (y == ny - 1) ? 0 : y + 1;
+        const int rc = y * nx, rm = ym * nx, rp = yp * nx;
+        // pull: population i arrives from x - v_i
+        T q[9];
+        q[0] = src[rc + x];
+        q[1] = src[1 * plane + rc + xm];
+        q[2] = src[2 * plane + rm + x];
+        q[3] = src[3 * plane + rc + xp];
+        q[4] = src[4 * plane + rp + x];
+        q[5] = src[5 * plane + rm + xm];
+        q[6] = src[6 * plane + rm + xp];
+        q[7] = src[7 * plane + rp + xp];
+        q[8] = src[8 * plane + rp + xm];
+        float d[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] = Codec<S>::decode(q[i], P, i);
+
+        float z[6] = {0, 0, 0, 0, 0, 0};
+        if constexpr (NOISE) {
+            const uint4 w = philox4x32_10(make_uint4((uint32_t)(rc + x), t, P.stream_id, 0u),
+                                          g.key0, g.key1);
+            normals6(w, z);
+        }
+        collide<NOISE>(d, P, z);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) gstore<NT>(dst + i * plane + rc + x, Codec<S>::encode(d[i], P, i));
+    }
+}
+
+template <int S, bool NT, bool NOISE>
+static hipError_t launch_step_tiles(const StepArgs &a, int nitems, int tw, int r, hipStream_t s)
+{
+    const dim3 grid(nitems), block(kThreads);
+#define FLB_TILE(TW_, R_)                                                                     \
+    if (tw == TW_ && r == R_) {                                                               \
+        hipLaunchKernelGGL((step_kernel<S, NT, NOISE, TW_, R_>), grid, block, 0, s, a);       \
+        return hipGetLastError();                                                             \
+    }
+    FLB_TILE(64, 1)
+    FLB_TILE(128, 1)
+    FLB_TILE(256, 1)
+    FLB_TILE(64, 2)
+    FLB_TILE(128, 2)
+    FLB_TILE(256, 2)
+    FLB_TILE(256, 4)
+#undef FLB_TILE
+    return hipErrorInvalidValue;
+}
+
+bool step_tile_supported(int tw, int r)
+{
+    return (tw == 64 && (r == 1 || r == 2)) || (tw == 128 && (r == 1 || r == 2)) ||
+           (tw == 256 && (r == 1 || r == 2 || r == 4));
+}
+
+hipError_t launch_step(const DeviceView &v, const StepItem *items, int nitems, int tile_w,
+                       int rows, uint32_t step_add, bool nontemporal, bool noise, hipStream_t s)
+{
+    StepArgs a;
+    a.src = v.pops[v.cur];
+    a.dst = v.pops[v.cur ^ 1];
+    a.params = v.params;
+    a.items = items;
+    a.step = v.step;
+    a.step_add = step_add;
+    a.key0 = (uint32_t)(v.seed & 0xFFFFFFFFu);
+    a.key1 = (uint32_t)(v.seed >> 32);
+#define FLB_SEL(S_)                                                                              \
+    if (v.storage == S_) {                                                                       \
+        if (nontemporal)                                                                         \
+            return noise ? launch_step_tiles<S_, true, true>(a, nitems, tile_w, rows, s)         \
+                         : launch_step_tiles<S_, true, false>(a, nitems, tile_w, rows, s);       \
+        return noise ? launch_step_tiles<S_, false, true>(a, nitems, tile_w, rows, s)            \
+                     : launch_step_tiles<S_, false, false>(a, nitems, tile_w, rows, s);          \
+    }
+    FLB_SEL(kF32)
+    FLB_SEL(kBF16)
+    FLB_SEL(kF16)
+#undef FLB_SEL
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------
+// Step counter
+// ---------------------------------------------------------------------
+__global__ void advance_step_kernel(uint32_t *step, uint32_t n)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step += n;
+}
+
+hipError_t launch_advance_step(uint32_t *step, uint32_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, s, step, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// Uniform equilibrium start, Eq. (2): every stored value is feq_i.
+// ---------------------------------------------------------------------
+template <int S>
+__global__ __launch_bounds__(kThreads) void init_kernel(void *pops, const LatticeParams *params,
+                                                        int lattice)
+{
+    using T = typename Codec<S>::T;
+    const LatticeParams &P = params[lattice];
+    const int64_t n = 9 * P.plane;
+    T *p = (T *)pops + P.base;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(k / P.plane);
+        p[k] = Codec<S>::encode(P.feq[i], P, i);
+    }
+}
+
+static int grid_for(int64_t n)
+{
+    int64_t b = (n + kThreads - 1) / kThreads;
+    return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+}
+
+hipError_t launch_init(const DeviceView &v, int lattice, int64_t plane, hipStream_t s)
+{
+    const dim3 grid(grid_for(9 * plane)), block(kThreads);
+    void *p = v.pops[v.cur];
+    if (v.storage == kF32)
+        hipLaunchKernelGGL(init_kernel<kF32>, grid, block, 0, s, p, v.params, lattice);
+    else if (v.storage == kBF16)
+        hipLaunchKernelGGL(init_kernel<kBF16>, grid, block, 0, s, p, v.params, lattice);
+    else
+        hipLaunchKernelGGL(init_kernel<kF16>, grid, block, 0, s, p, v.params, lattice);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// State export / import as full FP64 populations f_i(x) = w_i rho0 + d_i,
+// with d_i(x) = stored_i(x - v_i).
+// ---------------------------------------------------------------------
+__device__ constexpr double kWd[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+template <int S>
+__global__ __launch_bounds__(kThreads) void get_kernel(const void *pops,
+                                                       const LatticeParams *params, int lattice,
+                                                       double *out)
+{
+    using T = typename Codec<S>::T;
+    const LatticeParams &P = params[lattice];
+    const int nx = P.nx, ny = P.ny;
+    const int64_t V = P.plane;
+    const T *p = (const T *)pops + P.base;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 9 * V;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(k / V);
+        const int s = (int)(k - (int64_t)i * V);
+        const int y = s / nx, x = s - y * nx;
+        const int xs = wrap_add(x, -kVX[i], nx), ys = wrap_add(y, -kVY[i], ny);
+        const float d = Codec<S>::decode(p[(int64_t)i * V + ys * nx + xs], P, i);
+        out[k] = kWd[i] * (double)P.rho0 + (double)d;
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(kThreads) void set_kernel(void *pops, const LatticeParams *params,
+                                                       int lattice, const double *in)
+{
+    using T = typename Codec<S>::T;
+    const LatticeParams &P = params[lattice];
+    const int nx = P.nx, ny = P.ny;
+    const int64_t V = P.plane;
+    T *p = (T *)pops + P.base;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 9 * V;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(k / V);
+        const int s = (int)(k - (int64_t)i * V);
+        const int y = s / nx, x = s - y * nx;
+        // stored_i(x) holds f_i(x + v_i)
+        const int xd = wrap_add(x, kVX[i], nx), yd = wrap_add(y, kVY[i], ny);
+        const double f = in[(int64_t)i * V + yd * nx + xd];
+        p[k] = Codec<S>::encode((float)(f - kWd[i] * (double)P.rho0), P, i);
+    }
+}
+
+hipError_t launch_get(const DeviceView &v, int lattice, int nx, int ny, double *out_dev,
+                      hipStream_t s)
+{
+    const dim3 grid(grid_for(9LL * nx * ny)), block(kThreads);
+    const void *p = v.pops[v.cur];
+    if (v.storage == kF32)
+        hipLaunchKernelGGL(get_kernel<kF32>, grid, block, 0, s, p, v.params, lattice, out_dev);
+    else if (v.storage == kBF16)
+        hipLaunchKernelGGL(get_kernel<kBF16>, grid, block, 0, s, p, v.params, lattice, out_dev);
+    else
+        hipLaunchKernelGGL(get_kernel<kF16>, grid, block, 0, s, p, v.params, lattice, out_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_set(const DeviceView &v, int lattice, int nx, int ny, const double *in_dev,
+                      hipStream_t s)
+{
+    const dim3 grid(grid_for(9LL * nx * ny)), block(kThreads);
+    void *p = v.pops[v.cur];
+    if (v.storage == kF32)
+        hipLaunchKernelGGL(set_kernel<kF32>, grid, block, 0, s, p, v.params, lattice, in_dev);
+    else if (v.storage == kBF16)
+        hipLaunchKernelGGL(set_kernel<kBF16>, grid, block, 0, s, p, v.params, lattice, in_dev);
+    else
+        hipLaunchKernelGGL(set_kernel<kF16>, grid, block, 0, s, p, v.params, lattice, in_dev);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// FP64 sums: mass, momentum and the staggered momenta.  Deterministic:
+// fixed per-block partials, then one block adds them in a fixed order.
+// ---------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *out)
+{
+    __shared__ double red[NV][kThreads / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = v[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+        if (lane == 0) red[q][wv] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double x = 0;
+        for (int w2 = 0; w2 < kThreads / 64; ++w2) x += red[threadIdx.x][w2];
+        out[threadIdx.x] = x;
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(kThreads) void conservation_kernel(const void *pops,
+                                                                const LatticeParams *params,
+                                                                int lattice, double *part)
+{
+    using T = typename Codec<S>::T;
+    const LatticeParams &P = params[lattice];
+    const int nx = P.nx, ny = P.ny;
+    const int64_t V = P.plane;
+    const T *p = (const T *)pops + P.base;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < V;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(s / nx), x = (int)(s - (int64_t)y * nx);
+        double r = 0, jx = 0, jy = 0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int xs = wrap_add(x, -kVX[i], nx), ys = wrap_add(y, -kVY[i], ny);
+            const double d = (double)Codec<S>::decode(p[(int64_t)i * V + ys * nx + xs], P, i);
+            r += d;
+            jx += kVX[i] * d;
+            jy += kVY[i] * d;
+        }
+        acc[0] += r;
+        acc[1] += jx;
+        acc[2] += jy;
+        acc[3] += (x & 1) ? -jx : jx;
+        acc[4] += (y & 1) ? -jy : jy;
+    }
+    block_sum<5>(acc, part + 5 * blockIdx.x);
+}
+
+template <int NV>
+__global__ __launch_bounds__(kThreads) void reduce_parts_kernel(const double *part, int nparts,
+                                                                double *out)
+{
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0;
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) acc[q] += part[NV * b + q];
+    block_sum<NV>(acc, out);
+}
+
+hipError_t launch_conservation(const DeviceView &v, int lattice, int nx, int ny, double *part,
+                               int nblocks, double *out_dev, hipStream_t s)
+{
+    (void)nx;
+    (void)ny;
+    const dim3 grid(nblocks), block(kThreads);
+    const void *p = v.pops[v.cur];
+    if (v.storage == kF32)
+        hipLaunchKernelGGL(conservation_kernel<kF32>, grid, block, 0, s, p, v.params, lattice, part);
+    else if (v.storage == kBF16)
+        hipLaunchKernelGGL(conservation_kernel<kBF16>, grid, block, 0, s, p, v.params, lattice,
+                           part);
+    else
+        hipLaunchKernelGGL(conservation_kernel<kF16>, grid, block, 0, s, p, v.params, lattice, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_parts_kernel<5>, dim3(1), block, 0, s, part, nblocks, out_dev);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// Thermal start: add sqrt(mu rho0 w_i) z_i(x) to f_i(x) (stored at x - v_i),
+// then subtract each population's spatial mean of what was added.
+// ---------------------------------------------------------------------
+template <int S>
+__global__ __launch_bounds__(kThreads) void thermal_add_kernel(void *pops,
+                                                               const LatticeParams *params,
+                                                               int lattice, uint32_t key0,
+                                                               uint32_t key1, double *part)
+{
+    using T = typename Codec<S>::T;
+    const LatticeParams &P = params[lattice];
+    const int nx = P.nx, ny = P.ny;
+    const int64_t V = P.plane;
+    T *p = (T *)pops + P.base;
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < V;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(s / nx), x = (int)(s - (int64_t)y * nx);
+        float z[12];
+        normals6(philox4x32_10(make_uint4((uint32_t)s, 0xFFFFFFFFu, P.stream_id, 0u), key0, key1),
+                 z);
+        normals6(philox4x32_10(make_uint4((uint32_t)s, 0xFFFFFFFFu, P.stream_id, 1u), key0, key1),
+                 z + 6);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const float add = P.therm_amp[i] * z[i];
+            const int xs = wrap_add(x, -kVX[i], nx), ys = wrap_add(y, -kVY[i], ny);
+            T *q = p + (int64_t)i * V + ys * nx + xs;
+            *q = Codec<S>::encode(Codec<S>::decode(*q, P, i) + add, P, i);
+            acc[i] += (double)add;
+        }
+    }
+    block_sum<9>(acc, part + 9 * blockIdx.x);
+}
+
+template <int S>
+__global__ __launch_bounds__(kThreads) void thermal_sub_kernel(void *pops,
+                                                               const LatticeParams *params,
+                                                               int lattice, const double *sums)
+{
+    using T = typename Codec<S>::T;
+    const LatticeParams &P = params[lattice];
+    const int64_t V = P.plane;
+    T *p = (T *)pops + P.base;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 9 * V;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(k / V);
+        const float mean = (float)(sums[i] / (double)V);
+        p[k] = Codec<S>::encode(Codec<S>::decode(p[k], P, i) - mean, P, i);
+    }
+}
+
+hipError_t launch_thermalize(const DeviceView &v, int lattice, int nx, int ny, double *part,
+                             int nblocks, double *sums_dev, hipStream_t s)
+{
+    const uint32_t k0 = (uint32_t)(v.seed & 0xFFFFFFFFu), k1 = (uint32_t)(v.seed >> 32);
+    void *p = v.pops[v.cur];
+    const dim3 block(kThreads);
+    if (v.storage == kF32)
+        hipLaunchKernelGGL(thermal_add_kernel<kF32>, dim3(nblocks), block, 0, s, p, v.params,
+                           lattice, k0, k1, part);
+    else if (v.storage == kBF16)
+        hipLaunchKernelGGL(thermal_add_kernel<kBF16>, dim3(nblocks), block, 0, s, p, v.params,
+                           lattice, k0, k1, part);
+    else
+        hipLaunchKernelGGL(thermal_add_kernel<kF16>, dim3(nblocks), block, 0, s, p, v.params,
+                           lattice, k0, k1, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_parts_kernel<9>, dim3(1), block, 0, s, part, nblocks, sums_dev);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 grid(grid_for(9LL * nx * ny));
+    if (v.storage == kF32)
+        hipLaunchKernelGGL(thermal_sub_kernel<kF32>, grid, block, 0, s, p, v.params, lattice,
+                           sums_dev);
+    else if (v.storage == kBF16)
+        hipLaunchKernelGGL(thermal_sub_kernel<kBF16>, grid, block, 0, s, p, v.params, lattice,
+                           sums_dev);
+    else
+        hipLaunchKernelGGL(thermal_sub_kernel<kF16>, grid, block, 0, s, p, v.params, lattice,
+                           sums_dev);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// Noise words and normals as the step kernel computes them (testing).
+// ---------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void debug_noise_kernel(uint32_t key0, uint32_t key1,
+                                                               uint32_t stream_id, uint32_t t,
+                                                               int64_t site0, int64_t n,
+                                                               uint32_t *words, float *zout)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 w = philox4x32_10(make_uint4((uint32_t)(site0 + k), t, stream_id, 0u), key0,
+                                      key1);
+        float z[6];
+        normals6(w, z);
+        if (words) {
+            words[4 * k + 0] = w.x;
+            words[4 * k + 1] = w.y;
+            words[4 * k + 2] = w.z;
+            words[4 * k + 3] = w.w;
+        }
+        if (zout)
+            for (int q = 0; q < 6; ++q) zout[6 * k + q] = z[q];
+    }
+}
+
+hipError_t launch_debug_noise(uint64_t seed, uint32_t stream_id, uint32_t t, int64_t site0,
+                              int64_t n, uint32_t *words_dev, float *z_dev, hipStream_t s)
+{
+    hipLaunchKernelGGL(debug_noise_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s,
+                       (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), stream_id, t,
+                       site0, n, words_dev, z_dev);
+    return hipGetLastError();
+}
+
+// Zero-fill without hipMemset (safe inside captured graphs).
+__global__ __launch_bounds__(kThreads) void fill_kernel(double *p, int64_t n)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = 0.0;
+}
+
+hipError_t launch_fill(double *p, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for((int64_t)n)), dim3(kThreads), 0, s, p,
+                       (int64_t)n);
+    return hipGetLastError();
+}
+
+}  // namespace flbdev

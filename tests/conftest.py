@@ -19,3 +19,14 @@ def oracle_lib():
     import oracle
     oracle.build(force=not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")))
     return oracle
+
+
+@pytest.fixture(scope="session")
+def flb():
+    """The GPU library's Python binding (built in place if it is missing)."""
+    import paper_1010_1233_amd as pkg
+    if not os.path.exists(pkg.LIB_PATH):
+        from paper_1010_1233_amd import build
+        build.build()
+    pkg.lib()
+    return pkg

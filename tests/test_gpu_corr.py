@@ -1,0 +1,169 @@
+"""GPU parity of the correlator measurement (Eqs. 11-12) against the oracle.
+
+Paired runs (same seed and counters) follow the same trajectory to ~1e-6, so
+the accumulated sums agree element by element to a small relative tolerance;
+statistical runs check S_k = 1 and vanishing cross correlators at u0 = 0 on
+the GPU alone (Eq. 7), with the abstract's "< 0.5 %" on the cross correlators.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import lyapunov
+from stats_util import KEYS, block_means, zscores
+from paper_1010_1233_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TAU_C1 = workloads.tau_vector(0.8, 0.8, 1.0)
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _compare(acc_g, acc_o, rtol):
+    scale = np.abs(acc_o).reshape(15, -1).max(axis=1)
+    for q in range(15):
+        d = np.abs(acc_g[q] - acc_o[q]).max()
+        assert d <= rtol * max(scale[q], scale[:5].max() * 1e-3), (q, d, scale[q])
+
+
+@pytest.mark.parametrize("nx,ny", [(32, 32), (20, 20), (24, 18), (37, 23), (64, 8), (2, 2),
+                                   (128, 96), (3, 256)])
+def test_single_sample_matches_oracle(flb, oracle_lib, nx, ny):
+    note("sample", nx, ny)
+    g = flb.Lattice(nx, ny, TAU_C1, 1e-4, u0=(0.04, -0.01), seed=3)
+    o = oracle_lib.Lattice(nx, ny, TAU_C1, 1e-4, u0=(0.04, -0.01), seed=3)
+    g.thermalize()
+    o.thermalize()
+    g.step(7)
+    o.step(7)
+    g.accumulate()
+    o.sample()
+    acc, ns = g.read_correlators()
+    assert ns == 1 and acc.shape == o.acc.shape
+    assert np.all(acc[:, 0, 0] == 0)
+    _compare(acc, o.acc, 2e-4)
+
+
+def test_paired_run_config1(flb, oracle_lib):
+    """32^2, 2000 steps, a sample every 10 steps, thermal start."""
+    c = workloads.CONFIGS["c1_32"]
+    g = flb.Lattice(32, 32, c["tau"], c["theta"], seed=c["seed"])
+    o = oracle_lib.Lattice(32, 32, c["tau"], c["theta"], seed=c["seed"])
+    g.thermalize()
+    o.thermalize()
+    g.run(2000, 10)
+    o.run(2000, 10)
+    acc, ns = g.read_correlators()
+    assert ns == o.nsamples == 200
+    _compare(acc, o.acc, 1e-3)
+
+
+def test_graph_run_equals_plain_calls(flb):
+    a = flb.Lattice(48, 40, TAU_C1, 1e-4, seed=8)
+    b = flb.Lattice(48, 40, TAU_C1, 1e-4, seed=8)
+    a.thermalize()
+    b.thermalize()
+    a.run(103, 10)  # graph periods plus a ragged tail
+    for t in range(1, 104):
+        b.step(1)
+        if t % 10 == 0:
+            b.accumulate()
+    assert a.t == b.t == 103
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    ra, na = a.read_correlators()
+    rb, nb = b.read_correlators()
+    assert na == nb == 10
+    assert np.array_equal(ra, rb)
+    # odd period, started off-phase
+    a.run(37, 3)
+    for t in range(104, 141):
+        b.step(1)
+        if t % 3 == 0:
+            b.accumulate()
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    assert np.array_equal(a.read_correlators()[0], b.read_correlators()[0])
+
+
+def test_batch_correlators_equal_separate(flb):
+    specs = [dict(nx=32, ny=32, tau=TAU_C1, theta=1e-4, stream_id=0),
+             dict(nx=20, ny=12, tau=TAU_C1, theta=1e-4, u0=(0.05, 0.0), stream_id=1)]
+    b = flb.Lattice.batch(specs, seed=2)
+    b.thermalize()
+    b.run(100, 10)
+    for i, s in enumerate(specs):
+        g = flb.Lattice(s["nx"], s["ny"], s["tau"], s["theta"], u0=s.get("u0", (0, 0)), seed=2,
+                        stream_id=s["stream_id"])
+        g.thermalize()
+        g.run(100, 10)
+        assert np.array_equal(b.read_correlators(i)[0], g.read_correlators()[0])
+
+
+def test_reset_correlators(flb):
+    g = flb.Lattice(16, 16, TAU_C1, 1e-4)
+    g.run(50, 10)
+    g.reset_correlators()
+    acc, ns = g.read_correlators()
+    assert ns == 0 and not acc.any()
+
+
+def test_large_lattice_sample_matches_oracle(flb, oracle_lib):
+    """4096^2: one sample against the oracle's FP64 transform."""
+    c = workloads.CONFIGS["c5_4096"]
+    note("4096^2 sample")
+    g = flb.Lattice(4096, 4096, c["tau"], c["theta"], u0=c["u0"], seed=c["seed"])
+    o = oracle_lib.Lattice(4096, 4096, c["tau"], c["theta"], u0=c["u0"], seed=c["seed"])
+    f0 = workloads.perturbed(oracle_lib.equilibrium(1.0, *c["u0"]), 4096, 4096, 3e-3, seed=13)
+    g.set_populations(f0)
+    o.set_populations(f0)
+    del f0
+    g.accumulate()
+    o.sample()
+    acc, _ = g.read_correlators()
+    _compare(acc, o.acc, 1e-3)
+
+
+def _mask(nx, ny):
+    nh = nx // 2 + 1
+    m = np.ones((ny, nh), dtype=bool)
+    for ky in range(ny):
+        for kx in range(nh):
+            m[ky, kx] = not lyapunov.singular_k(nx, ny, kx, ky)
+    return m
+
+
+def test_structure_factors_are_one_on_gpu(flb):
+    """64^2 at u0 = 0 (config-2 relaxation times), thermal start: every S = 1
+    and every cross correlator 0 within the batch-means error; the k-averaged
+    cross correlators are below 0.5 %."""
+    nx = ny = 64
+    tau = workloads.CONFIGS["c2_256"]["tau"]
+    theta = 1e-4
+    g = flb.Lattice(nx, ny, tau, theta, seed=2)
+    g.thermalize()
+    g.step(2000)
+
+    def block():
+        g.reset_correlators()
+        g.run(20000, 10)
+        acc, ns = g.read_correlators()
+        return flb.normalize(acc, ns, nx, ny, theta, 1.0)
+
+    mean, sem = block_means(block, 16)
+    pred = lyapunov.predict(nx, ny, tau, theta)
+    m = _mask(nx, ny)
+    zs = []
+    for k in KEYS:
+        z = zscores(mean[k], sem[k], pred[k], m, model_err=9e-4)
+        note(k, "max|z|", np.abs(z).max())
+        assert np.abs(z).max() < 6.5
+        zs.append(z)
+    chi = (np.concatenate(zs) ** 2).mean()
+    note("mean z^2", chi)
+    assert 0.6 < chi < 1.7
+    for k in ("R_uxuy", "R_rhojx", "R_rhojy", "R_rhoux", "R_rhouy"):
+        assert abs(mean[k][m].mean()) < 0.005

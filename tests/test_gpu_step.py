@@ -1,0 +1,236 @@
+"""GPU parity of the fused step against the FP64 oracle (through the C ABI).
+
+Bars: the Philox words are bit-exact; the normals agree to |dz| <= 2e-5 (FP32
+hardware log/sqrt/sin/cos vs FP64 libm); populations agree to 1e-6 rho0 after
+one step and to 1e-5 rho0 after 10^3 steps (FP32 storage); the launch shape
+never changes a result (bit-identical across tiles, batches and graphs).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1010_1233_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TAU_C1 = workloads.tau_vector(0.8, 0.8, 1.0)
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def pair(flb, oracle_lib, nx, ny, tau, theta, u0=(0.0, 0.0), seed=1, stream_id=0, ladd=False,
+         storage="f32", rho0=1.0):
+    g = flb.Lattice(nx, ny, tau, theta, rho0=rho0, u0=u0, seed=seed, storage=storage,
+                    stream_id=stream_id, ladd=ladd)
+    o = oracle_lib.Lattice(nx, ny, tau, theta, rho0=rho0, u0=u0, seed=seed, stream_id=stream_id,
+                           ladd=ladd)
+    return g, o
+
+
+@pytest.mark.parametrize("seed,stream_id,t", [(1, 0, 0), (0xDEADBEEFCAFEF00D, 7, 123456),
+                                              (5, 95, 0xFFFFFFFE)])
+def test_noise_words_bit_exact_and_normals_close(flb, oracle_lib, seed, stream_id, t):
+    note("noise", seed, stream_id, t)
+    g = flb.Lattice(64, 64, TAU_C1, 1e-4, seed=seed, stream_id=stream_id)
+    n = 1 << 16
+    site0 = 1000
+    w, z = g.debug_noise(t, site0, n)
+    idx = np.r_[0:2000, n - 2000:n]
+    for k in idx:
+        ow = oracle_lib.noise_words(seed, stream_id, t, site0 + int(k), 0)
+        assert w[k].tolist() == ow.tolist(), k
+    zo = np.array([oracle_lib.normals_from_words(w[k]) for k in range(n)])
+    err = np.abs(z.astype(np.float64) - zo)
+    note("max |dz|", err.max())
+    assert err.max() <= 2e-5
+    g.close()
+
+
+def test_initial_state_is_the_equilibrium(flb, oracle_lib):
+    g, o = pair(flb, oracle_lib, 17, 9, TAU_C1, 1e-4, u0=(0.05, -0.02))
+    f = g.get_populations()
+    assert np.abs(f - o.f).max() < 1e-7
+
+
+@pytest.mark.parametrize("nx,ny", [(37, 23), (2, 2), (3, 5), (257, 3), (64, 64), (1000, 7),
+                                   (5, 300)])
+def test_one_step_from_random_state(flb, oracle_lib, nx, ny):
+    note("one step", nx, ny)
+    tau = workloads.tau_vector(0.7, 1.1, 1.3)
+    g, o = pair(flb, oracle_lib, nx, ny, tau, 1e-3, u0=(0.03, 0.01), seed=9, stream_id=3)
+    f0 = workloads.perturbed(oracle_lib.equilibrium(1.0, 0.03, 0.01), nx, ny, 0.01, seed=nx * ny)
+    g.set_populations(f0)
+    o.set_populations(f0)
+    assert np.abs(g.get_populations() - f0).max() < 1e-7
+    for _ in range(3):
+        g.step(1)
+        o.step(1)
+        err = np.abs(g.get_populations() - o.f).max()
+        note("  max |df|", err)
+        assert err < 1e-6
+
+
+def test_thousand_steps_config1(flb, oracle_lib):
+    """32^2, rho0 = 1, tau (.8,.8,1), theta = 1e-4, seed 1: max|df| <= 1e-5 rho0
+    after 10^3 steps."""
+    c = workloads.CONFIGS["c1_32"]
+    g, o = pair(flb, oracle_lib, c["nx"], c["ny"], c["tau"], c["theta"], seed=c["seed"])
+    g.step(1000)
+    o.step(1000)
+    err = np.abs(g.get_populations() - o.f).max()
+    note("c1 1e3 steps max |df|", err)
+    assert err <= 1e-5 * c["rho0"]
+    assert g.t == 1000
+
+
+def test_thousand_steps_mean_flow_and_thermal_start(flb, oracle_lib):
+    tau = workloads.tau_vector(0.6, 1.0, 1.0)
+    g, o = pair(flb, oracle_lib, 48, 40, tau, 1e-4, u0=(0.05, 0.0), seed=5, stream_id=2)
+    g.thermalize()
+    o.thermalize()
+    assert np.abs(g.get_populations() - o.f).max() < 1e-7
+    g.step(1000)
+    o.step(1000)
+    err = np.abs(g.get_populations() - o.f).max()
+    note("mean flow 1e3 steps max |df|", err)
+    assert err <= 1e-5
+
+
+def test_ghost_noise_switch(flb, oracle_lib):
+    g, o = pair(flb, oracle_lib, 20, 20, workloads.tau_vector(1, 1, 1), 1e-4, ladd=True)
+    g.step(200)
+    o.step(200)
+    assert np.abs(g.get_populations() - o.f).max() <= 1e-5
+
+
+def test_noise_free_uniform_state_stays(flb):
+    g = flb.Lattice(64, 32, workloads.tau_vector(0.6, 0.9, 1.3), 0.0, u0=(0.1, 0.03))
+    f0 = g.get_populations()
+    g.step(500)
+    assert np.abs(g.get_populations() - f0).max() <= 1e-6
+
+
+def test_conservation_sums_match_oracle(flb, oracle_lib):
+    g, o = pair(flb, oracle_lib, 40, 30, TAU_C1, 1e-3, u0=(0.02, 0.0), seed=3)
+    g.thermalize()
+    o.thermalize()
+    c0 = g.conservation()
+    assert np.abs(c0 - o.conservation()).max() < 1e-5
+    g.step(1001)
+    o.step(1001)
+    cg, co = g.conservation(), o.conservation()
+    note("conservation gpu", cg, "oracle", co)
+    assert np.abs(cg - co).max() < 2e-5
+    # mass and momentum stay put (FP32 storage: rounding random walk only)
+    assert np.abs(cg[:3] - c0[:3]).max() < 1e-3
+    # staggered momenta flip sign every step (even sides)
+    assert np.allclose(cg[3:], -c0[3:], atol=1e-4)
+
+
+def test_conservation_flags_nan(flb, oracle_lib):
+    g = flb.Lattice(8, 8, TAU_C1, 1e-4)
+    f = g.get_populations()
+    f[4, 3, 5] = np.nan
+    g.set_populations(f)
+    assert not np.all(np.isfinite(g.conservation()))
+
+
+@pytest.mark.parametrize("cfg", [(64, 1, 0), (128, 1, 1), (256, 1, 0), (64, 2, 1), (128, 2, 0),
+                                 (256, 2, 1), (256, 4, 0)])
+def test_launch_shape_does_not_change_results(flb, cfg):
+    nx, ny = 300, 37
+    ref = flb.Lattice(nx, ny, TAU_C1, 1e-3, seed=4)
+    ref.thermalize()
+    ref.step(20)
+    a = ref.get_populations()
+    g = flb.Lattice(nx, ny, TAU_C1, 1e-3, seed=4)
+    g.set_step_config(*cfg)
+    assert g.step_config() == (cfg[0], cfg[1], bool(cfg[2]))
+    g.thermalize()
+    g.step(20)
+    assert np.array_equal(g.get_populations(), a)
+
+
+def test_batch_equals_separate_lattices(flb):
+    specs = [dict(nx=33, ny=20, tau=TAU_C1, theta=1e-3, u0=(0.0, 0.0), stream_id=0),
+             dict(nx=64, ny=64, tau=workloads.tau_vector(0.6, 1.0, 1.0), theta=1e-4,
+                  u0=(0.05, 0.0), stream_id=1),
+             dict(nx=7, ny=129, tau=workloads.tau_vector(1.2, 0.9, 0.7), theta=2e-4,
+                  u0=(0.0, -0.03), stream_id=2)]
+    b = flb.Lattice.batch(specs, seed=11)
+    assert b.nlattices == 3
+    b.thermalize()
+    b.step(57)
+    for i, s in enumerate(specs):
+        g = flb.Lattice(s["nx"], s["ny"], s["tau"], s["theta"], u0=s["u0"], seed=11,
+                        stream_id=s["stream_id"])
+        g.thermalize()
+        g.step(57)
+        assert np.array_equal(b.get_populations(i), g.get_populations()), i
+
+
+def test_torch_stream_binding(flb):
+    torch = pytest.importorskip("torch")
+    s = torch.cuda.Stream()
+    a = flb.Lattice(40, 40, TAU_C1, 1e-3, seed=2)
+    a.set_stream(s)
+    a.step(30)
+    a.synchronize()
+    b = flb.Lattice(40, 40, TAU_C1, 1e-3, seed=2)
+    b.step(30)
+    assert np.array_equal(a.get_populations(), b.get_populations())
+
+
+def test_large_lattice_one_step(flb, oracle_lib):
+    """4096^2 (the 16.8M-site workload, u0_x = 0.05, tau_s = 0.6) in the
+    launch shape the benchmark times: one full step against the oracle."""
+    c = workloads.CONFIGS["c5_4096"]
+    note("4096^2 one step")
+    g, o = pair(flb, oracle_lib, c["nx"], c["ny"], c["tau"], c["theta"], u0=c["u0"],
+                seed=c["seed"])
+    f0 = workloads.perturbed(oracle_lib.equilibrium(1.0, *c["u0"]), c["nx"], c["ny"], 3e-3,
+                             seed=12)
+    g.set_populations(f0)
+    o.set_populations(f0)
+    del f0
+    g.step(1)
+    o.step(1)
+    err = np.abs(g.get_populations() - o.f).max()
+    note("4096^2 max |df|", err)
+    assert err < 1e-6
+
+
+def test_16bit_storage_tracks_oracle(flb, oracle_lib):
+    """BF16 / FP16 scaled deviations: quantisation error of the stored state
+    only (relative to the fluctuation scale sqrt(mu rho0 w_i))."""
+    tau = workloads.tau_vector(0.8, 1.0, 1.0)
+    for storage, tol in (("f16", 2e-3), ("bf16", 2e-2)):
+        g, o = pair(flb, oracle_lib, 32, 32, tau, 1e-4, storage=storage, seed=6)
+        assert g.storage_info() == (flb.STORAGE[storage], 2)
+        g.thermalize()
+        o.thermalize()
+        g.step(100)
+        o.step(100)
+        sc = np.sqrt(3e-4 * 4 / 9)
+        err = np.abs(g.get_populations() - o.f).max() / sc
+        note(storage, "relative err", err)
+        assert err < tol * 100 ** 0.5
+
+
+def test_invalid_calls_report_errors(flb):
+    g = flb.Lattice(8, 8, TAU_C1, 1e-4)
+    with pytest.raises(flb.FlbError):
+        g.step(-1)
+    with pytest.raises(flb.FlbError):
+        g.conservation(lattice=3)
+    with pytest.raises(flb.FlbError):
+        g.set_step_config(100, 1, 0)
+    import ctypes
+    buf = np.zeros(10)
+    rc = flb.lib().flb_read_correlators(g._h, 0, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        10, None)
+    assert rc == flb.ESIZE
