@@ -81,7 +81,8 @@ extern "C" {
  * where X_k = sum_x (X(x) - <X>) exp(-i k.x), k = 2 pi (kx/nx, ky/ny)
  * (Sec. 3, text after Eq. 11), u = j / rho at each site. */
 
-/* Largest side for which correlators are supported. */
+/* Largest side for which correlators are supported: powers of two up to
+ * FLB_MAX_FFT_SIDE, other lengths up to FLB_MAX_FFT_SIDE / 2. */
 #define FLB_MAX_FFT_SIDE 4096
 
 typedef struct flb flb_t;
@@ -147,7 +148,8 @@ int flb_run(flb_t *h, int64_t nsteps, int sample_every);
 /* Adds one sample of the current state of every lattice to its FP64
  * correlator sums (Eqs. 11-12, the kinds listed above), on the half plane
  * kx = 0..nx/2, ky = 0..ny-1; the k = 0 entry is left unchanged (the mean is
- * removed, Sec. 3).  FLB_ESIZE if a side exceeds FLB_MAX_FFT_SIDE.
+ * removed, Sec. 3).  FLB_ESIZE for sides beyond FLB_MAX_FFT_SIDE (powers
+ * of two) or FLB_MAX_FFT_SIDE / 2 (other lengths).
  * Enqueues only. */
 int flb_accumulate_correlators(flb_t *h);
 
@@ -206,12 +208,23 @@ int flb_lattice_info(flb_t *h, int lattice, int32_t *nx, int32_t *ny, int32_t *n
 /* Storage format and bytes per population value. */
 int flb_storage_info(flb_t *h, int32_t *storage, int32_t *bytes_per_value);
 
-/* Launch shape of the step kernel: tiles of tile_w sites along x (64, 128
- * or 256) by 256/tile_w thread rows, each thread updating `rows` rows (1, 2
- * or 4 depending on tile_w), and streaming (non-temporal) stores on or off.
- * Results do not depend on it.  FLB_EINVAL for an unsupported shape. */
-int flb_set_step_config(flb_t *h, int tile_w, int rows, int nontemporal);
-int flb_get_step_config(flb_t *h, int *tile_w, int *rows, int *nontemporal);
+/* Launch shape of the step kernel: blocks of tile_w threads along x (64,
+ * 128 or 256) by 256/tile_w rows, each thread updating `sites` consecutive
+ * sites of its row (1, 2 or 4) with one vector access per population, and
+ * streaming (non-temporal) stores on or off.  Results do not depend on it.
+ * FLB_EINVAL for an unsupported shape. */
+int flb_set_step_config(flb_t *h, int tile_w, int sites, int nontemporal);
+int flb_get_step_config(flb_t *h, int *tile_w, int *sites, int *nontemporal);
+
+/* Chooses the step kernel's launch shape by timing every supported shape
+ * (nsteps >= 1 steps each, HIP events on the handle's stream) on this
+ * handle's own lattices, and keeps the fastest.  The populations and the
+ * step counter are restored afterwards, so results are unchanged.  When the
+ * environment variable FLB_AUTOTUNE_CACHE names a file, choices are read
+ * from and appended to it, keyed by storage format, lattice count, total
+ * sites and largest side.  Synchronises. *ms_out (may be NULL) receives the
+ * chosen shape's time per step. */
+int flb_autotune(flb_t *h, int nsteps, double *ms_out);
 
 #ifdef __cplusplus
 }

@@ -83,6 +83,7 @@ SIGNATURES = {
     "flb_set_step_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int]),
     "flb_get_step_config": (ctypes.c_int, [ctypes.c_void_p, _intp, _intp, _intp]),
+    "flb_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp]),
 }
 
 
@@ -227,6 +228,14 @@ class Lattice:
         _check(lib().flb_get_step_config(self._h, ctypes.byref(a), ctypes.byref(b),
                                          ctypes.byref(c)))
         return a.value, b.value, bool(c.value)
+
+    def autotune(self, nsteps=10):
+        """Time every step-kernel launch shape on this handle and keep the
+        fastest (state unchanged); returns the chosen (tile_w, sites,
+        nontemporal) and its ms per step."""
+        ms = ctypes.c_double()
+        _check(lib().flb_autotune(self._h, int(nsteps), ctypes.byref(ms)))
+        return self.step_config(), ms.value
 
     def storage_info(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()

@@ -7,17 +7,22 @@
 // dM = M - <M> has no k = 0 component), and keeps the FP32 transforms free of
 // a large mean.
 //
-// Three kernels per sample:
-//   rows : one block per (lattice, row, signal) gathers the state, packs two
-//          real sequences into one complex line (jx + i jy, ux + i uy, or the
-//          density of two consecutive rows), transforms it along x in LDS and
-//          writes the half spectra kx = 0..nx/2 of both real sequences;
-//   cols : one block per (lattice, field, column block) transforms the half
-//          spectra along y in LDS, in place;
-//   accum: one thread per (ky, kx) forms the fifteen products of the five
-//          spectra and adds them to the FP64 sums.
-// Lines of power-of-two length use a radix-2 transform in LDS; other lengths
-// use Bluestein's chirp-z convolution with a power-of-two work length.
+// Per sample:
+//   rows   one block per group of rows gathers the state once, keeps the five
+//          fields in registers and transforms three packed complex lines per
+//          row (jx + i jy, ux + i uy, rho) along x through one LDS buffer;
+//          it writes the half spectra kx = 0..nx/2 of the five real fields.
+//   columns, power-of-two ny = P*Q (Q <= 64): pass A transforms the P-long
+//          strided columns (rows q, q+Q, ...) and applies the twiddles;
+//          pass B transforms Q consecutive rows of all five fields and adds
+//          the fifteen products to the FP64 sums straight from LDS.
+//   columns, other ny: one kernel transforms whole columns (Bluestein), a
+//          second one accumulates.
+// The LDS transforms are in-place decimation in time with radix-2 stages
+// fused three at a time (radix 8): a thread loads eight elements, runs three
+// butterfly stages in registers and stores them back, so a 4096-point line
+// takes four passes and four barriers.  Lines of other lengths use
+// Bluestein's chirp-z convolution with a power-of-two work length.
 #include "flb_device.h"
 
 namespace flbdev {
@@ -27,66 +32,146 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Radix-2 transform of `nlines` lines of length 2^lg held in LDS; element j
-// of line l at buf[l * ls + j * es].  Forward: exp(-2 pi i jk / m).
-__device__ void lds_fft(float2 *buf, int lg, int nlines, int ls, int es, const float2 *tw,
-                        bool inverse)
+__device__ __forceinline__ int bitrev(int j, int lg)
 {
-    if (lg == 0) return;
-    const int m = 1 << lg, hm = m >> 1;
-    for (int idx = threadIdx.x; idx < nlines * m; idx += blockDim.x) {
-        const int l = idx >> lg, j = idx & (m - 1);
-        const int r = (int)(__brev((unsigned)j) >> (32 - lg));
-        if (j < r) {
-            float2 *a = buf + l * ls + j * es, *b = buf + l * ls + r * es;
-            const float2 t = *a;
-            *a = *b;
-            *b = t;
+    return lg ? (int)(__brev((unsigned)j) >> (32 - lg)) : 0;
+}
+
+// exp(-2 pi i e / n) for 0 <= e < n, n a power of two <= kTwN, from the
+// half-circle table.
+__device__ __forceinline__ float2 twiddle(const float2 *tw, int e, int lgn)
+{
+    const int i = e << (kTwLog - lgn);
+    if (i < kTwN / 2) return tw[i];
+    const float2 w = tw[i - kTwN / 2];
+    return make_float2(-w.x, -w.y);
+}
+
+// LDS slot of element index i.  Rows are stored contiguously, and the
+// bit-reversed writes and first radix-8 passes would put a whole wave on a
+// few banks; one pad slot every 16 and every 256 elements spreads every
+// access pattern of the row kernel over all banks (two-way at most for
+// 8-byte elements).  Column layouts interleave lines and need no padding.
+template <bool PAD> __device__ __forceinline__ int lds_slot(int i)
+{
+    return PAD ? i + (i >> 4) + (i >> 8) : i;
+}
+
+__host__ __device__ constexpr int lds_padded_elems(int n) { return n + (n >> 4) + (n >> 8) + 1; }
+
+// One pass of R fused radix-2 stages s .. s+R-1 (1-based) over `nlines`
+// lines of length 2^lg; element e of line l at slot(l * ls + e * es).
+template <int R, bool PAD>
+__device__ __forceinline__ void dit_pass(float2 *buf, int lg, int s, int nlines, int ls, int es,
+                                         const float2 *tw, bool inverse)
+{
+    constexpr int G = 1 << R;
+    const int h = 1 << (s - 1);
+    const int lgg = lg - R;  // log2 of groups per line
+    const int total = nlines << lgg;
+    // Lines stored contiguously (ls > 1): neighbouring threads take
+    // neighbouring groups of one line.  Lines interleaved (ls == 1): they
+    // take the same group of neighbouring lines.  Either way a wave's LDS
+    // accesses are consecutive addresses.
+    const bool interleaved = (ls == 1);
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        int l, g;
+        if (interleaved) {
+            g = idx / nlines;
+            l = idx - g * nlines;
+        } else {
+            l = idx >> lgg;
+            g = idx & ((1 << lgg) - 1);
         }
+        const int k = g & (h - 1);
+        const int b = (g >> (s - 1)) << (s - 1 + R);
+        const int e0 = l * ls + (b + k) * es;
+        const int st = h * es;
+        float2 v[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) v[j] = buf[lds_slot<PAD>(e0 + j * st)];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int half = 1 << u;
+            const int S = s + u;
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                if (j & half) continue;
+                const int t = k + (j & (half - 1)) * h;
+                float2 w = tw[t << (kTwLog - S)];
+                if (inverse) w.y = -w.y;
+                const float2 x = cmul(w, v[j + half]);
+                v[j + half] = make_float2(v[j].x - x.x, v[j].y - x.y);
+                v[j] = make_float2(v[j].x + x.x, v[j].y + x.y);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) buf[lds_slot<PAD>(e0 + j * st)] = v[j];
     }
-    __syncthreads();
-    for (int s = 1; s <= lg; ++s) {
-        const int half = 1 << (s - 1);
-        const int shift = kTwLog - s;
-        for (int idx = threadIdx.x; idx < nlines * hm; idx += blockDim.x) {
-            const int l = idx >> (lg - 1), bb = idx & (hm - 1);
-            const int k = bb & (half - 1), grp = bb >> (s - 1);
-            const int i0 = grp * 2 * half + k, i1 = i0 + half;
-            float2 w = tw[k << shift];
-            if (inverse) w.y = -w.y;
-            float2 *pa = buf + l * ls + i0 * es, *pb = buf + l * ls + i1 * es;
-            const float2 a = *pa, t = cmul(w, *pb);
-            *pa = make_float2(a.x + t.x, a.y + t.y);
-            *pb = make_float2(a.x - t.x, a.y - t.y);
+}
+
+// In-place transform of lines given in bit-reversed order; natural order out.
+template <bool PAD>
+__device__ void lds_fft_dit(float2 *buf, int lg, int nlines, int ls, int es, const float2 *tw,
+                            bool inverse)
+{
+    int s = 1;
+    while (s <= lg) {
+        const int r = lg - s + 1;
+        if (r >= 3) {
+            dit_pass<3, PAD>(buf, lg, s, nlines, ls, es, tw, inverse);
+            s += 3;
+        } else if (r == 2) {
+            dit_pass<2, PAD>(buf, lg, s, nlines, ls, es, tw, inverse);
+            s += 2;
+        } else {
+            dit_pass<1, PAD>(buf, lg, s, nlines, ls, es, tw, inverse);
+            s += 1;
         }
         __syncthreads();
     }
 }
 
-// Length-n DFT of lines already multiplied by the chirp (Bluestein) or plain
-// (power of two), in place.  On exit element k < n of each line holds X_k.
-// Expects the data written and a barrier passed before the call.
+template <bool PAD>
+__device__ void lds_bitrev(float2 *buf, int lg, int nlines, int ls, int es)
+{
+    const int m = 1 << lg;
+    for (int idx = threadIdx.x; idx < nlines * m; idx += blockDim.x) {
+        const int l = idx >> lg, j = idx & (m - 1);
+        const int r = bitrev(j, lg);
+        if (j < r) {
+            const int a = lds_slot<PAD>(l * ls + j * es), b = lds_slot<PAD>(l * ls + r * es);
+            const float2 t = buf[a];
+            buf[a] = buf[b];
+            buf[b] = t;
+        }
+    }
+    __syncthreads();
+}
+
+// Length-n DFT of lines whose inputs were written at bit-reversed positions
+// (already multiplied by the chirp for Bluestein lengths), in place; on exit
+// element k < n holds X_k in natural order.
+template <bool PAD>
 __device__ void lds_line_dft(float2 *buf, const LinePlan &L, int nlines, int ls, int es,
                              const float2 *tables)
 {
     const float2 *tw = tables;
-    if (!L.bluestein) {
-        lds_fft(buf, L.log2m, nlines, ls, es, tw, false);
-        return;
-    }
-    lds_fft(buf, L.log2m, nlines, ls, es, tw, false);
+    lds_fft_dit<PAD>(buf, L.log2m, nlines, ls, es, tw, false);
+    if (!L.bluestein) return;
     const float2 *K = tables + L.kernel_off;
     for (int idx = threadIdx.x; idx < nlines * L.m; idx += blockDim.x) {
-        const int l = idx / L.m, j = idx - l * L.m;
-        float2 *p = buf + l * ls + j * es;
+        const int l = idx >> L.log2m, j = idx & (L.m - 1);
+        float2 *p = buf + lds_slot<PAD>(l * ls + j * es);
         *p = cmul(*p, K[j]);
     }
     __syncthreads();
-    lds_fft(buf, L.log2m, nlines, ls, es, tw, true);
+    lds_bitrev<PAD>(buf, L.log2m, nlines, ls, es);
+    lds_fft_dit<PAD>(buf, L.log2m, nlines, ls, es, tw, true);
     const float2 *C = tables + L.chirp_off;
     for (int idx = threadIdx.x; idx < nlines * L.n; idx += blockDim.x) {
         const int l = idx / L.n, j = idx - l * L.n;
-        float2 *p = buf + l * ls + j * es;
+        float2 *p = buf + lds_slot<PAD>(l * ls + j * es);
         *p = cmul(*p, C[j]);
     }
     __syncthreads();
@@ -108,16 +193,23 @@ __device__ __forceinline__ void site_fields(const typename Codec<S>::T *p, const
                                             int x, int y, float &drho, float &djx, float &djy,
                                             float &dux, float &duy)
 {
-    const int nx = P.nx, ny = P.ny, plane = (int)P.plane;
-    float r = 0, jx = 0, jy = 0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const int xs = wrap_add(x, -kVX[i], nx), ys = wrap_add(y, -kVY[i], ny);
-        const float d = Codec<S>::decode(p[i * plane + ys * nx + xs], P, i);
-        r += d;
-        jx += (float)kVX[i] * d;
-        jy += (float)kVY[i] * d;
-    }
+    const int nx = P.nx, ny = P.ny, px = P.px, plane = (int)P.plane;
+    const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+    const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
+    const int rc = y * px, rm = ym * px, rp = yp * px;
+    float d[9];
+    d[0] = Codec<S>::decode(p[rc + x], P, 0);
+    d[1] = Codec<S>::decode(p[1 * plane + rc + xm], P, 1);
+    d[2] = Codec<S>::decode(p[2 * plane + rm + x], P, 2);
+    d[3] = Codec<S>::decode(p[3 * plane + rc + xp], P, 3);
+    d[4] = Codec<S>::decode(p[4 * plane + rp + x], P, 4);
+    d[5] = Codec<S>::decode(p[5 * plane + rm + xm], P, 5);
+    d[6] = Codec<S>::decode(p[6 * plane + rm + xp], P, 6);
+    d[7] = Codec<S>::decode(p[7 * plane + rp + xp], P, 7);
+    d[8] = Codec<S>::decode(p[8 * plane + rp + xm], P, 8);
+    const float r = d[0] + (d[1] + d[3]) + (d[2] + d[4]) + (d[5] + d[7]) + (d[6] + d[8]);
+    const float jx = (d[1] - d[3]) + (d[5] - d[7]) - (d[6] - d[8]);
+    const float jy = (d[2] - d[4]) + (d[5] - d[7]) + (d[6] - d[8]);
     const float ir = 1.0f / (P.rho0 + r);
     drho = r;
     djx = jx - P.rho0 * P.u0x;
@@ -126,8 +218,12 @@ __device__ __forceinline__ void site_fields(const typename Codec<S>::T *p, const
     duy = jy * ir - P.u0y;
 }
 
+constexpr int kRowThreads = 1024;  // threads of a row-kernel block
+constexpr int kRowSites = 4;       // sites per thread: at most 4096 sites per block
+
+// item: lattice, first row, rows in this block
 template <int S>
-__global__ __launch_bounds__(kThreads) void corr_rows_kernel(CorrArgs g)
+__global__ __launch_bounds__(kRowThreads) void corr_rows_kernel(CorrArgs g)
 {
     using T = typename Codec<S>::T;
     extern __shared__ float2 lds[];
@@ -135,103 +231,110 @@ __global__ __launch_bounds__(kThreads) void corr_rows_kernel(CorrArgs g)
     if (it.lattice < 0) return;
     const LatticeParams &P = g.params[it.lattice];
     const LinePlan &L = g.plans[P.line_x];
-    const int nx = P.nx, ny = P.ny, nkx = P.nkx;
-    const int y = it.a, sig = it.b;
+    const int nx = P.nx, ny = P.ny, nkx = P.nkx, kxp = P.kxp;
+    const int y0 = it.a, nl = min(it.b, ny - y0);
+    const int m = L.m, lg = L.log2m;
     const T *p = (const T *)g.pops + P.base;
     const float2 *chirp = g.tables + L.chirp_off;
+    const int nsites = nl * nx;
 
-    for (int x = threadIdx.x; x < L.m; x += blockDim.x) {
-        float2 v = make_float2(0.f, 0.f);
-        if (x < nx) {
-            float dr, jx, jy, ux, uy;
-            site_fields<S>(p, P, x, y, dr, jx, jy, ux, uy);
-            if (sig == 0) {
-                v = make_float2(jx, jy);
-            } else if (sig == 1) {
-                v = make_float2(ux, uy);
-            } else {
-                v.x = dr;
-                if (y + 1 < ny) {
-                    site_fields<S>(p, P, x, y + 1, dr, jx, jy, ux, uy);
-                    v.y = dr;
-                }
-            }
-            if (L.bluestein) v = cmul(v, chirp[x]);
+    float fr[kRowSites], fjx[kRowSites], fjy[kRowSites], fux[kRowSites], fuy[kRowSites];
+#pragma unroll
+    for (int q = 0; q < kRowSites; ++q) {
+        const int idx = (int)threadIdx.x + q * kRowThreads;
+        fr[q] = fjx[q] = fjy[q] = fux[q] = fuy[q] = 0.0f;
+        if (idx < nsites) {
+            const int l = idx / nx, x = idx - l * nx;
+            site_fields<S>(p, P, x, y0 + l, fr[q], fjx[q], fjy[q], fux[q], fuy[q]);
         }
-        lds[x] = v;
     }
-    __syncthreads();
-    lds_line_dft(lds, L, 1, 0, 1, g.tables);
 
-    // Two real sequences a, b packed as z = a + i b:
-    // a_k = (z_k + conj z_{-k}) / 2, b_k = (z_k - conj z_{-k}) / (2i).
     float2 *spec = g.spec + P.spec_base;
-    const int64_t fstride = (int64_t)ny * nkx;
-    int fa, fb, ya = y, yb = y;
-    if (sig == 0) {
-        fa = 1; fb = 2;
-    } else if (sig == 1) {
-        fa = 3; fb = 4;
-    } else {
-        fa = 0; fb = 0; yb = y + 1;
-    }
-    for (int k = threadIdx.x; k < nkx; k += blockDim.x) {
-        const float2 zk = lds[k];
-        const float2 zm = lds[k == 0 ? 0 : nx - k];
-        const float2 a = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-        const float2 b = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
-        spec[fa * fstride + (int64_t)ya * nkx + k] = a;
-        if (yb < ny) spec[fb * fstride + (int64_t)yb * nkx + k] = b;
+    const int64_t fstride = (int64_t)ny * kxp;
+    for (int sig = 0; sig < 3; ++sig) {
+        // zero padding of Bluestein work lines, at bit-reversed positions
+        for (int e = threadIdx.x; e < nl * m; e += kRowThreads) {
+            const int l = e >> lg, j = e & (m - 1);
+            if (j >= nx) lds[lds_slot<true>(l * m + bitrev(j, lg))] = make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < kRowSites; ++q) {
+            const int idx = (int)threadIdx.x + q * kRowThreads;
+            if (idx < nsites) {
+                const int l = idx / nx, x = idx - l * nx;
+                float2 v = sig == 0 ? make_float2(fjx[q], fjy[q])
+                         : sig == 1 ? make_float2(fux[q], fuy[q]) : make_float2(fr[q], 0.f);
+                if (L.bluestein) v = cmul(v, chirp[x]);
+                lds[lds_slot<true>(l * m + bitrev(x, lg))] = v;
+            }
+        }
+        __syncthreads();
+        lds_line_dft<true>(lds, L, nl, m, 1, g.tables);
+
+        // two real sequences a, b packed as z = a + i b:
+        // a_k = (z_k + conj z_{-k}) / 2, b_k = (z_k - conj z_{-k}) / (2i)
+        const int fa = sig == 0 ? 1 : 3, fb = sig == 0 ? 2 : 4;
+        for (int e = threadIdx.x; e < nl * kxp; e += kRowThreads) {
+            const int l = e / kxp, k = e - l * kxp;
+            const int64_t row = (int64_t)(y0 + l) * kxp + k;
+            if (k >= nkx) {  // padding columns: keep them finite
+                if (sig == 2) spec[row] = make_float2(0.f, 0.f);
+                else {
+                    spec[fa * fstride + row] = make_float2(0.f, 0.f);
+                    spec[fb * fstride + row] = make_float2(0.f, 0.f);
+                }
+                continue;
+            }
+            const float2 zk = lds[lds_slot<true>(l * m + k)];
+            if (sig == 2) {
+                spec[row] = zk;
+            } else {
+                const float2 zm = lds[lds_slot<true>(l * m + (k == 0 ? 0 : nx - k))];
+                spec[fa * fstride + row] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+                spec[fb * fstride + row] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+            }
+        }
+        __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(kThreads) void corr_cols_kernel(CorrArgs g, int cb)
+// Power-of-two ny = P*Q, pass A.  item: lattice, field, first column, first q.
+// LDS [p][ql][c], 16 columns, nq q-values per block.
+__global__ __launch_bounds__(kThreads) void corr_cols_a_kernel(CorrArgs g)
 {
     extern __shared__ float2 lds[];
     const CorrItem it = g.items[blockIdx.x];
     if (it.lattice < 0) return;
     const LatticeParams &P = g.params[it.lattice];
-    const LinePlan &L = g.plans[P.line_y];
-    const int ny = P.ny, nkx = P.nkx;
-    const int f = it.a, c0 = it.b;
-    const int ncol = min(cb, nkx - c0);
-    float2 *col = g.spec + P.spec_base + (int64_t)f * ny * nkx + c0;
-    const float2 *chirp = g.tables + L.chirp_off;
-
-    for (int idx = threadIdx.x; idx < L.m * cb; idx += blockDim.x) {
-        const int j = idx / cb, c = idx - j * cb;
-        float2 v = make_float2(0.f, 0.f);
-        if (j < ny && c < ncol) {
-            v = col[(int64_t)j * nkx + c];
-            if (L.bluestein) v = cmul(v, chirp[j]);
-        }
-        lds[idx] = v;
+    const int f = it.a, c0 = it.b, q0 = it.c;
+    const int lgP = P.col_lgp, Pn = 1 << lgP, Q = P.col_q, kxp = P.kxp;
+    const int NL = P.col_nq * 16;
+    float2 *col = g.spec + P.spec_base + (int64_t)f * P.ny * kxp + c0;
+    for (int idx = threadIdx.x; idx < Pn * NL; idx += kThreads) {
+        const int pp = idx / NL, r = idx - pp * NL;
+        const int ql = r >> 4, c = r & 15;
+        lds[bitrev(pp, lgP) * NL + r] = col[(int64_t)(q0 + ql + Q * pp) * kxp + c];
     }
     __syncthreads();
-    lds_line_dft(lds, L, cb, 1, cb, g.tables);
-    for (int idx = threadIdx.x; idx < ny * cb; idx += blockDim.x) {
-        const int j = idx / cb, c = idx - j * cb;
-        if (c < ncol) col[(int64_t)j * nkx + c] = lds[idx];
+    lds_fft_dit<false>(lds, lgP, NL, 1, NL, g.tables, false);
+    const int lgN = P.col_lgn;
+    for (int idx = threadIdx.x; idx < Pn * NL; idx += kThreads) {
+        const int k1 = idx / NL, r = idx - k1 * NL;
+        const int ql = r >> 4, c = r & 15;
+        const int e = ((q0 + ql) * k1) & ((1 << lgN) - 1);
+        col[(int64_t)(q0 + ql + Q * k1) * kxp + c] = cmul(lds[idx], twiddle(g.tables, e, lgN));
     }
 }
 
-__global__ __launch_bounds__(kThreads) void corr_accum_kernel(CorrArgs g)
+// Fifteen products of the five spectra at one k, added to the sums.
+__device__ __forceinline__ void accumulate_k(double *a, int64_t kstride, const float2 (&X)[5])
 {
-    const CorrItem it = g.items[blockIdx.x];
-    if (it.lattice < 0) return;
-    const LatticeParams &P = g.params[it.lattice];
-    const int64_t nk = (int64_t)P.ny * P.nkx;
-    const int64_t k = (int64_t)it.a + threadIdx.x;
-    if (k >= nk || k == 0) return;  // k = 0 carries no fluctuation
-    const float2 *sp = g.spec + P.spec_base;
     double re[5], im[5];
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
-        const float2 v = sp[f * nk + k];
-        re[f] = v.x;
-        im[f] = v.y;
+        re[f] = X[f].x;
+        im[f] = X[f].y;
     }
-    double *a = g.acc + P.acc_base + k;
     // a b* = (ar br + ai bi) + i (ai br - ar bi)
 #define FLB_RE(u, v) (re[u] * re[v] + im[u] * im[v])
 #define FLB_IM(u, v) (im[u] * re[v] - re[u] * im[v])
@@ -242,7 +345,90 @@ __global__ __launch_bounds__(kThreads) void corr_accum_kernel(CorrArgs g)
 #undef FLB_RE
 #undef FLB_IM
 #pragma unroll
-    for (int q = 0; q < kKinds; ++q) a[q * nk] += val[q];
+    for (int q = 0; q < kKinds; ++q) a[q * kstride] += val[q];
+}
+
+// Power-of-two ny, pass B with accumulation.  item: lattice, first column, k1.
+// LDS [q][f][c]: the Q rows Q*k1 .. Q*k1+Q-1 of all five fields, 16 columns.
+__global__ __launch_bounds__(kThreads) void corr_cols_b_kernel(CorrArgs g)
+{
+    extern __shared__ float2 lds[];
+    const CorrItem it = g.items[blockIdx.x];
+    if (it.lattice < 0) return;
+    const LatticeParams &P = g.params[it.lattice];
+    const int c0 = it.a, k1 = it.b;
+    const int Q = P.col_q, lgQ = P.col_lgq, Pn = 1 << P.col_lgp;
+    const int ny = P.ny, nkx = P.nkx, kxp = P.kxp;
+    constexpr int NL = 5 * 16;
+    const float2 *spec = g.spec + P.spec_base + c0;
+    const int64_t fstride = (int64_t)ny * kxp;
+    for (int idx = threadIdx.x; idx < Q * NL; idx += kThreads) {
+        const int q = idx / NL, r = idx - q * NL;
+        const int f = r >> 4, c = r & 15;
+        lds[bitrev(q, lgQ) * NL + r] = spec[f * fstride + (int64_t)(Q * k1 + q) * kxp + c];
+    }
+    __syncthreads();
+    lds_fft_dit<false>(lds, lgQ, NL, 1, NL, g.tables, false);
+    double *acc = g.acc + P.acc_base;
+    for (int idx = threadIdx.x; idx < Q * 16; idx += kThreads) {
+        const int k2 = idx >> 4, c = idx & 15;
+        const int kx = c0 + c, ky = k1 + Pn * k2;
+        if (kx >= nkx || (kx == 0 && ky == 0)) continue;
+        float2 X[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) X[f] = lds[k2 * NL + f * 16 + c];
+        accumulate_k(acc + (int64_t)ky * kxp + kx, fstride, X);
+    }
+}
+
+// Other ny: whole columns, in place.  item: lattice, field, first column.
+__global__ __launch_bounds__(kThreads) void corr_cols_kernel(CorrArgs g, int cb)
+{
+    extern __shared__ float2 lds[];
+    const CorrItem it = g.items[blockIdx.x];
+    if (it.lattice < 0) return;
+    const LatticeParams &P = g.params[it.lattice];
+    const LinePlan &L = g.plans[P.line_y];
+    const int ny = P.ny, nkx = P.nkx, kxp = P.kxp;
+    const int f = it.a, c0 = it.b;
+    const int ncol = min(cb, nkx - c0);
+    float2 *col = g.spec + P.spec_base + (int64_t)f * ny * kxp + c0;
+    const float2 *chirp = g.tables + L.chirp_off;
+    for (int idx = threadIdx.x; idx < L.m * cb; idx += kThreads) {
+        const int j = idx / cb, c = idx - j * cb;
+        float2 v = make_float2(0.f, 0.f);
+        if (j < ny && c < ncol) {
+            v = col[(int64_t)j * kxp + c];
+            if (L.bluestein) v = cmul(v, chirp[j]);
+        }
+        lds[bitrev(j, L.log2m) * cb + c] = v;
+    }
+    __syncthreads();
+    lds_line_dft<false>(lds, L, cb, 1, cb, g.tables);
+    for (int idx = threadIdx.x; idx < ny * cb; idx += kThreads) {
+        const int j = idx / cb, c = idx - j * cb;
+        if (c < ncol) col[(int64_t)j * kxp + c] = lds[idx];
+    }
+}
+
+// Other ny: accumulation.  item: lattice, first k of the (ny, nkx) plane.
+__global__ __launch_bounds__(kThreads) void corr_accum_kernel(CorrArgs g)
+{
+    const CorrItem it = g.items[blockIdx.x];
+    if (it.lattice < 0) return;
+    const LatticeParams &P = g.params[it.lattice];
+    const int nkx = P.nkx, kxp = P.kxp;
+    const int64_t nk = (int64_t)P.ny * nkx;
+    const int64_t k = (int64_t)it.a + threadIdx.x;
+    if (k >= nk || k == 0) return;  // k = 0 carries no fluctuation
+    const int ky = (int)(k / nkx), kx = (int)(k - (int64_t)ky * nkx);
+    const int64_t o = (int64_t)ky * kxp + kx;
+    const int64_t fstride = (int64_t)P.ny * kxp;
+    const float2 *sp = g.spec + P.spec_base;
+    float2 X[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) X[f] = sp[f * fstride + o];
+    accumulate_k(g.acc + P.acc_base + o, fstride, X);
 }
 
 static CorrArgs make_args(const DeviceView &v, const CorrItem *items)
@@ -262,13 +448,29 @@ hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nite
                             int lds_bytes, hipStream_t s)
 {
     const CorrArgs g = make_args(v, items);
-    const dim3 grid(nitems), block(kThreads);
+    const dim3 grid(nitems), block(kRowThreads);
     if (v.storage == kF32)
         hipLaunchKernelGGL(corr_rows_kernel<kF32>, grid, block, lds_bytes, s, g);
     else if (v.storage == kBF16)
         hipLaunchKernelGGL(corr_rows_kernel<kBF16>, grid, block, lds_bytes, s, g);
     else
         hipLaunchKernelGGL(corr_rows_kernel<kF16>, grid, block, lds_bytes, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr_cols_a(const DeviceView &v, const CorrItem *items, int nitems,
+                              int lds_bytes, hipStream_t s)
+{
+    const CorrArgs g = make_args(v, items);
+    hipLaunchKernelGGL(corr_cols_a_kernel, dim3(nitems), dim3(kThreads), lds_bytes, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr_cols_b(const DeviceView &v, const CorrItem *items, int nitems,
+                              int lds_bytes, hipStream_t s)
+{
+    const CorrArgs g = make_args(v, items);
+    hipLaunchKernelGGL(corr_cols_b_kernel, dim3(nitems), dim3(kThreads), lds_bytes, s, g);
     return hipGetLastError();
 }
 

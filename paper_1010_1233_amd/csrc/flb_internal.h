@@ -2,7 +2,9 @@
 //
 // Device layout of one handle (all lattices of a batch share each buffer):
 //   pops[2]  : two population buffers (ping-pong), per lattice 9 planes of
-//              nx*ny values in the storage format, plane i at base + i*plane.
+//              ny rows of px values (px = nx rounded up to 4; the values
+//              past nx are padding, never part of the lattice) in the
+//              storage format, plane i at base + i*plane.
 //              They hold the POST-collision state of the last step; the
 //              state at time t (just after streaming) is
 //              f_i(x) = stored_i(x - v_i): every kernel that needs f(x)
@@ -10,8 +12,9 @@
 //   step     : one uint32 on the device, the time t of the next step, so
 //              that captured graphs replay with advancing noise counters.
 //   spec     : complex64 scratch for the correlator transforms, per lattice
-//              5 fields x ny x nkx (the half spectra of the real fields).
-//   acc      : FP64 correlator sums, per lattice FLB_NKINDS x ny x nkx.
+//              5 fields x ny x kxp (the half spectra of the real fields; kxp
+//              is nkx = nx/2+1 rounded up to 16 so column blocks are 128 B).
+//   acc      : FP64 correlator sums, per lattice FLB_NKINDS x ny x kxp.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,8 +31,10 @@ struct alignas(16) LatticeParams {
     int32_t nx, ny;
     int32_t nkx;              // nx/2 + 1
     int32_t tiles_x;          // step tiles along x
+    int32_t px;               // storage row pitch: nx rounded up to 4
+    int32_t pad1;
     int64_t base;             // element offset of population 0 in pops[]
-    int64_t plane;            // nx*ny
+    int64_t plane;            // px*ny
     int64_t spec_base;        // complex offset of field 0 in spec
     int64_t acc_base;         // double offset of kind 0 in acc
     float omega[6];           // 1/tau^a, a = 3..8
@@ -42,6 +47,12 @@ struct alignas(16) LatticeParams {
     uint32_t stream_id;
     int32_t line_x;           // index of the x-direction line plan
     int32_t line_y;           // index of the y-direction line plan
+    int32_t kxp;              // row pitch of spectra and sums: nkx rounded up to 16
+    int32_t col_pow2;         // ny is a power of two: columns by the P*Q split
+    int32_t col_q, col_lgq;   // Q = min(ny, 64) consecutive rows per pass-B block
+    int32_t col_lgp;          // P = ny / Q
+    int32_t col_lgn;          // log2 ny
+    int32_t col_nq;           // q values per pass-A block
     int32_t pad0;
 };
 
@@ -97,7 +108,7 @@ struct DeviceView {
 };
 
 hipError_t launch_step(const DeviceView &v, const StepItem *items, int nitems, int tile_w,
-                       int rows, uint32_t step_add, bool nontemporal, bool noise,
+                       int sites, uint32_t step_add, bool nontemporal, bool noise,
                        hipStream_t s);
 bool step_tile_supported(int tw, int r);
 hipError_t launch_advance_step(uint32_t *step, uint32_t n, hipStream_t s);
@@ -116,6 +127,10 @@ hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nite
                             int lds_bytes, hipStream_t s);
 hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int cb,
                             int lds_bytes, hipStream_t s);
+hipError_t launch_corr_cols_a(const DeviceView &v, const CorrItem *items, int nitems,
+                              int lds_bytes, hipStream_t s);
+hipError_t launch_corr_cols_b(const DeviceView &v, const CorrItem *items, int nitems,
+                              int lds_bytes, hipStream_t s);
 hipError_t launch_corr_accum(const DeviceView &v, const CorrItem *items, int nitems,
                              hipStream_t s);
 hipError_t launch_fill(double *p, size_t n, hipStream_t s);

@@ -75,8 +75,8 @@ struct flb {
     double *d_red = nullptr;  // reduction scratch
     int red_blocks = 1024;
 
-    // stepping
-    int tile_w = 256, rows = 1;
+    // stepping: tiles of tile_w threads along x, `sites` sites per thread
+    int tile_w = 256, sites = 1;
     bool nontemporal = false;
     StepItem *d_items = nullptr;
     int nitems = 0;
@@ -91,8 +91,9 @@ struct flb {
     double *d_acc = nullptr;
     int64_t spec_elems = 0, acc_elems = 0;
     CorrItem *d_rows = nullptr, *d_cols = nullptr, *d_accum = nullptr;
-    int n_rows = 0, n_cols = 0, n_accum = 0;
-    int rows_lds = 0, cols_lds = 0, cols_cb = 1;
+    CorrItem *d_cols_a = nullptr, *d_cols_b = nullptr;
+    int n_rows = 0, n_cols = 0, n_accum = 0, n_cols_a = 0, n_cols_b = 0;
+    int rows_lds = 0, cols_lds = 0, cols_cb = 1, cols_a_lds = 0, cols_b_lds = 0;
     int64_t nsamples = 0;
 
     // streams and graphs
@@ -133,7 +134,7 @@ int validate_spec(const flb_lattice_spec &s, int idx)
                  s.ny);
         return fail(FLB_EINVAL, buf);
     }
-    if ((int64_t)s.nx * s.ny * 9 >= (int64_t)1 << 31) {
+    if ((int64_t)(s.nx + 3) * s.ny * 9 >= (int64_t)1 << 31) {
         snprintf(buf, sizeof buf, "lattice %d: 9*nx*ny must stay below 2^31", idx);
         return fail(FLB_ESIZE, buf);
     }
@@ -160,7 +161,8 @@ LatticeParams make_params(const flb_lattice_spec &s, uint32_t flags)
     P.nx = s.nx;
     P.ny = s.ny;
     P.nkx = s.nx / 2 + 1;
-    P.plane = (int64_t)s.nx * s.ny;
+    P.px = (s.nx + 3) / 4 * 4;
+    P.plane = (int64_t)P.px * s.ny;
     const double mu = s.theta / kCs2;
     // scale of each stored moment relative to M^a: s3 = 3/2 M3, s4 = 3 M4,
     // s5 = M5, s6,7 = sqrt(3/2) M6,7, s8 = M8
@@ -223,11 +225,12 @@ int upload(T **dptr, const std::vector<T> &v)
 int build_step_items(flb_t *h)
 {
     const int TH = kThreads / h->tile_w;
+    const int TW = h->tile_w * h->sites;  // sites per tile row
     std::vector<StepItem> items;
     for (size_t l = 0; l < h->params.size(); ++l) {
         LatticeParams &P = h->params[l];
-        P.tiles_x = (P.nx + h->tile_w - 1) / h->tile_w;
-        const int tiles_y = (P.ny + TH * h->rows - 1) / (TH * h->rows);
+        P.tiles_x = (P.nx + TW - 1) / TW;
+        const int tiles_y = (P.ny + TH - 1) / TH;
         for (int t = 0; t < P.tiles_x * tiles_y; ++t) items.push_back({(int32_t)l, t});
     }
     items = xcd_order(items, StepItem{-1, 0});
@@ -280,9 +283,13 @@ int setup_correlators(flb_t *h)
     if (h->corr_ready) return FLB_OK;
     // tables below replace device buffers that queued kernels may still read
     FLB_HIP(hipStreamSynchronize(h->stream));
-    for (auto &P : h->params)
-        if (P.nx > FLB_MAX_FFT_SIDE || P.ny > FLB_MAX_FFT_SIDE)
-            return fail(FLB_ESIZE, "correlators support sides up to FLB_MAX_FFT_SIDE");
+    for (auto &P : h->params) {
+        const bool ok_x = is_pow2(P.nx) ? P.nx <= FLB_MAX_FFT_SIDE : P.nx <= FLB_MAX_FFT_SIDE / 2;
+        const bool ok_y = is_pow2(P.ny) ? P.ny <= FLB_MAX_FFT_SIDE : P.ny <= FLB_MAX_FFT_SIDE / 2;
+        if (!ok_x || !ok_y)
+            return fail(FLB_ESIZE, "correlators support power-of-two sides up to FLB_MAX_FFT_SIDE "
+                                   "and other sides up to FLB_MAX_FFT_SIDE/2");
+    }
 
     // tables: twiddles, then chirp and kernel of every Bluestein length
     std::vector<float2> tables(kTwN / 2);
@@ -332,45 +339,79 @@ int setup_correlators(flb_t *h)
     };
 
     int64_t spec = 0, acc = 0;
-    int max_mx = 1, max_my = 1;
+    int max_my_general = 1;
+    h->rows_lds = h->cols_a_lds = h->cols_b_lds = h->cols_lds = 0;
     for (auto &P : h->params) {
         P.line_x = plan_for(P.nx);
         P.line_y = plan_for(P.ny);
-        max_mx = std::max(max_mx, h->plans[P.line_x].m);
-        max_my = std::max(max_my, h->plans[P.line_y].m);
+        P.kxp = (P.nkx + 15) / 16 * 16;
+        P.col_pow2 = is_pow2(P.ny);
+        if (P.col_pow2) {
+            P.col_lgn = log2i(P.ny);
+            P.col_q = std::min(P.ny, 64);
+            P.col_lgq = log2i(P.col_q);
+            P.col_lgp = P.col_lgn - P.col_lgq;
+            const int Pn = 1 << P.col_lgp;
+            P.col_nq = std::min(P.col_q, std::max(1, 256 / Pn));
+            if (Pn > 1)
+                h->cols_a_lds = std::max(h->cols_a_lds, Pn * P.col_nq * 16 * (int)sizeof(float2));
+            h->cols_b_lds = std::max(h->cols_b_lds, P.col_q * 80 * (int)sizeof(float2));
+        } else {
+            max_my_general = std::max(max_my_general, h->plans[P.line_y].m);
+        }
         P.spec_base = spec;
         P.acc_base = acc;
-        spec += (int64_t)kFields * P.ny * P.nkx;
-        acc += (int64_t)kKinds * P.ny * P.nkx;
+        spec += (int64_t)kFields * P.ny * P.kxp;
+        acc += (int64_t)kKinds * P.ny * P.kxp;
     }
     h->spec_elems = spec;
     h->acc_elems = acc;
-    h->rows_lds = max_mx * (int)sizeof(float2);
-    h->cols_cb = std::max(1, std::min(16, 8192 / max_my));
-    h->cols_lds = max_my * h->cols_cb * (int)sizeof(float2);
+    h->cols_cb = std::max(1, std::min(16, 8192 / max_my_general));
+    h->cols_lds = max_my_general * h->cols_cb * (int)sizeof(float2);
 
-    std::vector<CorrItem> rows, cols, accum;
+    std::vector<CorrItem> rows, cols, accum, cols_a, cols_b;
     for (size_t l = 0; l < h->params.size(); ++l) {
         const LatticeParams &P = h->params[l];
-        for (int y = 0; y < P.ny; ++y) {
-            rows.push_back({(int32_t)l, y, 0, 0});
-            rows.push_back({(int32_t)l, y, 1, 0});
-            if ((y & 1) == 0) rows.push_back({(int32_t)l, y, 2, 0});
+        const int mx = h->plans[P.line_x].m;
+        // rows per block: up to 4096 work elements (32 KB of LDS); the row
+        // kernel holds at most 16 sites per thread
+        const int rb = std::max(1, std::min(P.ny, 4096 / mx));
+        // the row kernel pads its LDS lines (one slot per 16 and per 256)
+        const int slots = rb * mx + (rb * mx >> 4) + (rb * mx >> 8) + 1;
+        h->rows_lds = std::max(h->rows_lds, slots * (int)sizeof(float2));
+        for (int y = 0; y < P.ny; y += rb) rows.push_back({(int32_t)l, y, rb, 0});
+        if (P.col_pow2) {
+            const int Pn = 1 << P.col_lgp;
+            if (Pn > 1)
+                for (int f = 0; f < kFields; ++f)
+                    for (int c0 = 0; c0 < P.kxp; c0 += 16)
+                        for (int q0 = 0; q0 < P.col_q; q0 += P.col_nq)
+                            cols_a.push_back({(int32_t)l, f, c0, q0});
+            for (int c0 = 0; c0 < P.kxp; c0 += 16)
+                for (int k1 = 0; k1 < Pn; ++k1) cols_b.push_back({(int32_t)l, c0, k1, 0});
+        } else {
+            for (int f = 0; f < kFields; ++f)
+                for (int c0 = 0; c0 < P.nkx; c0 += h->cols_cb)
+                    cols.push_back({(int32_t)l, f, c0, 0});
+            const int64_t nk = (int64_t)P.ny * P.nkx;
+            for (int64_t k0 = 0; k0 < nk; k0 += kThreads)
+                accum.push_back({(int32_t)l, (int32_t)k0, 0, 0});
         }
-        for (int f = 0; f < kFields; ++f)
-            for (int c0 = 0; c0 < P.nkx; c0 += h->cols_cb) cols.push_back({(int32_t)l, f, c0, 0});
-        const int64_t nk = (int64_t)P.ny * P.nkx;
-        for (int64_t k0 = 0; k0 < nk; k0 += kThreads) accum.push_back({(int32_t)l, (int32_t)k0, 0, 0});
     }
     const CorrItem idle{-1, 0, 0, 0};
     rows = xcd_order(rows, idle);
+    cols_a = xcd_order(cols_a, idle);
+    cols_b = xcd_order(cols_b, idle);
     cols = xcd_order(cols, idle);
     h->n_rows = (int)rows.size();
     h->n_cols = (int)cols.size();
     h->n_accum = (int)accum.size();
+    h->n_cols_a = (int)cols_a.size();
+    h->n_cols_b = (int)cols_b.size();
     int rc;
     if ((rc = upload(&h->d_rows, rows)) || (rc = upload(&h->d_cols, cols)) ||
-        (rc = upload(&h->d_accum, accum)) || (rc = upload(&h->d_plans, h->plans)) ||
+        (rc = upload(&h->d_accum, accum)) || (rc = upload(&h->d_cols_a, cols_a)) ||
+        (rc = upload(&h->d_cols_b, cols_b)) || (rc = upload(&h->d_plans, h->plans)) ||
         (rc = upload(&h->d_tables, tables)) || (rc = upload(&h->d_params, h->params)))
         return rc;
     FLB_HIP(hipMalloc((void **)&h->d_spec, spec * sizeof(float2)));
@@ -386,8 +427,10 @@ int enqueue_sample(flb_t *h, hipStream_t s)
 {
     const DeviceView v = h->view();
     FLB_HIP(launch_corr_rows(v, h->d_rows, h->n_rows, h->rows_lds, s));
-    FLB_HIP(launch_corr_cols(v, h->d_cols, h->n_cols, h->cols_cb, h->cols_lds, s));
-    FLB_HIP(launch_corr_accum(v, h->d_accum, h->n_accum, s));
+    if (h->n_cols_a) FLB_HIP(launch_corr_cols_a(v, h->d_cols_a, h->n_cols_a, h->cols_a_lds, s));
+    if (h->n_cols_b) FLB_HIP(launch_corr_cols_b(v, h->d_cols_b, h->n_cols_b, h->cols_b_lds, s));
+    if (h->n_cols) FLB_HIP(launch_corr_cols(v, h->d_cols, h->n_cols, h->cols_cb, h->cols_lds, s));
+    if (h->n_accum) FLB_HIP(launch_corr_accum(v, h->d_accum, h->n_accum, s));
     return FLB_OK;
 }
 
@@ -395,7 +438,7 @@ int enqueue_sample(flb_t *h, hipStream_t s)
 int enqueue_steps(flb_t *h, int64_t n, hipStream_t s)
 {
     for (int64_t k = 0; k < n; ++k) {
-        FLB_HIP(launch_step(h->view(), h->d_items, h->nitems, h->tile_w, h->rows, (uint32_t)k,
+        FLB_HIP(launch_step(h->view(), h->d_items, h->nitems, h->tile_w, h->sites, (uint32_t)k,
                             h->nontemporal, h->noise, s));
         h->cur ^= 1;
     }
@@ -448,6 +491,13 @@ flb_t *create_impl(int n, const flb_lattice_spec *specs, uint64_t seed, int stor
     h->total_elems = off;
     // streaming stores pay off once a buffer no longer fits the last-level cache
     h->nontemporal = (double)off * h->elem_bytes > 256.0 * 1024 * 1024;
+    // measured on MI355X at 4096^2: FP32 is best with one site per thread
+    // (scalar accesses spread the 18 streams best), 16-bit storage with four
+    // (the ALU-bound form profits from fewer address computations)
+    if (h->elem_bytes == 2) {
+        h->tile_w = 128;
+        h->sites = 4;
+    }
 
     auto bail = [&](int rc) -> flb_t * {
         (void)rc;
@@ -464,12 +514,13 @@ flb_t *create_impl(int n, const flb_lattice_spec *specs, uint64_t seed, int stor
         return bail(0);
     }
     h->stream = h->own;
+    // both population buffers in one allocation
     const size_t bytes = (size_t)h->total_elems * h->elem_bytes;
-    for (int b = 0; b < 2; ++b)
-        if (hipMalloc(&h->pops[b], bytes) != hipSuccess) {
-            fail(FLB_ENOMEM, "population buffers: out of device memory");
-            return bail(0);
-        }
+    if (hipMalloc(&h->pops[0], 2 * bytes) != hipSuccess) {
+        fail(FLB_ENOMEM, "population buffers: out of device memory");
+        return bail(0);
+    }
+    h->pops[1] = (char *)h->pops[0] + bytes;
     if (hipMalloc((void **)&h->d_step, sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&h->d_red, (size_t)(h->red_blocks * 9 + 16) * sizeof(double)) !=
             hipSuccess) {
@@ -552,9 +603,9 @@ void flb_destroy(flb_t *h)
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->own) (void)hipStreamSynchronize(h->own);
     clear_graphs(h);
-    void *ptrs[] = {h->pops[0], h->pops[1], h->d_params, h->d_step, h->d_red, h->d_items,
+    void *ptrs[] = {h->pops[0], h->d_params, h->d_step, h->d_red, h->d_items,
                     h->d_plans, h->d_tables, h->d_spec, h->d_acc, h->d_rows, h->d_cols,
-                    h->d_accum};
+                    h->d_accum, h->d_cols_a, h->d_cols_b};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->ev) (void)hipEventDestroy(h->ev);
@@ -678,7 +729,10 @@ int flb_read_correlators(flb_t *h, int lattice, double *out, size_t n_doubles, i
     const size_t need = (size_t)kKinds * P.ny * P.nkx;
     if (n_doubles < need) return fail(FLB_ESIZE, "output buffer too small for the correlators");
     FLB_HIP(hipStreamSynchronize(h->stream));
-    FLB_HIP(hipMemcpy(out, h->d_acc + P.acc_base, need * sizeof(double), hipMemcpyDeviceToHost));
+    // device rows have pitch kxp >= nkx
+    FLB_HIP(hipMemcpy2D(out, (size_t)P.nkx * sizeof(double), h->d_acc + P.acc_base,
+                        (size_t)P.kxp * sizeof(double), (size_t)P.nkx * sizeof(double),
+                        (size_t)kKinds * P.ny, hipMemcpyDeviceToHost));
     if (nsamples) *nsamples = h->nsamples;
     return FLB_OK;
 }
@@ -698,7 +752,7 @@ int flb_get_populations(flb_t *h, int lattice, double *out, size_t n)
     if (check_lattice(h, lattice)) return FLB_EINVAL;
     if (!out) return fail(FLB_EINVAL, "out must not be NULL");
     const LatticeParams &P = h->params[lattice];
-    const size_t need = 9 * (size_t)P.plane;
+    const size_t need = 9 * (size_t)P.nx * (size_t)P.ny;
     if (n < need) return fail(FLB_ESIZE, "output buffer smaller than 9*nx*ny");
     double *d = nullptr;
     FLB_HIP(hipMalloc((void **)&d, need * sizeof(double)));
@@ -715,7 +769,7 @@ int flb_set_populations(flb_t *h, int lattice, const double *in, size_t n)
     if (check_lattice(h, lattice)) return FLB_EINVAL;
     if (!in) return fail(FLB_EINVAL, "in must not be NULL");
     const LatticeParams &P = h->params[lattice];
-    const size_t need = 9 * (size_t)P.plane;
+    const size_t need = 9 * (size_t)P.nx * (size_t)P.ny;
     if (n < need) return fail(FLB_ESIZE, "input buffer smaller than 9*nx*ny");
     double *d = nullptr;
     FLB_HIP(hipMalloc((void **)&d, need * sizeof(double)));
@@ -733,7 +787,8 @@ int flb_conservation(flb_t *h, int lattice, double out[5])
     if (check_lattice(h, lattice)) return FLB_EINVAL;
     if (!out) return fail(FLB_EINVAL, "out must not be NULL");
     const LatticeParams &P = h->params[lattice];
-    const int nb = (int)std::min<int64_t>(h->red_blocks, (P.plane + kThreads - 1) / kThreads);
+    const int nb = (int)std::min<int64_t>(h->red_blocks,
+                                          ((int64_t)P.nx * P.ny + kThreads - 1) / kThreads);
     double *res = h->d_red + (size_t)h->red_blocks * 9;
     FLB_HIP(launch_conservation(h->view(), lattice, P.nx, P.ny, h->d_red, nb, res, h->stream));
     FLB_HIP(hipStreamSynchronize(h->stream));
@@ -746,7 +801,8 @@ int flb_conservation_dev(flb_t *h, int lattice, double *out_dev)
     if (check_lattice(h, lattice)) return FLB_EINVAL;
     if (!out_dev) return fail(FLB_EINVAL, "out_dev must not be NULL");
     const LatticeParams &P = h->params[lattice];
-    const int nb = (int)std::min<int64_t>(h->red_blocks, (P.plane + kThreads - 1) / kThreads);
+    const int nb = (int)std::min<int64_t>(h->red_blocks,
+                                          ((int64_t)P.nx * P.ny + kThreads - 1) / kThreads);
     FLB_HIP(launch_conservation(h->view(), lattice, P.nx, P.ny, h->d_red, nb, out_dev, h->stream));
     return FLB_OK;
 }
@@ -756,7 +812,8 @@ int flb_thermalize(flb_t *h)
     if (check_handle(h)) return FLB_EINVAL;
     for (size_t l = 0; l < h->params.size(); ++l) {
         const LatticeParams &P = h->params[l];
-        const int nb = (int)std::min<int64_t>(h->red_blocks, (P.plane + kThreads - 1) / kThreads);
+        const int nb = (int)std::min<int64_t>(h->red_blocks,
+                                          ((int64_t)P.nx * P.ny + kThreads - 1) / kThreads);
         double *sums = h->d_red + (size_t)h->red_blocks * 9;
         FLB_HIP(launch_thermalize(h->view(), (int)l, P.nx, P.ny, h->d_red, nb, sums, h->stream));
     }
@@ -819,25 +876,125 @@ int flb_storage_info(flb_t *h, int32_t *storage, int32_t *bytes_per_value)
     return FLB_OK;
 }
 
-int flb_set_step_config(flb_t *h, int tile_w, int rows, int nontemporal)
+int flb_set_step_config(flb_t *h, int tile_w, int sites, int nontemporal)
 {
     if (check_handle(h)) return FLB_EINVAL;
-    if (!step_tile_supported(tile_w, rows)) return fail(FLB_EINVAL, "unsupported step tile");
+    if (!step_tile_supported(tile_w, sites)) return fail(FLB_EINVAL, "unsupported step tile");
     FLB_HIP(hipStreamSynchronize(h->stream));
     h->tile_w = tile_w;
-    h->rows = rows;
+    h->sites = sites;
     h->nontemporal = nontemporal != 0;
     clear_graphs(h);
     return build_step_items(h);
 }
 
-int flb_get_step_config(flb_t *h, int *tile_w, int *rows, int *nontemporal)
+int flb_get_step_config(flb_t *h, int *tile_w, int *sites, int *nontemporal)
 {
     if (check_handle(h)) return FLB_EINVAL;
     if (tile_w) *tile_w = h->tile_w;
-    if (rows) *rows = h->rows;
+    if (sites) *sites = h->sites;
     if (nontemporal) *nontemporal = h->nontemporal ? 1 : 0;
     return FLB_OK;
+}
+
+int flb_autotune(flb_t *h, int nsteps, double *ms_out)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (nsteps < 1) return fail(FLB_EINVAL, "nsteps must be >= 1");
+    int64_t total = 0;
+    int maxside = 0;
+    for (auto &P : h->params) {
+        total += (int64_t)P.nx * P.ny;
+        maxside = std::max(maxside, std::max(P.nx, P.ny));
+    }
+    char key[160];
+    snprintf(key, sizeof key, "flb-step:%d:%zu:%lld:%d:%d", h->storage, h->params.size(),
+             (long long)total, maxside, h->noise ? 1 : 0);
+    const char *cache = getenv("FLB_AUTOTUNE_CACHE");
+    if (cache) {
+        if (FILE *fp = fopen(cache, "r")) {
+            char k[160];
+            int tw, sv, nt;
+            double ms;
+            int found = 0;
+            while (fscanf(fp, "%159s %d %d %d %lf", k, &tw, &sv, &nt, &ms) == 5)
+                if (strcmp(k, key) == 0 && step_tile_supported(tw, sv)) {
+                    found = 1;
+                    h->tile_w = tw;
+                    h->sites = sv;
+                    h->nontemporal = nt != 0;
+                    if (ms_out) *ms_out = ms;
+                }
+            fclose(fp);
+            if (found) {
+                clear_graphs(h);
+                return build_step_items(h);
+            }
+        }
+    }
+
+    // save the state: the candidates advance it
+    FLB_HIP(hipStreamSynchronize(h->stream));
+    const size_t bytes = (size_t)h->total_elems * h->elem_bytes;
+    void *saved = nullptr;
+    FLB_HIP(hipMalloc(&saved, bytes));
+    uint32_t step0 = 0;
+    const int cur0 = h->cur;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = FLB_OK;
+    hipError_t e = hipMemcpyAsync(saved, h->pops[cur0], bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&step0, h->d_step, sizeof step0, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int best_tw = h->tile_w, best_sv = h->sites;
+    bool best_nt = h->nontemporal;
+    float best = 1e30f;
+    const int tws[3] = {64, 128, 256}, svs[3] = {1, 2, 4};
+    for (int a = 0; a < 3 && e == hipSuccess && rc == FLB_OK; ++a)
+        for (int b = 0; b < 3 && e == hipSuccess && rc == FLB_OK; ++b)
+            for (int nt = 0; nt < 2 && e == hipSuccess && rc == FLB_OK; ++nt) {
+                h->tile_w = tws[a];
+                h->sites = svs[b];
+                h->nontemporal = nt != 0;
+                if ((rc = build_step_items(h)) != FLB_OK) break;
+                if ((rc = enqueue_steps(h, 2, h->stream)) != FLB_OK) break;
+                e = hipEventRecord(e0, h->stream);
+                if (e == hipSuccess && (rc = enqueue_steps(h, nsteps, h->stream)) != FLB_OK) break;
+                if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e == hipSuccess && ms / nsteps < best) {
+                    best = ms / nsteps;
+                    best_tw = tws[a];
+                    best_sv = svs[b];
+                    best_nt = nt != 0;
+                }
+            }
+    // restore the state, the step counter and the buffer parity
+    h->cur = cur0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->pops[cur0], saved, bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->d_step, &step0, sizeof step0, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(saved);
+    if (rc != FLB_OK) return rc;
+    if (e != hipSuccess) return fail(FLB_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+    h->tile_w = best_tw;
+    h->sites = best_sv;
+    h->nontemporal = best_nt;
+    clear_graphs(h);
+    if (ms_out) *ms_out = best;
+    if (cache)
+        if (FILE *fp = fopen(cache, "a")) {
+            fprintf(fp, "%s %d %d %d %.6f\n", key, best_tw, best_sv, best_nt ? 1 : 0, (double)best);
+            fclose(fp);
+        }
+    return build_step_items(h);
 }
 
 }  // extern "C"

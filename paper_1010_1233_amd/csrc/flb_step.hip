@@ -90,67 +90,132 @@ struct StepArgs {
     uint32_t key0, key1;
 };
 
-template <int S, bool NT, bool NOISE, int TW, int R>
+// Collision of one site, including its noise draw.
+template <bool NOISE>
+__device__ __forceinline__ void update_site(float (&d)[9], const LatticeParams &P, uint32_t site,
+                                            uint32_t t, uint32_t key0, uint32_t key1)
+{
+    float z[6] = {0, 0, 0, 0, 0, 0};
+    if constexpr (NOISE) normals6(philox4x32_10(make_uint4(site, t, P.stream_id, 0u), key0, key1), z);
+    collide<NOISE>(d, P, z);
+}
+
+// V consecutive values of one storage row, as one vector access.
+template <typename T, int V> struct Vec {
+    typedef T type __attribute__((ext_vector_type(V)));
+};
+template <typename T> struct Vec<T, 1> {
+    typedef T type;
+};
+template <typename T, int V>
+__device__ __forceinline__ T lane(const typename Vec<T, V>::type &v, int k)
+{
+    if constexpr (V == 1) return v;
+    else return v[k];
+}
+
+// A block covers a tile of TX threads along x by kThreads/TX rows; a thread
+// updates V consecutive sites x0 .. x0+V-1 of its row.  Storage rows have a
+// pitch px (a multiple of 4), so the V values of one population are one
+// aligned vector access.  A population streaming along +x needs the value
+// left of the group (x0 - 1, periodic) and one streaming along -x the value
+// right of it (x0 + V): one extra scalar load each.  A group reaching past
+// the last site of a row (nx not a multiple of V) takes the site-by-site path.
+template <int S, bool NT, bool NOISE, int TX, int V>
 __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs g)
 {
     using T = typename Codec<S>::T;
-    constexpr int TH = kThreads / TW;
+    using VT = typename Vec<T, V>::type;
+    constexpr int TH = kThreads / TX;
     const StepItem it = g.items[blockIdx.x];
     if (it.lattice < 0) return;
     const LatticeParams &P = g.params[it.lattice];
-    const int nx = P.nx, ny = P.ny;
+    const int nx = P.nx, ny = P.ny, px = P.px;
     const int tx = it.tile % P.tiles_x, ty = it.tile / P.tiles_x;
-    const int x = tx * TW + (int)(threadIdx.x % TW);
-    if (x >= nx) return;  // no barriers below: a thread may leave early
-    const int y0 = ty * (TH * R) + (int)(threadIdx.x / TW);
+    const int x0 = (tx * TX + (int)(threadIdx.x % TX)) * V;
+    const int y = ty * TH + (int)(threadIdx.x / TX);
+    if (x0 >= nx || y >= ny) return;  // no barriers below: a thread may leave early
     const T *__restrict__ src = (const T *)g.src + P.base;
     T *__restrict__ dst = (T *)g.dst + P.base;
     const int plane = (int)P.plane;
-    const int xm = (x == 0) ? nx - 1 : x - 1;
-    const int xp = (x == nx - 1) ? 0 : x + 1;
     const uint32_t t = *g.step + g.step_add;
+    const int ym = (y == 0) ? ny - 1 : y - 1;
+    const int yp = (y == ny - 1) ? 0 : y + 1;
+    const int rc = y * px, rm = ym * px, rp = yp * px;
+    const int xm = (x0 == 0) ? nx - 1 : x0 - 1;       // left of the group
+    const uint32_t site0 = (uint32_t)(y * nx + x0);    // noise counter of site x0
 
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int y = y0 + r * TH;
-        if (y >= ny) break;
-        const int ym = (y == 0) ? ny - 1 : y - 1;
-        const int yp = (y == ny - 1) ? 0 : y + 1;
-        const int rc = y * nx, rm = ym * nx, rp = yp * nx;
+    if (x0 + V <= nx) {
+        const int xr = (x0 + V == nx) ? 0 : x0 + V;    // right of the group
         // pull: population i arrives from x - v_i
-        T q[9];
-        q[0] = src[rc + x];
-        q[1] = src[1 * plane + rc + xm];
-        q[2] = src[2 * plane + rm + x];
-        q[3] = src[3 * plane + rc + xp];
-        q[4] = src[4 * plane + rp + x];
-        q[5] = src[5 * plane + rm + xm];
-        q[6] = src[6 * plane + rm + xp];
-        q[7] = src[7 * plane + rp + xp];
-        q[8] = src[8 * plane + rp + xm];
-        float d[9];
+        const VT a0 = *(const VT *)(src + rc + x0);
+        const VT a1 = *(const VT *)(src + 1 * plane + rc + x0);
+        const VT a2 = *(const VT *)(src + 2 * plane + rm + x0);
+        const VT a3 = *(const VT *)(src + 3 * plane + rc + x0);
+        const VT a4 = *(const VT *)(src + 4 * plane + rp + x0);
+        const VT a5 = *(const VT *)(src + 5 * plane + rm + x0);
+        const VT a6 = *(const VT *)(src + 6 * plane + rm + x0);
+        const VT a7 = *(const VT *)(src + 7 * plane + rp + x0);
+        const VT a8 = *(const VT *)(src + 8 * plane + rp + x0);
+        const T e1 = src[1 * plane + rc + xm], e5 = src[5 * plane + rm + xm];
+        const T e8 = src[8 * plane + rp + xm];
+        const T e3 = src[3 * plane + rc + xr], e6 = src[6 * plane + rm + xr];
+        const T e7 = src[7 * plane + rp + xr];
+        T o[9][V];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) d[i] = Codec<S>::decode(q[i], P, i);
-
-        float z[6] = {0, 0, 0, 0, 0, 0};
-        if constexpr (NOISE) {
-            const uint4 w = philox4x32_10(make_uint4((uint32_t)(rc + x), t, P.stream_id, 0u),
-                                          g.key0, g.key1);
-            normals6(w, z);
+        for (int k = 0; k < V; ++k) {
+            float d[9];
+            d[0] = Codec<S>::decode(lane<T, V>(a0, k), P, 0);
+            d[2] = Codec<S>::decode(lane<T, V>(a2, k), P, 2);
+            d[4] = Codec<S>::decode(lane<T, V>(a4, k), P, 4);
+            d[1] = Codec<S>::decode(k > 0 ? lane<T, V>(a1, k - 1) : e1, P, 1);
+            d[5] = Codec<S>::decode(k > 0 ? lane<T, V>(a5, k - 1) : e5, P, 5);
+            d[8] = Codec<S>::decode(k > 0 ? lane<T, V>(a8, k - 1) : e8, P, 8);
+            d[3] = Codec<S>::decode(k < V - 1 ? lane<T, V>(a3, k + 1) : e3, P, 3);
+            d[6] = Codec<S>::decode(k < V - 1 ? lane<T, V>(a6, k + 1) : e6, P, 6);
+            d[7] = Codec<S>::decode(k < V - 1 ? lane<T, V>(a7, k + 1) : e7, P, 7);
+            update_site<NOISE>(d, P, site0 + (uint32_t)k, t, g.key0, g.key1);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) o[i][k] = Codec<S>::encode(d[i], P, i);
         }
-        collide<NOISE>(d, P, z);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) gstore<NT>(dst + i * plane + rc + x, Codec<S>::encode(d[i], P, i));
+        for (int i = 0; i < 9; ++i) {
+            VT v;
+            if constexpr (V == 1) {
+                v = o[i][0];
+            } else {
+#pragma unroll
+                for (int k = 0; k < V; ++k) v[k] = o[i][k];
+            }
+            gstore<NT>((VT *)(dst + i * plane + rc + x0), v);
+        }
+    } else {
+        for (int x = x0; x < nx; ++x) {
+            const int xl = (x == 0) ? nx - 1 : x - 1, xr = (x == nx - 1) ? 0 : x + 1;
+            float d[9];
+            d[0] = Codec<S>::decode(src[rc + x], P, 0);
+            d[1] = Codec<S>::decode(src[1 * plane + rc + xl], P, 1);
+            d[2] = Codec<S>::decode(src[2 * plane + rm + x], P, 2);
+            d[3] = Codec<S>::decode(src[3 * plane + rc + xr], P, 3);
+            d[4] = Codec<S>::decode(src[4 * plane + rp + x], P, 4);
+            d[5] = Codec<S>::decode(src[5 * plane + rm + xl], P, 5);
+            d[6] = Codec<S>::decode(src[6 * plane + rm + xr], P, 6);
+            d[7] = Codec<S>::decode(src[7 * plane + rp + xr], P, 7);
+            d[8] = Codec<S>::decode(src[8 * plane + rp + xl], P, 8);
+            update_site<NOISE>(d, P, (uint32_t)(y * nx + x), t, g.key0, g.key1);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) gstore<NT>(dst + i * plane + rc + x, Codec<S>::encode(d[i], P, i));
+        }
     }
 }
 
 template <int S, bool NT, bool NOISE>
-static hipError_t launch_step_tiles(const StepArgs &a, int nitems, int tw, int r, hipStream_t s)
+static hipError_t launch_step_tiles(const StepArgs &a, int nitems, int tx, int v, hipStream_t s)
 {
     const dim3 grid(nitems), block(kThreads);
-#define FLB_TILE(TW_, R_)                                                                     \
-    if (tw == TW_ && r == R_) {                                                               \
-        hipLaunchKernelGGL((step_kernel<S, NT, NOISE, TW_, R_>), grid, block, 0, s, a);       \
+#define FLB_TILE(TX_, V_)                                                                     \
+    if (tx == TX_ && v == V_) {                                                               \
+        hipLaunchKernelGGL((step_kernel<S, NT, NOISE, TX_, V_>), grid, block, 0, s, a);       \
         return hipGetLastError();                                                             \
     }
     FLB_TILE(64, 1)
@@ -159,19 +224,20 @@ static hipError_t launch_step_tiles(const StepArgs &a, int nitems, int tw, int r
     FLB_TILE(64, 2)
     FLB_TILE(128, 2)
     FLB_TILE(256, 2)
+    FLB_TILE(64, 4)
+    FLB_TILE(128, 4)
     FLB_TILE(256, 4)
 #undef FLB_TILE
     return hipErrorInvalidValue;
 }
 
-bool step_tile_supported(int tw, int r)
+bool step_tile_supported(int tx, int v)
 {
-    return (tw == 64 && (r == 1 || r == 2)) || (tw == 128 && (r == 1 || r == 2)) ||
-           (tw == 256 && (r == 1 || r == 2 || r == 4));
+    return (tx == 64 || tx == 128 || tx == 256) && (v == 1 || v == 2 || v == 4);
 }
 
 hipError_t launch_step(const DeviceView &v, const StepItem *items, int nitems, int tile_w,
-                       int rows, uint32_t step_add, bool nontemporal, bool noise, hipStream_t s)
+                       int sites, uint32_t step_add, bool nontemporal, bool noise, hipStream_t s)
 {
     StepArgs a;
     a.src = v.pops[v.cur];
@@ -185,10 +251,10 @@ hipError_t launch_step(const DeviceView &v, const StepItem *items, int nitems, i
 #define FLB_SEL(S_)                                                                              \
     if (v.storage == S_) {                                                                       \
         if (nontemporal)                                                                         \
-            return noise ? launch_step_tiles<S_, true, true>(a, nitems, tile_w, rows, s)         \
-                         : launch_step_tiles<S_, true, false>(a, nitems, tile_w, rows, s);       \
-        return noise ? launch_step_tiles<S_, false, true>(a, nitems, tile_w, rows, s)            \
-                     : launch_step_tiles<S_, false, false>(a, nitems, tile_w, rows, s);          \
+            return noise ? launch_step_tiles<S_, true, true>(a, nitems, tile_w, sites, s)        \
+                         : launch_step_tiles<S_, true, false>(a, nitems, tile_w, sites, s);      \
+        return noise ? launch_step_tiles<S_, false, true>(a, nitems, tile_w, sites, s)           \
+                     : launch_step_tiles<S_, false, false>(a, nitems, tile_w, sites, s);         \
     }
     FLB_SEL(kF32)
     FLB_SEL(kBF16)
@@ -262,8 +328,8 @@ __global__ __launch_bounds__(kThreads) void get_kernel(const void *pops,
 {
     using T = typename Codec<S>::T;
     const LatticeParams &P = params[lattice];
-    const int nx = P.nx, ny = P.ny;
-    const int64_t V = P.plane;
+    const int nx = P.nx, ny = P.ny, px = P.px;
+    const int64_t V = (int64_t)nx * ny, plane = P.plane;
     const T *p = (const T *)pops + P.base;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 9 * V;
          k += (int64_t)gridDim.x * blockDim.x) {
@@ -271,7 +337,7 @@ __global__ __launch_bounds__(kThreads) void get_kernel(const void *pops,
         const int s = (int)(k - (int64_t)i * V);
         const int y = s / nx, x = s - y * nx;
         const int xs = wrap_add(x, -kVX[i], nx), ys = wrap_add(y, -kVY[i], ny);
-        const float d = Codec<S>::decode(p[(int64_t)i * V + ys * nx + xs], P, i);
+        const float d = Codec<S>::decode(p[(int64_t)i * plane + ys * px + xs], P, i);
         out[k] = kWd[i] * (double)P.rho0 + (double)d;
     }
 }
@@ -282,8 +348,8 @@ __global__ __launch_bounds__(kThreads) void set_kernel(void *pops, const Lattice
 {
     using T = typename Codec<S>::T;
     const LatticeParams &P = params[lattice];
-    const int nx = P.nx, ny = P.ny;
-    const int64_t V = P.plane;
+    const int nx = P.nx, ny = P.ny, px = P.px;
+    const int64_t V = (int64_t)nx * ny, plane = P.plane;
     T *p = (T *)pops + P.base;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 9 * V;
          k += (int64_t)gridDim.x * blockDim.x) {
@@ -293,7 +359,7 @@ __global__ __launch_bounds__(kThreads) void set_kernel(void *pops, const Lattice
         // stored_i(x) holds f_i(x + v_i)
         const int xd = wrap_add(x, kVX[i], nx), yd = wrap_add(y, kVY[i], ny);
         const double f = in[(int64_t)i * V + yd * nx + xd];
-        p[k] = Codec<S>::encode((float)(f - kWd[i] * (double)P.rho0), P, i);
+        p[(int64_t)i * plane + y * px + x] = Codec<S>::encode((float)(f - kWd[i] * (double)P.rho0), P, i);
     }
 }
 
@@ -356,8 +422,8 @@ __global__ __launch_bounds__(kThreads) void conservation_kernel(const void *pops
 {
     using T = typename Codec<S>::T;
     const LatticeParams &P = params[lattice];
-    const int nx = P.nx, ny = P.ny;
-    const int64_t V = P.plane;
+    const int nx = P.nx, ny = P.ny, px = P.px;
+    const int64_t V = (int64_t)nx * ny, plane = P.plane;
     const T *p = (const T *)pops + P.base;
     double acc[5] = {0, 0, 0, 0, 0};
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < V;
@@ -367,7 +433,7 @@ __global__ __launch_bounds__(kThreads) void conservation_kernel(const void *pops
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const int xs = wrap_add(x, -kVX[i], nx), ys = wrap_add(y, -kVY[i], ny);
-            const double d = (double)Codec<S>::decode(p[(int64_t)i * V + ys * nx + xs], P, i);
+            const double d = (double)Codec<S>::decode(p[(int64_t)i * plane + ys * px + xs], P, i);
             r += d;
             jx += kVX[i] * d;
             jy += kVY[i] * d;
@@ -426,8 +492,8 @@ __global__ __launch_bounds__(kThreads) void thermal_add_kernel(void *pops,
 {
     using T = typename Codec<S>::T;
     const LatticeParams &P = params[lattice];
-    const int nx = P.nx, ny = P.ny;
-    const int64_t V = P.plane;
+    const int nx = P.nx, ny = P.ny, px = P.px;
+    const int64_t V = (int64_t)nx * ny, plane = P.plane;
     T *p = (T *)pops + P.base;
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < V;
@@ -442,7 +508,7 @@ __global__ __launch_bounds__(kThreads) void thermal_add_kernel(void *pops,
         for (int i = 0; i < 9; ++i) {
             const float add = P.therm_amp[i] * z[i];
             const int xs = wrap_add(x, -kVX[i], nx), ys = wrap_add(y, -kVY[i], ny);
-            T *q = p + (int64_t)i * V + ys * nx + xs;
+            T *q = p + (int64_t)i * plane + ys * px + xs;
             *q = Codec<S>::encode(Codec<S>::decode(*q, P, i) + add, P, i);
             acc[i] += (double)add;
         }
@@ -457,13 +523,17 @@ __global__ __launch_bounds__(kThreads) void thermal_sub_kernel(void *pops,
 {
     using T = typename Codec<S>::T;
     const LatticeParams &P = params[lattice];
-    const int64_t V = P.plane;
+    const int nx = P.nx, px = P.px;
+    const int64_t V = (int64_t)nx * P.ny, plane = P.plane;
     T *p = (T *)pops + P.base;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 9 * V;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(k / V);
+        const int s = (int)(k - (int64_t)i * V);
+        const int y = s / nx, x = s - y * nx;
         const float mean = (float)(sums[i] / (double)V);
-        p[k] = Codec<S>::encode(Codec<S>::decode(p[k], P, i) - mean, P, i);
+        T *q = p + (int64_t)i * plane + y * px + x;
+        *q = Codec<S>::encode(Codec<S>::decode(*q, P, i) - mean, P, i);
     }
 }
 

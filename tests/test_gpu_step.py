@@ -140,9 +140,11 @@ def test_conservation_flags_nan(flb, oracle_lib):
 
 
 @pytest.mark.parametrize("cfg", [(64, 1, 0), (128, 1, 1), (256, 1, 0), (64, 2, 1), (128, 2, 0),
-                                 (256, 2, 1), (256, 4, 0)])
+                                 (256, 2, 1), (64, 4, 0), (128, 4, 1), (256, 4, 0)])
 def test_launch_shape_does_not_change_results(flb, cfg):
-    nx, ny = 300, 37
+    """Every (threads along x, sites per thread, streaming stores) shape gives
+    bit-identical states; 301 columns leave a ragged group at each row end."""
+    nx, ny = 301, 37
     ref = flb.Lattice(nx, ny, TAU_C1, 1e-3, seed=4)
     ref.thermalize()
     ref.step(20)
@@ -234,3 +236,26 @@ def test_invalid_calls_report_errors(flb):
     rc = flb.lib().flb_read_correlators(g._h, 0, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                         10, None)
     assert rc == flb.ESIZE
+
+
+def test_autotune_keeps_state_and_caches(flb, tmp_path, monkeypatch):
+    monkeypatch.setenv("FLB_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    ref = flb.Lattice(257, 130, TAU_C1, 1e-3, seed=12)
+    g = flb.Lattice(257, 130, TAU_C1, 1e-3, seed=12)
+    for h in (ref, g):
+        h.thermalize()
+        h.step(5)
+    cfg, ms = g.autotune(3)
+    assert ms > 0 and cfg[0] in (64, 128, 256) and cfg[1] in (1, 2, 4)
+    assert g.t == 5
+    assert np.array_equal(g.get_populations(), ref.get_populations())
+    g.step(7)
+    ref.step(7)
+    assert np.array_equal(g.get_populations(), ref.get_populations())
+    lines = (tmp_path / "tune.txt").read_text().splitlines()
+    assert len(lines) == 1
+    # second handle of the same shape: the choice comes from the cache file
+    h = flb.Lattice(257, 130, TAU_C1, 1e-3, seed=1)
+    cfg2, ms2 = h.autotune(3)
+    assert cfg2 == cfg and abs(ms2 - ms) < 1e-9
+    assert len((tmp_path / "tune.txt").read_text().splitlines()) == 1
