@@ -19,7 +19,11 @@ The JSON line also carries
   cpu_baseline  the FP64 oracle, single thread, on a bounded sample of the
                 same workload;
   forms         step-kernel rates of the other storage formats and of the
-                noise-free step (the paper's ghost-noise overhead).
+                noise-free step (the paper's ghost-noise overhead), and the
+                batched forms (96 x 512^2 Galilean-invariance sweep, 64
+                uneven lattices) through graph-replayed sampling periods.
+Every handle's step-kernel launch shape is chosen by the library's autotuner
+before timing.
 """
 from __future__ import annotations
 
@@ -80,6 +84,31 @@ def time_step_kernel(torch, g, stream, n):
     return e0.elapsed_time(e1) / n
 
 
+def batched_form(torch, flb, stream, specs, storage, periods=10):
+    """Whole path (graph-replayed periods of SAMPLE_EVERY steps + a sample)
+    and step-only rates of one batched handle."""
+    b = flb.Lattice.batch(specs, seed=3, storage=storage)
+    b.set_stream(stream)
+    b.thermalize()
+    shape, _ = b.autotune(5)
+    sites = sum(s["nx"] * s["ny"] for s in specs)
+    b.run(2 * SAMPLE_EVERY, SAMPLE_EVERY)  # capture the graphs
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.run(periods * SAMPLE_EVERY, SAMPLE_EVERY)
+    e1.record(stream)
+    e1.synchronize()
+    ms_period = e0.elapsed_time(e1) / periods
+    step_ms = time_step_kernel(torch, b, stream, 20)
+    bpv = b.storage_info()[1]
+    b.close()
+    return {"lattices": len(specs), "sites": sites, "launch_shape": list(shape),
+            "path_glups": SAMPLE_EVERY * sites / (ms_period * 1e-3) / 1e9,
+            "step_glups": sites / (step_ms * 1e-3) / 1e9,
+            "step_achieved_GBs": 18 * bpv * sites / (step_ms * 1e-3) / 1e9,
+            "sample_ms": max(ms_period - SAMPLE_EVERY * step_ms, 0.0)}
+
+
 def cpu_baseline(workloads, name, max_side=2048):
     """The oracle (FP64, one thread) on a bounded sample of the same workload:
     the same parameters on a lattice of at most max_side^2 sites, ten steps
@@ -128,6 +157,8 @@ def main():
     print(f"bench: {args.workload} {c['nx']}x{c['ny']} storage={args.storage} "
           f"step config={g.step_config()}", file=sys.stderr, flush=True)
     g.thermalize()
+    tuned, _ = g.autotune(5)
+    print(f"bench: autotuned step config {tuned}", file=sys.stderr, flush=True)
     cons = torch.zeros((args.steps + args.warmup, 5), dtype=torch.float64, device="cuda")
 
     def bench_step(i, ev=None):
@@ -189,7 +220,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": STEP_KERNEL,
                      "algorithmic_bytes_per_launch": algo_bytes,
-                     "avg_launch_ms": step_ms},
+                     "avg_launch_ms": step_ms, "launch_shape": list(tuned)},
         "step_kernel_glups": V / (step_ms * 1e-3) / 1e9,
         "sample_ms": max(ms_per_step - SAMPLE_EVERY * step_ms, 0.0),
         "mass_drift": drift,
@@ -205,6 +236,7 @@ def main():
                 h, _ = make_lattice(flb, workloads, args.workload, st)
                 h.set_stream(stream)
                 h.thermalize()
+                h.autotune(5)
                 time_step_kernel(torch, h, stream, 5)
                 ms = time_step_kernel(torch, h, stream, 50)
                 b = h.storage_info()[1]
@@ -215,11 +247,16 @@ def main():
             h = flb.Lattice(cq["nx"], cq["ny"], cq["tau"], 0.0, rho0=cq["rho0"], u0=cq["u0"],
                             seed=cq["seed"], storage=args.storage)
             h.set_stream(stream)
+            h.autotune(5)
             time_step_kernel(torch, h, stream, 5)
             ms = time_step_kernel(torch, h, stream, 50)
             forms["noise_off_" + args.storage] = {"step_glups": V / (ms * 1e-3) / 1e9}
             out["noise_overhead"] = step_ms / ms - 1.0
             h.close()
+            for name, specs in (("batched_gi_96x512", workloads.gi_sweep_specs()),
+                                ("batched_uneven_64", workloads.uneven_batch_specs())):
+                forms[name] = batched_form(torch, flb, stream, specs, args.storage)
+                print(f"bench: {name} {forms[name]}", file=sys.stderr, flush=True)
         out["forms"] = forms
 
     if not args.no_cpu_baseline:
