@@ -257,5 +257,5 @@ def test_autotune_keeps_state_and_caches(flb, tmp_path, monkeypatch):
     # second handle of the same shape: the choice comes from the cache file
     h = flb.Lattice(257, 130, TAU_C1, 1e-3, seed=1)
     cfg2, ms2 = h.autotune(3)
-    assert cfg2 == cfg and abs(ms2 - ms) < 1e-9
+    assert cfg2 == cfg and abs(ms2 - ms) < 1e-5  # cached with 6 decimals
     assert len((tmp_path / "tune.txt").read_text().splitlines()) == 1
