@@ -178,6 +178,12 @@ int flb_set_populations(flb_t *h, int lattice, const double *in, size_t n);
  * non-finite.  Synchronises. */
 int flb_conservation(flb_t *h, int lattice, double out[5]);
 
+/* The same five sums, for the state of the most recent correlator sample:
+ * every sample computes them from its fluctuation fields at no extra pass
+ * over the populations (FP32 per site, FP64 sums).  FLB_ESTATE if no sample
+ * was taken since creation or the last reset.  Synchronises. */
+int flb_sample_conservation(flb_t *h, int lattice, double out[5]);
+
 /* As flb_conservation, but enqueue-only: the five sums are written to
  * out_dev, 5 doubles of DEVICE memory (e.g. a torch tensor's data_ptr())
  * owned by the caller. */

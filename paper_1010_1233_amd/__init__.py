@@ -73,6 +73,7 @@ SIGNATURES = {
     "flb_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_size_t]),
     "flb_conservation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp]),
     "flb_conservation_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "flb_sample_conservation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp]),
     "flb_thermalize": (ctypes.c_int, [ctypes.c_void_p]),
     "flb_debug_noise": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32,
                                        ctypes.c_int64, ctypes.c_int64, _u32p, _fp]),
@@ -259,6 +260,12 @@ class Lattice:
     def conservation(self, lattice=0):
         out = np.zeros(5)
         _check(lib().flb_conservation(self._h, lattice, _dptr(out)))
+        return out
+
+    def sample_conservation(self, lattice=0):
+        """The five sums of the state of the most recent correlator sample."""
+        out = np.zeros(5)
+        _check(lib().flb_sample_conservation(self._h, lattice, _dptr(out)))
         return out
 
     def conservation_dev(self, out_ptr, lattice=0):

@@ -59,11 +59,31 @@ template <bool PAD> __device__ __forceinline__ int lds_slot(int i)
 
 __host__ __device__ constexpr int lds_padded_elems(int n) { return n + (n >> 4) + (n >> 8) + 1; }
 
+// w * exp(-/+ 2 pi i m / 2^(u+1)) for the compile-time root index (u, m):
+// multiplications by 1 and -i are free, by exp(-i pi/4) two multiplies.
+template <int U, int M, bool INV>
+__device__ __forceinline__ float2 rotate(float2 w)
+{
+    constexpr int q = (M << (2 - U)) & 7;  // the root as a multiple of pi/4
+    constexpr float c = 0.70710678118654752f;
+    float2 r = w;
+    if constexpr (q & 1) {  // exp(-i pi/4) (forward) or exp(+i pi/4) (inverse)
+        r = INV ? make_float2(c * (w.x - w.y), c * (w.x + w.y))
+                : make_float2(c * (w.x + w.y), c * (w.y - w.x));
+    }
+    if constexpr (q & 2) r = INV ? make_float2(-r.y, r.x) : make_float2(r.y, -r.x);  // -/+ i
+    if constexpr (q & 4) r = make_float2(-r.x, -r.y);
+    return r;
+}
+
 // One pass of R fused radix-2 stages s .. s+R-1 (1-based) over `nlines`
-// lines of length 2^lg; element e of line l at slot(l * ls + e * es).
-template <int R, bool PAD>
+// lines of length 2^lg; element e of line l at slot(l * ls + e * es).  The
+// pass needs twiddles exp(-2 pi i (k + m h) / (h 2^(u+1))) for sub-stage u;
+// all are w^(2^(R-1-u)) times a fixed 2^(u+1)-th root of unity, with
+// w = exp(-2 pi i k / (h 2^R)) the one value read from the table.
+template <int R, bool PAD, bool INV>
 __device__ __forceinline__ void dit_pass(float2 *buf, int lg, int s, int nlines, int ls, int es,
-                                         const float2 *tw, bool inverse)
+                                         const float2 *tw)
 {
     constexpr int G = 1 << R;
     const int h = 1 << (s - 1);
@@ -74,6 +94,9 @@ __device__ __forceinline__ void dit_pass(float2 *buf, int lg, int s, int nlines,
     // take the same group of neighbouring lines.  Either way a wave's LDS
     // accesses are consecutive addresses.
     const bool interleaved = (ls == 1);
+    const int st = h * es;
+    const bool linear = !PAD || (st & 255) == 0;  // padded slots advance uniformly
+    const int sst = PAD ? st + (st >> 4) + (st >> 8) : st;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         int l, g;
         if (interleaved) {
@@ -86,46 +109,61 @@ __device__ __forceinline__ void dit_pass(float2 *buf, int lg, int s, int nlines,
         const int k = g & (h - 1);
         const int b = (g >> (s - 1)) << (s - 1 + R);
         const int e0 = l * ls + (b + k) * es;
-        const int st = h * es;
+        int slot[G];
+        if (linear) {
+            const int s0 = lds_slot<PAD>(e0);
+#pragma unroll
+            for (int j = 0; j < G; ++j) slot[j] = s0 + j * sst;
+        } else {
+#pragma unroll
+            for (int j = 0; j < G; ++j) slot[j] = lds_slot<PAD>(e0 + j * st);
+        }
         float2 v[G];
 #pragma unroll
-        for (int j = 0; j < G; ++j) v[j] = buf[lds_slot<PAD>(e0 + j * st)];
+        for (int j = 0; j < G; ++j) v[j] = buf[slot[j]];
+        float2 w = tw[k << (kTwLog - (s + R - 1))];
+        if (INV) w.y = -w.y;
+        float2 base[3];
+        base[R - 1] = w;
+        if constexpr (R >= 2) base[R - 2] = cmul(w, w);
+        if constexpr (R >= 3) base[0] = cmul(base[1], base[1]);
 #pragma unroll
         for (int u = 0; u < R; ++u) {
             const int half = 1 << u;
-            const int S = s + u;
 #pragma unroll
             for (int j = 0; j < G; ++j) {
                 if (j & half) continue;
-                const int t = k + (j & (half - 1)) * h;
-                float2 w = tw[t << (kTwLog - S)];
-                if (inverse) w.y = -w.y;
-                const float2 x = cmul(w, v[j + half]);
+                const int m = j & (half - 1);
+                float2 t;
+                if (u == 0) t = base[0];
+                else if (u == 1) t = m ? rotate<1, 1, INV>(base[1]) : base[1];
+                else t = m == 0 ? base[2] : m == 1 ? rotate<2, 1, INV>(base[2])
+                       : m == 2 ? rotate<2, 2, INV>(base[2]) : rotate<2, 3, INV>(base[2]);
+                const float2 x = cmul(t, v[j + half]);
                 v[j + half] = make_float2(v[j].x - x.x, v[j].y - x.y);
                 v[j] = make_float2(v[j].x + x.x, v[j].y + x.y);
             }
         }
 #pragma unroll
-        for (int j = 0; j < G; ++j) buf[lds_slot<PAD>(e0 + j * st)] = v[j];
+        for (int j = 0; j < G; ++j) buf[slot[j]] = v[j];
     }
 }
 
 // In-place transform of lines given in bit-reversed order; natural order out.
-template <bool PAD>
-__device__ void lds_fft_dit(float2 *buf, int lg, int nlines, int ls, int es, const float2 *tw,
-                            bool inverse)
+template <bool PAD, bool INV>
+__device__ void lds_fft_dit(float2 *buf, int lg, int nlines, int ls, int es, const float2 *tw)
 {
     int s = 1;
     while (s <= lg) {
         const int r = lg - s + 1;
         if (r >= 3) {
-            dit_pass<3, PAD>(buf, lg, s, nlines, ls, es, tw, inverse);
+            dit_pass<3, PAD, INV>(buf, lg, s, nlines, ls, es, tw);
             s += 3;
         } else if (r == 2) {
-            dit_pass<2, PAD>(buf, lg, s, nlines, ls, es, tw, inverse);
+            dit_pass<2, PAD, INV>(buf, lg, s, nlines, ls, es, tw);
             s += 2;
         } else {
-            dit_pass<1, PAD>(buf, lg, s, nlines, ls, es, tw, inverse);
+            dit_pass<1, PAD, INV>(buf, lg, s, nlines, ls, es, tw);
             s += 1;
         }
         __syncthreads();
@@ -157,7 +195,7 @@ __device__ void lds_line_dft(float2 *buf, const LinePlan &L, int nlines, int ls,
                              const float2 *tables)
 {
     const float2 *tw = tables;
-    lds_fft_dit<PAD>(buf, L.log2m, nlines, ls, es, tw, false);
+    lds_fft_dit<PAD, false>(buf, L.log2m, nlines, ls, es, tw);
     if (!L.bluestein) return;
     const float2 *K = tables + L.kernel_off;
     for (int idx = threadIdx.x; idx < nlines * L.m; idx += blockDim.x) {
@@ -167,7 +205,7 @@ __device__ void lds_line_dft(float2 *buf, const LinePlan &L, int nlines, int ls,
     }
     __syncthreads();
     lds_bitrev<PAD>(buf, L.log2m, nlines, ls, es);
-    lds_fft_dit<PAD>(buf, L.log2m, nlines, ls, es, tw, true);
+    lds_fft_dit<PAD, true>(buf, L.log2m, nlines, ls, es, tw);
     const float2 *C = tables + L.chirp_off;
     for (int idx = threadIdx.x; idx < nlines * L.n; idx += blockDim.x) {
         const int l = idx / L.n, j = idx - l * L.n;
@@ -185,7 +223,30 @@ struct CorrArgs {
     const CorrItem *items;
     float2 *spec;
     double *acc;
+    float *fields;
+    double *csum_part;
+    double *csum;
 };
+
+// Block sum of five doubles into out[0..4] (deterministic order).
+__device__ __forceinline__ void block_sum5(double (&v)[5], double *out)
+{
+    __shared__ double red[5][kThreads / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        double x = v[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+        if (lane == 0) red[q][wv] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double x = 0;
+        for (int w = 0; w < kThreads / 64; ++w) x += red[threadIdx.x][w];
+        out[threadIdx.x] = x;
+    }
+}
 
 // Fluctuation fields at site (x, y) of the current state.
 template <int S>
@@ -218,83 +279,118 @@ __device__ __forceinline__ void site_fields(const typename Codec<S>::T *p, const
     duy = jy * ir - P.u0y;
 }
 
-constexpr int kRowThreads = 1024;  // threads of a row-kernel block
-constexpr int kRowSites = 4;       // sites per thread: at most 4096 sites per block
-
-// item: lattice, first row, rows in this block
+// Fluctuation fields of the current state, one thread per column of a tile
+// of 256 sites x kFieldRows rows, written as five FP32 planes [5][ny][nx]
+// (d rho, d jx, d jy, d ux, d uy), together with the FP64 conservation sums
+// of the same state (mass, momentum, staggered momenta) as per-block
+// partials.  item: lattice, tile, index of the block's partial.
 template <int S>
-__global__ __launch_bounds__(kRowThreads) void corr_rows_kernel(CorrArgs g)
+__global__ __launch_bounds__(kThreads) void corr_fields_kernel(CorrArgs g)
 {
     using T = typename Codec<S>::T;
+    const CorrItem it = g.items[blockIdx.x];
+    if (it.lattice < 0) return;
+    const LatticeParams &P = g.params[it.lattice];
+    const int nx = P.nx, ny = P.ny;
+    const int tx = it.a % P.fld_tiles_x, ty = it.a / P.fld_tiles_x;
+    const int x = tx * kThreads + (int)threadIdx.x;
+    double acc[5] = {0, 0, 0, 0, 0};
+    if (x < nx) {
+        const T *p = (const T *)g.pops + P.base;
+        const int64_t fs = (int64_t)nx * ny;
+        const int y1 = min(ny, (ty + 1) * kFieldRows);
+        for (int y = ty * kFieldRows; y < y1; ++y) {
+            float dr, jx, jy, ux, uy;
+            site_fields<S>(p, P, x, y, dr, jx, jy, ux, uy);
+            float *f = g.fields + P.fld_base + (int64_t)y * nx + x;
+            f[0] = dr;
+            f[fs] = jx;
+            f[2 * fs] = jy;
+            f[3 * fs] = ux;
+            f[4 * fs] = uy;
+            const double Jx = (double)jx + (double)P.rho0 * (double)P.u0x;
+            const double Jy = (double)jy + (double)P.rho0 * (double)P.u0y;
+            acc[0] += dr;
+            acc[1] += Jx;
+            acc[2] += Jy;
+            acc[3] += (x & 1) ? -Jx : Jx;
+            acc[4] += (y & 1) ? -Jy : Jy;
+        }
+    }
+    block_sum5(acc, g.csum_part + 5 * (int64_t)it.b);
+}
+
+// Sums each lattice's field-kernel partials into its five conservation sums.
+__global__ __launch_bounds__(kThreads) void corr_csum_kernel(CorrArgs g, int nlat)
+{
+    const int l = blockIdx.x;
+    if (l >= nlat) return;
+    const LatticeParams &P = g.params[l];
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < P.fld_nparts; b += kThreads)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc[q] += g.csum_part[5 * ((int64_t)P.fld_part0 + b) + q];
+    block_sum5(acc, g.csum + 5 * (int64_t)l);
+}
+
+// Row transforms of the fields: one block per (lattice, group of rows,
+// signal); signal 0 packs jx + i jy, 1 ux + i uy, 2 rho alone.  Writes the
+// half spectra kx = 0..nx/2 of the five real fields.
+// item: lattice, first row, rows in this block, signal
+__global__ __launch_bounds__(kThreads) void corr_rowfft_kernel(CorrArgs g)
+{
     extern __shared__ float2 lds[];
     const CorrItem it = g.items[blockIdx.x];
     if (it.lattice < 0) return;
     const LatticeParams &P = g.params[it.lattice];
     const LinePlan &L = g.plans[P.line_x];
     const int nx = P.nx, ny = P.ny, nkx = P.nkx, kxp = P.kxp;
-    const int y0 = it.a, nl = min(it.b, ny - y0);
+    const int y0 = it.a, nl = min(it.b, ny - y0), sig = it.c;
     const int m = L.m, lg = L.log2m;
-    const T *p = (const T *)g.pops + P.base;
     const float2 *chirp = g.tables + L.chirp_off;
-    const int nsites = nl * nx;
+    const int64_t fs = (int64_t)nx * ny;
+    const float *fa_p = g.fields + P.fld_base + (sig == 0 ? fs : sig == 1 ? 3 * fs : 0);
+    const float *fb_p = fa_p + fs;
 
-    float fr[kRowSites], fjx[kRowSites], fjy[kRowSites], fux[kRowSites], fuy[kRowSites];
-#pragma unroll
-    for (int q = 0; q < kRowSites; ++q) {
-        const int idx = (int)threadIdx.x + q * kRowThreads;
-        fr[q] = fjx[q] = fjy[q] = fux[q] = fuy[q] = 0.0f;
-        if (idx < nsites) {
-            const int l = idx / nx, x = idx - l * nx;
-            site_fields<S>(p, P, x, y0 + l, fr[q], fjx[q], fjy[q], fux[q], fuy[q]);
+    for (int e = threadIdx.x; e < nl * m; e += kThreads) {
+        const int l = e >> lg, x = e & (m - 1);
+        float2 v = make_float2(0.f, 0.f);
+        if (x < nx) {
+            const int64_t o = (int64_t)(y0 + l) * nx + x;
+            v.x = fa_p[o];
+            if (sig != 2) v.y = fb_p[o];
+            if (L.bluestein) v = cmul(v, chirp[x]);
         }
+        lds[lds_slot<true>(l * m + bitrev(x, lg))] = v;
     }
+    __syncthreads();
+    lds_line_dft<true>(lds, L, nl, m, 1, g.tables);
 
+    // two real sequences a, b packed as z = a + i b:
+    // a_k = (z_k + conj z_{-k}) / 2, b_k = (z_k - conj z_{-k}) / (2i)
     float2 *spec = g.spec + P.spec_base;
     const int64_t fstride = (int64_t)ny * kxp;
-    for (int sig = 0; sig < 3; ++sig) {
-        // zero padding of Bluestein work lines, at bit-reversed positions
-        for (int e = threadIdx.x; e < nl * m; e += kRowThreads) {
-            const int l = e >> lg, j = e & (m - 1);
-            if (j >= nx) lds[lds_slot<true>(l * m + bitrev(j, lg))] = make_float2(0.f, 0.f);
-        }
-#pragma unroll
-        for (int q = 0; q < kRowSites; ++q) {
-            const int idx = (int)threadIdx.x + q * kRowThreads;
-            if (idx < nsites) {
-                const int l = idx / nx, x = idx - l * nx;
-                float2 v = sig == 0 ? make_float2(fjx[q], fjy[q])
-                         : sig == 1 ? make_float2(fux[q], fuy[q]) : make_float2(fr[q], 0.f);
-                if (L.bluestein) v = cmul(v, chirp[x]);
-                lds[lds_slot<true>(l * m + bitrev(x, lg))] = v;
-            }
-        }
-        __syncthreads();
-        lds_line_dft<true>(lds, L, nl, m, 1, g.tables);
-
-        // two real sequences a, b packed as z = a + i b:
-        // a_k = (z_k + conj z_{-k}) / 2, b_k = (z_k - conj z_{-k}) / (2i)
-        const int fa = sig == 0 ? 1 : 3, fb = sig == 0 ? 2 : 4;
-        for (int e = threadIdx.x; e < nl * kxp; e += kRowThreads) {
-            const int l = e / kxp, k = e - l * kxp;
-            const int64_t row = (int64_t)(y0 + l) * kxp + k;
-            if (k >= nkx) {  // padding columns: keep them finite
-                if (sig == 2) spec[row] = make_float2(0.f, 0.f);
-                else {
-                    spec[fa * fstride + row] = make_float2(0.f, 0.f);
-                    spec[fb * fstride + row] = make_float2(0.f, 0.f);
-                }
-                continue;
-            }
-            const float2 zk = lds[lds_slot<true>(l * m + k)];
+    const int fa = sig == 0 ? 1 : 3, fb = sig == 0 ? 2 : 4;
+    for (int e = threadIdx.x; e < nl * kxp; e += kThreads) {
+        const int l = e / kxp, k = e - l * kxp;
+        const int64_t row = (int64_t)(y0 + l) * kxp + k;
+        if (k >= nkx) {  // padding columns: keep them finite
             if (sig == 2) {
-                spec[row] = zk;
+                spec[row] = make_float2(0.f, 0.f);
             } else {
-                const float2 zm = lds[lds_slot<true>(l * m + (k == 0 ? 0 : nx - k))];
-                spec[fa * fstride + row] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-                spec[fb * fstride + row] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+                spec[fa * fstride + row] = make_float2(0.f, 0.f);
+                spec[fb * fstride + row] = make_float2(0.f, 0.f);
             }
+            continue;
         }
-        __syncthreads();
+        const float2 zk = lds[lds_slot<true>(l * m + k)];
+        if (sig == 2) {
+            spec[row] = zk;
+        } else {
+            const float2 zm = lds[lds_slot<true>(l * m + (k == 0 ? 0 : nx - k))];
+            spec[fa * fstride + row] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+            spec[fb * fstride + row] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+        }
     }
 }
 
@@ -316,7 +412,7 @@ __global__ __launch_bounds__(kThreads) void corr_cols_a_kernel(CorrArgs g)
         lds[bitrev(pp, lgP) * NL + r] = col[(int64_t)(q0 + ql + Q * pp) * kxp + c];
     }
     __syncthreads();
-    lds_fft_dit<false>(lds, lgP, NL, 1, NL, g.tables, false);
+    lds_fft_dit<false, false>(lds, lgP, NL, 1, NL, g.tables);
     const int lgN = P.col_lgn;
     for (int idx = threadIdx.x; idx < Pn * NL; idx += kThreads) {
         const int k1 = idx / NL, r = idx - k1 * NL;
@@ -368,7 +464,7 @@ __global__ __launch_bounds__(kThreads) void corr_cols_b_kernel(CorrArgs g)
         lds[bitrev(q, lgQ) * NL + r] = spec[f * fstride + (int64_t)(Q * k1 + q) * kxp + c];
     }
     __syncthreads();
-    lds_fft_dit<false>(lds, lgQ, NL, 1, NL, g.tables, false);
+    lds_fft_dit<false, false>(lds, lgQ, NL, 1, NL, g.tables);
     double *acc = g.acc + P.acc_base;
     for (int idx = threadIdx.x; idx < Q * 16; idx += kThreads) {
         const int k2 = idx >> 4, c = idx & 15;
@@ -441,20 +537,34 @@ static CorrArgs make_args(const DeviceView &v, const CorrItem *items)
     g.items = items;
     g.spec = v.spec;
     g.acc = v.acc;
+    g.fields = v.fields;
+    g.csum_part = v.csum_part;
+    g.csum = v.csum;
     return g;
+}
+
+hipError_t launch_corr_fields(const DeviceView &v, const CorrItem *items, int nitems,
+                              hipStream_t s)
+{
+    const CorrArgs g = make_args(v, items);
+    const dim3 grid(nitems), block(kThreads);
+    if (v.storage == kF32)
+        hipLaunchKernelGGL(corr_fields_kernel<kF32>, grid, block, 0, s, g);
+    else if (v.storage == kBF16)
+        hipLaunchKernelGGL(corr_fields_kernel<kBF16>, grid, block, 0, s, g);
+    else
+        hipLaunchKernelGGL(corr_fields_kernel<kF16>, grid, block, 0, s, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(corr_csum_kernel, dim3(v.nlat), block, 0, s, g, v.nlat);
+    return hipGetLastError();
 }
 
 hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems,
                             int lds_bytes, hipStream_t s)
 {
     const CorrArgs g = make_args(v, items);
-    const dim3 grid(nitems), block(kRowThreads);
-    if (v.storage == kF32)
-        hipLaunchKernelGGL(corr_rows_kernel<kF32>, grid, block, lds_bytes, s, g);
-    else if (v.storage == kBF16)
-        hipLaunchKernelGGL(corr_rows_kernel<kBF16>, grid, block, lds_bytes, s, g);
-    else
-        hipLaunchKernelGGL(corr_rows_kernel<kF16>, grid, block, lds_bytes, s, g);
+    hipLaunchKernelGGL(corr_rowfft_kernel, dim3(nitems), dim3(kThreads), lds_bytes, s, g);
     return hipGetLastError();
 }
 

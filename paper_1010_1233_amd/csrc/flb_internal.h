@@ -15,6 +15,8 @@
 //              5 fields x ny x kxp (the half spectra of the real fields; kxp
 //              is nkx = nx/2+1 rounded up to 16 so column blocks are 128 B).
 //   acc      : FP64 correlator sums, per lattice FLB_NKINDS x ny x kxp.
+//   fields   : FP32 fluctuation fields of the sampled state, 5 x ny x nx
+//              per lattice, and the FP64 conservation sums of that state.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,6 +27,7 @@ namespace flbdev {
 constexpr int kThreads = 256;
 constexpr int kFields = 5;   // delta rho, delta jx, delta jy, delta ux, delta uy
 constexpr int kKinds = 15;
+constexpr int kFieldRows = 16;  // rows per block of the field kernel
 
 // Per-lattice constants, read by every kernel through scalar loads.
 struct alignas(16) LatticeParams {
@@ -53,7 +56,10 @@ struct alignas(16) LatticeParams {
     int32_t col_lgp;          // P = ny / Q
     int32_t col_lgn;          // log2 ny
     int32_t col_nq;           // q values per pass-A block
-    int32_t pad0;
+    int32_t fld_tiles_x;      // field-kernel tiles (256 sites) per row band
+    int64_t fld_base;         // float offset of this lattice's five field planes
+    int32_t fld_part0;        // first conservation partial of this lattice
+    int32_t fld_nparts;       // number of them
 };
 
 // How to transform one line of length n in LDS.  Powers of two are done
@@ -100,6 +106,9 @@ struct DeviceView {
     uint32_t *step_rw;
     float2 *spec;
     double *acc;
+    float *fields;                    // [5][ny][nx] FP32 per lattice
+    double *csum_part;                // field-kernel partial sums
+    double *csum;                     // [nlat][5] sums of the last sample
     const LinePlan *plans;            // device
     const float2 *tables;             // device: twiddles, chirps, kernels
     uint64_t seed;
@@ -123,6 +132,8 @@ hipError_t launch_thermalize(const DeviceView &v, int lattice, int nx, int ny, d
                              int nblocks, double *mean_dev, hipStream_t s);
 hipError_t launch_debug_noise(uint64_t seed, uint32_t stream_id, uint32_t t, int64_t site0,
                               int64_t n, uint32_t *words_dev, float *z_dev, hipStream_t s);
+hipError_t launch_corr_fields(const DeviceView &v, const CorrItem *items, int nitems,
+                              hipStream_t s);
 hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems,
                             int lds_bytes, hipStream_t s);
 hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int cb,

@@ -91,8 +91,10 @@ struct flb {
     double *d_acc = nullptr;
     int64_t spec_elems = 0, acc_elems = 0;
     CorrItem *d_rows = nullptr, *d_cols = nullptr, *d_accum = nullptr;
-    CorrItem *d_cols_a = nullptr, *d_cols_b = nullptr;
-    int n_rows = 0, n_cols = 0, n_accum = 0, n_cols_a = 0, n_cols_b = 0;
+    CorrItem *d_cols_a = nullptr, *d_cols_b = nullptr, *d_fld = nullptr;
+    int n_rows = 0, n_cols = 0, n_accum = 0, n_cols_a = 0, n_cols_b = 0, n_fld = 0;
+    float *d_fields = nullptr;
+    double *d_csum_part = nullptr, *d_csum = nullptr;
     int rows_lds = 0, cols_lds = 0, cols_cb = 1, cols_a_lds = 0, cols_b_lds = 0;
     int64_t nsamples = 0;
 
@@ -113,6 +115,9 @@ struct flb {
         v.step_rw = d_step;
         v.spec = d_spec;
         v.acc = d_acc;
+        v.fields = d_fields;
+        v.csum_part = d_csum_part;
+        v.csum = d_csum;
         v.plans = d_plans;
         v.tables = d_tables;
         v.seed = seed;
@@ -338,7 +343,8 @@ int setup_correlators(flb_t *h)
         return id;
     };
 
-    int64_t spec = 0, acc = 0;
+    int64_t spec = 0, acc = 0, fld = 0;
+    int nparts = 0;
     int max_my_general = 1;
     h->rows_lds = h->cols_a_lds = h->cols_b_lds = h->cols_lds = 0;
     for (auto &P : h->params) {
@@ -363,23 +369,31 @@ int setup_correlators(flb_t *h)
         P.acc_base = acc;
         spec += (int64_t)kFields * P.ny * P.kxp;
         acc += (int64_t)kKinds * P.ny * P.kxp;
+        P.fld_base = fld;
+        fld += ((int64_t)kFields * P.nx * P.ny + 63) / 64 * 64;
+        P.fld_tiles_x = (P.nx + kThreads - 1) / kThreads;
+        P.fld_part0 = nparts;
+        P.fld_nparts = P.fld_tiles_x * ((P.ny + kFieldRows - 1) / kFieldRows);
+        nparts += P.fld_nparts;
     }
     h->spec_elems = spec;
     h->acc_elems = acc;
     h->cols_cb = std::max(1, std::min(16, 8192 / max_my_general));
     h->cols_lds = max_my_general * h->cols_cb * (int)sizeof(float2);
 
-    std::vector<CorrItem> rows, cols, accum, cols_a, cols_b;
+    std::vector<CorrItem> rows, cols, accum, cols_a, cols_b, flds;
     for (size_t l = 0; l < h->params.size(); ++l) {
         const LatticeParams &P = h->params[l];
+        for (int t = 0; t < P.fld_nparts; ++t)
+            flds.push_back({(int32_t)l, t, P.fld_part0 + t, 0});
         const int mx = h->plans[P.line_x].m;
-        // rows per block: up to 4096 work elements (32 KB of LDS); the row
-        // kernel holds at most 16 sites per thread
+        // rows per block: up to 4096 work elements (32 KB of LDS)
         const int rb = std::max(1, std::min(P.ny, 4096 / mx));
         // the row kernel pads its LDS lines (one slot per 16 and per 256)
         const int slots = rb * mx + (rb * mx >> 4) + (rb * mx >> 8) + 1;
         h->rows_lds = std::max(h->rows_lds, slots * (int)sizeof(float2));
-        for (int y = 0; y < P.ny; y += rb) rows.push_back({(int32_t)l, y, rb, 0});
+        for (int y = 0; y < P.ny; y += rb)
+            for (int sig = 0; sig < 3; ++sig) rows.push_back({(int32_t)l, y, rb, sig});
         if (P.col_pow2) {
             const int Pn = 1 << P.col_lgp;
             if (Pn > 1)
@@ -399,6 +413,7 @@ int setup_correlators(flb_t *h)
         }
     }
     const CorrItem idle{-1, 0, 0, 0};
+    flds = xcd_order(flds, idle);
     rows = xcd_order(rows, idle);
     cols_a = xcd_order(cols_a, idle);
     cols_b = xcd_order(cols_b, idle);
@@ -408,14 +423,20 @@ int setup_correlators(flb_t *h)
     h->n_accum = (int)accum.size();
     h->n_cols_a = (int)cols_a.size();
     h->n_cols_b = (int)cols_b.size();
+    h->n_fld = (int)flds.size();
     int rc;
-    if ((rc = upload(&h->d_rows, rows)) || (rc = upload(&h->d_cols, cols)) ||
+    if ((rc = upload(&h->d_fld, flds)) || (rc = upload(&h->d_rows, rows)) ||
+        (rc = upload(&h->d_cols, cols)) ||
         (rc = upload(&h->d_accum, accum)) || (rc = upload(&h->d_cols_a, cols_a)) ||
         (rc = upload(&h->d_cols_b, cols_b)) || (rc = upload(&h->d_plans, h->plans)) ||
         (rc = upload(&h->d_tables, tables)) || (rc = upload(&h->d_params, h->params)))
         return rc;
     FLB_HIP(hipMalloc((void **)&h->d_spec, spec * sizeof(float2)));
     FLB_HIP(hipMalloc((void **)&h->d_acc, acc * sizeof(double)));
+    FLB_HIP(hipMalloc((void **)&h->d_fields, fld * sizeof(float)));
+    FLB_HIP(hipMalloc((void **)&h->d_csum_part, (size_t)nparts * 5 * sizeof(double)));
+    FLB_HIP(hipMalloc((void **)&h->d_csum, h->params.size() * 5 * sizeof(double)));
+    FLB_HIP(launch_fill(h->d_csum, h->params.size() * 5, h->stream));
     FLB_HIP(launch_fill(h->d_acc, (size_t)acc, h->stream));
     h->nsamples = 0;
     h->corr_ready = true;
@@ -426,6 +447,7 @@ int setup_correlators(flb_t *h)
 int enqueue_sample(flb_t *h, hipStream_t s)
 {
     const DeviceView v = h->view();
+    FLB_HIP(launch_corr_fields(v, h->d_fld, h->n_fld, s));
     FLB_HIP(launch_corr_rows(v, h->d_rows, h->n_rows, h->rows_lds, s));
     if (h->n_cols_a) FLB_HIP(launch_corr_cols_a(v, h->d_cols_a, h->n_cols_a, h->cols_a_lds, s));
     if (h->n_cols_b) FLB_HIP(launch_corr_cols_b(v, h->d_cols_b, h->n_cols_b, h->cols_b_lds, s));
@@ -605,7 +627,8 @@ void flb_destroy(flb_t *h)
     clear_graphs(h);
     void *ptrs[] = {h->pops[0], h->d_params, h->d_step, h->d_red, h->d_items,
                     h->d_plans, h->d_tables, h->d_spec, h->d_acc, h->d_rows, h->d_cols,
-                    h->d_accum, h->d_cols_a, h->d_cols_b};
+                    h->d_accum, h->d_cols_a, h->d_cols_b, h->d_fld, h->d_fields,
+                    h->d_csum_part, h->d_csum};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->ev) (void)hipEventDestroy(h->ev);
@@ -793,6 +816,18 @@ int flb_conservation(flb_t *h, int lattice, double out[5])
     FLB_HIP(launch_conservation(h->view(), lattice, P.nx, P.ny, h->d_red, nb, res, h->stream));
     FLB_HIP(hipStreamSynchronize(h->stream));
     FLB_HIP(hipMemcpy(out, res, 5 * sizeof(double), hipMemcpyDeviceToHost));
+    return FLB_OK;
+}
+
+int flb_sample_conservation(flb_t *h, int lattice, double out[5])
+{
+    if (check_lattice(h, lattice)) return FLB_EINVAL;
+    if (!out) return fail(FLB_EINVAL, "out must not be NULL");
+    if (!h->corr_ready || h->nsamples == 0)
+        return fail(FLB_ESTATE, "no correlator sample taken since the last reset");
+    FLB_HIP(hipStreamSynchronize(h->stream));
+    FLB_HIP(hipMemcpy(out, h->d_csum + 5 * (size_t)lattice, 5 * sizeof(double),
+                      hipMemcpyDeviceToHost));
     return FLB_OK;
 }
 

@@ -167,3 +167,20 @@ def test_structure_factors_are_one_on_gpu(flb):
     assert 0.6 < chi < 1.7
     for k in ("R_uxuy", "R_rhojx", "R_rhojy", "R_rhoux", "R_rhouy"):
         assert abs(mean[k][m].mean()) < 0.005
+
+
+def test_sample_records_conservation_sums(flb, oracle_lib):
+    """Each sample also returns the FP64 mass/momentum/staggered sums of the
+    sampled state: they match the dedicated conservation call and the oracle."""
+    g = flb.Lattice(48, 36, TAU_C1, 1e-3, u0=(0.03, -0.01), seed=5)
+    o = oracle_lib.Lattice(48, 36, TAU_C1, 1e-3, u0=(0.03, -0.01), seed=5)
+    with pytest.raises(flb.FlbError):
+        g.sample_conservation()
+    g.thermalize()
+    o.thermalize()
+    g.step(13)
+    o.step(13)
+    g.accumulate()
+    cs = g.sample_conservation()
+    assert np.abs(cs - g.conservation()).max() < 1e-5
+    assert np.abs(cs - o.conservation()).max() < 1e-5
