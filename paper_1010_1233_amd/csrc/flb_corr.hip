@@ -215,6 +215,8 @@ __device__ void lds_line_dft(float2 *buf, const LinePlan &L, int nlines, int ls,
     __syncthreads();
 }
 
+constexpr int kFftThreads = 512;  // threads of the transform kernels
+
 struct CorrArgs {
     const void *pops;
     const LatticeParams *params;
@@ -337,7 +339,7 @@ __global__ __launch_bounds__(kThreads) void corr_csum_kernel(CorrArgs g, int nla
 // signal); signal 0 packs jx + i jy, 1 ux + i uy, 2 rho alone.  Writes the
 // half spectra kx = 0..nx/2 of the five real fields.
 // item: lattice, first row, rows in this block, signal
-__global__ __launch_bounds__(kThreads) void corr_rowfft_kernel(CorrArgs g)
+__global__ __launch_bounds__(kFftThreads) void corr_rowfft_kernel(CorrArgs g)
 {
     extern __shared__ float2 lds[];
     const CorrItem it = g.items[blockIdx.x];
@@ -352,7 +354,7 @@ __global__ __launch_bounds__(kThreads) void corr_rowfft_kernel(CorrArgs g)
     const float *fa_p = g.fields + P.fld_base + (sig == 0 ? fs : sig == 1 ? 3 * fs : 0);
     const float *fb_p = fa_p + fs;
 
-    for (int e = threadIdx.x; e < nl * m; e += kThreads) {
+    for (int e = threadIdx.x; e < nl * m; e += kFftThreads) {
         const int l = e >> lg, x = e & (m - 1);
         float2 v = make_float2(0.f, 0.f);
         if (x < nx) {
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(kThreads) void corr_rowfft_kernel(CorrArgs g)
     float2 *spec = g.spec + P.spec_base;
     const int64_t fstride = (int64_t)ny * kxp;
     const int fa = sig == 0 ? 1 : 3, fb = sig == 0 ? 2 : 4;
-    for (int e = threadIdx.x; e < nl * kxp; e += kThreads) {
+    for (int e = threadIdx.x; e < nl * kxp; e += kFftThreads) {
         const int l = e / kxp, k = e - l * kxp;
         const int64_t row = (int64_t)(y0 + l) * kxp + k;
         if (k >= nkx) {  // padding columns: keep them finite
@@ -396,7 +398,7 @@ __global__ __launch_bounds__(kThreads) void corr_rowfft_kernel(CorrArgs g)
 
 // Power-of-two ny = P*Q, pass A.  item: lattice, field, first column, first q.
 // LDS [p][ql][c], 16 columns, nq q-values per block.
-__global__ __launch_bounds__(kThreads) void corr_cols_a_kernel(CorrArgs g)
+__global__ __launch_bounds__(kFftThreads) void corr_cols_a_kernel(CorrArgs g)
 {
     extern __shared__ float2 lds[];
     const CorrItem it = g.items[blockIdx.x];
@@ -406,7 +408,7 @@ __global__ __launch_bounds__(kThreads) void corr_cols_a_kernel(CorrArgs g)
     const int lgP = P.col_lgp, Pn = 1 << lgP, Q = P.col_q, kxp = P.kxp;
     const int NL = P.col_nq * 16;
     float2 *col = g.spec + P.spec_base + (int64_t)f * P.ny * kxp + c0;
-    for (int idx = threadIdx.x; idx < Pn * NL; idx += kThreads) {
+    for (int idx = threadIdx.x; idx < Pn * NL; idx += kFftThreads) {
         const int pp = idx / NL, r = idx - pp * NL;
         const int ql = r >> 4, c = r & 15;
         lds[bitrev(pp, lgP) * NL + r] = col[(int64_t)(q0 + ql + Q * pp) * kxp + c];
@@ -414,7 +416,7 @@ __global__ __launch_bounds__(kThreads) void corr_cols_a_kernel(CorrArgs g)
     __syncthreads();
     lds_fft_dit<false, false>(lds, lgP, NL, 1, NL, g.tables);
     const int lgN = P.col_lgn;
-    for (int idx = threadIdx.x; idx < Pn * NL; idx += kThreads) {
+    for (int idx = threadIdx.x; idx < Pn * NL; idx += kFftThreads) {
         const int k1 = idx / NL, r = idx - k1 * NL;
         const int ql = r >> 4, c = r & 15;
         const int e = ((q0 + ql) * k1) & ((1 << lgN) - 1);
@@ -446,7 +448,7 @@ __device__ __forceinline__ void accumulate_k(double *a, int64_t kstride, const f
 
 // Power-of-two ny, pass B with accumulation.  item: lattice, first column, k1.
 // LDS [q][f][c]: the Q rows Q*k1 .. Q*k1+Q-1 of all five fields, 16 columns.
-__global__ __launch_bounds__(kThreads) void corr_cols_b_kernel(CorrArgs g)
+__global__ __launch_bounds__(kFftThreads) void corr_cols_b_kernel(CorrArgs g)
 {
     extern __shared__ float2 lds[];
     const CorrItem it = g.items[blockIdx.x];
@@ -458,7 +460,7 @@ __global__ __launch_bounds__(kThreads) void corr_cols_b_kernel(CorrArgs g)
     constexpr int NL = 5 * 16;
     const float2 *spec = g.spec + P.spec_base + c0;
     const int64_t fstride = (int64_t)ny * kxp;
-    for (int idx = threadIdx.x; idx < Q * NL; idx += kThreads) {
+    for (int idx = threadIdx.x; idx < Q * NL; idx += kFftThreads) {
         const int q = idx / NL, r = idx - q * NL;
         const int f = r >> 4, c = r & 15;
         lds[bitrev(q, lgQ) * NL + r] = spec[f * fstride + (int64_t)(Q * k1 + q) * kxp + c];
@@ -466,7 +468,7 @@ __global__ __launch_bounds__(kThreads) void corr_cols_b_kernel(CorrArgs g)
     __syncthreads();
     lds_fft_dit<false, false>(lds, lgQ, NL, 1, NL, g.tables);
     double *acc = g.acc + P.acc_base;
-    for (int idx = threadIdx.x; idx < Q * 16; idx += kThreads) {
+    for (int idx = threadIdx.x; idx < Q * 16; idx += kFftThreads) {
         const int k2 = idx >> 4, c = idx & 15;
         const int kx = c0 + c, ky = k1 + Pn * k2;
         if (kx >= nkx || (kx == 0 && ky == 0)) continue;
@@ -478,7 +480,7 @@ __global__ __launch_bounds__(kThreads) void corr_cols_b_kernel(CorrArgs g)
 }
 
 // Other ny: whole columns, in place.  item: lattice, field, first column.
-__global__ __launch_bounds__(kThreads) void corr_cols_kernel(CorrArgs g, int cb)
+__global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g, int cb)
 {
     extern __shared__ float2 lds[];
     const CorrItem it = g.items[blockIdx.x];
@@ -490,7 +492,7 @@ __global__ __launch_bounds__(kThreads) void corr_cols_kernel(CorrArgs g, int cb)
     const int ncol = min(cb, nkx - c0);
     float2 *col = g.spec + P.spec_base + (int64_t)f * ny * kxp + c0;
     const float2 *chirp = g.tables + L.chirp_off;
-    for (int idx = threadIdx.x; idx < L.m * cb; idx += kThreads) {
+    for (int idx = threadIdx.x; idx < L.m * cb; idx += kFftThreads) {
         const int j = idx / cb, c = idx - j * cb;
         float2 v = make_float2(0.f, 0.f);
         if (j < ny && c < ncol) {
@@ -501,7 +503,7 @@ __global__ __launch_bounds__(kThreads) void corr_cols_kernel(CorrArgs g, int cb)
     }
     __syncthreads();
     lds_line_dft<false>(lds, L, cb, 1, cb, g.tables);
-    for (int idx = threadIdx.x; idx < ny * cb; idx += kThreads) {
+    for (int idx = threadIdx.x; idx < ny * cb; idx += kFftThreads) {
         const int j = idx / cb, c = idx - j * cb;
         if (c < ncol) col[(int64_t)j * kxp + c] = lds[idx];
     }
@@ -564,7 +566,7 @@ hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nite
                             int lds_bytes, hipStream_t s)
 {
     const CorrArgs g = make_args(v, items);
-    hipLaunchKernelGGL(corr_rowfft_kernel, dim3(nitems), dim3(kThreads), lds_bytes, s, g);
+    hipLaunchKernelGGL(corr_rowfft_kernel, dim3(nitems), dim3(kFftThreads), lds_bytes, s, g);
     return hipGetLastError();
 }
 
@@ -572,7 +574,7 @@ hipError_t launch_corr_cols_a(const DeviceView &v, const CorrItem *items, int ni
                               int lds_bytes, hipStream_t s)
 {
     const CorrArgs g = make_args(v, items);
-    hipLaunchKernelGGL(corr_cols_a_kernel, dim3(nitems), dim3(kThreads), lds_bytes, s, g);
+    hipLaunchKernelGGL(corr_cols_a_kernel, dim3(nitems), dim3(kFftThreads), lds_bytes, s, g);
     return hipGetLastError();
 }
 
@@ -580,7 +582,7 @@ hipError_t launch_corr_cols_b(const DeviceView &v, const CorrItem *items, int ni
                               int lds_bytes, hipStream_t s)
 {
     const CorrArgs g = make_args(v, items);
-    hipLaunchKernelGGL(corr_cols_b_kernel, dim3(nitems), dim3(kThreads), lds_bytes, s, g);
+    hipLaunchKernelGGL(corr_cols_b_kernel, dim3(nitems), dim3(kFftThreads), lds_bytes, s, g);
     return hipGetLastError();
 }
 
@@ -588,7 +590,7 @@ hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nite
                             int lds_bytes, hipStream_t s)
 {
     const CorrArgs g = make_args(v, items);
-    hipLaunchKernelGGL(corr_cols_kernel, dim3(nitems), dim3(kThreads), lds_bytes, s, g, cb);
+    hipLaunchKernelGGL(corr_cols_kernel, dim3(nitems), dim3(kFftThreads), lds_bytes, s, g, cb);
     return hipGetLastError();
 }
 
