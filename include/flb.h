@@ -102,7 +102,9 @@ typedef struct flb_lattice_spec {
  * (c = 1), time t = 0, FP32 storage, stream_id 0, noise on all of 3..8.
  * tau: 9 doubles (host).  u0: 2 doubles (host).  Returns NULL on invalid
  * input (nx or ny < 2, non-finite values, rho0 <= 0, theta < 0,
- * tau[a] <= 1/2 for a >= 3, |u0| >= c_s) or on allocation failure. */
+ * tau[a] <= 1/2 for a >= 3, |u0| >= c_s), for a lattice whose populations
+ * exceed 4 GiB (9 x nx x ny x 4 bytes, about 119M sites), or on allocation
+ * failure. */
 flb_t *flb_create(int nx, int ny, const double tau[9], double theta, double rho0,
                   const double u0[2], uint64_t seed);
 

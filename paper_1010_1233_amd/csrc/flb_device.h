@@ -37,7 +37,9 @@ __device__ __forceinline__ void normals6(uint4 w, float z[6])
         const float r = fmaf((float)(wv[p] >> 9), 0x1p-23f, 0x1p-24f);
         const uint32_t al = ((wv[p] & 0x1FFu) << 10) | ((w.w >> (10 * p)) & 0x3FFu);
         const float a = fmaf((float)al, 0x1p-19f, 0x1p-20f);
-        const float R = __builtin_amdgcn_sqrtf(-2.0f * logf(r));
+        // r >= 2^-24 is never denormal: the hardware log2 needs no range
+        // handling; -2 ln r = -2 ln(2) log2 r
+        const float R = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(r));
         z[2 * p] = R * __builtin_amdgcn_cosf(a);
         z[2 * p + 1] = R * __builtin_amdgcn_sinf(a);
     }
@@ -77,7 +79,7 @@ template <> struct Codec<kBF16> {
     }
     static __device__ __forceinline__ T encode(float d, const LatticeParams &P, int i)
     {
-        return f32_to_bf16((d - P.feq[i]) * P.inv_scale[i]);
+        return f32_to_bf16(fmaf(d, P.inv_scale[i], -P.feq_scaled[i]));
     }
 };
 
@@ -89,7 +91,7 @@ template <> struct Codec<kF16> {
     }
     static __device__ __forceinline__ T encode(float d, const LatticeParams &P, int i)
     {
-        return (T)((d - P.feq[i]) * P.inv_scale[i]);
+        return (T)fmaf(d, P.inv_scale[i], -P.feq_scaled[i]);
     }
 };
 

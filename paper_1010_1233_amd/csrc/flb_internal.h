@@ -46,6 +46,7 @@ struct alignas(16) LatticeParams {
     float feq[9];             // f_i^0(rho0,u0) - w_i rho0 (16-bit reference state)
     float scale[9];           // sqrt(mu rho0 w_i) (16-bit storage scale)
     float inv_scale[9];
+    float feq_scaled[9];      // feq * inv_scale
     float therm_amp[9];       // sqrt(mu rho0 w_i) for the thermal start
     uint32_t stream_id;
     int32_t line_x;           // index of the x-direction line plan

@@ -139,8 +139,9 @@ int validate_spec(const flb_lattice_spec &s, int idx)
                  s.ny);
         return fail(FLB_EINVAL, buf);
     }
-    if ((int64_t)(s.nx + 3) * s.ny * 9 >= (int64_t)1 << 31) {
-        snprintf(buf, sizeof buf, "lattice %d: 9*nx*ny must stay below 2^31", idx);
+    if ((int64_t)(s.nx + 3) * s.ny * 9 * 4 >= (int64_t)1 << 32) {
+        snprintf(buf, sizeof buf, "lattice %d: its populations must fit in 4 GiB "
+                 "(9*nx*ny*4 bytes, about 119M sites)", idx);
         return fail(FLB_ESIZE, buf);
     }
     for (int a = 0; a < 9; ++a)
@@ -190,6 +191,7 @@ LatticeParams make_params(const flb_lattice_spec &s, uint32_t flags)
         P.feq[i] = (float)(s.rho0 * kW[i] * (3.0 * uv + 4.5 * uv * uv - 1.5 * uu));
         P.scale[i] = (float)std::sqrt(mu_store * s.rho0 * kW[i]);
         P.inv_scale[i] = 1.0f / P.scale[i];
+        P.feq_scaled[i] = P.feq[i] * P.inv_scale[i];
         P.therm_amp[i] = (float)std::sqrt(mu * s.rho0 * kW[i]);
     }
     P.stream_id = s.stream_id;

@@ -121,6 +121,18 @@ __device__ __forceinline__ T lane(const typename Vec<T, V>::type &v, int k)
 // left of the group (x0 - 1, periodic) and one streaming along -x the value
 // right of it (x0 + V): one extra scalar load each.  A group reaching past
 // the last site of a row (nx not a multiple of V) takes the site-by-site path.
+// Element `off` of a lattice's buffer through a 32-bit byte offset (a
+// lattice's populations are limited to 4 GiB), so that the address is a
+// scalar base plus a 32-bit vector offset.
+template <typename U, typename T> __device__ __forceinline__ const U *at(const T *base, uint32_t off)
+{
+    return reinterpret_cast<const U *>(reinterpret_cast<const char *>(base) + off * (uint32_t)sizeof(T));
+}
+template <typename U, typename T> __device__ __forceinline__ U *at(T *base, uint32_t off)
+{
+    return reinterpret_cast<U *>(reinterpret_cast<char *>(base) + off * (uint32_t)sizeof(T));
+}
+
 template <int S, bool NT, bool NOISE, int TX, int V>
 __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs g)
 {
@@ -130,37 +142,41 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs g)
     const StepItem it = g.items[blockIdx.x];
     if (it.lattice < 0) return;
     const LatticeParams &P = g.params[it.lattice];
-    const int nx = P.nx, ny = P.ny, px = P.px;
+    const int nx = P.nx, ny = P.ny;
+    const uint32_t px = (uint32_t)P.px;
     const int tx = it.tile % P.tiles_x, ty = it.tile / P.tiles_x;
     const int x0 = (tx * TX + (int)(threadIdx.x % TX)) * V;
     const int y = ty * TH + (int)(threadIdx.x / TX);
     if (x0 >= nx || y >= ny) return;  // no barriers below: a thread may leave early
+    // wave-uniform bases and unsigned 32-bit offsets: addresses are a scalar
+    // base plus a vector offset, no 64-bit arithmetic per access
     const T *__restrict__ src = (const T *)g.src + P.base;
     T *__restrict__ dst = (T *)g.dst + P.base;
-    const int plane = (int)P.plane;
+    const uint32_t plane = (uint32_t)P.plane;
     const uint32_t t = *g.step + g.step_add;
-    const int ym = (y == 0) ? ny - 1 : y - 1;
-    const int yp = (y == ny - 1) ? 0 : y + 1;
-    const int rc = y * px, rm = ym * px, rp = yp * px;
-    const int xm = (x0 == 0) ? nx - 1 : x0 - 1;       // left of the group
-    const uint32_t site0 = (uint32_t)(y * nx + x0);    // noise counter of site x0
+    const uint32_t ym = (y == 0) ? ny - 1 : y - 1;
+    const uint32_t yp = (y == ny - 1) ? 0 : y + 1;
+    const uint32_t rc = (uint32_t)y * px, rm = ym * px, rp = yp * px;
+    const uint32_t ux0 = (uint32_t)x0;
+    const uint32_t xm = (x0 == 0) ? nx - 1 : x0 - 1;  // left of the group
+    const uint32_t site0 = (uint32_t)(y * nx + x0);   // noise counter of site x0
 
     if (x0 + V <= nx) {
-        const int xr = (x0 + V == nx) ? 0 : x0 + V;    // right of the group
+        const uint32_t xr = (x0 + V == nx) ? 0u : (uint32_t)(x0 + V);  // right of the group
         // pull: population i arrives from x - v_i
-        const VT a0 = *(const VT *)(src + rc + x0);
-        const VT a1 = *(const VT *)(src + 1 * plane + rc + x0);
-        const VT a2 = *(const VT *)(src + 2 * plane + rm + x0);
-        const VT a3 = *(const VT *)(src + 3 * plane + rc + x0);
-        const VT a4 = *(const VT *)(src + 4 * plane + rp + x0);
-        const VT a5 = *(const VT *)(src + 5 * plane + rm + x0);
-        const VT a6 = *(const VT *)(src + 6 * plane + rm + x0);
-        const VT a7 = *(const VT *)(src + 7 * plane + rp + x0);
-        const VT a8 = *(const VT *)(src + 8 * plane + rp + x0);
-        const T e1 = src[1 * plane + rc + xm], e5 = src[5 * plane + rm + xm];
-        const T e8 = src[8 * plane + rp + xm];
-        const T e3 = src[3 * plane + rc + xr], e6 = src[6 * plane + rm + xr];
-        const T e7 = src[7 * plane + rp + xr];
+        const VT a0 = *at<VT>(src, rc + ux0);
+        const VT a1 = *at<VT>(src, 1 * plane + rc + ux0);
+        const VT a2 = *at<VT>(src, 2 * plane + rm + ux0);
+        const VT a3 = *at<VT>(src, 3 * plane + rc + ux0);
+        const VT a4 = *at<VT>(src, 4 * plane + rp + ux0);
+        const VT a5 = *at<VT>(src, 5 * plane + rm + ux0);
+        const VT a6 = *at<VT>(src, 6 * plane + rm + ux0);
+        const VT a7 = *at<VT>(src, 7 * plane + rp + ux0);
+        const VT a8 = *at<VT>(src, 8 * plane + rp + ux0);
+        const T e1 = *at<T>(src, 1 * plane + rc + xm), e5 = *at<T>(src, 5 * plane + rm + xm);
+        const T e8 = *at<T>(src, 8 * plane + rp + xm);
+        const T e3 = *at<T>(src, 3 * plane + rc + xr), e6 = *at<T>(src, 6 * plane + rm + xr);
+        const T e7 = *at<T>(src, 7 * plane + rp + xr);
         T o[9][V];
 #pragma unroll
         for (int k = 0; k < V; ++k) {
@@ -187,24 +203,25 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs g)
 #pragma unroll
                 for (int k = 0; k < V; ++k) v[k] = o[i][k];
             }
-            gstore<NT>((VT *)(dst + i * plane + rc + x0), v);
+            gstore<NT>(at<VT>(dst, i * plane + rc + ux0), v);
         }
     } else {
         for (int x = x0; x < nx; ++x) {
-            const int xl = (x == 0) ? nx - 1 : x - 1, xr = (x == nx - 1) ? 0 : x + 1;
+            const uint32_t ux = (uint32_t)x;
+            const uint32_t xl = (x == 0) ? nx - 1 : x - 1, xr = (x == nx - 1) ? 0 : x + 1;
             float d[9];
-            d[0] = Codec<S>::decode(src[rc + x], P, 0);
-            d[1] = Codec<S>::decode(src[1 * plane + rc + xl], P, 1);
-            d[2] = Codec<S>::decode(src[2 * plane + rm + x], P, 2);
-            d[3] = Codec<S>::decode(src[3 * plane + rc + xr], P, 3);
-            d[4] = Codec<S>::decode(src[4 * plane + rp + x], P, 4);
-            d[5] = Codec<S>::decode(src[5 * plane + rm + xl], P, 5);
-            d[6] = Codec<S>::decode(src[6 * plane + rm + xr], P, 6);
-            d[7] = Codec<S>::decode(src[7 * plane + rp + xr], P, 7);
-            d[8] = Codec<S>::decode(src[8 * plane + rp + xl], P, 8);
+            d[0] = Codec<S>::decode(*at<T>(src, rc + ux), P, 0);
+            d[1] = Codec<S>::decode(*at<T>(src, 1 * plane + rc + xl), P, 1);
+            d[2] = Codec<S>::decode(*at<T>(src, 2 * plane + rm + ux), P, 2);
+            d[3] = Codec<S>::decode(*at<T>(src, 3 * plane + rc + xr), P, 3);
+            d[4] = Codec<S>::decode(*at<T>(src, 4 * plane + rp + ux), P, 4);
+            d[5] = Codec<S>::decode(*at<T>(src, 5 * plane + rm + xl), P, 5);
+            d[6] = Codec<S>::decode(*at<T>(src, 6 * plane + rm + xr), P, 6);
+            d[7] = Codec<S>::decode(*at<T>(src, 7 * plane + rp + xr), P, 7);
+            d[8] = Codec<S>::decode(*at<T>(src, 8 * plane + rp + xl), P, 8);
             update_site<NOISE>(d, P, (uint32_t)(y * nx + x), t, g.key0, g.key1);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) gstore<NT>(dst + i * plane + rc + x, Codec<S>::encode(d[i], P, i));
+            for (int i = 0; i < 9; ++i) gstore<NT>(at<T>(dst, i * plane + rc + ux), Codec<S>::encode(d[i], P, i));
         }
     }
 }

@@ -88,7 +88,8 @@ def _create(flb, nx=8, ny=8, tau=None, theta=1e-4, rho0=1.0, u0=(0.0, 0.0), stor
     (dict(u0=(float("nan"), 0.0)), "u0"),
     (dict(storage=7), "storage"),
     (dict(flags=8), "flags"),
-    (dict(nx=100000, ny=100000), "2^31"),
+    (dict(nx=100000, ny=100000), "4 GiB"),
+    (dict(nx=11000, ny=11000), "4 GiB"),
 ])
 def test_invalid_creation_is_rejected_on_the_host(flb, kw, msg):
     h = _create(flb, **kw)

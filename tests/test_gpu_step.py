@@ -46,7 +46,7 @@ def test_noise_words_bit_exact_and_normals_close(flb, oracle_lib, seed, stream_i
     zo = np.array([oracle_lib.normals_from_words(w[k]) for k in range(n)])
     err = np.abs(z.astype(np.float64) - zo)
     note("max |dz|", err.max())
-    assert err.max() <= 2e-5
+    assert err.max() <= 5e-6  # measured 6.6e-7 on MI355X
     g.close()
 
 
