@@ -51,20 +51,39 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, storage):
-    """HBM bytes per step-kernel launch from the committed counter summary,
-    or None when it is missing or was taken on a different kernel source."""
+def shape_key(workload, storage, shape):
+    tw, sites, nt = shape
+    return f"{workload}/{storage}/{tw}x{sites}/nt{int(bool(nt))}"
+
+
+def measured_traffic(workload, storage, shape):
+    """HBM bytes per step-kernel launch of this launch shape from the
+    committed counter summary, or None when it is missing or was taken on a
+    different kernel source."""
     path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    key = f"{workload}/{storage}"
-    e = d.get(key)
+    e = d.get(shape_key(workload, storage, shape))
     if not e or e.get("kernel_source_hash") != kernel_source_hash():
         return None
     return e.get("bytes_per_launch")
+
+
+def sweep_shapes(flb, workloads, name, storage, steps=5):
+    """Runs every step-kernel launch shape for a few steps (no timing): the
+    workload for per-shape hardware-counter runs."""
+    g, c = make_lattice(flb, workloads, name, storage)
+    g.thermalize()
+    for tw in (64, 128, 256):
+        for sites in (1, 2, 4):
+            for nt in (0, 1):
+                g.set_step_config(tw, sites, nt)
+                g.step(steps)
+    g.synchronize()
+    print(f"sweep-shapes: {name} {storage}: 18 shapes x {steps} steps", flush=True)
 
 
 def make_lattice(flb, workloads, name, storage):
@@ -90,7 +109,7 @@ def batched_form(torch, flb, stream, specs, storage, periods=10):
     b = flb.Lattice.batch(specs, seed=3, storage=storage)
     b.set_stream(stream)
     b.thermalize()
-    shape, _ = b.autotune(5)
+    shape, _ = b.autotune(20)
     sites = sum(s["nx"] * s["ny"] for s in specs)
     b.run(2 * SAMPLE_EVERY, SAMPLE_EVERY)  # capture the graphs
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -136,6 +155,11 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--sweep-shapes", action="store_true",
+                    help="only run every step-kernel launch shape briefly (for counter runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 603,979,776 bytes device to device three times "
+                         "(the known-size reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -150,6 +174,17 @@ def main():
     from paper_1010_1233_amd import workloads
 
     assert torch.cuda.is_available(), "no GPU visible"
+    if args.copy_calibration:
+        a = torch.ones(9 * 4096 * 4096, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"copy-calibration: 3 x {a.numel() * 4} bytes", flush=True)
+        return 0
+    if args.sweep_shapes:
+        sweep_shapes(flb, workloads, args.workload, args.storage)
+        return 0
     stream = torch.cuda.Stream()
     g, c = make_lattice(flb, workloads, args.workload, args.storage)
     g.set_stream(stream)
@@ -157,7 +192,7 @@ def main():
     print(f"bench: {args.workload} {c['nx']}x{c['ny']} storage={args.storage} "
           f"step config={g.step_config()}", file=sys.stderr, flush=True)
     g.thermalize()
-    tuned, _ = g.autotune(5)
+    tuned, _ = g.autotune(20)
     print(f"bench: autotuned step config {tuned}", file=sys.stderr, flush=True)
     cons0 = g.conservation()
 
@@ -187,7 +222,7 @@ def main():
     bytes_per_value = g.storage_info()[1]
     algo_bytes = 18 * bytes_per_value * V  # 9 loads + 9 stores per site
     achieved = algo_bytes / (step_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, args.storage)
+    traffic = measured_traffic(args.workload, args.storage, tuned)
     drift = float(abs(g.sample_conservation()[0] - cons0[0]))
 
     # correlator sanity (matched S(k)): k-averaged S(rho) over the run
@@ -234,7 +269,7 @@ def main():
                 h, _ = make_lattice(flb, workloads, args.workload, st)
                 h.set_stream(stream)
                 h.thermalize()
-                h.autotune(5)
+                h.autotune(20)
                 time_step_kernel(torch, h, stream, 5)
                 ms = time_step_kernel(torch, h, stream, 50)
                 b = h.storage_info()[1]
@@ -245,7 +280,7 @@ def main():
             h = flb.Lattice(cq["nx"], cq["ny"], cq["tau"], 0.0, rho0=cq["rho0"], u0=cq["u0"],
                             seed=cq["seed"], storage=args.storage)
             h.set_stream(stream)
-            h.autotune(5)
+            h.autotune(20)
             time_step_kernel(torch, h, stream, 5)
             ms = time_step_kernel(torch, h, stream, 50)
             forms["noise_off_" + args.storage] = {"step_glups": V / (ms * 1e-3) / 1e9}

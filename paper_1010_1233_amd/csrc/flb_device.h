@@ -57,29 +57,17 @@ template <> struct Codec<kF32> {
     static __device__ __forceinline__ T encode(float d, const LatticeParams &, int) { return d; }
 };
 
-__device__ __forceinline__ float bf16_to_f32(uint16_t h)
-{
-    return __uint_as_float((uint32_t)h << 16);
-}
-
-__device__ __forceinline__ uint16_t f32_to_bf16(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7F800000u) == 0x7F800000u)           // inf / nan: keep, quiet nans
-        return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
-    u += 0x7FFFu + ((u >> 16) & 1u);                // round to nearest even
-    return (uint16_t)(u >> 16);
-}
-
+// bfloat16 through the native type: gfx950 converts with one
+// round-to-nearest-even instruction (v_cvt_pk_bf16_f32).
 template <> struct Codec<kBF16> {
-    using T = uint16_t;
+    using T = __bf16;
     static __device__ __forceinline__ float decode(T v, const LatticeParams &P, int i)
     {
-        return fmaf(bf16_to_f32(v), P.scale[i], P.feq[i]);
+        return fmaf((float)v, P.scale[i], P.feq[i]);
     }
     static __device__ __forceinline__ T encode(float d, const LatticeParams &P, int i)
     {
-        return f32_to_bf16(fmaf(d, P.inv_scale[i], -P.feq_scaled[i]));
+        return (T)fmaf(d, P.inv_scale[i], -P.feq_scaled[i]);
     }
 };
 
