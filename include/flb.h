@@ -207,6 +207,13 @@ int flb_debug_noise(flb_t *h, int lattice, uint32_t t, int64_t site0, int64_t ns
 /* Number of steps taken so far (the t of the next step). */
 int64_t flb_get_step(flb_t *h);
 
+/* Sets the time of the next step (0 <= t < 2^32 - 1).  With
+ * flb_set_populations this resumes a run from a saved state: the noise is a
+ * function of (seed, site, t, stream_id) only, so the continuation is the
+ * same as an uninterrupted run (bit-identical for FP32 storage).
+ * Synchronises. */
+int flb_set_step(flb_t *h, int64_t t);
+
 /* Number of lattices in the handle (-1 on error). */
 int flb_num_lattices(flb_t *h);
 

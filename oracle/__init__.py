@@ -77,8 +77,9 @@ def lib():
         L.oracle_nkx.argtypes = [ctypes.c_int]
         L.oracle_nkx.restype = ctypes.c_int
         L.oracle_sample.argtypes = [cp, _dp, _dp]
+        L.oracle_sample_moments.argtypes = [cp, _dp, _dp]
         L.oracle_run.argtypes = [cp, _dp, _dp, ctypes.c_uint32, ctypes.c_int64,
-                                 ctypes.c_int, _dp]
+                                 ctypes.c_int, _dp, _dp]
         L.oracle_run.restype = ctypes.c_int64
         _lib = L
     return _lib
@@ -186,7 +187,7 @@ class Lattice:
     """
 
     def __init__(self, nx, ny, tau, theta, rho0=1.0, u0=(0.0, 0.0), seed=1,
-                 stream_id=0, ladd=False, thermalize=False):
+                 stream_id=0, ladd=False, thermalize=False, moments=False):
         self.cfg = Cfg()
         self.cfg.nx, self.cfg.ny = int(nx), int(ny)
         for a in range(9):
@@ -203,6 +204,8 @@ class Lattice:
             lib().oracle_thermalize(ctypes.byref(self.cfg), _p(self.f))
         self.t = 0
         self.acc = np.zeros((NKINDS, self.ny, nkx(self.nx)))
+        # |dM^a(k)|^2 of the six non-conserved moments, a = 3..8 (if asked for)
+        self.acc_m = np.zeros((6, self.ny, nkx(self.nx))) if moments else None
         self.nsamples = 0
 
     @property
@@ -224,13 +227,17 @@ class Lattice:
         """nsteps steps, sampling at every t with t % sample_every == 0."""
         ns = lib().oracle_run(ctypes.byref(self.cfg), _p(self.f), _p(self._tmp), self.t,
                               int(nsteps), int(sample_every),
-                              _p(self.acc) if sample_every > 0 else None)
+                              _p(self.acc) if sample_every > 0 else None,
+                              _p(self.acc_m) if sample_every > 0 and self.acc_m is not None
+                              else None)
         self.t += int(nsteps)
         self.nsamples += int(ns)
         return int(ns)
 
     def sample(self):
         lib().oracle_sample(ctypes.byref(self.cfg), _p(self.f), _p(self.acc))
+        if self.acc_m is not None:
+            lib().oracle_sample_moments(ctypes.byref(self.cfg), _p(self.f), _p(self.acc_m))
         self.nsamples += 1
 
     def conservation(self):
@@ -268,3 +275,12 @@ def normalized(acc, nsamples, nx, ny, theta, rho0):
         "R_rhouy": (m[13] + 1j * m[14]) / (V * mu * cs),
     }
     return out
+
+
+def normalized_moments(acc_m, nsamples, nx, ny, theta, rho0):
+    """S(M^a) = <|dM^a_k|^2> / (V mu rho0), a = 3..8 (Eq. 11: every moment of
+    the Hermite-normalised basis has per-site variance mu rho0 at rest)."""
+    V = nx * ny
+    mu = 3.0 * theta
+    m = acc_m / max(nsamples, 1)
+    return {"S_M%d" % a: m[a - 3] / (V * mu * rho0) for a in range(3, 9)}

@@ -481,12 +481,51 @@ void oracle_sample(const oracle_cfg *c, const double *f, double *acc)
     free(im);
 }
 
+/* Structure factors of the six non-conserved moments (Eq. 11 applied to
+ * every moment of Eq. 9, Sec. 3): adds |dM^a(k)|^2, a = 3..8, of the current
+ * (pre-collision) state to accm[a-3][ky][kx] (same k layout as
+ * oracle_sample), where M^a(x) = sum_i m_i^a f_i(x) (Eq. 3) and
+ * dM^a = M^a - <M^a>_x.  The conserved moments are rho and sqrt(3) j_a,
+ * already covered by oracle_sample. */
+void oracle_sample_moments(const oracle_cfg *c, const double *f, double *accm)
+{
+    init_tables();
+    const int nx = c->nx, ny = c->ny, nh = oracle_nkx(nx);
+    const size_t V = (size_t)nx * (size_t)ny;
+    double *re = (double *)malloc(sizeof(double) * 6 * V);
+    double *im = (double *)calloc(6 * V, sizeof(double));
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            double fs[9], Mo[9];
+            for (int i = 0; i < 9; ++i) fs[i] = f[idx(c, i, y, x)];
+            oracle_moments(fs, Mo);
+            for (int a = 3; a < 9; ++a) re[(size_t)(a - 3) * V + (size_t)y * nx + x] = Mo[a];
+        }
+    for (int q = 0; q < 6; ++q) {
+        double mean = 0.0;
+        for (size_t s = 0; s < V; ++s) mean += re[q * V + s];
+        mean /= (double)V;
+        for (size_t s = 0; s < V; ++s) re[q * V + s] -= mean;
+        oracle_dft2(re + q * V, im + q * V, nx, ny);
+    }
+    const size_t P = (size_t)ny * (size_t)nh;
+    for (int q = 0; q < 6; ++q)
+        for (int ky = 0; ky < ny; ++ky)
+            for (int kx = 0; kx < nh; ++kx) {
+                size_t s = q * V + (size_t)ky * nx + kx;
+                accm[q * P + (size_t)ky * nh + kx] += re[s] * re[s] + im[s] * im[s];
+            }
+    free(re);
+    free(im);
+}
+
 /* Run nsteps steps from time t0, sampling (into acc, if not NULL) the state
- * at every time t > t0 with t % sample_every == 0.  f holds the state on
- * entry and on return; tmp is scratch of the same size.  Returns the number
- * of samples taken. */
+ * at every time t > t0 with t % sample_every == 0; the moment structure
+ * factors go to accm when it is not NULL.  f holds the state on entry and on
+ * return; tmp is scratch of the same size.  Returns the number of samples
+ * taken. */
 int64_t oracle_run(const oracle_cfg *c, double *f, double *tmp, uint32_t t0, int64_t nsteps,
-                   int sample_every, double *acc)
+                   int sample_every, double *acc, double *accm)
 {
     const size_t n = (size_t)9 * (size_t)c->nx * (size_t)c->ny;
     int64_t ns = 0;
@@ -496,6 +535,7 @@ int64_t oracle_run(const oracle_cfg *c, double *f, double *tmp, uint32_t t0, int
         memcpy(f, tmp, n * sizeof(double));
         if (acc && sample_every > 0 && ((uint64_t)t + 1) % (uint64_t)sample_every == 0) {
             oracle_sample(c, f, acc);
+            if (accm) oracle_sample_moments(c, f, accm);
             ++ns;
         }
     }

@@ -78,6 +78,7 @@ SIGNATURES = {
     "flb_debug_noise": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32,
                                        ctypes.c_int64, ctypes.c_int64, _u32p, _fp]),
     "flb_get_step": (ctypes.c_int64, [ctypes.c_void_p]),
+    "flb_set_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
     "flb_num_lattices": (ctypes.c_int, [ctypes.c_void_p]),
     "flb_lattice_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _i32p, _i32p, _i32p]),
     "flb_storage_info": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i32p]),
@@ -220,6 +221,10 @@ class Lattice:
     @property
     def t(self):
         return int(lib().flb_get_step(self._h))
+
+    @t.setter
+    def t(self, value):
+        _check(lib().flb_set_step(self._h, int(value)))
 
     def set_step_config(self, tile_w, rows, nontemporal):
         _check(lib().flb_set_step_config(self._h, int(tile_w), int(rows), int(nontemporal)))

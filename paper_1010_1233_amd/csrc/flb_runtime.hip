@@ -889,6 +889,17 @@ int64_t flb_get_step(flb_t *h)
     return h->t;
 }
 
+int flb_set_step(flb_t *h, int64_t t)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (t < 0 || t >= (int64_t)0xFFFFFFFF) return fail(FLB_EINVAL, "t outside [0, 2^32 - 1)");
+    const uint32_t v = (uint32_t)t;
+    FLB_HIP(hipStreamSynchronize(h->stream));
+    FLB_HIP(hipMemcpy(h->d_step, &v, sizeof v, hipMemcpyHostToDevice));
+    h->t = t;
+    return FLB_OK;
+}
+
 int flb_num_lattices(flb_t *h)
 {
     if (check_handle(h)) return -1;

@@ -124,7 +124,8 @@ def predict(nx, ny, tau, theta, rho0=1.0, u0=(0.0, 0.0), ladd=False):
     """Stationary normalised correlators on the (ny, nx//2+1) half plane.
 
     Returns a dict with the same keys and normalisation as the oracle's
-    ``normalized``; singular k carry NaN.
+    ``normalized`` (plus S_M3..S_M8, the structure factors of the
+    non-conserved moments, normalised by mu rho0); singular k carry NaN.
     """
     u0 = np.asarray(u0, dtype=float)
     nh = nx // 2 + 1
@@ -134,8 +135,9 @@ def predict(nx, ny, tau, theta, rho0=1.0, u0=(0.0, 0.0), ladd=False):
     Q = noise_cov(tau, theta, rho0, ladd)
     v, _, _ = basis()
     one, lx, ly, lux, luy = _functionals(rho0, u0)
+    _, _, mb = basis()
     keys = ["S_rho", "S_jx", "S_jy", "S_ux", "S_uy", "R_uxuy", "R_rhojx", "R_rhojy",
-            "R_rhoux", "R_rhouy"]
+            "R_rhoux", "R_rhouy"] + ["S_M%d" % a for a in range(3, 9)]
     out = {k: np.full((ny, nh), np.nan, dtype=complex) for k in keys}
     for ky_i in range(ny):
         for kx_i in range(nh):
@@ -159,6 +161,8 @@ def predict(nx, ny, tau, theta, rho0=1.0, u0=(0.0, 0.0), ladd=False):
             out["R_rhojy"][ky_i, kx_i] = c(one, ly) / (mu * rho0 * cs)
             out["R_rhoux"][ky_i, kx_i] = c(one, lux) / (mu * cs)
             out["R_rhouy"][ky_i, kx_i] = c(one, luy) / (mu * cs)
+            for a in range(3, 9):
+                out["S_M%d" % a][ky_i, kx_i] = c(mb[a], mb[a]) / (mu * rho0)
     for k in keys:
         if k.startswith("S_"):
             out[k] = out[k].real

@@ -259,3 +259,21 @@ def test_autotune_keeps_state_and_caches(flb, tmp_path, monkeypatch):
     cfg2, ms2 = h.autotune(3)
     assert cfg2 == cfg and abs(ms2 - ms) < 1e-5  # cached with 6 decimals
     assert len((tmp_path / "tune.txt").read_text().splitlines()) == 1
+
+
+def test_resume_from_saved_state_is_bit_identical(flb):
+    """Checkpoint = populations + t (the noise is counter-based): a new handle
+    given both continues exactly like the uninterrupted run."""
+    ref = flb.Lattice(40, 24, TAU_C1, 1e-3, u0=(0.02, 0.0), seed=77, stream_id=5)
+    ref.thermalize()
+    ref.step(123)
+    saved, t = ref.get_populations(), ref.t
+    ref.step(50)
+    g = flb.Lattice(40, 24, TAU_C1, 1e-3, u0=(0.02, 0.0), seed=77, stream_id=5)
+    g.set_populations(saved)
+    g.t = t
+    assert g.t == 123
+    g.step(50)
+    assert np.array_equal(g.get_populations(), ref.get_populations())
+    with pytest.raises(flb.FlbError):
+        g.t = -1
