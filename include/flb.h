@@ -72,6 +72,10 @@ extern "C" {
 /* Creation flags. */
 #define FLB_FLAG_NO_GHOST_NOISE 1u /* zero noise on moments 6..8: the older
                                       scheme Sec. 3 compares against */
+#define FLB_FLAG_MOMENT_SPECTRA 2u /* also accumulate the structure factors of
+                                      the six non-conserved moments (Eq. 11
+                                      for every moment of Eq. 9; Sec. 3 checks
+                                      all nine): kinds 15..20 */
 
 /* Correlator kinds, first index of the accumulator array. */
 #define FLB_NKINDS 15
@@ -79,7 +83,11 @@ extern "C" {
  *  5,6  Re,Im ux_k uy_k*     7,8  Re,Im rho_k jx_k*    9,10 Re,Im rho_k jy_k*
  *  11,12 Re,Im rho_k ux_k*   13,14 Re,Im rho_k uy_k*
  * where X_k = sum_x (X(x) - <X>) exp(-i k.x), k = 2 pi (kx/nx, ky/ny)
- * (Sec. 3, text after Eq. 11), u = j / rho at each site. */
+ * (Sec. 3, text after Eq. 11), u = j / rho at each site.
+ * With FLB_FLAG_MOMENT_SPECTRA, six more kinds follow:
+ *  15 + (a - 3)  |M^a_k|^2, a = 3..8, M^a = sum_i m_i^a f_i (Eq. 3, Eq. 9)
+ * (the conserved moments M^0..M^2 are rho and sqrt(3) j, kinds 0..2). */
+#define FLB_NKINDS_MOMENTS 21
 
 /* Largest side for which correlators are supported: powers of two up to
  * FLB_MAX_FFT_SIDE, other lengths up to FLB_MAX_FFT_SIDE / 2. */
@@ -156,9 +164,9 @@ int flb_run(flb_t *h, int64_t nsteps, int sample_every);
 int flb_accumulate_correlators(flb_t *h);
 
 /* Copies lattice `lattice`'s raw FP64 sums to out[kind][ky][kx] (host), with
- * kind < FLB_NKINDS, ky < ny, kx < nx/2+1, and writes the number of samples
- * taken to *nsamples (may be NULL).  n_doubles must be at least
- * FLB_NKINDS*ny*(nx/2+1), else FLB_ESIZE.  Synchronises. */
+ * kind < flb_num_kinds(h), ky < ny, kx < nx/2+1, and writes the number of
+ * samples taken to *nsamples (may be NULL).  n_doubles must be at least
+ * flb_num_kinds(h)*ny*(nx/2+1), else FLB_ESIZE.  Synchronises. */
 int flb_read_correlators(flb_t *h, int lattice, double *out, size_t n_doubles,
                          int64_t *nsamples);
 
@@ -203,6 +211,11 @@ int flb_thermalize(flb_t *h);
  * Synchronises.  For testing. */
 int flb_debug_noise(flb_t *h, int lattice, uint32_t t, int64_t site0, int64_t nsites,
                     uint32_t *words_out, float *z_out);
+
+/* Number of correlator kinds the handle accumulates: FLB_NKINDS, or
+ * FLB_NKINDS_MOMENTS with FLB_FLAG_MOMENT_SPECTRA; negative on a NULL
+ * handle. */
+int flb_num_kinds(flb_t *h);
 
 /* Number of steps taken so far (the t of the next step). */
 int64_t flb_get_step(flb_t *h);

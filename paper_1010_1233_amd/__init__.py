@@ -22,10 +22,13 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "flb.h")
 OK, EINVAL, ENOMEM, EHIP, ESIZE, ESTATE = 0, -1, -2, -3, -4, -5
 STORAGE = {"f32": 0, "bf16": 1, "f16": 2}
 FLAG_NO_GHOST_NOISE = 1
+FLAG_MOMENT_SPECTRA = 2
 NKINDS = 15
+NKINDS_MOMENTS = 21
 KINDS = ("rho_rho", "jx_jx", "jy_jy", "ux_ux", "uy_uy",
          "re_ux_uy", "im_ux_uy", "re_rho_jx", "im_rho_jx", "re_rho_jy", "im_rho_jy",
          "re_rho_ux", "im_rho_ux", "re_rho_uy", "im_rho_uy")
+MOMENT_KINDS = tuple("M%d_M%d" % (a, a) for a in range(3, 9))
 
 
 class FlbError(RuntimeError):
@@ -79,6 +82,7 @@ SIGNATURES = {
                                        ctypes.c_int64, ctypes.c_int64, _u32p, _fp]),
     "flb_get_step": (ctypes.c_int64, [ctypes.c_void_p]),
     "flb_set_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "flb_num_kinds": (ctypes.c_int, [ctypes.c_void_p]),
     "flb_num_lattices": (ctypes.c_int, [ctypes.c_void_p]),
     "flb_lattice_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _i32p, _i32p, _i32p]),
     "flb_storage_info": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i32p]),
@@ -149,12 +153,13 @@ class Lattice:
     """
 
     def __init__(self, nx=None, ny=None, tau=None, theta=None, rho0=1.0, u0=(0.0, 0.0),
-                 seed=1, storage="f32", stream_id=0, ladd=False, _handle=None):
+                 seed=1, storage="f32", stream_id=0, ladd=False, moments=False,
+                 _handle=None):
         L = lib()
         if _handle is None:
             t = np.ascontiguousarray(tau, dtype=np.float64)
             u = np.ascontiguousarray(u0, dtype=np.float64)
-            flags = FLAG_NO_GHOST_NOISE if ladd else 0
+            flags = _flags(ladd, moments)
             _handle = L.flb_create_ex(int(nx), int(ny), _dptr(t), float(theta), float(rho0),
                                       _dptr(u), int(seed), STORAGE[storage], int(stream_id),
                                       flags)
@@ -169,16 +174,17 @@ class Lattice:
                                       ctypes.byref(nk_)))
             self._shapes.append((nx_.value, ny_.value, nk_.value))
         self.nx, self.ny, self.nkx = self._shapes[0]
+        self.nkinds = L.flb_num_kinds(self._h)
 
     @classmethod
-    def batch(cls, specs, seed=1, storage="f32", ladd=False):
+    def batch(cls, specs, seed=1, storage="f32", ladd=False, moments=False):
         """specs: list of dicts with nx, ny, tau, theta, rho0, u0, stream_id."""
         arr = (LatticeSpec * len(specs))()
         for i, s in enumerate(specs):
             arr[i] = make_spec(s["nx"], s["ny"], s["tau"], s["theta"], s.get("rho0", 1.0),
                                s.get("u0", (0.0, 0.0)), s.get("stream_id", i))
         h = lib().flb_create_batch(len(specs), arr, int(seed), STORAGE[storage],
-                                   FLAG_NO_GHOST_NOISE if ladd else 0)
+                                   _flags(ladd, moments))
         if not h:
             raise FlbError(EINVAL, last_error())
         return cls(_handle=h)
@@ -295,9 +301,10 @@ class Lattice:
         _check(lib().flb_reset_correlators(self._h))
 
     def read_correlators(self, lattice=0):
-        """(raw FP64 sums [15][ny][nx//2+1], number of samples)."""
+        """(raw FP64 sums [nkinds][ny][nx//2+1], number of samples); nkinds is
+        15, or 21 with the moment spectra."""
         nx, ny, nk = self._shapes[lattice]
-        out = np.empty((NKINDS, ny, nk), dtype=np.float64)
+        out = np.empty((self.nkinds, ny, nk), dtype=np.float64)
         ns = ctypes.c_int64()
         _check(lib().flb_read_correlators(self._h, lattice, _dptr(out), out.size,
                                           ctypes.byref(ns)))
@@ -312,12 +319,15 @@ def normalize(acc, nsamples, nx, ny, theta, rho0):
     S(u_a) = rho0 <|u_a|^2> / (V theta) (N^{u_a} = 1/(rho0 V k_B T));
     R(u_x, u_y) = rho0 <u_x u_y*> / (V theta) (Eq. 12);
     R(rho, j_a) = <rho j_a*> / (V mu rho0 c_s); R(rho, u_a) = <rho u_a*> / (V mu c_s).
+    With the moment spectra (21 kinds) also S(M^a) = <|M^a_k|^2> / (V mu rho0),
+    a = 3..8: every moment of the Hermite-normalised basis has per-site
+    variance mu rho0 at rest.
     """
     V = float(nx) * float(ny)
     mu = 3.0 * theta
     cs = 3.0 ** -0.5
     m = np.asarray(acc) / max(int(nsamples), 1)
-    return {
+    out = {
         "S_rho": m[0] / (V * mu * rho0),
         "S_jx": m[1] / (V * rho0 * theta),
         "S_jy": m[2] / (V * rho0 * theta),
@@ -329,3 +339,11 @@ def normalize(acc, nsamples, nx, ny, theta, rho0):
         "R_rhoux": (m[11] + 1j * m[12]) / (V * mu * cs),
         "R_rhouy": (m[13] + 1j * m[14]) / (V * mu * cs),
     }
+    if m.shape[0] == NKINDS_MOMENTS:
+        for a in range(3, 9):
+            out["S_M%d" % a] = m[NKINDS + a - 3] / (V * mu * rho0)
+    return out
+
+
+def _flags(ladd, moments):
+    return (FLAG_NO_GHOST_NOISE if ladd else 0) | (FLAG_MOMENT_SPECTRA if moments else 0)

@@ -228,6 +228,7 @@ struct CorrArgs {
     float *fields;
     double *csum_part;
     double *csum;
+    int set;  // field set: 0 = rho, j, u; 1 = moments 3..8
 };
 
 // Block sum of five doubles into out[0..4] (deterministic order).
@@ -250,17 +251,16 @@ __device__ __forceinline__ void block_sum5(double (&v)[5], double *out)
     }
 }
 
-// Fluctuation fields at site (x, y) of the current state.
+// Deviations f_i - w_i rho0 arriving at site (x, y): the current state
+// pulled along each velocity (streaming, Eq. 1).
 template <int S>
-__device__ __forceinline__ void site_fields(const typename Codec<S>::T *p, const LatticeParams &P,
-                                            int x, int y, float &drho, float &djx, float &djy,
-                                            float &dux, float &duy)
+__device__ __forceinline__ void pull_site(const typename Codec<S>::T *p, const LatticeParams &P,
+                                          int x, int y, float (&d)[9])
 {
     const int nx = P.nx, ny = P.ny, px = P.px, plane = (int)P.plane;
     const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
     const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
     const int rc = y * px, rm = ym * px, rp = yp * px;
-    float d[9];
     d[0] = Codec<S>::decode(p[rc + x], P, 0);
     d[1] = Codec<S>::decode(p[1 * plane + rc + xm], P, 1);
     d[2] = Codec<S>::decode(p[2 * plane + rm + x], P, 2);
@@ -270,6 +270,16 @@ __device__ __forceinline__ void site_fields(const typename Codec<S>::T *p, const
     d[6] = Codec<S>::decode(p[6 * plane + rm + xp], P, 6);
     d[7] = Codec<S>::decode(p[7 * plane + rp + xp], P, 7);
     d[8] = Codec<S>::decode(p[8 * plane + rp + xm], P, 8);
+}
+
+// Fluctuation fields at site (x, y) of the current state.
+template <int S>
+__device__ __forceinline__ void site_fields(const typename Codec<S>::T *p, const LatticeParams &P,
+                                            int x, int y, float &drho, float &djx, float &djy,
+                                            float &dux, float &duy)
+{
+    float d[9];
+    pull_site<S>(p, P, x, y, d);
     const float r = d[0] + (d[1] + d[3]) + (d[2] + d[4]) + (d[5] + d[7]) + (d[6] + d[8]);
     const float jx = (d[1] - d[3]) + (d[5] - d[7]) - (d[6] - d[8]);
     const float jy = (d[2] - d[4]) + (d[5] - d[7]) + (d[6] - d[8]);
@@ -281,12 +291,34 @@ __device__ __forceinline__ void site_fields(const typename Codec<S>::T *p, const
     duy = jy * ir - P.u0y;
 }
 
-// Fluctuation fields of the current state, one thread per column of a tile
-// of 256 sites x kFieldRows rows, written as five FP32 planes [5][ny][nx]
-// (d rho, d jx, d jy, d ux, d uy), together with the FP64 conservation sums
-// of the same state (mass, momentum, staggered momenta) as per-block
-// partials.  item: lattice, tile, index of the block's partial.
+// Non-conserved moments M^3..M^8 (rows of Eq. 9) at site (x, y).  The rows
+// are orthogonal to M^0 under the weights, so the moments of the deviations
+// are the moments themselves.
 template <int S>
+__device__ __forceinline__ void site_moments(const typename Codec<S>::T *p,
+                                             const LatticeParams &P, int x, int y,
+                                             float (&M)[6])
+{
+    float d[9];
+    pull_site<S>(p, P, x, y, d);
+    const float axis = (d[1] + d[3]) + (d[2] + d[4]);
+    const float diag = (d[5] + d[7]) + (d[6] + d[8]);
+    const float s32 = 1.2247448713915890f, s6 = 2.4494897427831781f;
+    M[0] = 1.5f * ((d[1] + d[3]) - (d[2] + d[4]));
+    M[1] = 3.0f * ((d[5] + d[7]) - (d[6] + d[8]));
+    M[2] = fmaf(0.5f, axis, fmaf(2.0f, diag, -d[0]));
+    M[3] = fmaf(s32, d[3] - d[1], s6 * ((d[5] - d[7]) + (d[8] - d[6])));
+    M[4] = fmaf(s32, d[4] - d[2], s6 * ((d[5] - d[7]) + (d[6] - d[8])));
+    M[5] = fmaf(0.5f, d[0], fmaf(2.0f, diag, -axis));
+}
+
+// Fluctuation fields of the current state, one thread per column of a tile
+// of 256 sites x kFieldRows rows, written as FP32 planes [nf][ny][nx].
+// SET 0: d rho, d jx, d jy, d ux, d uy, together with the FP64 conservation
+// sums of the same state (mass, momentum, staggered momenta) as per-block
+// partials.  SET 1: the six non-conserved moments.
+// item: lattice, tile, index of the block's partial.
+template <int S, int SET>
 __global__ __launch_bounds__(kThreads) void corr_fields_kernel(CorrArgs g)
 {
     using T = typename Codec<S>::T;
@@ -296,11 +328,22 @@ __global__ __launch_bounds__(kThreads) void corr_fields_kernel(CorrArgs g)
     const int nx = P.nx, ny = P.ny;
     const int tx = it.a % P.fld_tiles_x, ty = it.a / P.fld_tiles_x;
     const int x = tx * kThreads + (int)threadIdx.x;
+    const T *p = (const T *)g.pops + P.base;
+    const int64_t fs = (int64_t)nx * ny;
+    const int y1 = min(ny, (ty + 1) * kFieldRows);
+    if constexpr (SET == 1) {
+        if (x >= nx) return;
+        for (int y = ty * kFieldRows; y < y1; ++y) {
+            float M[6];
+            site_moments<S>(p, P, x, y, M);
+            float *f = g.fields + P.fld_base + (int64_t)y * nx + x;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) f[q * fs] = M[q];
+        }
+        return;
+    }
     double acc[5] = {0, 0, 0, 0, 0};
     if (x < nx) {
-        const T *p = (const T *)g.pops + P.base;
-        const int64_t fs = (int64_t)nx * ny;
-        const int y1 = min(ny, (ty + 1) * kFieldRows);
         for (int y = ty * kFieldRows; y < y1; ++y) {
             float dr, jx, jy, ux, uy;
             site_fields<S>(p, P, x, y, dr, jx, jy, ux, uy);
@@ -336,8 +379,9 @@ __global__ __launch_bounds__(kThreads) void corr_csum_kernel(CorrArgs g, int nla
 }
 
 // Row transforms of the fields: one block per (lattice, group of rows,
-// signal); signal 0 packs jx + i jy, 1 ux + i uy, 2 rho alone.  Writes the
-// half spectra kx = 0..nx/2 of the five real fields.
+// signal).  Set 0: signal 0 packs jx + i jy, 1 ux + i uy, 2 rho alone; set 1:
+// signal s packs M^(3+2s) + i M^(4+2s).  Writes the half spectra
+// kx = 0..nx/2 of the real fields.
 // item: lattice, first row, rows in this block, signal
 __global__ __launch_bounds__(kFftThreads) void corr_rowfft_kernel(CorrArgs g)
 {
@@ -351,7 +395,10 @@ __global__ __launch_bounds__(kFftThreads) void corr_rowfft_kernel(CorrArgs g)
     const int m = L.m, lg = L.log2m;
     const float2 *chirp = g.tables + L.chirp_off;
     const int64_t fs = (int64_t)nx * ny;
-    const float *fa_p = g.fields + P.fld_base + (sig == 0 ? fs : sig == 1 ? 3 * fs : 0);
+    // field pair (fa, fa + 1), or fa alone for rho
+    const int fa = g.set ? 2 * sig : (sig == 0 ? 1 : sig == 1 ? 3 : 0);
+    const bool pair = g.set || sig != 2;
+    const float *fa_p = g.fields + P.fld_base + fa * fs;
     const float *fb_p = fa_p + fs;
 
     for (int e = threadIdx.x; e < nl * m; e += kFftThreads) {
@@ -360,7 +407,7 @@ __global__ __launch_bounds__(kFftThreads) void corr_rowfft_kernel(CorrArgs g)
         if (x < nx) {
             const int64_t o = (int64_t)(y0 + l) * nx + x;
             v.x = fa_p[o];
-            if (sig != 2) v.y = fb_p[o];
+            if (pair) v.y = fb_p[o];
             if (L.bluestein) v = cmul(v, chirp[x]);
         }
         lds[lds_slot<true>(l * m + bitrev(x, lg))] = v;
@@ -372,22 +419,18 @@ __global__ __launch_bounds__(kFftThreads) void corr_rowfft_kernel(CorrArgs g)
     // a_k = (z_k + conj z_{-k}) / 2, b_k = (z_k - conj z_{-k}) / (2i)
     float2 *spec = g.spec + P.spec_base;
     const int64_t fstride = (int64_t)ny * kxp;
-    const int fa = sig == 0 ? 1 : 3, fb = sig == 0 ? 2 : 4;
+    const int fb = fa + 1;
     for (int e = threadIdx.x; e < nl * kxp; e += kFftThreads) {
         const int l = e / kxp, k = e - l * kxp;
         const int64_t row = (int64_t)(y0 + l) * kxp + k;
         if (k >= nkx) {  // padding columns: keep them finite
-            if (sig == 2) {
-                spec[row] = make_float2(0.f, 0.f);
-            } else {
-                spec[fa * fstride + row] = make_float2(0.f, 0.f);
-                spec[fb * fstride + row] = make_float2(0.f, 0.f);
-            }
+            spec[fa * fstride + row] = make_float2(0.f, 0.f);
+            if (pair) spec[fb * fstride + row] = make_float2(0.f, 0.f);
             continue;
         }
         const float2 zk = lds[lds_slot<true>(l * m + k)];
-        if (sig == 2) {
-            spec[row] = zk;
+        if (!pair) {
+            spec[fa * fstride + row] = zk;
         } else {
             const float2 zm = lds[lds_slot<true>(l * m + (k == 0 ? 0 : nx - k))];
             spec[fa * fstride + row] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
@@ -446,10 +489,34 @@ __device__ __forceinline__ void accumulate_k(double *a, int64_t kstride, const f
     for (int q = 0; q < kKinds; ++q) a[q * kstride] += val[q];
 }
 
+// Squared moduli of the six moment spectra at one k, added to kinds
+// kKinds .. kKinds + 5.
+__device__ __forceinline__ void accumulate_moments_k(double *a, int64_t kstride,
+                                                     const float2 (&X)[6])
+{
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const double re = X[f].x, im = X[f].y;
+        a[(kKinds + f) * kstride] += re * re + im * im;
+    }
+}
+
+template <int SET, int NF>
+__device__ __forceinline__ void accumulate_set(double *a, int64_t kstride, const float2 (&X)[NF])
+{
+    if constexpr (SET == 0)
+        accumulate_k(a, kstride, X);
+    else
+        accumulate_moments_k(a, kstride, X);
+}
+
 // Power-of-two ny, pass B with accumulation.  item: lattice, first column, k1.
-// LDS [q][f][c]: the Q rows Q*k1 .. Q*k1+Q-1 of all five fields, 16 columns.
+// LDS [q][f][c]: the Q rows Q*k1 .. Q*k1+Q-1 of all fields of the set, 16
+// columns.
+template <int SET>
 __global__ __launch_bounds__(kFftThreads) void corr_cols_b_kernel(CorrArgs g)
 {
+    constexpr int NF = SET ? 6 : 5;
     extern __shared__ float2 lds[];
     const CorrItem it = g.items[blockIdx.x];
     if (it.lattice < 0) return;
@@ -457,7 +524,7 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_b_kernel(CorrArgs g)
     const int c0 = it.a, k1 = it.b;
     const int Q = P.col_q, lgQ = P.col_lgq, Pn = 1 << P.col_lgp;
     const int ny = P.ny, nkx = P.nkx, kxp = P.kxp;
-    constexpr int NL = 5 * 16;
+    constexpr int NL = NF * 16;
     const float2 *spec = g.spec + P.spec_base + c0;
     const int64_t fstride = (int64_t)ny * kxp;
     for (int idx = threadIdx.x; idx < Q * NL; idx += kFftThreads) {
@@ -472,10 +539,10 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_b_kernel(CorrArgs g)
         const int k2 = idx >> 4, c = idx & 15;
         const int kx = c0 + c, ky = k1 + Pn * k2;
         if (kx >= nkx || (kx == 0 && ky == 0)) continue;
-        float2 X[5];
+        float2 X[NF];
 #pragma unroll
-        for (int f = 0; f < 5; ++f) X[f] = lds[k2 * NL + f * 16 + c];
-        accumulate_k(acc + (int64_t)ky * kxp + kx, fstride, X);
+        for (int f = 0; f < NF; ++f) X[f] = lds[k2 * NL + f * 16 + c];
+        accumulate_set<SET, NF>(acc + (int64_t)ky * kxp + kx, fstride, X);
     }
 }
 
@@ -510,8 +577,10 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g, int 
 }
 
 // Other ny: accumulation.  item: lattice, first k of the (ny, nkx) plane.
+template <int SET>
 __global__ __launch_bounds__(kThreads) void corr_accum_kernel(CorrArgs g)
 {
+    constexpr int NF = SET ? 6 : 5;
     const CorrItem it = g.items[blockIdx.x];
     if (it.lattice < 0) return;
     const LatticeParams &P = g.params[it.lattice];
@@ -523,13 +592,13 @@ __global__ __launch_bounds__(kThreads) void corr_accum_kernel(CorrArgs g)
     const int64_t o = (int64_t)ky * kxp + kx;
     const int64_t fstride = (int64_t)P.ny * kxp;
     const float2 *sp = g.spec + P.spec_base;
-    float2 X[5];
+    float2 X[NF];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) X[f] = sp[f * fstride + o];
-    accumulate_k(g.acc + P.acc_base + o, fstride, X);
+    for (int f = 0; f < NF; ++f) X[f] = sp[f * fstride + o];
+    accumulate_set<SET, NF>(g.acc + P.acc_base + o, fstride, X);
 }
 
-static CorrArgs make_args(const DeviceView &v, const CorrItem *items)
+static CorrArgs make_args(const DeviceView &v, const CorrItem *items, int set)
 {
     CorrArgs g;
     g.pops = v.pops[v.cur];
@@ -542,30 +611,41 @@ static CorrArgs make_args(const DeviceView &v, const CorrItem *items)
     g.fields = v.fields;
     g.csum_part = v.csum_part;
     g.csum = v.csum;
+    g.set = set;
     return g;
 }
 
-hipError_t launch_corr_fields(const DeviceView &v, const CorrItem *items, int nitems,
+template <int SET>
+static void fields_for_set(const DeviceView &v, const CorrArgs &g, dim3 grid, hipStream_t s)
+{
+    const dim3 block(kThreads);
+    if (v.storage == kF32)
+        hipLaunchKernelGGL((corr_fields_kernel<kF32, SET>), grid, block, 0, s, g);
+    else if (v.storage == kBF16)
+        hipLaunchKernelGGL((corr_fields_kernel<kBF16, SET>), grid, block, 0, s, g);
+    else
+        hipLaunchKernelGGL((corr_fields_kernel<kF16, SET>), grid, block, 0, s, g);
+}
+
+hipError_t launch_corr_fields(const DeviceView &v, const CorrItem *items, int nitems, int set,
                               hipStream_t s)
 {
-    const CorrArgs g = make_args(v, items);
-    const dim3 grid(nitems), block(kThreads);
-    if (v.storage == kF32)
-        hipLaunchKernelGGL(corr_fields_kernel<kF32>, grid, block, 0, s, g);
-    else if (v.storage == kBF16)
-        hipLaunchKernelGGL(corr_fields_kernel<kBF16>, grid, block, 0, s, g);
-    else
-        hipLaunchKernelGGL(corr_fields_kernel<kF16>, grid, block, 0, s, g);
+    const CorrArgs g = make_args(v, items, set);
+    if (set == 1) {
+        fields_for_set<1>(v, g, dim3(nitems), s);
+        return hipGetLastError();
+    }
+    fields_for_set<0>(v, g, dim3(nitems), s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(corr_csum_kernel, dim3(v.nlat), block, 0, s, g, v.nlat);
+    hipLaunchKernelGGL(corr_csum_kernel, dim3(v.nlat), dim3(kThreads), 0, s, g, v.nlat);
     return hipGetLastError();
 }
 
-hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems,
+hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems, int set,
                             int lds_bytes, hipStream_t s)
 {
-    const CorrArgs g = make_args(v, items);
+    const CorrArgs g = make_args(v, items, set);
     hipLaunchKernelGGL(corr_rowfft_kernel, dim3(nitems), dim3(kFftThreads), lds_bytes, s, g);
     return hipGetLastError();
 }
@@ -573,32 +653,40 @@ hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nite
 hipError_t launch_corr_cols_a(const DeviceView &v, const CorrItem *items, int nitems,
                               int lds_bytes, hipStream_t s)
 {
-    const CorrArgs g = make_args(v, items);
+    const CorrArgs g = make_args(v, items, 0);
     hipLaunchKernelGGL(corr_cols_a_kernel, dim3(nitems), dim3(kFftThreads), lds_bytes, s, g);
     return hipGetLastError();
 }
 
-hipError_t launch_corr_cols_b(const DeviceView &v, const CorrItem *items, int nitems,
+hipError_t launch_corr_cols_b(const DeviceView &v, const CorrItem *items, int nitems, int set,
                               int lds_bytes, hipStream_t s)
 {
-    const CorrArgs g = make_args(v, items);
-    hipLaunchKernelGGL(corr_cols_b_kernel, dim3(nitems), dim3(kFftThreads), lds_bytes, s, g);
+    const CorrArgs g = make_args(v, items, set);
+    if (set == 1)
+        hipLaunchKernelGGL(corr_cols_b_kernel<1>, dim3(nitems), dim3(kFftThreads), lds_bytes, s,
+                           g);
+    else
+        hipLaunchKernelGGL(corr_cols_b_kernel<0>, dim3(nitems), dim3(kFftThreads), lds_bytes, s,
+                           g);
     return hipGetLastError();
 }
 
 hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int cb,
                             int lds_bytes, hipStream_t s)
 {
-    const CorrArgs g = make_args(v, items);
+    const CorrArgs g = make_args(v, items, 0);
     hipLaunchKernelGGL(corr_cols_kernel, dim3(nitems), dim3(kFftThreads), lds_bytes, s, g, cb);
     return hipGetLastError();
 }
 
-hipError_t launch_corr_accum(const DeviceView &v, const CorrItem *items, int nitems,
+hipError_t launch_corr_accum(const DeviceView &v, const CorrItem *items, int nitems, int set,
                              hipStream_t s)
 {
-    const CorrArgs g = make_args(v, items);
-    hipLaunchKernelGGL(corr_accum_kernel, dim3(nitems), dim3(kThreads), 0, s, g);
+    const CorrArgs g = make_args(v, items, set);
+    if (set == 1)
+        hipLaunchKernelGGL(corr_accum_kernel<1>, dim3(nitems), dim3(kThreads), 0, s, g);
+    else
+        hipLaunchKernelGGL(corr_accum_kernel<0>, dim3(nitems), dim3(kThreads), 0, s, g);
     return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ namespace flbdev {
 constexpr int kThreads = 256;
 constexpr int kFields = 5;   // delta rho, delta jx, delta jy, delta ux, delta uy
 constexpr int kKinds = 15;
+constexpr int kMomentFields = 6;  // M^3 .. M^8, with the moment spectra
 constexpr int kFieldRows = 16;  // rows per block of the field kernel
 
 // Per-lattice constants, read by every kernel through scalar loads.
@@ -107,7 +108,7 @@ struct DeviceView {
     uint32_t *step_rw;
     float2 *spec;
     double *acc;
-    float *fields;                    // [5][ny][nx] FP32 per lattice
+    float *fields;                    // [nf][ny][nx] FP32 per lattice (nf = 5, or 6)
     double *csum_part;                // field-kernel partial sums
     double *csum;                     // [nlat][5] sums of the last sample
     const LinePlan *plans;            // device
@@ -133,17 +134,19 @@ hipError_t launch_thermalize(const DeviceView &v, int lattice, int nx, int ny, d
                              int nblocks, double *mean_dev, hipStream_t s);
 hipError_t launch_debug_noise(uint64_t seed, uint32_t stream_id, uint32_t t, int64_t site0,
                               int64_t n, uint32_t *words_dev, float *z_dev, hipStream_t s);
-hipError_t launch_corr_fields(const DeviceView &v, const CorrItem *items, int nitems,
+// set: 0 = rho, j, u (kKinds kinds, plus the conservation sums); 1 = the
+// six non-conserved moments (kinds kKinds .. kKinds + 5)
+hipError_t launch_corr_fields(const DeviceView &v, const CorrItem *items, int nitems, int set,
                               hipStream_t s);
-hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems,
+hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems, int set,
                             int lds_bytes, hipStream_t s);
 hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int cb,
                             int lds_bytes, hipStream_t s);
 hipError_t launch_corr_cols_a(const DeviceView &v, const CorrItem *items, int nitems,
                               int lds_bytes, hipStream_t s);
-hipError_t launch_corr_cols_b(const DeviceView &v, const CorrItem *items, int nitems,
+hipError_t launch_corr_cols_b(const DeviceView &v, const CorrItem *items, int nitems, int set,
                               int lds_bytes, hipStream_t s);
-hipError_t launch_corr_accum(const DeviceView &v, const CorrItem *items, int nitems,
+hipError_t launch_corr_accum(const DeviceView &v, const CorrItem *items, int nitems, int set,
                              hipStream_t s);
 hipError_t launch_fill(double *p, size_t n, hipStream_t s);
 

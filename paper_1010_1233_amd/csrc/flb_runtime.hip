@@ -93,6 +93,12 @@ struct flb {
     CorrItem *d_rows = nullptr, *d_cols = nullptr, *d_accum = nullptr;
     CorrItem *d_cols_a = nullptr, *d_cols_b = nullptr, *d_fld = nullptr;
     int n_rows = 0, n_cols = 0, n_accum = 0, n_cols_a = 0, n_cols_b = 0, n_fld = 0;
+    // moment spectra (FLB_FLAG_MOMENT_SPECTRA): a second field set of six
+    // moments through the same transforms, into kinds kKinds .. kKinds + 5
+    bool moments = false;
+    int nkinds = kKinds, nfld = kFields;
+    CorrItem *d_cols_a_m = nullptr, *d_cols_m = nullptr;
+    int n_cols_a_m = 0, n_cols_m = 0;
     float *d_fields = nullptr;
     double *d_csum_part = nullptr, *d_csum = nullptr;
     int rows_lds = 0, cols_lds = 0, cols_cb = 1, cols_a_lds = 0, cols_b_lds = 0;
@@ -363,16 +369,17 @@ int setup_correlators(flb_t *h)
             P.col_nq = std::min(P.col_q, std::max(1, 256 / Pn));
             if (Pn > 1)
                 h->cols_a_lds = std::max(h->cols_a_lds, Pn * P.col_nq * 16 * (int)sizeof(float2));
-            h->cols_b_lds = std::max(h->cols_b_lds, P.col_q * 80 * (int)sizeof(float2));
+            h->cols_b_lds =
+                std::max(h->cols_b_lds, P.col_q * 16 * h->nfld * (int)sizeof(float2));
         } else {
             max_my_general = std::max(max_my_general, h->plans[P.line_y].m);
         }
         P.spec_base = spec;
         P.acc_base = acc;
-        spec += (int64_t)kFields * P.ny * P.kxp;
-        acc += (int64_t)kKinds * P.ny * P.kxp;
+        spec += (int64_t)h->nfld * P.ny * P.kxp;
+        acc += (int64_t)h->nkinds * P.ny * P.kxp;
         P.fld_base = fld;
-        fld += ((int64_t)kFields * P.nx * P.ny + 63) / 64 * 64;
+        fld += ((int64_t)h->nfld * P.nx * P.ny + 63) / 64 * 64;
         P.fld_tiles_x = (P.nx + kThreads - 1) / kThreads;
         P.fld_part0 = nparts;
         P.fld_nparts = P.fld_tiles_x * ((P.ny + kFieldRows - 1) / kFieldRows);
@@ -383,7 +390,7 @@ int setup_correlators(flb_t *h)
     h->cols_cb = std::max(1, std::min(16, 8192 / max_my_general));
     h->cols_lds = max_my_general * h->cols_cb * (int)sizeof(float2);
 
-    std::vector<CorrItem> rows, cols, accum, cols_a, cols_b, flds;
+    std::vector<CorrItem> rows, cols, accum, cols_a, cols_b, flds, cols_a_m, cols_m;
     for (size_t l = 0; l < h->params.size(); ++l) {
         const LatticeParams &P = h->params[l];
         for (int t = 0; t < P.fld_nparts; ++t)
@@ -399,16 +406,20 @@ int setup_correlators(flb_t *h)
         if (P.col_pow2) {
             const int Pn = 1 << P.col_lgp;
             if (Pn > 1)
-                for (int f = 0; f < kFields; ++f)
+                for (int f = 0; f < h->nfld; ++f)
                     for (int c0 = 0; c0 < P.kxp; c0 += 16)
-                        for (int q0 = 0; q0 < P.col_q; q0 += P.col_nq)
-                            cols_a.push_back({(int32_t)l, f, c0, q0});
+                        for (int q0 = 0; q0 < P.col_q; q0 += P.col_nq) {
+                            if (f < kFields) cols_a.push_back({(int32_t)l, f, c0, q0});
+                            cols_a_m.push_back({(int32_t)l, f, c0, q0});
+                        }
             for (int c0 = 0; c0 < P.kxp; c0 += 16)
                 for (int k1 = 0; k1 < Pn; ++k1) cols_b.push_back({(int32_t)l, c0, k1, 0});
         } else {
-            for (int f = 0; f < kFields; ++f)
-                for (int c0 = 0; c0 < P.nkx; c0 += h->cols_cb)
-                    cols.push_back({(int32_t)l, f, c0, 0});
+            for (int f = 0; f < h->nfld; ++f)
+                for (int c0 = 0; c0 < P.nkx; c0 += h->cols_cb) {
+                    if (f < kFields) cols.push_back({(int32_t)l, f, c0, 0});
+                    cols_m.push_back({(int32_t)l, f, c0, 0});
+                }
             const int64_t nk = (int64_t)P.ny * P.nkx;
             for (int64_t k0 = 0; k0 < nk; k0 += kThreads)
                 accum.push_back({(int32_t)l, (int32_t)k0, 0, 0});
@@ -420,6 +431,15 @@ int setup_correlators(flb_t *h)
     cols_a = xcd_order(cols_a, idle);
     cols_b = xcd_order(cols_b, idle);
     cols = xcd_order(cols, idle);
+    if (h->moments) {
+        cols_a_m = xcd_order(cols_a_m, idle);
+        cols_m = xcd_order(cols_m, idle);
+    } else {
+        cols_a_m.clear();
+        cols_m.clear();
+    }
+    h->n_cols_a_m = (int)cols_a_m.size();
+    h->n_cols_m = (int)cols_m.size();
     h->n_rows = (int)rows.size();
     h->n_cols = (int)cols.size();
     h->n_accum = (int)accum.size();
@@ -430,7 +450,8 @@ int setup_correlators(flb_t *h)
     if ((rc = upload(&h->d_fld, flds)) || (rc = upload(&h->d_rows, rows)) ||
         (rc = upload(&h->d_cols, cols)) ||
         (rc = upload(&h->d_accum, accum)) || (rc = upload(&h->d_cols_a, cols_a)) ||
-        (rc = upload(&h->d_cols_b, cols_b)) || (rc = upload(&h->d_plans, h->plans)) ||
+        (rc = upload(&h->d_cols_b, cols_b)) || (rc = upload(&h->d_cols_a_m, cols_a_m)) ||
+        (rc = upload(&h->d_cols_m, cols_m)) || (rc = upload(&h->d_plans, h->plans)) ||
         (rc = upload(&h->d_tables, tables)) || (rc = upload(&h->d_params, h->params)))
         return rc;
     FLB_HIP(hipMalloc((void **)&h->d_spec, spec * sizeof(float2)));
@@ -449,12 +470,20 @@ int setup_correlators(flb_t *h)
 int enqueue_sample(flb_t *h, hipStream_t s)
 {
     const DeviceView v = h->view();
-    FLB_HIP(launch_corr_fields(v, h->d_fld, h->n_fld, s));
-    FLB_HIP(launch_corr_rows(v, h->d_rows, h->n_rows, h->rows_lds, s));
-    if (h->n_cols_a) FLB_HIP(launch_corr_cols_a(v, h->d_cols_a, h->n_cols_a, h->cols_a_lds, s));
-    if (h->n_cols_b) FLB_HIP(launch_corr_cols_b(v, h->d_cols_b, h->n_cols_b, h->cols_b_lds, s));
-    if (h->n_cols) FLB_HIP(launch_corr_cols(v, h->d_cols, h->n_cols, h->cols_cb, h->cols_lds, s));
-    if (h->n_accum) FLB_HIP(launch_corr_accum(v, h->d_accum, h->n_accum, s));
+    for (int set = 0; set < (h->moments ? 2 : 1); ++set) {
+        // the moment set reuses the field and spectrum buffers after set 0
+        const CorrItem *ca = set ? h->d_cols_a_m : h->d_cols_a;
+        const CorrItem *cg = set ? h->d_cols_m : h->d_cols;
+        const int na = set ? h->n_cols_a_m : h->n_cols_a;
+        const int ng = set ? h->n_cols_m : h->n_cols;
+        FLB_HIP(launch_corr_fields(v, h->d_fld, h->n_fld, set, s));
+        FLB_HIP(launch_corr_rows(v, h->d_rows, h->n_rows, set, h->rows_lds, s));
+        if (na) FLB_HIP(launch_corr_cols_a(v, ca, na, h->cols_a_lds, s));
+        if (h->n_cols_b)
+            FLB_HIP(launch_corr_cols_b(v, h->d_cols_b, h->n_cols_b, set, h->cols_b_lds, s));
+        if (ng) FLB_HIP(launch_corr_cols(v, cg, ng, h->cols_cb, h->cols_lds, s));
+        if (h->n_accum) FLB_HIP(launch_corr_accum(v, h->d_accum, h->n_accum, set, s));
+    }
     return FLB_OK;
 }
 
@@ -490,7 +519,7 @@ flb_t *create_impl(int n, const flb_lattice_spec *specs, uint64_t seed, int stor
         fail(FLB_EINVAL, "unknown storage format");
         return nullptr;
     }
-    if (flags & ~FLB_FLAG_NO_GHOST_NOISE) {
+    if (flags & ~(FLB_FLAG_NO_GHOST_NOISE | FLB_FLAG_MOMENT_SPECTRA)) {
         fail(FLB_EINVAL, "unknown flags");
         return nullptr;
     }
@@ -501,6 +530,9 @@ flb_t *create_impl(int n, const flb_lattice_spec *specs, uint64_t seed, int stor
     h->storage = storage;
     h->elem_bytes = storage == FLB_STORAGE_F32 ? 4 : 2;
     h->flags = flags;
+    h->moments = (flags & FLB_FLAG_MOMENT_SPECTRA) != 0;
+    h->nkinds = h->moments ? FLB_NKINDS_MOMENTS : FLB_NKINDS;
+    h->nfld = h->moments ? kMomentFields : kFields;
     h->seed = seed;
     h->specs.assign(specs, specs + n);
     int64_t off = 0;
@@ -630,7 +662,7 @@ void flb_destroy(flb_t *h)
     void *ptrs[] = {h->pops[0], h->d_params, h->d_step, h->d_red, h->d_items,
                     h->d_plans, h->d_tables, h->d_spec, h->d_acc, h->d_rows, h->d_cols,
                     h->d_accum, h->d_cols_a, h->d_cols_b, h->d_fld, h->d_fields,
-                    h->d_csum_part, h->d_csum};
+                    h->d_csum_part, h->d_csum, h->d_cols_a_m, h->d_cols_m};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->ev) (void)hipEventDestroy(h->ev);
@@ -751,13 +783,13 @@ int flb_read_correlators(flb_t *h, int lattice, double *out, size_t n_doubles, i
     int rc = setup_correlators(h);
     if (rc) return rc;
     const LatticeParams &P = h->params[lattice];
-    const size_t need = (size_t)kKinds * P.ny * P.nkx;
+    const size_t need = (size_t)h->nkinds * P.ny * P.nkx;
     if (n_doubles < need) return fail(FLB_ESIZE, "output buffer too small for the correlators");
     FLB_HIP(hipStreamSynchronize(h->stream));
     // device rows have pitch kxp >= nkx
     FLB_HIP(hipMemcpy2D(out, (size_t)P.nkx * sizeof(double), h->d_acc + P.acc_base,
                         (size_t)P.kxp * sizeof(double), (size_t)P.nkx * sizeof(double),
-                        (size_t)kKinds * P.ny, hipMemcpyDeviceToHost));
+                        (size_t)h->nkinds * P.ny, hipMemcpyDeviceToHost));
     if (nsamples) *nsamples = h->nsamples;
     return FLB_OK;
 }
@@ -898,6 +930,12 @@ int flb_set_step(flb_t *h, int64_t t)
     FLB_HIP(hipMemcpy(h->d_step, &v, sizeof v, hipMemcpyHostToDevice));
     h->t = t;
     return FLB_OK;
+}
+
+int flb_num_kinds(flb_t *h)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    return h->nkinds;
 }
 
 int flb_num_lattices(flb_t *h)

@@ -88,6 +88,7 @@ def _create(flb, nx=8, ny=8, tau=None, theta=1e-4, rho0=1.0, u0=(0.0, 0.0), stor
     (dict(u0=(float("nan"), 0.0)), "u0"),
     (dict(storage=7), "storage"),
     (dict(flags=8), "flags"),
+    (dict(flags=4), "flags"),
     (dict(nx=100000, ny=100000), "4 GiB"),
     (dict(nx=11000, ny=11000), "4 GiB"),
 ])
@@ -101,6 +102,8 @@ def test_null_handle_calls_fail_cleanly(flb):
     L = flb.lib()
     assert L.flb_step(None, 1) == flb.EINVAL
     assert L.flb_num_lattices(None) == -1
+    assert L.flb_num_kinds(None) == flb.EINVAL
+    assert L.flb_set_step(None, 0) == flb.EINVAL
     assert "NULL" in flb.last_error()
     L.flb_destroy(None)
 

@@ -184,3 +184,57 @@ def test_sample_records_conservation_sums(flb, oracle_lib):
     cs = g.sample_conservation()
     assert np.abs(cs - g.conservation()).max() < 1e-5
     assert np.abs(cs - o.conservation()).max() < 1e-5
+
+
+@pytest.mark.parametrize("nx,ny", [(32, 32), (24, 18), (37, 23), (128, 96), (256, 128), (2, 2)])
+def test_moment_spectra_match_oracle(flb, oracle_lib, nx, ny):
+    """Kinds 15..20 (|M^a_k|^2, a = 3..8) of one sample against the oracle;
+    the first fifteen kinds are unchanged by the extra field set."""
+    note("moments", nx, ny)
+    kw = dict(u0=(0.03, 0.01), seed=6)
+    g = flb.Lattice(nx, ny, TAU_C1, 1e-4, moments=True, **kw)
+    h = flb.Lattice(nx, ny, TAU_C1, 1e-4, **kw)
+    o = oracle_lib.Lattice(nx, ny, TAU_C1, 1e-4, moments=True, **kw)
+    for L in (g, h, o):
+        L.thermalize()
+        L.step(5)
+    g.accumulate()
+    h.accumulate()
+    o.sample()
+    acc, ns = g.read_correlators()
+    assert ns == 1 and acc.shape[0] == flb.NKINDS_MOMENTS == g.nkinds
+    assert np.array_equal(acc[:15], h.read_correlators()[0])
+    assert np.all(acc[15:, 0, 0] == 0)
+    scale = np.abs(o.acc_m).reshape(6, -1).max(axis=1)
+    for a in range(6):
+        d = np.abs(acc[15 + a] - o.acc_m[a]).max()
+        assert d <= 2e-4 * scale.max(), (a, d, scale[a])
+
+
+def test_moment_spectra_paired_run_and_batch(flb, oracle_lib):
+    """Paired 2000-step run with a sample every 10 steps, and a batch of two
+    lattices of different shapes, with the moment spectra on."""
+    c = workloads.CONFIGS["c1_32"]
+    g = flb.Lattice(32, 32, c["tau"], c["theta"], seed=c["seed"], moments=True)
+    o = oracle_lib.Lattice(32, 32, c["tau"], c["theta"], seed=c["seed"], moments=True)
+    g.thermalize()
+    o.thermalize()
+    g.run(2000, 10)
+    o.run(2000, 10)
+    acc, ns = g.read_correlators()
+    assert ns == o.nsamples == 200
+    _compare(acc[:15], o.acc, 1e-3)
+    d = np.abs(acc[15:] - o.acc_m).max()
+    assert d <= 1e-3 * np.abs(o.acc_m).max()
+
+    specs = [dict(nx=32, ny=16, tau=TAU_C1, theta=1e-4, stream_id=0),
+             dict(nx=20, ny=12, tau=TAU_C1, theta=1e-4, u0=(0.05, 0.0), stream_id=1)]
+    b = flb.Lattice.batch(specs, seed=2, moments=True)
+    b.thermalize()
+    b.run(100, 10)
+    for i, s in enumerate(specs):
+        one = flb.Lattice(s["nx"], s["ny"], s["tau"], s["theta"], u0=s.get("u0", (0, 0)),
+                          seed=2, stream_id=s["stream_id"], moments=True)
+        one.thermalize()
+        one.run(100, 10)
+        assert np.array_equal(b.read_correlators(i)[0], one.read_correlators()[0])
