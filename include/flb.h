@@ -239,7 +239,9 @@ int flb_storage_info(flb_t *h, int32_t *storage, int32_t *bytes_per_value);
 /* Launch shape of the step kernel: blocks of tile_w threads along x (64,
  * 128 or 256) by 256/tile_w rows, each thread updating `sites` consecutive
  * sites of its row (1, 2 or 4) with one vector access per population, and
- * streaming (non-temporal) stores on or off.  Results do not depend on it.
+ * the streaming (non-temporal) hint on or off for those accesses (all
+ * stores, and the loads of each thread's own sites).  Results do not depend
+ * on it.
  * FLB_EINVAL for an unsupported shape. */
 int flb_set_step_config(flb_t *h, int tile_w, int sites, int nontemporal);
 int flb_get_step_config(flb_t *h, int *tile_w, int *sites, int *nontemporal);

@@ -83,13 +83,20 @@ template <> struct Codec<kF16> {
     }
 };
 
-// Plain or streaming (non-temporal) global stores.
+// Plain or streaming (non-temporal) global stores and loads.
 template <bool NT, typename T> __device__ __forceinline__ void gstore(T *p, T v)
 {
     if constexpr (NT)
         __builtin_nontemporal_store(v, p);
     else
         *p = v;
+}
+template <bool NT, typename T> __device__ __forceinline__ T gload(const T *p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
 }
 
 // D2Q9 velocities in the order of Sec. 3.

@@ -545,11 +545,13 @@ flb_t *create_impl(int n, const flb_lattice_spec *specs, uint64_t seed, int stor
         h->params.push_back(P);
     }
     h->total_elems = off;
-    // streaming stores pay off once a buffer no longer fits the last-level cache
+    // streaming accesses pay off once a buffer no longer fits the last-level
+    // cache
     h->nontemporal = (double)off * h->elem_bytes > 256.0 * 1024 * 1024;
     // measured on MI355X at 4096^2: FP32 is best with one site per thread
-    // (scalar accesses spread the 18 streams best), 16-bit storage with four
-    // (the ALU-bound form profits from fewer address computations)
+    // (scalar accesses spread the 18 streams best; with the streaming hint
+    // 77.9 GLUPS against at most 75.9 for other shapes), 16-bit storage with
+    // four (the ALU-bound form profits from fewer address computations)
     if (h->elem_bytes == 2) {
         h->tile_w = 128;
         h->sites = 4;

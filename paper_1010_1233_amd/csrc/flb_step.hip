@@ -163,16 +163,19 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs g)
 
     if (x0 + V <= nx) {
         const uint32_t xr = (x0 + V == nx) ? 0u : (uint32_t)(x0 + V);  // right of the group
-        // pull: population i arrives from x - v_i
-        const VT a0 = *at<VT>(src, rc + ux0);
-        const VT a1 = *at<VT>(src, 1 * plane + rc + ux0);
-        const VT a2 = *at<VT>(src, 2 * plane + rm + ux0);
-        const VT a3 = *at<VT>(src, 3 * plane + rc + ux0);
-        const VT a4 = *at<VT>(src, 4 * plane + rp + ux0);
-        const VT a5 = *at<VT>(src, 5 * plane + rm + ux0);
-        const VT a6 = *at<VT>(src, 6 * plane + rm + ux0);
-        const VT a7 = *at<VT>(src, 7 * plane + rp + ux0);
-        const VT a8 = *at<VT>(src, 8 * plane + rp + ux0);
+        // pull: population i arrives from x - v_i.  With streaming stores the
+        // group's own values are read with the non-temporal hint too; the
+        // edge values stay ordinary loads, as their lines are shared with the
+        // neighbouring groups.
+        const VT a0 = gload<NT>(at<VT>(src, rc + ux0));
+        const VT a1 = gload<NT>(at<VT>(src, 1 * plane + rc + ux0));
+        const VT a2 = gload<NT>(at<VT>(src, 2 * plane + rm + ux0));
+        const VT a3 = gload<NT>(at<VT>(src, 3 * plane + rc + ux0));
+        const VT a4 = gload<NT>(at<VT>(src, 4 * plane + rp + ux0));
+        const VT a5 = gload<NT>(at<VT>(src, 5 * plane + rm + ux0));
+        const VT a6 = gload<NT>(at<VT>(src, 6 * plane + rm + ux0));
+        const VT a7 = gload<NT>(at<VT>(src, 7 * plane + rp + ux0));
+        const VT a8 = gload<NT>(at<VT>(src, 8 * plane + rp + ux0));
         const T e1 = *at<T>(src, 1 * plane + rc + xm), e5 = *at<T>(src, 5 * plane + rm + xm);
         const T e8 = *at<T>(src, 8 * plane + rp + xm);
         const T e3 = *at<T>(src, 3 * plane + rc + xr), e6 = *at<T>(src, 6 * plane + rm + xr);
