@@ -8,10 +8,13 @@
 // a large mean.
 //
 // Per sample:
-//   rows   one block per group of rows gathers the state once, keeps the five
-//          fields in registers and transforms three packed complex lines per
-//          row (jx + i jy, ux + i uy, rho) along x through one LDS buffer;
-//          it writes the half spectra kx = 0..nx/2 of the five real fields.
+//   rows   one block per group of rows gathers the state once, keeps rho and
+//          j of its sites in registers and transforms three packed complex
+//          lines per row (jx + i jy, ux + i uy, rho) along x through one LDS
+//          buffer; it writes the half spectra kx = 0..nx/2 of the five real
+//          fields and the FP64 conservation partials of its rows.  (The
+//          optional moment set goes through FP32 field planes and a separate
+//          row kernel.)
 //   columns, power-of-two ny = P*Q (Q <= 64): pass A transforms the P-long
 //          strided columns (rows q, q+Q, ...) and applies the twiddles;
 //          pass B transforms Q consecutive rows of all five fields and adds
@@ -151,7 +154,7 @@ __device__ __forceinline__ void dit_pass(float2 *buf, int lg, int s, int nlines,
 
 // In-place transform of lines given in bit-reversed order; natural order out.
 template <bool PAD, bool INV>
-__device__ void lds_fft_dit(float2 *buf, int lg, int nlines, int ls, int es, const float2 *tw)
+__device__ __forceinline__ void lds_fft_dit(float2 *buf, int lg, int nlines, int ls, int es, const float2 *tw)
 {
     int s = 1;
     while (s <= lg) {
@@ -171,7 +174,7 @@ __device__ void lds_fft_dit(float2 *buf, int lg, int nlines, int ls, int es, con
 }
 
 template <bool PAD>
-__device__ void lds_bitrev(float2 *buf, int lg, int nlines, int ls, int es)
+__device__ __forceinline__ void lds_bitrev(float2 *buf, int lg, int nlines, int ls, int es)
 {
     const int m = 1 << lg;
     for (int idx = threadIdx.x; idx < nlines * m; idx += blockDim.x) {
@@ -191,7 +194,7 @@ __device__ void lds_bitrev(float2 *buf, int lg, int nlines, int ls, int es)
 // (already multiplied by the chirp for Bluestein lengths), in place; on exit
 // element k < n holds X_k in natural order.
 template <bool PAD>
-__device__ void lds_line_dft(float2 *buf, const LinePlan &L, int nlines, int ls, int es,
+__device__ __forceinline__ void lds_line_dft(float2 *buf, const LinePlan &L, int nlines, int ls, int es,
                              const float2 *tables)
 {
     const float2 *tw = tables;
@@ -216,6 +219,10 @@ __device__ void lds_line_dft(float2 *buf, const LinePlan &L, int nlines, int ls,
 }
 
 constexpr int kFftThreads = 512;  // threads of the transform kernels
+// Global loads of the transform kernels are issued kBatch per thread before
+// any of them is used, so that each thread keeps several requests in flight
+// (one load per loop iteration leaves the kernels latency-bound).
+constexpr int kBatch = 8;
 
 struct CorrArgs {
     const void *pops;
@@ -224,6 +231,7 @@ struct CorrArgs {
     const float2 *tables;
     const CorrItem *items;
     float2 *spec;
+    float2 *stash;  // spectra of a sample whose products are not yet added
     double *acc;
     float *fields;
     double *csum_part;
@@ -231,10 +239,11 @@ struct CorrArgs {
     int set;  // field set: 0 = rho, j, u; 1 = moments 3..8
 };
 
-// Block sum of five doubles into out[0..4] (deterministic order).
-__device__ __forceinline__ void block_sum5(double (&v)[5], double *out)
+// Block sum of five doubles into out[0..4] (deterministic order), for
+// blocks of NT threads.
+template <int NT> __device__ __forceinline__ void block_sum5(double (&v)[5], double *out)
 {
-    __shared__ double red[5][kThreads / 64];
+    __shared__ double red[5][NT / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
@@ -246,7 +255,7 @@ __device__ __forceinline__ void block_sum5(double (&v)[5], double *out)
     __syncthreads();
     if (threadIdx.x < 5) {
         double x = 0;
-        for (int w = 0; w < kThreads / 64; ++w) x += red[threadIdx.x][w];
+        for (int w = 0; w < NT / 64; ++w) x += red[threadIdx.x][w];
         out[threadIdx.x] = x;
     }
 }
@@ -272,25 +281,6 @@ __device__ __forceinline__ void pull_site(const typename Codec<S>::T *p, const L
     d[8] = Codec<S>::decode(p[8 * plane + rp + xm], P, 8);
 }
 
-// Fluctuation fields at site (x, y) of the current state.
-template <int S>
-__device__ __forceinline__ void site_fields(const typename Codec<S>::T *p, const LatticeParams &P,
-                                            int x, int y, float &drho, float &djx, float &djy,
-                                            float &dux, float &duy)
-{
-    float d[9];
-    pull_site<S>(p, P, x, y, d);
-    const float r = d[0] + (d[1] + d[3]) + (d[2] + d[4]) + (d[5] + d[7]) + (d[6] + d[8]);
-    const float jx = (d[1] - d[3]) + (d[5] - d[7]) - (d[6] - d[8]);
-    const float jy = (d[2] - d[4]) + (d[5] - d[7]) + (d[6] - d[8]);
-    const float ir = 1.0f / (P.rho0 + r);
-    drho = r;
-    djx = jx - P.rho0 * P.u0x;
-    djy = jy - P.rho0 * P.u0y;
-    dux = jx * ir - P.u0x;
-    duy = jy * ir - P.u0y;
-}
-
 // Non-conserved moments M^3..M^8 (rows of Eq. 9) at site (x, y).  The rows
 // are orthogonal to M^0 under the weights, so the moments of the deviations
 // are the moments themselves.
@@ -312,60 +302,124 @@ __device__ __forceinline__ void site_moments(const typename Codec<S>::T *p,
     M[5] = fmaf(0.5f, d[0], fmaf(2.0f, diag, -axis));
 }
 
-// Fluctuation fields of the current state, one thread per column of a tile
-// of 256 sites x kFieldRows rows, written as FP32 planes [nf][ny][nx].
-// SET 0: d rho, d jx, d jy, d ux, d uy, together with the FP64 conservation
-// sums of the same state (mass, momentum, staggered momenta) as per-block
-// partials.  SET 1: the six non-conserved moments.
-// item: lattice, tile, index of the block's partial.
-template <int S, int SET>
-__global__ __launch_bounds__(kThreads) void corr_fields_kernel(CorrArgs g)
+// Writes the packed half spectra of one group of transformed lines: for the
+// pair z = a + i b of two real sequences, a_k = (z_k + conj z_{-k}) / 2 and
+// b_k = (z_k - conj z_{-k}) / (2i) go to fields fa and fa + 1; a single real
+// sequence (pair false) goes to field fa as is.  kx = 0..nx/2, padding
+// columns up to kxp zeroed.
+__device__ __forceinline__ void store_row_spectra(const float2 *lds, const LatticeParams &P,
+                                                  float2 *spec, int y0, int nl, int m, int fa,
+                                                  bool pair)
+{
+    const int nx = P.nx, nkx = P.nkx, kxp = P.kxp;
+    const int64_t fstride = (int64_t)P.ny * kxp;
+    float2 *sa = spec + fa * fstride, *sb = sa + fstride;
+    for (int e = threadIdx.x; e < nl * kxp; e += kFftThreads) {
+        const int l = e / kxp, k = e - l * kxp;
+        const int64_t row = (int64_t)(y0 + l) * kxp + k;
+        if (k >= nkx) {  // padding columns: keep them finite
+            sa[row] = make_float2(0.f, 0.f);
+            if (pair) sb[row] = make_float2(0.f, 0.f);
+            continue;
+        }
+        const float2 zk = lds[lds_slot<true>(l * m + k)];
+        if (!pair) {
+            sa[row] = zk;
+        } else {
+            const float2 zm = lds[lds_slot<true>(l * m + (k == 0 ? 0 : nx - k))];
+            sa[row] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+            sb[row] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+        }
+    }
+}
+
+// Field set 0, fields and row transforms in one pass: a block takes a group
+// of rows (nl * m <= 4096 line elements), gathers the state of its sites once
+// (pull along each velocity, Eq. 1), keeps rho - rho0 and j in registers and
+// transforms three packed lines through one LDS buffer: jx + i jy and
+// ux + i uy of the fluctuations d j = j - rho0 u0, d u = j / rho - u0, then
+// rho - rho0 alone.  It also writes the FP64 conservation sums of its rows
+// (mass, momentum, staggered momenta) as one partial.  BLUE: the lattice's
+// rows use Bluestein's transform (other lengths than powers of two); the two
+// cases are separate instantiations so that the power-of-two one carries no
+// chirp state in registers.
+// item: lattice, first row, rows, index of the block's partial.
+template <int S, bool BLUE>
+__global__ __launch_bounds__(kFftThreads) void corr_rows_kernel(CorrArgs g)
 {
     using T = typename Codec<S>::T;
+    constexpr int E = 4096 / kFftThreads;  // line elements per thread
+    extern __shared__ float2 lds[];
     const CorrItem it = g.items[blockIdx.x];
     if (it.lattice < 0) return;
     const LatticeParams &P = g.params[it.lattice];
-    const int nx = P.nx, ny = P.ny;
-    const int tx = it.a % P.fld_tiles_x, ty = it.a / P.fld_tiles_x;
-    const int x = tx * kThreads + (int)threadIdx.x;
+    const LinePlan &L = g.plans[P.line_x];
+    const int nx = P.nx;
+    const int y0 = it.a, nl = min(it.b, P.ny - y0);
+    const int m = L.m, lg = L.log2m, ne = nl * m;
     const T *p = (const T *)g.pops + P.base;
-    const int64_t fs = (int64_t)nx * ny;
-    const int y1 = min(ny, (ty + 1) * kFieldRows);
-    if constexpr (SET == 1) {
-        if (x >= nx) return;
-        for (int y = ty * kFieldRows; y < y1; ++y) {
-            float M[6];
-            site_moments<S>(p, P, x, y, M);
-            float *f = g.fields + P.fld_base + (int64_t)y * nx + x;
-#pragma unroll
-            for (int q = 0; q < 6; ++q) f[q * fs] = M[q];
-        }
-        return;
-    }
+
+    float r[E], jx[E], jy[E];
     double acc[5] = {0, 0, 0, 0, 0};
-    if (x < nx) {
-        for (int y = ty * kFieldRows; y < y1; ++y) {
-            float dr, jx, jy, ux, uy;
-            site_fields<S>(p, P, x, y, dr, jx, jy, ux, uy);
-            float *f = g.fields + P.fld_base + (int64_t)y * nx + x;
-            f[0] = dr;
-            f[fs] = jx;
-            f[2 * fs] = jy;
-            f[3 * fs] = ux;
-            f[4 * fs] = uy;
-            const double Jx = (double)jx + (double)P.rho0 * (double)P.u0x;
-            const double Jy = (double)jy + (double)P.rho0 * (double)P.u0y;
-            acc[0] += dr;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int e = (int)threadIdx.x + j * kFftThreads, l = e >> lg, x = e & (m - 1);
+        r[j] = jx[j] = jy[j] = 0.f;
+        if (e < ne && x < nx) {
+            float d[9];
+            pull_site<S>(p, P, x, y0 + l, d);
+            r[j] = d[0] + (d[1] + d[3]) + (d[2] + d[4]) + (d[5] + d[7]) + (d[6] + d[8]);
+            jx[j] = (d[1] - d[3]) + (d[5] - d[7]) - (d[6] - d[8]);
+            jy[j] = (d[2] - d[4]) + (d[5] - d[7]) + (d[6] - d[8]);
+            const double Jx = jx[j], Jy = jy[j];
+            acc[0] += r[j];
             acc[1] += Jx;
             acc[2] += Jy;
             acc[3] += (x & 1) ? -Jx : Jx;
-            acc[4] += (y & 1) ? -Jy : Jy;
+            acc[4] += ((y0 + l) & 1) ? -Jy : Jy;
         }
     }
-    block_sum5(acc, g.csum_part + 5 * (int64_t)it.b);
+    block_sum5<kFftThreads>(acc, g.csum_part + 5 * (int64_t)it.c);
+
+    const float2 *chirp = g.tables + L.chirp_off;
+    float2 *spec = g.spec + P.spec_base;
+    const float jx0 = P.rho0 * P.u0x, jy0 = P.rho0 * P.u0y;
+#pragma unroll 1
+    for (int sig = 0; sig < 3; ++sig) {
+        // (the block sum and every earlier signal's reads of LDS are behind a
+        // barrier before the lines are written)
+        __syncthreads();
+        // the line indices are recomputed for every signal rather than kept
+        // in registers through the transforms
+        int tid = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid));
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int e = tid + j * kFftThreads, l = e >> lg, x = e & (m - 1);
+            if (e >= ne) break;
+            float2 v = make_float2(0.f, 0.f);
+            if (x < nx) {
+                if (sig == 0) {
+                    v = make_float2(jx[j] - jx0, jy[j] - jy0);
+                } else if (sig == 1) {
+                    const float ir = 1.0f / (P.rho0 + r[j]);
+                    v = make_float2(jx[j] * ir - P.u0x, jy[j] * ir - P.u0y);
+                } else {
+                    v.x = r[j];
+                }
+                if (BLUE) v = cmul(v, chirp[x]);
+            }
+            lds[lds_slot<true>(l * m + bitrev(x, lg))] = v;
+        }
+        __syncthreads();
+        if (BLUE) lds_line_dft<true>(lds, L, nl, m, 1, g.tables);
+        else lds_fft_dit<true, false>(lds, lg, nl, m, 1, g.tables);
+        // spectra: 1, 2 = jx, jy; 3, 4 = ux, uy; 0 = rho
+        store_row_spectra(lds, P, spec, y0, nl, m, sig == 0 ? 1 : sig == 1 ? 3 : 0, sig != 2);
+    }
 }
 
-// Sums each lattice's field-kernel partials into its five conservation sums.
+// Sums each lattice's row-kernel partials into its five conservation sums.
 __global__ __launch_bounds__(kThreads) void corr_csum_kernel(CorrArgs g, int nlat)
 {
     const int l = blockIdx.x;
@@ -375,68 +429,78 @@ __global__ __launch_bounds__(kThreads) void corr_csum_kernel(CorrArgs g, int nla
     for (int b = threadIdx.x; b < P.fld_nparts; b += kThreads)
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc[q] += g.csum_part[5 * ((int64_t)P.fld_part0 + b) + q];
-    block_sum5(acc, g.csum + 5 * (int64_t)l);
+    block_sum5<kThreads>(acc, g.csum + 5 * (int64_t)l);
 }
 
-// Row transforms of the fields: one block per (lattice, group of rows,
-// signal).  Set 0: signal 0 packs jx + i jy, 1 ux + i uy, 2 rho alone; set 1:
-// signal s packs M^(3+2s) + i M^(4+2s).  Writes the half spectra
-// kx = 0..nx/2 of the real fields.
+// Field set 1: the six non-conserved moments of the current state as FP32
+// planes [6][ny][nx], one thread per column of a tile of 256 sites x
+// kFieldRows rows.  item: lattice, tile.
+template <int S>
+__global__ __launch_bounds__(kThreads) void corr_moment_fields_kernel(CorrArgs g)
+{
+    using T = typename Codec<S>::T;
+    const CorrItem it = g.items[blockIdx.x];
+    if (it.lattice < 0) return;
+    const LatticeParams &P = g.params[it.lattice];
+    const int nx = P.nx, ny = P.ny;
+    const int tx = it.a % P.fld_tiles_x, ty = it.a / P.fld_tiles_x;
+    const int x = tx * kThreads + (int)threadIdx.x;
+    if (x >= nx) return;
+    const T *p = (const T *)g.pops + P.base;
+    const int64_t fs = (int64_t)nx * ny;
+    const int y1 = min(ny, (ty + 1) * kFieldRows);
+    for (int y = ty * kFieldRows; y < y1; ++y) {
+        float M[6];
+        site_moments<S>(p, P, x, y, M);
+        float *f = g.fields + P.fld_base + (int64_t)y * nx + x;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) f[q * fs] = M[q];
+    }
+}
+
+// Field set 1, row transforms: one block per (lattice, group of rows,
+// signal s), s packing M^(3+2s) + i M^(4+2s).
 // item: lattice, first row, rows in this block, signal
-__global__ __launch_bounds__(kFftThreads) void corr_rowfft_kernel(CorrArgs g)
+__global__ __launch_bounds__(kFftThreads) void corr_moment_rows_kernel(CorrArgs g)
 {
     extern __shared__ float2 lds[];
     const CorrItem it = g.items[blockIdx.x];
     if (it.lattice < 0) return;
     const LatticeParams &P = g.params[it.lattice];
     const LinePlan &L = g.plans[P.line_x];
-    const int nx = P.nx, ny = P.ny, nkx = P.nkx, kxp = P.kxp;
-    const int y0 = it.a, nl = min(it.b, ny - y0), sig = it.c;
+    const int nx = P.nx, ny = P.ny;
+    const int y0 = it.a, nl = min(it.b, ny - y0), fa = 2 * it.c;
     const int m = L.m, lg = L.log2m;
     const float2 *chirp = g.tables + L.chirp_off;
     const int64_t fs = (int64_t)nx * ny;
-    // field pair (fa, fa + 1), or fa alone for rho
-    const int fa = g.set ? 2 * sig : (sig == 0 ? 1 : sig == 1 ? 3 : 0);
-    const bool pair = g.set || sig != 2;
     const float *fa_p = g.fields + P.fld_base + fa * fs;
     const float *fb_p = fa_p + fs;
 
-    for (int e = threadIdx.x; e < nl * m; e += kFftThreads) {
-        const int l = e >> lg, x = e & (m - 1);
-        float2 v = make_float2(0.f, 0.f);
-        if (x < nx) {
-            const int64_t o = (int64_t)(y0 + l) * nx + x;
-            v.x = fa_p[o];
-            if (pair) v.y = fb_p[o];
-            if (L.bluestein) v = cmul(v, chirp[x]);
+    const int ne = nl * m;
+    for (int e0 = threadIdx.x; e0 < ne; e0 += kBatch * kFftThreads) {
+        float va[kBatch], vb[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int e = e0 + j * kFftThreads, l = e >> lg, x = e & (m - 1);
+            va[j] = vb[j] = 0.f;
+            if (e < ne && x < nx) {
+                const int64_t o = (int64_t)(y0 + l) * nx + x;
+                va[j] = fa_p[o];
+                vb[j] = fb_p[o];
+            }
         }
-        lds[lds_slot<true>(l * m + bitrev(x, lg))] = v;
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int e = e0 + j * kFftThreads, l = e >> lg, x = e & (m - 1);
+            if (e >= ne) break;
+            float2 v = make_float2(va[j], vb[j]);
+            if (L.bluestein && x < nx) v = cmul(v, chirp[x]);
+            lds[lds_slot<true>(l * m + bitrev(x, lg))] = v;
+        }
     }
     __syncthreads();
     lds_line_dft<true>(lds, L, nl, m, 1, g.tables);
-
-    // two real sequences a, b packed as z = a + i b:
-    // a_k = (z_k + conj z_{-k}) / 2, b_k = (z_k - conj z_{-k}) / (2i)
-    float2 *spec = g.spec + P.spec_base;
-    const int64_t fstride = (int64_t)ny * kxp;
-    const int fb = fa + 1;
-    for (int e = threadIdx.x; e < nl * kxp; e += kFftThreads) {
-        const int l = e / kxp, k = e - l * kxp;
-        const int64_t row = (int64_t)(y0 + l) * kxp + k;
-        if (k >= nkx) {  // padding columns: keep them finite
-            spec[fa * fstride + row] = make_float2(0.f, 0.f);
-            if (pair) spec[fb * fstride + row] = make_float2(0.f, 0.f);
-            continue;
-        }
-        const float2 zk = lds[lds_slot<true>(l * m + k)];
-        if (!pair) {
-            spec[fa * fstride + row] = zk;
-        } else {
-            const float2 zm = lds[lds_slot<true>(l * m + (k == 0 ? 0 : nx - k))];
-            spec[fa * fstride + row] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-            spec[fb * fstride + row] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
-        }
-    }
+    store_row_spectra(lds, P, g.spec + P.spec_base, y0, nl, m, fa, true);
 }
 
 // Power-of-two ny = P*Q, pass A.  item: lattice, field, first column, first q.
@@ -451,24 +515,41 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_a_kernel(CorrArgs g)
     const int lgP = P.col_lgp, Pn = 1 << lgP, Q = P.col_q, kxp = P.kxp;
     const int NL = P.col_nq * 16;
     float2 *col = g.spec + P.spec_base + (int64_t)f * P.ny * kxp + c0;
-    for (int idx = threadIdx.x; idx < Pn * NL; idx += kFftThreads) {
-        const int pp = idx / NL, r = idx - pp * NL;
-        const int ql = r >> 4, c = r & 15;
-        lds[bitrev(pp, lgP) * NL + r] = col[(int64_t)(q0 + ql + Q * pp) * kxp + c];
+    const int ne = Pn * NL;
+    for (int i0 = threadIdx.x; i0 < ne; i0 += kBatch * kFftThreads) {
+        float2 v[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int idx = i0 + j * kFftThreads, pp = idx / NL, r = idx - pp * NL;
+            if (idx < ne) v[j] = col[(int64_t)(q0 + (r >> 4) + Q * pp) * kxp + (r & 15)];
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int idx = i0 + j * kFftThreads, pp = idx / NL, r = idx - pp * NL;
+            if (idx < ne) lds[bitrev(pp, lgP) * NL + r] = v[j];
+        }
     }
     __syncthreads();
     lds_fft_dit<false, false>(lds, lgP, NL, 1, NL, g.tables);
     const int lgN = P.col_lgn;
-    for (int idx = threadIdx.x; idx < Pn * NL; idx += kFftThreads) {
-        const int k1 = idx / NL, r = idx - k1 * NL;
-        const int ql = r >> 4, c = r & 15;
-        const int e = ((q0 + ql) * k1) & ((1 << lgN) - 1);
-        col[(int64_t)(q0 + ql + Q * k1) * kxp + c] = cmul(lds[idx], twiddle(g.tables, e, lgN));
+    for (int i0 = threadIdx.x; i0 < ne; i0 += kBatch * kFftThreads) {
+        float2 w[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int idx = i0 + j * kFftThreads, k1 = idx / NL, r = idx - k1 * NL;
+            if (idx < ne) w[j] = twiddle(g.tables, ((q0 + (r >> 4)) * k1) & ((1 << lgN) - 1), lgN);
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int idx = i0 + j * kFftThreads, k1 = idx / NL, r = idx - k1 * NL;
+            if (idx < ne)
+                col[(int64_t)(q0 + (r >> 4) + Q * k1) * kxp + (r & 15)] = cmul(lds[idx], w[j]);
+        }
     }
 }
 
-// Fifteen products of the five spectra at one k, added to the sums.
-__device__ __forceinline__ void accumulate_k(double *a, int64_t kstride, const float2 (&X)[5])
+// Fifteen products of the five spectra at one k, in FP64.
+__device__ __forceinline__ void products_k(double (&val)[kKinds], const float2 (&X)[5])
 {
     double re[5], im[5];
 #pragma unroll
@@ -479,14 +560,35 @@ __device__ __forceinline__ void accumulate_k(double *a, int64_t kstride, const f
     // a b* = (ar br + ai bi) + i (ai br - ar bi)
 #define FLB_RE(u, v) (re[u] * re[v] + im[u] * im[v])
 #define FLB_IM(u, v) (im[u] * re[v] - re[u] * im[v])
-    const double val[kKinds] = {FLB_RE(0, 0), FLB_RE(1, 1), FLB_RE(2, 2), FLB_RE(3, 3),
-                                FLB_RE(4, 4), FLB_RE(3, 4), FLB_IM(3, 4), FLB_RE(0, 1),
-                                FLB_IM(0, 1), FLB_RE(0, 2), FLB_IM(0, 2), FLB_RE(0, 3),
-                                FLB_IM(0, 3), FLB_RE(0, 4), FLB_IM(0, 4)};
+    const double p[kKinds] = {FLB_RE(0, 0), FLB_RE(1, 1), FLB_RE(2, 2), FLB_RE(3, 3),
+                              FLB_RE(4, 4), FLB_RE(3, 4), FLB_IM(3, 4), FLB_RE(0, 1),
+                              FLB_IM(0, 1), FLB_RE(0, 2), FLB_IM(0, 2), FLB_RE(0, 3),
+                              FLB_IM(0, 3), FLB_RE(0, 4), FLB_IM(0, 4)};
 #undef FLB_RE
 #undef FLB_IM
 #pragma unroll
+    for (int q = 0; q < kKinds; ++q) val[q] = p[q];
+}
+
+// Adds the products of one sample at one k to the sums.
+__device__ __forceinline__ void accumulate_k(double *a, int64_t kstride, const float2 (&X)[5])
+{
+    double val[kKinds];
+    products_k(val, X);
+#pragma unroll
     for (int q = 0; q < kKinds; ++q) a[q * kstride] += val[q];
+}
+
+// Adds the products of two samples at one k to the sums in one
+// read-modify-write of the FP64 sums.
+__device__ __forceinline__ void accumulate_pair_k(double *a, int64_t kstride,
+                                                  const float2 (&X)[5], const float2 (&Y)[5])
+{
+    double u[kKinds], w[kKinds];
+    products_k(u, X);
+    products_k(w, Y);
+#pragma unroll
+    for (int q = 0; q < kKinds; ++q) a[q * kstride] += u[q] + w[q];
 }
 
 // Squared moduli of the six moment spectra at one k, added to kinds
@@ -512,8 +614,12 @@ __device__ __forceinline__ void accumulate_set(double *a, int64_t kstride, const
 
 // Power-of-two ny, pass B with accumulation.  item: lattice, first column, k1.
 // LDS [q][f][c]: the Q rows Q*k1 .. Q*k1+Q-1 of all fields of the set, 16
-// columns.
-template <int SET>
+// columns.  MODE (field set 0): kAccDirect adds this sample's products;
+// kAccStash keeps its spectra in the stash instead; kAccPair adds the
+// products of this sample and of the stashed one in one read-modify-write
+// of the FP64 sums (the sums are the same, the HBM traffic for them is
+// halved over a pair of samples).
+template <int SET, int MODE>
 __global__ __launch_bounds__(kFftThreads) void corr_cols_b_kernel(CorrArgs g)
 {
     constexpr int NF = SET ? 6 : 5;
@@ -527,22 +633,43 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_b_kernel(CorrArgs g)
     constexpr int NL = NF * 16;
     const float2 *spec = g.spec + P.spec_base + c0;
     const int64_t fstride = (int64_t)ny * kxp;
-    for (int idx = threadIdx.x; idx < Q * NL; idx += kFftThreads) {
-        const int q = idx / NL, r = idx - q * NL;
-        const int f = r >> 4, c = r & 15;
-        lds[bitrev(q, lgQ) * NL + r] = spec[f * fstride + (int64_t)(Q * k1 + q) * kxp + c];
+    const int ne = Q * NL;
+    for (int i0 = threadIdx.x; i0 < ne; i0 += kBatch * kFftThreads) {
+        float2 v[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int idx = i0 + j * kFftThreads, q = idx / NL, r = idx - q * NL;
+            if (idx < ne) v[j] = spec[(r >> 4) * fstride + (int64_t)(Q * k1 + q) * kxp + (r & 15)];
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int idx = i0 + j * kFftThreads, q = idx / NL, r = idx - q * NL;
+            if (idx < ne) lds[bitrev(q, lgQ) * NL + r] = v[j];
+        }
     }
     __syncthreads();
     lds_fft_dit<false, false>(lds, lgQ, NL, 1, NL, g.tables);
     double *acc = g.acc + P.acc_base;
+    float2 *stash = g.stash + P.spec_base;
     for (int idx = threadIdx.x; idx < Q * 16; idx += kFftThreads) {
         const int k2 = idx >> 4, c = idx & 15;
         const int kx = c0 + c, ky = k1 + Pn * k2;
         if (kx >= nkx || (kx == 0 && ky == 0)) continue;
+        const int64_t o = (int64_t)ky * kxp + kx;
         float2 X[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) X[f] = lds[k2 * NL + f * 16 + c];
-        accumulate_set<SET, NF>(acc + (int64_t)ky * kxp + kx, fstride, X);
+        if constexpr (MODE == kAccStash) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) stash[f * fstride + o] = X[f];
+        } else if constexpr (MODE == kAccPair) {
+            float2 Y[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) Y[f] = stash[f * fstride + o];
+            accumulate_pair_k(acc + o, fstride, X, Y);
+        } else {
+            accumulate_set<SET, NF>(acc + o, fstride, X);
+        }
     }
 }
 
@@ -607,6 +734,7 @@ static CorrArgs make_args(const DeviceView &v, const CorrItem *items, int set)
     g.tables = v.tables;
     g.items = items;
     g.spec = v.spec;
+    g.stash = v.stash;
     g.acc = v.acc;
     g.fields = v.fields;
     g.csum_part = v.csum_part;
@@ -615,38 +743,57 @@ static CorrArgs make_args(const DeviceView &v, const CorrItem *items, int set)
     return g;
 }
 
-template <int SET>
-static void fields_for_set(const DeviceView &v, const CorrArgs &g, dim3 grid, hipStream_t s)
+template <bool BLUE>
+static void rows_for(const DeviceView &v, const CorrArgs &g, int nitems, int lds_bytes,
+                     hipStream_t s)
 {
-    const dim3 block(kThreads);
+    const dim3 grid(nitems), block(kFftThreads);
     if (v.storage == kF32)
-        hipLaunchKernelGGL((corr_fields_kernel<kF32, SET>), grid, block, 0, s, g);
+        hipLaunchKernelGGL((corr_rows_kernel<kF32, BLUE>), grid, block, lds_bytes, s, g);
     else if (v.storage == kBF16)
-        hipLaunchKernelGGL((corr_fields_kernel<kBF16, SET>), grid, block, 0, s, g);
+        hipLaunchKernelGGL((corr_rows_kernel<kBF16, BLUE>), grid, block, lds_bytes, s, g);
     else
-        hipLaunchKernelGGL((corr_fields_kernel<kF16, SET>), grid, block, 0, s, g);
+        hipLaunchKernelGGL((corr_rows_kernel<kF16, BLUE>), grid, block, lds_bytes, s, g);
 }
 
-hipError_t launch_corr_fields(const DeviceView &v, const CorrItem *items, int nitems, int set,
-                              hipStream_t s)
+hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems,
+                            const CorrItem *blue_items, int nblue, int lds_bytes, hipStream_t s)
 {
-    const CorrArgs g = make_args(v, items, set);
-    if (set == 1) {
-        fields_for_set<1>(v, g, dim3(nitems), s);
-        return hipGetLastError();
+    if (nitems) {
+        rows_for<false>(v, make_args(v, items, 0), nitems, lds_bytes, s);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    fields_for_set<0>(v, g, dim3(nitems), s);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (nblue) {
+        rows_for<true>(v, make_args(v, blue_items, 0), nblue, lds_bytes, s);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const CorrArgs g = make_args(v, items, 0);
     hipLaunchKernelGGL(corr_csum_kernel, dim3(v.nlat), dim3(kThreads), 0, s, g, v.nlat);
     return hipGetLastError();
 }
 
-hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems, int set,
-                            int lds_bytes, hipStream_t s)
+hipError_t launch_corr_moment_fields(const DeviceView &v, const CorrItem *items, int nitems,
+                                     hipStream_t s)
 {
-    const CorrArgs g = make_args(v, items, set);
-    hipLaunchKernelGGL(corr_rowfft_kernel, dim3(nitems), dim3(kFftThreads), lds_bytes, s, g);
+    const CorrArgs g = make_args(v, items, 1);
+    const dim3 grid(nitems), block(kThreads);
+    if (v.storage == kF32)
+        hipLaunchKernelGGL(corr_moment_fields_kernel<kF32>, grid, block, 0, s, g);
+    else if (v.storage == kBF16)
+        hipLaunchKernelGGL(corr_moment_fields_kernel<kBF16>, grid, block, 0, s, g);
+    else
+        hipLaunchKernelGGL(corr_moment_fields_kernel<kF16>, grid, block, 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr_moment_rows(const DeviceView &v, const CorrItem *items, int nitems,
+                                   int lds_bytes, hipStream_t s)
+{
+    const CorrArgs g = make_args(v, items, 1);
+    hipLaunchKernelGGL(corr_moment_rows_kernel, dim3(nitems), dim3(kFftThreads), lds_bytes, s,
+                       g);
     return hipGetLastError();
 }
 
@@ -659,15 +806,28 @@ hipError_t launch_corr_cols_a(const DeviceView &v, const CorrItem *items, int ni
 }
 
 hipError_t launch_corr_cols_b(const DeviceView &v, const CorrItem *items, int nitems, int set,
-                              int lds_bytes, hipStream_t s)
+                              int mode, int lds_bytes, hipStream_t s)
 {
     const CorrArgs g = make_args(v, items, set);
+    const dim3 grid(nitems), block(kFftThreads);
     if (set == 1)
-        hipLaunchKernelGGL(corr_cols_b_kernel<1>, dim3(nitems), dim3(kFftThreads), lds_bytes, s,
-                           g);
+        hipLaunchKernelGGL((corr_cols_b_kernel<1, kAccDirect>), grid, block, lds_bytes, s, g);
+    else if (mode == kAccStash)
+        hipLaunchKernelGGL((corr_cols_b_kernel<0, kAccStash>), grid, block, lds_bytes, s, g);
+    else if (mode == kAccPair)
+        hipLaunchKernelGGL((corr_cols_b_kernel<0, kAccPair>), grid, block, lds_bytes, s, g);
     else
-        hipLaunchKernelGGL(corr_cols_b_kernel<0>, dim3(nitems), dim3(kFftThreads), lds_bytes, s,
-                           g);
+        hipLaunchKernelGGL((corr_cols_b_kernel<0, kAccDirect>), grid, block, lds_bytes, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nitems,
+                             hipStream_t s)
+{
+    // the stash has the layout of the spectra: accumulate it as a sample
+    CorrArgs g = make_args(v, items, 0);
+    g.spec = v.stash;
+    hipLaunchKernelGGL(corr_accum_kernel<0>, dim3(nitems), dim3(kThreads), 0, s, g);
     return hipGetLastError();
 }
 

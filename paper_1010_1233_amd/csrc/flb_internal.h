@@ -107,8 +107,9 @@ struct DeviceView {
     const uint32_t *step;             // device step counter
     uint32_t *step_rw;
     float2 *spec;
+    float2 *stash;                    // spectra awaiting accumulation (layout of spec)
     double *acc;
-    float *fields;                    // [nf][ny][nx] FP32 per lattice (nf = 5, or 6)
+    float *fields;                    // [6][ny][nx] FP32 moment planes per lattice
     double *csum_part;                // field-kernel partial sums
     double *csum;                     // [nlat][5] sums of the last sample
     const LinePlan *plans;            // device
@@ -134,18 +135,29 @@ hipError_t launch_thermalize(const DeviceView &v, int lattice, int nx, int ny, d
                              int nblocks, double *mean_dev, hipStream_t s);
 hipError_t launch_debug_noise(uint64_t seed, uint32_t stream_id, uint32_t t, int64_t site0,
                               int64_t n, uint32_t *words_dev, float *z_dev, hipStream_t s);
-// set: 0 = rho, j, u (kKinds kinds, plus the conservation sums); 1 = the
-// six non-conserved moments (kinds kKinds .. kKinds + 5)
-hipError_t launch_corr_fields(const DeviceView &v, const CorrItem *items, int nitems, int set,
-                              hipStream_t s);
-hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems, int set,
-                            int lds_bytes, hipStream_t s);
+// Field set 0 (rho, j, u; kKinds kinds): fused fields + row transforms
+// (items of power-of-two rows and of Bluestein rows), then the conservation
+// sums of the sampled state.
+hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems,
+                            const CorrItem *blue_items, int nblue, int lds_bytes, hipStream_t s);
+// Field set 1 (the six non-conserved moments, kinds kKinds .. kKinds + 5):
+// FP32 field planes, then row transforms.
+hipError_t launch_corr_moment_fields(const DeviceView &v, const CorrItem *items, int nitems,
+                                     hipStream_t s);
+hipError_t launch_corr_moment_rows(const DeviceView &v, const CorrItem *items, int nitems,
+                                   int lds_bytes, hipStream_t s);
+// Column passes and accumulation; set selects the fields and kinds as above.
 hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int cb,
                             int lds_bytes, hipStream_t s);
 hipError_t launch_corr_cols_a(const DeviceView &v, const CorrItem *items, int nitems,
                               int lds_bytes, hipStream_t s);
+// Accumulation modes of column pass B for field set 0 (power-of-two ny).
+enum AccMode : int { kAccDirect = 0, kAccStash = 1, kAccPair = 2 };
 hipError_t launch_corr_cols_b(const DeviceView &v, const CorrItem *items, int nitems, int set,
-                              int lds_bytes, hipStream_t s);
+                              int mode, int lds_bytes, hipStream_t s);
+// Adds the products of the stashed spectra to the sums (field set 0).
+hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nitems,
+                             hipStream_t s);
 hipError_t launch_corr_accum(const DeviceView &v, const CorrItem *items, int nitems, int set,
                              hipStream_t s);
 hipError_t launch_fill(double *p, size_t n, hipStream_t s);

@@ -46,11 +46,16 @@ const double kW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
 const int kVx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 const int kVy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
+// A captured sampling period: its length, the buffer holding the state at
+// its start and whether a stashed sample is pending (which decides the
+// accumulation mode of its sample).
 struct GraphKey {
-    int every, parity;
+    int every, parity, pending;
     bool operator<(const GraphKey &o) const
     {
-        return every < o.every || (every == o.every && parity < o.parity);
+        if (every != o.every) return every < o.every;
+        if (parity != o.parity) return parity < o.parity;
+        return pending < o.pending;
     }
 };
 
@@ -97,8 +102,16 @@ struct flb {
     // moments through the same transforms, into kinds kKinds .. kKinds + 5
     bool moments = false;
     int nkinds = kKinds, nfld = kFields;
-    CorrItem *d_cols_a_m = nullptr, *d_cols_m = nullptr;
-    int n_cols_a_m = 0, n_cols_m = 0;
+    CorrItem *d_cols_a_m = nullptr, *d_cols_m = nullptr, *d_rows_m = nullptr;
+    int n_cols_a_m = 0, n_cols_m = 0, n_rows_m = 0;
+    CorrItem *d_rows_blue = nullptr;  // rows of lattices with Bluestein row transforms
+    int n_rows_blue = 0;
+    // deferred accumulation (power-of-two ny): every other sample stashes its
+    // spectra and the next one adds both samples' products at once
+    bool defer = false, pending = false;
+    float2 *d_stash = nullptr;
+    CorrItem *d_flush = nullptr;
+    int n_flush = 0;
     float *d_fields = nullptr;
     double *d_csum_part = nullptr, *d_csum = nullptr;
     int rows_lds = 0, cols_lds = 0, cols_cb = 1, cols_a_lds = 0, cols_b_lds = 0;
@@ -120,6 +133,7 @@ struct flb {
         v.step = d_step;
         v.step_rw = d_step;
         v.spec = d_spec;
+        v.stash = d_stash;
         v.acc = d_acc;
         v.fields = d_fields;
         v.csum_part = d_csum_part;
@@ -378,11 +392,15 @@ int setup_correlators(flb_t *h)
         P.acc_base = acc;
         spec += (int64_t)h->nfld * P.ny * P.kxp;
         acc += (int64_t)h->nkinds * P.ny * P.kxp;
+        // FP32 moment planes, only with the moment spectra
         P.fld_base = fld;
-        fld += ((int64_t)h->nfld * P.nx * P.ny + 63) / 64 * 64;
+        if (h->moments) fld += ((int64_t)kMomentFields * P.nx * P.ny + 63) / 64 * 64;
         P.fld_tiles_x = (P.nx + kThreads - 1) / kThreads;
+        // one conservation partial per row group of the row kernel
+        const int mx = h->plans[P.line_x].m;
+        const int rb = std::max(1, std::min(P.ny, 4096 / mx));
         P.fld_part0 = nparts;
-        P.fld_nparts = P.fld_tiles_x * ((P.ny + kFieldRows - 1) / kFieldRows);
+        P.fld_nparts = (P.ny + rb - 1) / rb;
         nparts += P.fld_nparts;
     }
     h->spec_elems = spec;
@@ -390,19 +408,27 @@ int setup_correlators(flb_t *h)
     h->cols_cb = std::max(1, std::min(16, 8192 / max_my_general));
     h->cols_lds = max_my_general * h->cols_cb * (int)sizeof(float2);
 
-    std::vector<CorrItem> rows, cols, accum, cols_a, cols_b, flds, cols_a_m, cols_m;
+    std::vector<CorrItem> rows, cols, accum, cols_a, cols_b, flds, cols_a_m, cols_m, rows_m;
+    std::vector<CorrItem> rows_blue, flush;
     for (size_t l = 0; l < h->params.size(); ++l) {
         const LatticeParams &P = h->params[l];
-        for (int t = 0; t < P.fld_nparts; ++t)
-            flds.push_back({(int32_t)l, t, P.fld_part0 + t, 0});
+        if (h->moments) {
+            const int ntiles = P.fld_tiles_x * ((P.ny + kFieldRows - 1) / kFieldRows);
+            for (int t = 0; t < ntiles; ++t) flds.push_back({(int32_t)l, t, 0, 0});
+        }
         const int mx = h->plans[P.line_x].m;
-        // rows per block: up to 4096 work elements (32 KB of LDS)
+        // rows per block: up to 4096 line elements (32 KB of LDS), which the
+        // row kernels assume
         const int rb = std::max(1, std::min(P.ny, 4096 / mx));
-        // the row kernel pads its LDS lines (one slot per 16 and per 256)
+        if (rb * mx > 4096) return fail(FLB_ESIZE, "row transform longer than 4096 elements");
+        // the row kernels pad their LDS lines (one slot per 16 and per 256)
         const int slots = rb * mx + (rb * mx >> 4) + (rb * mx >> 8) + 1;
         h->rows_lds = std::max(h->rows_lds, slots * (int)sizeof(float2));
-        for (int y = 0; y < P.ny; y += rb)
-            for (int sig = 0; sig < 3; ++sig) rows.push_back({(int32_t)l, y, rb, sig});
+        for (int y = 0, part = P.fld_part0; y < P.ny; y += rb, ++part) {
+            (h->plans[P.line_x].bluestein ? rows_blue : rows).push_back({(int32_t)l, y, rb, part});
+            if (h->moments)
+                for (int sig = 0; sig < 3; ++sig) rows_m.push_back({(int32_t)l, y, rb, sig});
+        }
         if (P.col_pow2) {
             const int Pn = 1 << P.col_lgp;
             if (Pn > 1)
@@ -414,6 +440,9 @@ int setup_correlators(flb_t *h)
                         }
             for (int c0 = 0; c0 < P.kxp; c0 += 16)
                 for (int k1 = 0; k1 < Pn; ++k1) cols_b.push_back({(int32_t)l, c0, k1, 0});
+            const int64_t nk = (int64_t)P.ny * P.nkx;
+            for (int64_t k0 = 0; k0 < nk; k0 += kThreads)
+                flush.push_back({(int32_t)l, (int32_t)k0, 0, 0});
         } else {
             for (int f = 0; f < h->nfld; ++f)
                 for (int c0 = 0; c0 < P.nkx; c0 += h->cols_cb) {
@@ -428,18 +457,25 @@ int setup_correlators(flb_t *h)
     const CorrItem idle{-1, 0, 0, 0};
     flds = xcd_order(flds, idle);
     rows = xcd_order(rows, idle);
+    rows_blue = xcd_order(rows_blue, idle);
+    h->n_rows_blue = (int)rows_blue.size();
     cols_a = xcd_order(cols_a, idle);
     cols_b = xcd_order(cols_b, idle);
     cols = xcd_order(cols, idle);
     if (h->moments) {
         cols_a_m = xcd_order(cols_a_m, idle);
         cols_m = xcd_order(cols_m, idle);
+        rows_m = xcd_order(rows_m, idle);
     } else {
         cols_a_m.clear();
         cols_m.clear();
     }
     h->n_cols_a_m = (int)cols_a_m.size();
     h->n_cols_m = (int)cols_m.size();
+    h->n_rows_m = (int)rows_m.size();
+    h->n_flush = (int)flush.size();
+    h->defer = !cols_b.empty();
+    h->pending = false;
     h->n_rows = (int)rows.size();
     h->n_cols = (int)cols.size();
     h->n_accum = (int)accum.size();
@@ -451,12 +487,15 @@ int setup_correlators(flb_t *h)
         (rc = upload(&h->d_cols, cols)) ||
         (rc = upload(&h->d_accum, accum)) || (rc = upload(&h->d_cols_a, cols_a)) ||
         (rc = upload(&h->d_cols_b, cols_b)) || (rc = upload(&h->d_cols_a_m, cols_a_m)) ||
-        (rc = upload(&h->d_cols_m, cols_m)) || (rc = upload(&h->d_plans, h->plans)) ||
+        (rc = upload(&h->d_cols_m, cols_m)) || (rc = upload(&h->d_rows_m, rows_m)) ||
+        (rc = upload(&h->d_rows_blue, rows_blue)) || (rc = upload(&h->d_flush, flush)) ||
+        (rc = upload(&h->d_plans, h->plans)) ||
         (rc = upload(&h->d_tables, tables)) || (rc = upload(&h->d_params, h->params)))
         return rc;
     FLB_HIP(hipMalloc((void **)&h->d_spec, spec * sizeof(float2)));
     FLB_HIP(hipMalloc((void **)&h->d_acc, acc * sizeof(double)));
-    FLB_HIP(hipMalloc((void **)&h->d_fields, fld * sizeof(float)));
+    if (fld > 0) FLB_HIP(hipMalloc((void **)&h->d_fields, fld * sizeof(float)));
+    if (h->defer) FLB_HIP(hipMalloc((void **)&h->d_stash, spec * sizeof(float2)));
     FLB_HIP(hipMalloc((void **)&h->d_csum_part, (size_t)nparts * 5 * sizeof(double)));
     FLB_HIP(hipMalloc((void **)&h->d_csum, h->params.size() * 5 * sizeof(double)));
     FLB_HIP(launch_fill(h->d_csum, h->params.size() * 5, h->stream));
@@ -471,19 +510,36 @@ int enqueue_sample(flb_t *h, hipStream_t s)
 {
     const DeviceView v = h->view();
     for (int set = 0; set < (h->moments ? 2 : 1); ++set) {
-        // the moment set reuses the field and spectrum buffers after set 0
+        // the moment set reuses the spectrum buffer after set 0
         const CorrItem *ca = set ? h->d_cols_a_m : h->d_cols_a;
         const CorrItem *cg = set ? h->d_cols_m : h->d_cols;
         const int na = set ? h->n_cols_a_m : h->n_cols_a;
         const int ng = set ? h->n_cols_m : h->n_cols;
-        FLB_HIP(launch_corr_fields(v, h->d_fld, h->n_fld, set, s));
-        FLB_HIP(launch_corr_rows(v, h->d_rows, h->n_rows, set, h->rows_lds, s));
+        if (set == 0) {
+            FLB_HIP(launch_corr_rows(v, h->d_rows, h->n_rows, h->d_rows_blue, h->n_rows_blue,
+                                     h->rows_lds, s));
+        } else {
+            FLB_HIP(launch_corr_moment_fields(v, h->d_fld, h->n_fld, s));
+            FLB_HIP(launch_corr_moment_rows(v, h->d_rows_m, h->n_rows_m, h->rows_lds, s));
+        }
         if (na) FLB_HIP(launch_corr_cols_a(v, ca, na, h->cols_a_lds, s));
-        if (h->n_cols_b)
-            FLB_HIP(launch_corr_cols_b(v, h->d_cols_b, h->n_cols_b, set, h->cols_b_lds, s));
+        if (h->n_cols_b) {
+            const int mode = (set || !h->defer) ? kAccDirect : h->pending ? kAccPair : kAccStash;
+            FLB_HIP(launch_corr_cols_b(v, h->d_cols_b, h->n_cols_b, set, mode, h->cols_b_lds, s));
+        }
         if (ng) FLB_HIP(launch_corr_cols(v, cg, ng, h->cols_cb, h->cols_lds, s));
         if (h->n_accum) FLB_HIP(launch_corr_accum(v, h->d_accum, h->n_accum, set, s));
     }
+    if (h->defer) h->pending = !h->pending;
+    return FLB_OK;
+}
+
+// Adds a stashed sample's products to the sums before they are read.
+int flush_pending(flb_t *h)
+{
+    if (!h->pending) return FLB_OK;
+    FLB_HIP(launch_corr_flush(h->view(), h->d_flush, h->n_flush, h->stream));
+    h->pending = false;
     return FLB_OK;
 }
 
@@ -664,7 +720,8 @@ void flb_destroy(flb_t *h)
     void *ptrs[] = {h->pops[0], h->d_params, h->d_step, h->d_red, h->d_items,
                     h->d_plans, h->d_tables, h->d_spec, h->d_acc, h->d_rows, h->d_cols,
                     h->d_accum, h->d_cols_a, h->d_cols_b, h->d_fld, h->d_fields,
-                    h->d_csum_part, h->d_csum, h->d_cols_a_m, h->d_cols_m};
+                    h->d_csum_part, h->d_csum, h->d_cols_a_m, h->d_cols_m, h->d_rows_m,
+                    h->d_rows_blue, h->d_stash, h->d_flush};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->ev) (void)hipEventDestroy(h->ev);
@@ -717,18 +774,20 @@ int flb_accumulate_correlators(flb_t *h)
 // One period of `every` steps followed by a sample, from a captured graph.
 static int run_period_graph(flb_t *h, int every)
 {
-    const GraphKey key{every, h->cur};
+    const GraphKey key{every, h->cur, h->pending ? 1 : 0};
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
         // capture on the handle's own stream (capturing the legacy default
         // stream is not allowed), then launch on the current stream
         const int cur0 = h->cur;
+        const bool pending0 = h->pending;
         FLB_HIP(hipStreamBeginCapture(h->own, hipStreamCaptureModeRelaxed));
         int rc = enqueue_steps(h, every, h->own);
         if (!rc) rc = enqueue_sample(h, h->own);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(h->own, &g);
         h->cur = cur0;
+        h->pending = pending0;
         if (rc) {
             if (g) (void)hipGraphDestroy(g);
             return rc;
@@ -743,6 +802,7 @@ static int run_period_graph(flb_t *h, int every)
     }
     FLB_HIP(hipGraphLaunch(it->second, h->stream));
     if (every & 1) h->cur ^= 1;
+    if (h->defer) h->pending = !h->pending;
     h->t += every;
     h->nsamples += 1;
     return FLB_OK;
@@ -787,6 +847,7 @@ int flb_read_correlators(flb_t *h, int lattice, double *out, size_t n_doubles, i
     const LatticeParams &P = h->params[lattice];
     const size_t need = (size_t)h->nkinds * P.ny * P.nkx;
     if (n_doubles < need) return fail(FLB_ESIZE, "output buffer too small for the correlators");
+    if ((rc = flush_pending(h))) return rc;
     FLB_HIP(hipStreamSynchronize(h->stream));
     // device rows have pitch kxp >= nkx
     FLB_HIP(hipMemcpy2D(out, (size_t)P.nkx * sizeof(double), h->d_acc + P.acc_base,
@@ -803,6 +864,7 @@ int flb_reset_correlators(flb_t *h)
     if (rc) return rc;
     FLB_HIP(launch_fill(h->d_acc, (size_t)h->acc_elems, h->stream));
     h->nsamples = 0;
+    h->pending = false;  // a stashed sample is dropped with the sums
     return FLB_OK;
 }
 

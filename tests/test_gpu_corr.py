@@ -238,3 +238,36 @@ def test_moment_spectra_paired_run_and_batch(flb, oracle_lib):
         one.thermalize()
         one.run(100, 10)
         assert np.array_equal(b.read_correlators(i)[0], one.read_correlators()[0])
+
+
+def test_reads_between_paired_samples(flb, oracle_lib):
+    """Power-of-two sides add the products of two samples at a time; a read
+    with one sample outstanding adds it first.  Reading after every sample,
+    twice in a row, or only at the end all give the oracle's sums."""
+    kw = dict(u0=(0.02, 0.0), seed=12)
+    a = flb.Lattice(64, 32, TAU_C1, 1e-4, **kw)
+    b = flb.Lattice(64, 32, TAU_C1, 1e-4, **kw)
+    o = oracle_lib.Lattice(64, 32, TAU_C1, 1e-4, **kw)
+    for L in (a, b, o):
+        L.thermalize()
+    for n in range(1, 6):
+        for L in (a, b, o):
+            L.step(3)
+        a.accumulate()
+        b.accumulate()
+        o.sample()
+        r1, n1 = a.read_correlators()
+        r2, n2 = a.read_correlators()
+        assert n1 == n2 == n and np.array_equal(r1, r2)
+        _compare(r1, o.acc, 2e-4)
+    rb, nb = b.read_correlators()
+    assert nb == 5
+    _compare(rb, o.acc, 2e-4)
+    assert np.abs(rb - r1).max() <= 1e-12 * np.abs(rb).max()
+    # a reset drops an outstanding sample together with the sums
+    a.accumulate()
+    a.reset_correlators()
+    a.accumulate()
+    o.acc[...] = 0
+    o.sample()
+    _compare(a.read_correlators()[0], o.acc, 2e-4)
