@@ -247,8 +247,9 @@ int flb_set_step_config(flb_t *h, int tile_w, int sites, int nontemporal);
 int flb_get_step_config(flb_t *h, int *tile_w, int *sites, int *nontemporal);
 
 /* Chooses the step kernel's launch shape by timing every supported shape
- * (nsteps >= 1 steps each, HIP events on the handle's stream) on this
- * handle's own lattices, and keeps the fastest.  The populations and the
+ * (nsteps >= 1 steps each, HIP events on the handle's stream, in three
+ * round-robin passes of which each shape keeps its fastest) on this
+ * handle's own lattices, and keeps the fastest shape.  The populations and the
  * step counter are restored afterwards, so results are unchanged.  When the
  * environment variable FLB_AUTOTUNE_CACHE names a file, choices are read
  * from and appended to it, keyed by storage format, lattice count, total
