@@ -109,7 +109,7 @@ def batched_form(torch, flb, stream, specs, storage, periods=10):
     b = flb.Lattice.batch(specs, seed=3, storage=storage)
     b.set_stream(stream)
     b.thermalize()
-    shape, _ = b.autotune(20)
+    shape, _ = b.autotune(50)
     sites = sum(s["nx"] * s["ny"] for s in specs)
     b.run(2 * SAMPLE_EVERY, SAMPLE_EVERY)  # capture the graphs
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -192,7 +192,7 @@ def main():
     print(f"bench: {args.workload} {c['nx']}x{c['ny']} storage={args.storage} "
           f"step config={g.step_config()}", file=sys.stderr, flush=True)
     g.thermalize()
-    tuned, _ = g.autotune(20)
+    tuned, _ = g.autotune(50)
     print(f"bench: autotuned step config {tuned}", file=sys.stderr, flush=True)
     cons0 = g.conservation()
 
@@ -269,7 +269,7 @@ def main():
                 h, _ = make_lattice(flb, workloads, args.workload, st)
                 h.set_stream(stream)
                 h.thermalize()
-                h.autotune(20)
+                h.autotune(50)
                 time_step_kernel(torch, h, stream, 5)
                 ms = time_step_kernel(torch, h, stream, 50)
                 b = h.storage_info()[1]
@@ -280,7 +280,7 @@ def main():
             h = flb.Lattice(cq["nx"], cq["ny"], cq["tau"], 0.0, rho0=cq["rho0"], u0=cq["u0"],
                             seed=cq["seed"], storage=args.storage)
             h.set_stream(stream)
-            h.autotune(20)
+            h.autotune(50)
             time_step_kernel(torch, h, stream, 5)
             ms = time_step_kernel(torch, h, stream, 50)
             forms["noise_off_" + args.storage] = {"step_glups": V / (ms * 1e-3) / 1e9}
