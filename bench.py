@@ -181,6 +181,16 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(f"copy-calibration: 3 x {a.numel() * 4} bytes", flush=True)
+        # the same copy timed: the runtime's practical copy bandwidth
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / 20
+        print(f"copy-calibration: device copy {2 * a.numel() * 4 / (ms * 1e-3) / 1e9:.0f} GB/s "
+              f"(read + write) over {a.numel() * 4} bytes", flush=True)
         return 0
     if args.sweep_shapes:
         sweep_shapes(flb, workloads, args.workload, args.storage)

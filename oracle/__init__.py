@@ -18,6 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRC_DQ = os.path.join(_HERE, "oracle_ddqq.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 _u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -31,7 +32,7 @@ def build(force: bool = True) -> str:
         tmp = _LIB + ".tmp"
         subprocess.check_call(
             ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
-             "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+             "-Wall", "-Wextra", "-o", tmp, _SRC, _SRC_DQ, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -43,6 +44,18 @@ class Cfg(ctypes.Structure):
         ("tau", ctypes.c_double * 9),
         ("theta", ctypes.c_double), ("rho0", ctypes.c_double),
         ("u0x", ctypes.c_double), ("u0y", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32),
+        ("ladd", ctypes.c_int),
+    ]
+
+
+class DqCfg(ctypes.Structure):
+    """Mirror of ``oracle_dq_cfg`` in oracle_ddqq.c."""
+    _fields_ = [
+        ("model", ctypes.c_int), ("n", ctypes.c_int * 3),
+        ("tau", ctypes.c_double * 15),
+        ("theta", ctypes.c_double), ("rho0", ctypes.c_double),
+        ("u0", ctypes.c_double * 3),
         ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32),
         ("ladd", ctypes.c_int),
     ]
@@ -81,6 +94,19 @@ def lib():
         L.oracle_run.argtypes = [cp, _dp, _dp, ctypes.c_uint32, ctypes.c_int64,
                                  ctypes.c_int, _dp, _dp]
         L.oracle_run.restype = ctypes.c_int64
+        dq = ctypes.POINTER(DqCfg)
+        L.oracle_dft3.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.oracle_dq_tables.argtypes = [ctypes.c_int, _ip, _ip, _ip, _dp, _dp]
+        L.oracle_dq_nkinds.argtypes = [ctypes.c_int]
+        L.oracle_dq_equilibrium.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp]
+        L.oracle_dq_init.argtypes = [dq, _dp]
+        L.oracle_dq_step.argtypes = [dq, _dp, _dp, ctypes.c_uint32]
+        L.oracle_dq_conservation.argtypes = [dq, _dp, _dp]
+        L.oracle_dq_thermalize.argtypes = [dq, _dp]
+        L.oracle_dq_sample.argtypes = [dq, _dp, _dp]
+        L.oracle_dq_run.argtypes = [dq, _dp, _dp, ctypes.c_uint32, ctypes.c_int64,
+                                    ctypes.c_int, _dp]
+        L.oracle_dq_run.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -284,3 +310,145 @@ def normalized_moments(acc_m, nsamples, nx, ny, theta, rho0):
     mu = 3.0 * theta
     m = acc_m / max(nsamples, 1)
     return {"S_M%d" % a: m[a - 3] / (V * mu * rho0) for a in range(3, 9)}
+
+
+# ---------------------------------------------------------------------------
+# Other velocity sets (D1Q3, D3Q15; D2Q9 through the same generic code)
+# ---------------------------------------------------------------------------
+DQ_MODELS = {"D1Q3": 13, "D2Q9": 29, "D3Q15": 315}
+
+
+def dq_tables(model):
+    """(D, v[Q][3], w[Q], m[Q][Q]) of a velocity set: the moments are the
+    model's velocity polynomials orthonormalised under the weights (Eq. 4)."""
+    D, Q = ctypes.c_int(), ctypes.c_int()
+    v = np.zeros(45, dtype=np.int32)
+    w = np.zeros(15)
+    m = np.zeros(225)
+    rc = lib().oracle_dq_tables(DQ_MODELS[model], ctypes.byref(D), ctypes.byref(Q),
+                                _p(v, _ip), _p(w), _p(m))
+    assert rc == 0
+    q = Q.value
+    return D.value, v[:3 * q].reshape(q, 3), w[:q].copy(), m[:q * q].reshape(q, q).copy()
+
+
+def dq_equilibrium(model, rho, u):
+    """Eq. (2) (c = 1) on the velocity set of `model`."""
+    u = np.ascontiguousarray(list(u) + [0.0] * (3 - len(u)), dtype=np.float64)
+    f0 = np.zeros(15)
+    assert lib().oracle_dq_equilibrium(DQ_MODELS[model], float(rho), _p(u), _p(f0)) == 0
+    return f0[:len(dq_tables(model)[2])].copy()
+
+
+def dq_nkinds(model):
+    return int(lib().oracle_dq_nkinds(DQ_MODELS[model]))
+
+
+def dft3(x):
+    """In-place-style 3-D transform of a complex array of shape (nz, ny, nx)."""
+    x = np.asarray(x, dtype=complex)
+    nz, ny, nx = x.shape
+    re = np.ascontiguousarray(x.real)
+    im = np.ascontiguousarray(x.imag)
+    lib().oracle_dft3(_p(re), _p(im), nx, ny, nz)
+    return re + 1j * im
+
+
+class DqLattice:
+    """A periodic lattice of the generic oracle: sides (nx, ny, nz) with the
+    unused ones 1; ``f`` is f[i][z][y][x], pre-collision."""
+
+    def __init__(self, model, sides, tau, theta, rho0=1.0, u0=(0.0, 0.0, 0.0), seed=1,
+                 stream_id=0, ladd=False, thermalize=False):
+        self.model = model
+        self.D, v, w, _ = dq_tables(model)
+        self.Q = len(w)
+        sides = list(sides) + [1] * (3 - len(sides))
+        self.cfg = DqCfg()
+        self.cfg.model = DQ_MODELS[model]
+        for a in range(3):
+            self.cfg.n[a] = int(sides[a])
+        for a in range(self.Q):
+            self.cfg.tau[a] = float(tau[a])
+        self.cfg.theta, self.cfg.rho0 = float(theta), float(rho0)
+        u0 = list(u0) + [0.0] * (3 - len(u0))
+        for a in range(3):
+            self.cfg.u0[a] = float(u0[a])
+        self.cfg.seed, self.cfg.stream_id = int(seed), int(stream_id)
+        self.cfg.ladd = int(bool(ladd))
+        self.sides = tuple(sides)
+        nx, ny, nz = self.sides
+        self.f = np.zeros((self.Q, nz, ny, nx))
+        self._tmp = np.zeros_like(self.f)
+        lib().oracle_dq_init(ctypes.byref(self.cfg), _p(self.f))
+        if thermalize:
+            self.thermalize()
+        self.t = 0
+        self.nkinds = dq_nkinds(model)
+        self.acc = np.zeros((self.nkinds, nz, ny, nx // 2 + 1))
+        self.nsamples = 0
+
+    def set_populations(self, f):
+        self.f[...] = np.asarray(f, dtype=np.float64).reshape(self.f.shape)
+
+    def step(self, n=1):
+        for _ in range(n):
+            lib().oracle_dq_step(ctypes.byref(self.cfg), _p(self.f), _p(self._tmp), self.t)
+            self.f, self._tmp = self._tmp, self.f
+            self.t += 1
+
+    def run(self, nsteps, sample_every=0):
+        ns = lib().oracle_dq_run(ctypes.byref(self.cfg), _p(self.f), _p(self._tmp), self.t,
+                                 int(nsteps), int(sample_every),
+                                 _p(self.acc) if sample_every > 0 else None)
+        self.t += int(nsteps)
+        self.nsamples += int(ns)
+        return int(ns)
+
+    def sample(self):
+        lib().oracle_dq_sample(ctypes.byref(self.cfg), _p(self.f), _p(self.acc))
+        self.nsamples += 1
+
+    def conservation(self):
+        o = np.zeros(4)
+        lib().oracle_dq_conservation(ctypes.byref(self.cfg), _p(self.f), _p(o))
+        return o
+
+    def thermalize(self):
+        lib().oracle_dq_thermalize(ctypes.byref(self.cfg), _p(self.f))
+
+
+def dq_kind_names(D, Q):
+    """Names of the generic oracle's correlator kinds, in order."""
+    ax = "xyz"
+    names = ["rho_rho"] + [f"j{ax[a]}_j{ax[a]}" for a in range(D)]
+    names += [f"u{ax[a]}_u{ax[a]}" for a in range(D)]
+    if D >= 2:
+        names += ["re_ux_uy", "im_ux_uy"]
+    names += [f"M{a}_M{a}" for a in range(D + 1, Q)]
+    return names
+
+
+def dq_normalized(acc, nsamples, D, Q, sides, theta, rho0):
+    """Structure factors of the generic kinds: S(rho) = <|rho_k|^2>/(V mu rho0),
+    S(j_a) = <|j_a|^2>/(V rho0 theta), S(u_a) = rho0 <|u_a|^2>/(V theta),
+    R(u_x,u_y) = rho0 <u_x u_y*>/(V theta), S(M^a) = <|M^a|^2>/(V mu rho0)."""
+    V = float(np.prod(sides))
+    mu = 3.0 * theta
+    m = acc / max(nsamples, 1)
+    ax = "xyz"
+    out = {"S_rho": m[0] / (V * mu * rho0)}
+    k = 1
+    for a in range(D):
+        out["S_j" + ax[a]] = m[k] / (V * rho0 * theta)
+        k += 1
+    for a in range(D):
+        out["S_u" + ax[a]] = rho0 * m[k] / (V * theta)
+        k += 1
+    if D >= 2:
+        out["R_uxuy"] = rho0 * (m[k] + 1j * m[k + 1]) / (V * theta)
+        k += 2
+    for a in range(D + 1, Q):
+        out["S_M%d" % a] = m[k] / (V * mu * rho0)
+        k += 1
+    return out

@@ -408,6 +408,33 @@ void oracle_dft2(double *re, double *im, int nx, int ny)
     free(wi);
 }
 
+/* Three-dimensional transform of an nz x ny x nx complex field, in place
+ * (x fastest); sides of 1 are allowed, so it also serves one and two
+ * dimensions. */
+void oracle_dft3(double *re, double *im, int nx, int ny, int nz)
+{
+    int nmax = nx > ny ? nx : ny;
+    if (nz > nmax) nmax = nz;
+    double *wr = (double *)malloc(sizeof(double) * nmax);
+    double *wi = (double *)malloc(sizeof(double) * nmax);
+    const size_t pl = (size_t)nx * ny;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y) {
+            const size_t o = z * pl + (size_t)y * nx;
+            dft_line(re + o, im + o, nx, 1, wr, wi);
+        }
+    if (ny > 1)
+        for (int z = 0; z < nz; ++z)
+            for (int x = 0; x < nx; ++x) {
+                const size_t o = z * pl + x;
+                dft_line(re + o, im + o, ny, (size_t)nx, wr, wi);
+            }
+    if (nz > 1)
+        for (size_t o = 0; o < pl; ++o) dft_line(re + o, im + o, nz, pl, wr, wi);
+    free(wr);
+    free(wi);
+}
+
 /* ------------------------------------------------------------------ */
 /* Correlator sample, Eq. (11) and Eq. (12)                            */
 /* ------------------------------------------------------------------ */
