@@ -90,6 +90,25 @@ SIGNATURES = {
                                            ctypes.c_int]),
     "flb_get_step_config": (ctypes.c_int, [ctypes.c_void_p, _intp, _intp, _intp]),
     "flb_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp]),
+    # other velocity sets (flb_dq.h)
+    "flb_dq_tables": (ctypes.c_int, [ctypes.c_int, _i32p, _i32p, _i32p, _dp, _dp]),
+    "flb_dq_create": (ctypes.c_void_p, [ctypes.c_int, _i32p, _dp, ctypes.c_double,
+                                        ctypes.c_double, _dp, ctypes.c_uint64, ctypes.c_uint32,
+                                        ctypes.c_uint32]),
+    "flb_dq_destroy": (None, [ctypes.c_void_p]),
+    "flb_dq_info": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i32p, _i32p]),
+    "flb_dq_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "flb_dq_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
+    "flb_dq_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "flb_dq_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int]),
+    "flb_dq_get_step": (ctypes.c_int64, [ctypes.c_void_p]),
+    "flb_dq_accumulate": (ctypes.c_int, [ctypes.c_void_p]),
+    "flb_dq_read": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_size_t, _i64p]),
+    "flb_dq_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "flb_dq_get_populations": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_size_t]),
+    "flb_dq_set_populations": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_size_t]),
+    "flb_dq_thermalize": (ctypes.c_int, [ctypes.c_void_p]),
+    "flb_dq_conservation": (ctypes.c_int, [ctypes.c_void_p, _dp]),
 }
 
 
@@ -347,3 +366,132 @@ def normalize(acc, nsamples, nx, ny, theta, rho0):
 
 def _flags(ladd, moments):
     return (FLAG_NO_GHOST_NOISE if ladd else 0) | (FLAG_MOMENT_SPECTRA if moments else 0)
+
+
+# ---------------------------------------------------------------------------
+# Other velocity sets (include/flb_dq.h)
+# ---------------------------------------------------------------------------
+DQ_MODELS = {"D1Q3": 13, "D2Q9": 29, "D3Q15": 315}
+
+
+def dq_tables(model):
+    """(D, v[Q][3], w[Q], m[Q][Q]) of a velocity set, as the library builds them."""
+    D, Q = ctypes.c_int32(), ctypes.c_int32()
+    v = np.zeros(45, dtype=np.int32)
+    w = np.zeros(15)
+    m = np.zeros(225)
+    _check(lib().flb_dq_tables(DQ_MODELS[model], ctypes.byref(D), ctypes.byref(Q),
+                               v.ctypes.data_as(_i32p), _dptr(w), _dptr(m)))
+    q = Q.value
+    return D.value, v[:3 * q].reshape(q, 3).copy(), w[:q].copy(), m[:q * q].reshape(q, q).copy()
+
+
+class DqLattice:
+    """One periodic lattice of another velocity set (D1Q3, D2Q9 or D3Q15) on
+    the GPU; sides (nx, ny, nz) with the unused ones 1."""
+
+    def __init__(self, model, sides, tau, theta, rho0=1.0, u0=(0.0, 0.0, 0.0), seed=1,
+                 stream_id=0, ladd=False):
+        L = lib()
+        sides = list(sides) + [1] * (3 - len(sides))
+        n = np.ascontiguousarray(sides, dtype=np.int32)
+        t = np.ascontiguousarray(tau, dtype=np.float64)
+        u = np.ascontiguousarray(list(u0) + [0.0] * (3 - len(u0)), dtype=np.float64)
+        h = L.flb_dq_create(DQ_MODELS[model], n.ctypes.data_as(_i32p), _dptr(t), float(theta),
+                            float(rho0), _dptr(u), int(seed), int(stream_id),
+                            FLAG_NO_GHOST_NOISE if ladd else 0)
+        if not h:
+            raise FlbError(EINVAL, last_error())
+        self._h = h
+        self.model = model
+        self.sides = tuple(int(x) for x in sides)
+        D, Q, K = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(L.flb_dq_info(h, ctypes.byref(D), ctypes.byref(Q), ctypes.byref(K)))
+        self.D, self.Q, self.nkinds = D.value, Q.value, K.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().flb_dq_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def t(self):
+        return int(lib().flb_dq_get_step(self._h))
+
+    def set_stream(self, stream):
+        ptr = stream if isinstance(stream, int) else getattr(stream, "cuda_stream", 0)
+        _check(lib().flb_dq_set_stream(self._h, ctypes.c_void_p(ptr)))
+
+    def synchronize(self):
+        _check(lib().flb_dq_synchronize(self._h))
+
+    def step(self, n=1):
+        _check(lib().flb_dq_step(self._h, int(n)))
+
+    def run(self, nsteps, sample_every=0):
+        _check(lib().flb_dq_run(self._h, int(nsteps), int(sample_every)))
+
+    def thermalize(self):
+        _check(lib().flb_dq_thermalize(self._h))
+
+    def accumulate(self):
+        _check(lib().flb_dq_accumulate(self._h))
+
+    def reset_correlators(self):
+        _check(lib().flb_dq_reset(self._h))
+
+    def read_correlators(self):
+        """(raw FP64 sums [nkinds][nz][ny][nx//2+1], number of samples)."""
+        nx, ny, nz = self.sides
+        out = np.empty((self.nkinds, nz, ny, nx // 2 + 1))
+        ns = ctypes.c_int64()
+        _check(lib().flb_dq_read(self._h, _dptr(out), out.size, ctypes.byref(ns)))
+        return out, ns.value
+
+    def get_populations(self):
+        nx, ny, nz = self.sides
+        out = np.empty((self.Q, nz, ny, nx))
+        _check(lib().flb_dq_get_populations(self._h, _dptr(out), out.size))
+        return out
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        nx, ny, nz = self.sides
+        assert f.size == self.Q * nx * ny * nz
+        _check(lib().flb_dq_set_populations(self._h, _dptr(f), f.size))
+
+    def conservation(self):
+        out = np.zeros(4)
+        _check(lib().flb_dq_conservation(self._h, _dptr(out)))
+        return out
+
+
+def dq_normalize(acc, nsamples, D, Q, sides, theta, rho0):
+    """Structure factors of the flb_dq.h kinds: S(rho) = <|rho_k|^2>/(V mu rho0),
+    S(j_a) = <|j_a|^2>/(V rho0 theta), S(u_a) = rho0 <|u_a|^2>/(V theta),
+    R(u_x,u_y) = rho0 <u_x u_y*>/(V theta), S(M^a) = <|M^a|^2>/(V mu rho0)."""
+    V = float(np.prod(sides))
+    mu = 3.0 * theta
+    m = np.asarray(acc) / max(int(nsamples), 1)
+    ax = "xyz"
+    out = {"S_rho": m[0] / (V * mu * rho0)}
+    k = 1
+    for a in range(D):
+        out["S_j" + ax[a]] = m[k] / (V * rho0 * theta)
+        k += 1
+    for a in range(D):
+        out["S_u" + ax[a]] = rho0 * m[k] / (V * theta)
+        k += 1
+    if D >= 2:
+        out["R_uxuy"] = rho0 * (m[k] + 1j * m[k + 1]) / (V * theta)
+        k += 2
+    for a in range(D + 1, Q):
+        out["S_M%d" % a] = m[k] / (V * mu * rho0)
+        k += 1
+    return out

@@ -10,7 +10,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["flb_runtime.hip", "flb_step.hip", "flb_corr.hip"]
+SOURCES = ["flb_runtime.hip", "flb_step.hip", "flb_corr.hip", "flb_dq.hip"]
 LIB = os.path.join(HERE, "libflb.so")
 ARCH = "gfx950"
 

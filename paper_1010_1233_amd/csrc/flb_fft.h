@@ -1,0 +1,208 @@
+// flb_fft.h -- LDS line transforms shared by the correlator kernels.
+//
+// The LDS transforms are in-place decimation in time with radix-2 stages
+// fused three at a time (radix 8): a thread loads eight elements, runs three
+// butterfly stages in registers and stores them back, so a 4096-point line
+// takes four passes and four barriers.  Lines of other lengths use
+// Bluestein's chirp-z convolution with a power-of-two work length.
+#pragma once
+
+#include "flb_device.h"
+
+namespace flbdev {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ __forceinline__ int bitrev(int j, int lg)
+{
+    return lg ? (int)(__brev((unsigned)j) >> (32 - lg)) : 0;
+}
+
+// exp(-2 pi i e / n) for 0 <= e < n, n a power of two <= kTwN, from the
+// half-circle table.
+__device__ __forceinline__ float2 twiddle(const float2 *tw, int e, int lgn)
+{
+    const int i = e << (kTwLog - lgn);
+    if (i < kTwN / 2) return tw[i];
+    const float2 w = tw[i - kTwN / 2];
+    return make_float2(-w.x, -w.y);
+}
+
+// LDS slot of element index i.  Rows are stored contiguously, and the
+// bit-reversed writes and first radix-8 passes would put a whole wave on a
+// few banks; one pad slot every 16 and every 256 elements spreads every
+// access pattern of the row kernel over all banks (two-way at most for
+// 8-byte elements).  Column layouts interleave lines and need no padding.
+template <bool PAD> __device__ __forceinline__ int lds_slot(int i)
+{
+    return PAD ? i + (i >> 4) + (i >> 8) : i;
+}
+
+__host__ __device__ constexpr int lds_padded_elems(int n) { return n + (n >> 4) + (n >> 8) + 1; }
+
+// w * exp(-/+ 2 pi i m / 2^(u+1)) for the compile-time root index (u, m):
+// multiplications by 1 and -i are free, by exp(-i pi/4) two multiplies.
+template <int U, int M, bool INV>
+__device__ __forceinline__ float2 rotate(float2 w)
+{
+    constexpr int q = (M << (2 - U)) & 7;  // the root as a multiple of pi/4
+    constexpr float c = 0.70710678118654752f;
+    float2 r = w;
+    if constexpr (q & 1) {  // exp(-i pi/4) (forward) or exp(+i pi/4) (inverse)
+        r = INV ? make_float2(c * (w.x - w.y), c * (w.x + w.y))
+                : make_float2(c * (w.x + w.y), c * (w.y - w.x));
+    }
+    if constexpr (q & 2) r = INV ? make_float2(-r.y, r.x) : make_float2(r.y, -r.x);  // -/+ i
+    if constexpr (q & 4) r = make_float2(-r.x, -r.y);
+    return r;
+}
+
+// One pass of R fused radix-2 stages s .. s+R-1 (1-based) over `nlines`
+// lines of length 2^lg; element e of line l at slot(l * ls + e * es).  The
+// pass needs twiddles exp(-2 pi i (k + m h) / (h 2^(u+1))) for sub-stage u;
+// all are w^(2^(R-1-u)) times a fixed 2^(u+1)-th root of unity, with
+// w = exp(-2 pi i k / (h 2^R)) the one value read from the table.
+template <int R, bool PAD, bool INV>
+__device__ __forceinline__ void dit_pass(float2 *buf, int lg, int s, int nlines, int ls, int es,
+                                         const float2 *tw)
+{
+    constexpr int G = 1 << R;
+    const int h = 1 << (s - 1);
+    const int lgg = lg - R;  // log2 of groups per line
+    const int total = nlines << lgg;
+    // Lines stored contiguously (ls > 1): neighbouring threads take
+    // neighbouring groups of one line.  Lines interleaved (ls == 1): they
+    // take the same group of neighbouring lines.  Either way a wave's LDS
+    // accesses are consecutive addresses.
+    const bool interleaved = (ls == 1);
+    const int st = h * es;
+    const bool linear = !PAD || (st & 255) == 0;  // padded slots advance uniformly
+    const int sst = PAD ? st + (st >> 4) + (st >> 8) : st;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        int l, g;
+        if (interleaved) {
+            g = idx / nlines;
+            l = idx - g * nlines;
+        } else {
+            l = idx >> lgg;
+            g = idx & ((1 << lgg) - 1);
+        }
+        const int k = g & (h - 1);
+        const int b = (g >> (s - 1)) << (s - 1 + R);
+        const int e0 = l * ls + (b + k) * es;
+        int slot[G];
+        if (linear) {
+            const int s0 = lds_slot<PAD>(e0);
+#pragma unroll
+            for (int j = 0; j < G; ++j) slot[j] = s0 + j * sst;
+        } else {
+#pragma unroll
+            for (int j = 0; j < G; ++j) slot[j] = lds_slot<PAD>(e0 + j * st);
+        }
+        float2 v[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) v[j] = buf[slot[j]];
+        float2 w = tw[k << (kTwLog - (s + R - 1))];
+        if (INV) w.y = -w.y;
+        float2 base[3];
+        base[R - 1] = w;
+        if constexpr (R >= 2) base[R - 2] = cmul(w, w);
+        if constexpr (R >= 3) base[0] = cmul(base[1], base[1]);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int half = 1 << u;
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                if (j & half) continue;
+                const int m = j & (half - 1);
+                float2 t;
+                if (u == 0) t = base[0];
+                else if (u == 1) t = m ? rotate<1, 1, INV>(base[1]) : base[1];
+                else t = m == 0 ? base[2] : m == 1 ? rotate<2, 1, INV>(base[2])
+                       : m == 2 ? rotate<2, 2, INV>(base[2]) : rotate<2, 3, INV>(base[2]);
+                const float2 x = cmul(t, v[j + half]);
+                v[j + half] = make_float2(v[j].x - x.x, v[j].y - x.y);
+                v[j] = make_float2(v[j].x + x.x, v[j].y + x.y);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) buf[slot[j]] = v[j];
+    }
+}
+
+// In-place transform of lines given in bit-reversed order; natural order out.
+template <bool PAD, bool INV>
+__device__ __forceinline__ void lds_fft_dit(float2 *buf, int lg, int nlines, int ls, int es, const float2 *tw)
+{
+    int s = 1;
+    while (s <= lg) {
+        const int r = lg - s + 1;
+        if (r >= 3) {
+            dit_pass<3, PAD, INV>(buf, lg, s, nlines, ls, es, tw);
+            s += 3;
+        } else if (r == 2) {
+            dit_pass<2, PAD, INV>(buf, lg, s, nlines, ls, es, tw);
+            s += 2;
+        } else {
+            dit_pass<1, PAD, INV>(buf, lg, s, nlines, ls, es, tw);
+            s += 1;
+        }
+        __syncthreads();
+    }
+}
+
+template <bool PAD>
+__device__ __forceinline__ void lds_bitrev(float2 *buf, int lg, int nlines, int ls, int es)
+{
+    const int m = 1 << lg;
+    for (int idx = threadIdx.x; idx < nlines * m; idx += blockDim.x) {
+        const int l = idx >> lg, j = idx & (m - 1);
+        const int r = bitrev(j, lg);
+        if (j < r) {
+            const int a = lds_slot<PAD>(l * ls + j * es), b = lds_slot<PAD>(l * ls + r * es);
+            const float2 t = buf[a];
+            buf[a] = buf[b];
+            buf[b] = t;
+        }
+    }
+    __syncthreads();
+}
+
+// Length-n DFT of lines whose inputs were written at bit-reversed positions
+// (already multiplied by the chirp for Bluestein lengths), in place; on exit
+// element k < n holds X_k in natural order.
+template <bool PAD>
+__device__ __forceinline__ void lds_line_dft(float2 *buf, const LinePlan &L, int nlines, int ls, int es,
+                             const float2 *tables)
+{
+    const float2 *tw = tables;
+    lds_fft_dit<PAD, false>(buf, L.log2m, nlines, ls, es, tw);
+    if (!L.bluestein) return;
+    const float2 *K = tables + L.kernel_off;
+    for (int idx = threadIdx.x; idx < nlines * L.m; idx += blockDim.x) {
+        const int l = idx >> L.log2m, j = idx & (L.m - 1);
+        float2 *p = buf + lds_slot<PAD>(l * ls + j * es);
+        *p = cmul(*p, K[j]);
+    }
+    __syncthreads();
+    lds_bitrev<PAD>(buf, L.log2m, nlines, ls, es);
+    lds_fft_dit<PAD, true>(buf, L.log2m, nlines, ls, es, tw);
+    const float2 *C = tables + L.chirp_off;
+    for (int idx = threadIdx.x; idx < nlines * L.n; idx += blockDim.x) {
+        const int l = idx / L.n, j = idx - l * L.n;
+        float2 *p = buf + lds_slot<PAD>(l * ls + j * es);
+        *p = cmul(*p, C[j]);
+    }
+    __syncthreads();
+}
+
+constexpr int kFftThreads = 512;  // threads of the transform kernels
+// Global loads of the transform kernels are issued kBatch per thread before
+// any of them is used, so that each thread keeps several requests in flight
+// (one load per loop iteration leaves the kernels latency-bound).
+constexpr int kBatch = 8;
+
+}  // namespace flbdev

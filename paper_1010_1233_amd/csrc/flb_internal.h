@@ -22,6 +22,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <string>
+#include <vector>
+
 namespace flbdev {
 
 constexpr int kThreads = 256;
@@ -161,5 +165,24 @@ hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nit
 hipError_t launch_corr_accum(const DeviceView &v, const CorrItem *items, int nitems, int set,
                              hipStream_t s);
 hipError_t launch_fill(double *p, size_t n, hipStream_t s);
+
+// ---------------------------------------------------------------------
+// Host helpers shared by the runtimes.
+// ---------------------------------------------------------------------
+// Records the message returned by flb_last_error(); returns code.
+int set_error(int code, const std::string &msg);
+
+// Line plans and their tables: the twiddle table first, then the chirp and
+// the transformed chirp kernel of every Bluestein length.
+struct LineTables {
+    std::vector<LinePlan> plans;
+    std::vector<float2> tables;
+    std::map<int, int> plan_of;
+    LineTables();
+    int plan_for(int n);  // index of the plan of length n (built on first use)
+};
+// Lengths the LDS line transforms support: powers of two up to 4096, other
+// lengths up to 2048.
+bool line_length_ok(int n);
 
 }  // namespace flbdev

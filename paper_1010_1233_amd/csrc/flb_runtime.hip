@@ -24,14 +24,18 @@
 using namespace flbdev;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-int fail(int code, const std::string &msg)
+int flbdev::set_error(int code, const std::string &msg)
 {
     g_err = msg;
     return code;
 }
+
+namespace {
+
+int fail(int code, const std::string &msg) { return set_error(code, msg); }
 
 #define FLB_HIP(call)                                                                       \
     do {                                                                                    \
@@ -305,65 +309,76 @@ void host_fft(std::vector<std::complex<double>> &a)
     }
 }
 
+}  // namespace
+
+bool flbdev::line_length_ok(int n)
+{
+    return is_pow2(n) ? n <= FLB_MAX_FFT_SIDE : n <= FLB_MAX_FFT_SIDE / 2;
+}
+
+flbdev::LineTables::LineTables() : tables(kTwN / 2)
+{
+    for (int k = 0; k < kTwN / 2; ++k) {
+        const double ang = -2.0 * M_PI * k / kTwN;
+        tables[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+}
+
+int flbdev::LineTables::plan_for(int n)
+{
+    auto it = plan_of.find(n);
+    if (it != plan_of.end()) return it->second;
+    LinePlan L;
+    std::memset(&L, 0, sizeof L);
+    L.n = n;
+    if (is_pow2(n)) {
+        L.m = n;
+        L.bluestein = 0;
+    } else {
+        L.m = 1 << log2i(2 * n - 1);
+        L.bluestein = 1;
+        L.chirp_off = (int64_t)tables.size();
+        std::vector<std::complex<double>> c(n);
+        for (int j = 0; j < n; ++j) {
+            const long long q = ((long long)j * j) % (2LL * n);  // exp(-i pi j^2 / n)
+            const double ang = -M_PI * (double)q / n;
+            c[j] = std::complex<double>(std::cos(ang), std::sin(ang));
+            tables.push_back(make_float2((float)c[j].real(), (float)c[j].imag()));
+        }
+        std::vector<std::complex<double>> b(L.m, 0.0);
+        for (int j = 0; j < n; ++j) {
+            b[j] = std::conj(c[j]);
+            if (j > 0) b[L.m - j] = std::conj(c[j]);
+        }
+        host_fft(b);
+        L.kernel_off = (int64_t)tables.size();
+        for (int j = 0; j < L.m; ++j) {
+            const auto v = b[j] / (double)L.m;  // inverse transform's 1/m folded in
+            tables.push_back(make_float2((float)v.real(), (float)v.imag()));
+        }
+    }
+    L.log2m = log2i(L.m);
+    const int id = (int)plans.size();
+    plans.push_back(L);
+    plan_of[n] = id;
+    return id;
+}
+
+namespace {
+
 int setup_correlators(flb_t *h)
 {
     if (h->corr_ready) return FLB_OK;
     // tables below replace device buffers that queued kernels may still read
     FLB_HIP(hipStreamSynchronize(h->stream));
     for (auto &P : h->params) {
-        const bool ok_x = is_pow2(P.nx) ? P.nx <= FLB_MAX_FFT_SIDE : P.nx <= FLB_MAX_FFT_SIDE / 2;
-        const bool ok_y = is_pow2(P.ny) ? P.ny <= FLB_MAX_FFT_SIDE : P.ny <= FLB_MAX_FFT_SIDE / 2;
-        if (!ok_x || !ok_y)
+        if (!line_length_ok(P.nx) || !line_length_ok(P.ny))
             return fail(FLB_ESIZE, "correlators support power-of-two sides up to FLB_MAX_FFT_SIDE "
                                    "and other sides up to FLB_MAX_FFT_SIDE/2");
     }
 
-    // tables: twiddles, then chirp and kernel of every Bluestein length
-    std::vector<float2> tables(kTwN / 2);
-    for (int k = 0; k < kTwN / 2; ++k) {
-        const double ang = -2.0 * M_PI * k / kTwN;
-        tables[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-    }
-    std::map<int, int> plan_of;
-    h->plans.clear();
-    auto plan_for = [&](int n) {
-        auto it = plan_of.find(n);
-        if (it != plan_of.end()) return it->second;
-        LinePlan L;
-        std::memset(&L, 0, sizeof L);
-        L.n = n;
-        if (is_pow2(n)) {
-            L.m = n;
-            L.bluestein = 0;
-        } else {
-            L.m = 1 << log2i(2 * n - 1);
-            L.bluestein = 1;
-            L.chirp_off = (int64_t)tables.size();
-            std::vector<std::complex<double>> c(n);
-            for (int j = 0; j < n; ++j) {
-                const long long q = ((long long)j * j) % (2LL * n);  // exp(-i pi j^2 / n)
-                const double ang = -M_PI * (double)q / n;
-                c[j] = std::complex<double>(std::cos(ang), std::sin(ang));
-                tables.push_back(make_float2((float)c[j].real(), (float)c[j].imag()));
-            }
-            std::vector<std::complex<double>> b(L.m, 0.0);
-            for (int j = 0; j < n; ++j) {
-                b[j] = std::conj(c[j]);
-                if (j > 0) b[L.m - j] = std::conj(c[j]);
-            }
-            host_fft(b);
-            L.kernel_off = (int64_t)tables.size();
-            for (int j = 0; j < L.m; ++j) {
-                const auto v = b[j] / (double)L.m;  // inverse transform's 1/m folded in
-                tables.push_back(make_float2((float)v.real(), (float)v.imag()));
-            }
-        }
-        L.log2m = log2i(L.m);
-        const int id = (int)h->plans.size();
-        h->plans.push_back(L);
-        plan_of[n] = id;
-        return id;
-    };
+    LineTables lt;
+    auto plan_for = [&](int n) { return lt.plan_for(n); };
 
     int64_t spec = 0, acc = 0, fld = 0;
     int nparts = 0;
@@ -386,7 +401,7 @@ int setup_correlators(flb_t *h)
             h->cols_b_lds =
                 std::max(h->cols_b_lds, P.col_q * 16 * h->nfld * (int)sizeof(float2));
         } else {
-            max_my_general = std::max(max_my_general, h->plans[P.line_y].m);
+            max_my_general = std::max(max_my_general, lt.plans[P.line_y].m);
         }
         P.spec_base = spec;
         P.acc_base = acc;
@@ -397,7 +412,7 @@ int setup_correlators(flb_t *h)
         if (h->moments) fld += ((int64_t)kMomentFields * P.nx * P.ny + 63) / 64 * 64;
         P.fld_tiles_x = (P.nx + kThreads - 1) / kThreads;
         // one conservation partial per row group of the row kernel
-        const int mx = h->plans[P.line_x].m;
+        const int mx = lt.plans[P.line_x].m;
         const int rb = std::max(1, std::min(P.ny, 4096 / mx));
         P.fld_part0 = nparts;
         P.fld_nparts = (P.ny + rb - 1) / rb;
@@ -408,6 +423,7 @@ int setup_correlators(flb_t *h)
     h->cols_cb = std::max(1, std::min(16, 8192 / max_my_general));
     h->cols_lds = max_my_general * h->cols_cb * (int)sizeof(float2);
 
+    h->plans = lt.plans;
     std::vector<CorrItem> rows, cols, accum, cols_a, cols_b, flds, cols_a_m, cols_m, rows_m;
     std::vector<CorrItem> rows_blue, flush;
     for (size_t l = 0; l < h->params.size(); ++l) {
@@ -416,7 +432,7 @@ int setup_correlators(flb_t *h)
             const int ntiles = P.fld_tiles_x * ((P.ny + kFieldRows - 1) / kFieldRows);
             for (int t = 0; t < ntiles; ++t) flds.push_back({(int32_t)l, t, 0, 0});
         }
-        const int mx = h->plans[P.line_x].m;
+        const int mx = lt.plans[P.line_x].m;
         // rows per block: up to 4096 line elements (32 KB of LDS), which the
         // row kernels assume
         const int rb = std::max(1, std::min(P.ny, 4096 / mx));
@@ -425,7 +441,7 @@ int setup_correlators(flb_t *h)
         const int slots = rb * mx + (rb * mx >> 4) + (rb * mx >> 8) + 1;
         h->rows_lds = std::max(h->rows_lds, slots * (int)sizeof(float2));
         for (int y = 0, part = P.fld_part0; y < P.ny; y += rb, ++part) {
-            (h->plans[P.line_x].bluestein ? rows_blue : rows).push_back({(int32_t)l, y, rb, part});
+            (lt.plans[P.line_x].bluestein ? rows_blue : rows).push_back({(int32_t)l, y, rb, part});
             if (h->moments)
                 for (int sig = 0; sig < 3; ++sig) rows_m.push_back({(int32_t)l, y, rb, sig});
         }
@@ -490,7 +506,7 @@ int setup_correlators(flb_t *h)
         (rc = upload(&h->d_cols_m, cols_m)) || (rc = upload(&h->d_rows_m, rows_m)) ||
         (rc = upload(&h->d_rows_blue, rows_blue)) || (rc = upload(&h->d_flush, flush)) ||
         (rc = upload(&h->d_plans, h->plans)) ||
-        (rc = upload(&h->d_tables, tables)) || (rc = upload(&h->d_params, h->params)))
+        (rc = upload(&h->d_tables, lt.tables)) || (rc = upload(&h->d_params, h->params)))
         return rc;
     FLB_HIP(hipMalloc((void **)&h->d_spec, spec * sizeof(float2)));
     FLB_HIP(hipMalloc((void **)&h->d_acc, acc * sizeof(double)));

@@ -19,9 +19,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "flb.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"\b(flb_[a-z_0-9]+)\s*\(", src)
+    names = []
+    for h in ("flb.h", "flb_dq.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"\b(flb_[a-z_0-9]+)\s*\(", src)
     return sorted(set(names))
 
 
@@ -115,3 +117,46 @@ def test_batch_rejects_bad_spec(flb):
     assert not flb.lib().flb_create_batch(2, specs, 1, 0, 0)
     assert "lattice 1" in flb.last_error()
     assert not flb.lib().flb_create_batch(0, specs, 1, 0, 0)
+
+
+def test_dq_tables_on_the_host(flb):
+    """The library's tables of the other velocity sets are orthonormal under
+    the weights (Eq. 4) and D2Q9's equal the printed rows of Eq. (9)."""
+    for model, q in (("D1Q3", 3), ("D2Q9", 9), ("D3Q15", 15)):
+        D, v, w, m = flb.dq_tables(model)
+        assert len(w) == q and abs(w.sum() - 1) < 1e-15
+        assert np.abs((m * w) @ m.T - np.eye(q)).max() < 1e-14
+    _, v, w, m = flb.dq_tables("D2Q9")
+    s3, s32, s6 = np.sqrt(3), np.sqrt(1.5), np.sqrt(6)
+    eq9_row6 = np.array([0, -s32, 0, s32, 0, s6, -s6, -s6, s6])
+    assert np.abs(m[6] - eq9_row6).max() < 1e-14
+    assert np.abs(m[8] - np.array([0.5, -1, -1, -1, -1, 2, 2, 2, 2])).max() < 1e-14
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(model=99), "unknown model"),
+    (dict(n=(1, 8, 8)), ">= 2"),
+    (dict(n=(8, 8, 2), model=29), "unused sides"),
+    (dict(tau0=0.5), "tau[4]"),
+    (dict(theta=-1.0), "theta"),
+    (dict(u0=(0.5, 0.3, 0.2)), "sound speed"),
+    (dict(u0=(0.1, 0.0, 0.0), model=13, n=(16, 1, 1), u0y=0.1), "unused axis"),
+    (dict(n=(1024, 1024, 1024)), "4 GiB"),
+    (dict(flags=8), "flags"),
+])
+def test_dq_invalid_creation_is_rejected_on_the_host(flb, kw, msg):
+    model = kw.get("model", 315)
+    n = np.ascontiguousarray(kw.get("n", (8, 8, 8)), dtype=np.int32)
+    tau = np.ones(15)
+    if "tau0" in kw:
+        tau[4] = kw["tau0"]
+    u0 = list(kw.get("u0", (0.0, 0.0, 0.0)))
+    if "u0y" in kw:
+        u0[1] = kw["u0y"]
+    u = np.ascontiguousarray(u0, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    h = flb.lib().flb_dq_create(model, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                tau.ctypes.data_as(dp), kw.get("theta", 1e-4), 1.0,
+                                u.ctypes.data_as(dp), 1, 0, kw.get("flags", 0))
+    assert not h
+    assert msg in flb.last_error()
