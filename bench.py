@@ -6,8 +6,8 @@
 One benchmark step is one pass of the whole path on the workload: ten fused
 collide+noise+stream updates of every site and one correlator sample (field
 extraction with the FP64 conservation sums of the sampled state, 2-D
-transforms, FP64 accumulation of the fifteen products).  W untimed steps, then K timed steps bracketed by
-device synchronisation.  `value` is site updates per second (GLUPS) over the
+transforms, FP64 accumulation of the fifteen products).  W untimed steps,
+then K timed steps bracketed by device synchronisation.  `value` is site updates per second (GLUPS) over the
 timed region, inputs resident in HBM.
 
 The JSON line also carries
@@ -21,7 +21,9 @@ The JSON line also carries
   forms         step-kernel rates of the other storage formats and of the
                 noise-free step (the paper's ghost-noise overhead), and the
                 batched forms (96 x 512^2 Galilean-invariance sweep, 64
-                uneven lattices) through graph-replayed sampling periods.
+                uneven lattices) through graph-replayed sampling periods,
+                and the other velocity sets (D3Q15 at 256^3 with its
+                correlators, D1Q3 at 2^26 sites).
 Every handle's step-kernel launch shape is chosen by the library's autotuner
 before timing.
 """
@@ -126,6 +128,40 @@ def batched_form(torch, flb, stream, specs, storage, periods=10):
             "step_glups": sites / (step_ms * 1e-3) / 1e9,
             "step_achieved_GBs": 18 * bpv * sites / (step_ms * 1e-3) / 1e9,
             "sample_ms": max(ms_period - SAMPLE_EVERY * step_ms, 0.0)}
+
+
+def velocity_set_form(torch, flb, stream, model, sides, sample=True, periods=5):
+    """Step (and, where the sides allow correlators, whole-path) rates of one
+    lattice of another velocity set: FP32 deviations, Q loads + Q stores per
+    site."""
+    D, _, w, _ = flb.dq_tables(model)
+    Q = len(w)
+    tau = [1.0] * (D + 1) + [0.8] * (D * (D + 1) // 2) + [1.0] * (Q - 1 - D - D * (D + 1) // 2)
+    g = flb.DqLattice(model, sides, tau, 1e-4, u0=[0.05, 0.0, 0.0][:D], seed=7)
+    g.set_stream(stream)
+    g.thermalize()
+    sites = g.sides[0] * g.sides[1] * g.sides[2]
+    g.step(5)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.step(20)
+    e1.record(stream)
+    e1.synchronize()
+    step_ms = e0.elapsed_time(e1) / 20
+    out = {"sites": sites, "bytes_per_site": 2 * Q * 4,
+           "step_glups": sites / (step_ms * 1e-3) / 1e9,
+           "step_achieved_GBs": 2 * Q * 4 * sites / (step_ms * 1e-3) / 1e9}
+    if sample:
+        g.run(2 * SAMPLE_EVERY, SAMPLE_EVERY)
+        e0.record(stream)
+        g.run(periods * SAMPLE_EVERY, SAMPLE_EVERY)
+        e1.record(stream)
+        e1.synchronize()
+        ms_period = e0.elapsed_time(e1) / periods
+        out["path_glups"] = SAMPLE_EVERY * sites / (ms_period * 1e-3) / 1e9
+        out["sample_ms"] = max(ms_period - SAMPLE_EVERY * step_ms, 0.0)
+    g.close()
+    return out
 
 
 def cpu_baseline(workloads, name, max_side=2048):
@@ -300,6 +336,13 @@ def main():
                                 ("batched_uneven_64", workloads.uneven_batch_specs())):
                 forms[name] = batched_form(torch, flb, stream, specs, args.storage)
                 print(f"bench: {name} {forms[name]}", file=sys.stderr, flush=True)
+            # the other velocity sets the paper tested (Sec. 3)
+            forms["d3q15_256x256x256"] = velocity_set_form(torch, flb, stream, "D3Q15",
+                                                           (256, 256, 256))
+            forms["d1q3_67108864"] = velocity_set_form(torch, flb, stream, "D1Q3", (1 << 26,),
+                                                       sample=False)
+            print(f"bench: velocity sets {forms['d3q15_256x256x256']} {forms['d1q3_67108864']}",
+                  file=sys.stderr, flush=True)
         out["forms"] = forms
 
     if not args.no_cpu_baseline:

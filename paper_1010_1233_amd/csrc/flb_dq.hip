@@ -84,7 +84,18 @@ __device__ __forceinline__ bool dq_site(const DqParams &P, int &x, int &y, int &
     return x < P.n[0];
 }
 
-template <int MODEL>
+// Element `off` of a buffer through a 32-bit byte offset from a wave-uniform
+// base (a buffer is below 4 GiB).
+__device__ __forceinline__ const float *dq_at(const float *base, uint32_t off)
+{
+    return reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + off * 4u);
+}
+__device__ __forceinline__ float *dq_at(float *base, uint32_t off)
+{
+    return reinterpret_cast<float *>(reinterpret_cast<char *>(base) + off * 4u);
+}
+
+template <int MODEL, bool NT = false>
 __device__ __forceinline__ void dq_pull(const float *__restrict__ src, const DqParams &P, int x, int y,
                                         int z, uint32_t V, float (&d)[DqSet<MODEL>::Q])
 {
@@ -95,7 +106,8 @@ __device__ __forceinline__ void dq_pull(const float *__restrict__ src, const DqP
         const int xs = S::v[i][0] ? wrapi(x - S::v[i][0], nx) : x;
         const int ys = S::v[i][1] ? wrapi(y - S::v[i][1], ny) : y;
         const int zs = S::v[i][2] ? wrapi(z - S::v[i][2], nz) : z;
-        d[i] = src[(uint32_t)i * V + (uint32_t)xs + (uint32_t)nx * ((uint32_t)ys + (uint32_t)ny * (uint32_t)zs)];
+        d[i] = gload<NT>(dq_at(src, (uint32_t)i * V + (uint32_t)xs +
+                                        (uint32_t)nx * ((uint32_t)ys + (uint32_t)ny * (uint32_t)zs)));
     }
 }
 
@@ -113,7 +125,9 @@ __device__ __forceinline__ void dq_moments(const DqParams &P, const float (&d)[D
     }
 }
 
-template <int MODEL, bool NOISE>
+// NT: streaming (non-temporal) loads and stores, for buffers well beyond the
+// last-level cache.
+template <int MODEL, bool NOISE, bool NT>
 __global__ __launch_bounds__(kDqThreads) void dq_step_kernel(const float *__restrict__ src,
                                                              float *__restrict__ dst,
                                                              const DqParams *__restrict__ Pp,
@@ -127,7 +141,7 @@ __global__ __launch_bounds__(kDqThreads) void dq_step_kernel(const float *__rest
     const uint32_t V = (uint32_t)P.n[0] * (uint32_t)P.n[1] * (uint32_t)P.n[2];
     const uint32_t site = (uint32_t)x + (uint32_t)P.n[0] * ((uint32_t)y + (uint32_t)P.n[1] * (uint32_t)z);
     float d[Q], M[Q];
-    dq_pull<MODEL>(src, P, x, y, z, V, d);
+    dq_pull<MODEL, NT>(src, P, x, y, z, V, d);
     dq_moments<MODEL>(P, d, M);
     const float rho = P.rho0 + M[0];
     const float ir = 1.0f / rho;
@@ -182,7 +196,7 @@ __global__ __launch_bounds__(kDqThreads) void dq_step_kernel(const float *__rest
 #pragma unroll
         for (int al = 0; al < D; ++al)
             if (S::v[i][al]) c += S::v[i][al] > 0 ? 3.f * lj[al] : -3.f * lj[al];
-        dst[(uint32_t)i * V + out] = d[i] + fmaf(-P.w[i], c, inc[i]);
+        gstore<NT>(dq_at(dst, (uint32_t)i * V + out), d[i] + fmaf(-P.w[i], c, inc[i]));
     }
 }
 
@@ -486,6 +500,7 @@ struct flb_dq {
     double rho0 = 1.0;
     uint64_t seed = 0;
     bool noise = false;
+    bool nontemporal = false;  // streaming accesses (buffers beyond 256 MB)
     DqParams P;
     DqParams *d_P = nullptr;
     float *pops[2] = {nullptr, nullptr};
@@ -599,12 +614,19 @@ int enqueue_steps(flb_dq *h, int64_t n)
         float *dst = h->pops[h->cur ^ 1];
         DQ_HIP(dispatch(h->model, [&](auto mc) {
             constexpr int MODEL = decltype(mc)::value;
-            if (h->noise)
-                hipLaunchKernelGGL((dq_step_kernel<MODEL, true>), dim3(grid_sites(h)),
-                                   dim3(kDqThreads), 0, h->stream, src, dst, h->d_P, t, k0, k1);
+            const dim3 grid(grid_sites(h)), block(kDqThreads);
+            if (h->noise && h->nontemporal)
+                hipLaunchKernelGGL((dq_step_kernel<MODEL, true, true>), grid, block, 0, h->stream,
+                                   src, dst, h->d_P, t, k0, k1);
+            else if (h->noise)
+                hipLaunchKernelGGL((dq_step_kernel<MODEL, true, false>), grid, block, 0, h->stream,
+                                   src, dst, h->d_P, t, k0, k1);
+            else if (h->nontemporal)
+                hipLaunchKernelGGL((dq_step_kernel<MODEL, false, true>), grid, block, 0, h->stream,
+                                   src, dst, h->d_P, t, k0, k1);
             else
-                hipLaunchKernelGGL((dq_step_kernel<MODEL, false>), dim3(grid_sites(h)),
-                                   dim3(kDqThreads), 0, h->stream, src, dst, h->d_P, t, k0, k1);
+                hipLaunchKernelGGL((dq_step_kernel<MODEL, false, false>), grid, block, 0,
+                                   h->stream, src, dst, h->d_P, t, k0, k1);
             return hipGetLastError();
         }));
         h->cur ^= 1;
@@ -816,6 +838,7 @@ flb_dq_t *flb_dq_create(int model, const int32_t n[3], const double *tau, double
         return bail(FLB_EHIP, "stream creation failed");
     h->stream = h->own;
     const size_t bytes = (size_t)Q * h->V * sizeof(float);
+    h->nontemporal = bytes > 256u * 1024 * 1024;
     if (hipMalloc((void **)&h->pops[0], 2 * bytes) != hipSuccess)
         return bail(FLB_ENOMEM, "population buffers: out of device memory");
     h->pops[1] = h->pops[0] + (size_t)Q * h->V;

@@ -201,3 +201,19 @@ def test_d1q3_structure_factors_are_one_on_gpu(flb):
         mean = np.stack([b[k] for b in blocks]).mean(0)[m].mean()
         note(f"  <{k}> - 1 = {mean - 1:.2e}")
         assert abs(mean - 1) < 3e-3
+
+
+def test_large_lattice_with_streaming_accesses(flb, oracle_lib):
+    """A D3Q15 lattice whose population buffer exceeds 256 MB takes the
+    streaming (non-temporal) step: one noisy step from the thermal start
+    against the oracle."""
+    sides = (256, 192, 128)
+    note("large D3Q15", sides)
+    tau = _tau(3, 15)
+    g = flb.DqLattice("D3Q15", sides, tau, 1e-4, u0=(0.02, 0.0, 0.01), seed=6)
+    o = oracle_lib.DqLattice("D3Q15", sides, tau, 1e-4, u0=(0.02, 0.0, 0.01), seed=6)
+    g.thermalize()
+    o.thermalize()
+    g.step(2)
+    o.step(2)
+    assert np.abs(g.get_populations() - o.f).max() < 2e-6
