@@ -12,10 +12,11 @@ timed region, inputs resident in HBM.
 
 The JSON line also carries
   roofline      the step kernel (dominant): algorithmic bytes per launch
-                (9 reads + 9 writes per site) over its average duration,
-                measured with HIP events on the stream it runs on, within
-                the timed region; HBM traffic from rocprofv3 counters when a
-                summary for the current kernel source is committed;
+                (9 reads + 9 writes per site; the time-blocked kernel does
+                two steps per launch on the same bytes) over its average
+                duration, measured with HIP events on the stream it runs on,
+                within the timed region; HBM traffic from rocprofv3 counters
+                when a summary for the current kernel source is committed;
   cpu_baseline  the FP64 oracle, single thread, on a bounded sample of the
                 same workload;
   forms         step-kernel rates of the other storage formats and of the
@@ -53,12 +54,30 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def shape_key(workload, storage, shape):
+def shape_key(workload, storage, shape, blocking=(1, 64)):
+    """Key of a launch shape: one-step kernels by threads x sites, the
+    two-step kernel by its tile width."""
     tw, sites, nt = shape
+    if blocking[0] == 2:
+        return f"{workload}/{storage}/step2_{blocking[1]}/nt{int(bool(nt))}"
     return f"{workload}/{storage}/{tw}x{sites}/nt{int(bool(nt))}"
 
 
-def measured_traffic(workload, storage, shape):
+def launch_figures(g, sites, step_ms):
+    """The dominant kernel's launch: which kernel, steps per launch, its
+    duration and its algorithmic bytes (one read and one write of the 9
+    populations per site and launch, whatever the steps per launch)."""
+    steps, tile2 = g.time_blocking()
+    bpv = g.storage_info()[1]
+    launch_ms = steps * step_ms
+    algo = 18 * bpv * sites
+    return {"kernel": "step2_kernel" if steps == 2 else STEP_KERNEL,
+            "steps_per_launch": steps, "avg_launch_ms": launch_ms,
+            "algorithmic_bytes_per_launch": algo,
+            "achieved_GBs": algo / (launch_ms * 1e-3) / 1e9}
+
+
+def measured_traffic(workload, storage, shape, blocking=(1, 64)):
     """HBM bytes per step-kernel launch of this launch shape from the
     committed counter summary, or None when it is missing or was taken on a
     different kernel source."""
@@ -68,7 +87,7 @@ def measured_traffic(workload, storage, shape):
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    e = d.get(shape_key(workload, storage, shape))
+    e = d.get(shape_key(workload, storage, shape, blocking))
     if not e or e.get("kernel_source_hash") != kernel_source_hash():
         return None
     return e.get("bytes_per_launch")
@@ -84,8 +103,15 @@ def sweep_shapes(flb, workloads, name, storage, steps=5):
             for nt in (0, 1):
                 g.set_step_config(tw, sites, nt)
                 g.step(steps)
+    for tile2 in (64, 128):
+        for nt in (0, 1):
+            g.set_step_config(256, 1, nt)
+            g.set_time_blocking(2, tile2)
+            g.step(2 * steps)
+    g.set_time_blocking(1, 64)
     g.synchronize()
-    print(f"sweep-shapes: {name} {storage}: 18 shapes x {steps} steps", flush=True)
+    print(f"sweep-shapes: {name} {storage}: 18 one-step shapes x {steps} steps, "
+          f"4 two-step shapes x {steps} launches", flush=True)
 
 
 def make_lattice(flb, workloads, name, storage):
@@ -121,12 +147,14 @@ def batched_form(torch, flb, stream, specs, storage, periods=10):
     e1.synchronize()
     ms_period = e0.elapsed_time(e1) / periods
     step_ms = time_step_kernel(torch, b, stream, 20)
-    bpv = b.storage_info()[1]
+    lf = launch_figures(b, sites, step_ms)
+    shape = list(shape) + [list(b.time_blocking())]
     b.close()
-    return {"lattices": len(specs), "sites": sites, "launch_shape": list(shape),
+    return {"lattices": len(specs), "sites": sites, "launch_shape": shape,
             "path_glups": SAMPLE_EVERY * sites / (ms_period * 1e-3) / 1e9,
             "step_glups": sites / (step_ms * 1e-3) / 1e9,
-            "step_achieved_GBs": 18 * bpv * sites / (step_ms * 1e-3) / 1e9,
+            "steps_per_launch": lf["steps_per_launch"],
+            "step_achieved_GBs": lf["achieved_GBs"],
             "sample_ms": max(ms_period - SAMPLE_EVERY * step_ms, 0.0)}
 
 
@@ -239,7 +267,9 @@ def main():
           f"step config={g.step_config()}", file=sys.stderr, flush=True)
     g.thermalize()
     tuned, _ = g.autotune(50)
-    print(f"bench: autotuned step config {tuned}", file=sys.stderr, flush=True)
+    blocking = g.time_blocking()
+    print(f"bench: autotuned step config {tuned}, steps per launch {blocking}", file=sys.stderr,
+          flush=True)
     cons0 = g.conservation()
 
     def bench_step(i, ev=None):
@@ -265,10 +295,9 @@ def main():
     step_ms = sum(a.elapsed_time(b) for a, b in evs) / (args.steps * SAMPLE_EVERY)
     ms_per_step = elapsed * 1e3 / args.steps
     value = args.steps * SAMPLE_EVERY * V / elapsed / 1e9
-    bytes_per_value = g.storage_info()[1]
-    algo_bytes = 18 * bytes_per_value * V  # 9 loads + 9 stores per site
-    achieved = algo_bytes / (step_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, args.storage, tuned)
+    launch = launch_figures(g, V, step_ms)
+    achieved = launch["achieved_GBs"]
+    traffic = measured_traffic(args.workload, args.storage, tuned, blocking)
     drift = float(abs(g.sample_conservation()[0] - cons0[0]))
 
     # correlator sanity (matched S(k)): k-averaged S(rho) over the run
@@ -297,9 +326,11 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": STEP_KERNEL,
-                     "algorithmic_bytes_per_launch": algo_bytes,
-                     "avg_launch_ms": step_ms, "launch_shape": list(tuned)},
+                     "traffic": traffic, "kernel": launch["kernel"],
+                     "steps_per_launch": launch["steps_per_launch"],
+                     "algorithmic_bytes_per_launch": launch["algorithmic_bytes_per_launch"],
+                     "avg_launch_ms": launch["avg_launch_ms"],
+                     "launch_shape": list(tuned) + [list(blocking)]},
         "step_kernel_glups": V / (step_ms * 1e-3) / 1e9,
         "sample_ms": max(ms_per_step - SAMPLE_EVERY * step_ms, 0.0),
         "mass_drift": drift,
@@ -316,11 +347,12 @@ def main():
                 h.set_stream(stream)
                 h.thermalize()
                 h.autotune(50)
-                time_step_kernel(torch, h, stream, 5)
+                time_step_kernel(torch, h, stream, 6)
                 ms = time_step_kernel(torch, h, stream, 50)
-                b = h.storage_info()[1]
+                lf = launch_figures(h, V, ms)
                 forms[st] = {"step_glups": V / (ms * 1e-3) / 1e9,
-                             "achieved_GBs": 18 * b * V / (ms * 1e-3) / 1e9}
+                             "steps_per_launch": lf["steps_per_launch"],
+                             "achieved_GBs": lf["achieved_GBs"]}
                 h.close()
             cq = dict(workloads.CONFIGS[args.workload])
             h = flb.Lattice(cq["nx"], cq["ny"], cq["tau"], 0.0, rho0=cq["rho0"], u0=cq["u0"],

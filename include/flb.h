@@ -246,10 +246,22 @@ int flb_storage_info(flb_t *h, int32_t *storage, int32_t *bytes_per_value);
 int flb_set_step_config(flb_t *h, int tile_w, int sites, int nontemporal);
 int flb_get_step_config(flb_t *h, int *tile_w, int *sites, int *nontemporal);
 
+/* Time blocking: steps_per_launch = 2 runs pairs of steps in one kernel
+ * launch (tiles of tile_w x 1024/tile_w sites, tile_w 64 or 128; each block
+ * collides its tile and a one-site halo at t, keeps them on chip and
+ * collides the tile again at t+1), so the populations cross HBM once per two
+ * steps; an odd last step uses the one-step kernel.  Every site sees the
+ * same arithmetic, noise counters and storage rounding as with one step per
+ * launch: results do not depend on it.  steps_per_launch = 1 (default) turns
+ * it off.  FLB_EINVAL for other values. */
+int flb_set_time_blocking(flb_t *h, int steps_per_launch, int tile_w);
+int flb_get_time_blocking(flb_t *h, int *steps_per_launch, int *tile_w);
+
 /* Chooses the step kernel's launch shape by timing every supported shape
  * (nsteps >= 1 steps each, HIP events on the handle's stream, in three
  * round-robin passes of which each shape keeps its fastest) on this
- * handle's own lattices, and keeps the fastest shape.  The populations and the
+ * handle's own lattices, the time-blocked shapes included (per step), and
+ * keeps the fastest.  The populations and the
  * step counter are restored afterwards, so results are unchanged.  When the
  * environment variable FLB_AUTOTUNE_CACHE names a file, choices are read
  * from and appended to it, keyed by storage format, lattice count, total

@@ -89,6 +89,8 @@ SIGNATURES = {
     "flb_set_step_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int]),
     "flb_get_step_config": (ctypes.c_int, [ctypes.c_void_p, _intp, _intp, _intp]),
+    "flb_set_time_blocking": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "flb_get_time_blocking": (ctypes.c_int, [ctypes.c_void_p, _intp, _intp]),
     "flb_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp]),
     # other velocity sets (flb_dq.h)
     "flb_dq_tables": (ctypes.c_int, [ctypes.c_int, _i32p, _i32p, _i32p, _dp, _dp]),
@@ -260,10 +262,22 @@ class Lattice:
                                          ctypes.byref(c)))
         return a.value, b.value, bool(c.value)
 
+    def set_time_blocking(self, steps_per_launch, tile_w=64):
+        """1: one step per kernel launch; 2: pairs of steps per launch (the
+        populations cross HBM once per two steps), tiles of tile_w x
+        1024/tile_w sites (tile_w 64 or 128)."""
+        _check(lib().flb_set_time_blocking(self._h, int(steps_per_launch), int(tile_w)))
+
+    def time_blocking(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(lib().flb_get_time_blocking(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def autotune(self, nsteps=10):
-        """Time every step-kernel launch shape on this handle and keep the
-        fastest (state unchanged); returns the chosen (tile_w, sites,
-        nontemporal) and its ms per step."""
+        """Time every step-kernel launch shape on this handle, the
+        time-blocked ones included, and keep the fastest (state unchanged);
+        returns the chosen (tile_w, sites, nontemporal) and its ms per step
+        (``time_blocking()`` tells whether pairs of steps won)."""
         ms = ctypes.c_double()
         _check(lib().flb_autotune(self._h, int(nsteps), ctypes.byref(ms)))
         return self.step_config(), ms.value

@@ -57,6 +57,18 @@ template <> struct Codec<kF32> {
     static __device__ __forceinline__ T encode(float d, const LatticeParams &, int) { return d; }
 };
 
+// The FP32 value of an encode, materialised before its conversion to 16
+// bits: otherwise the compiler merges the FMA and the conversion into one
+// mixed-precision instruction in most contexts but not all (it rounds once,
+// the separate pair twice), and results would depend on the launch shape.
+// The empty statement is opaque to instruction selection but, having no side
+// effects, leaves the scheduler free.
+__device__ __forceinline__ float round_point(float q)
+{
+    asm("" : "+v"(q));
+    return q;
+}
+
 // bfloat16 through the native type: gfx950 converts with one
 // round-to-nearest-even instruction (v_cvt_pk_bf16_f32).
 template <> struct Codec<kBF16> {
@@ -67,7 +79,7 @@ template <> struct Codec<kBF16> {
     }
     static __device__ __forceinline__ T encode(float d, const LatticeParams &P, int i)
     {
-        return (T)fmaf(d, P.inv_scale[i], -P.feq_scaled[i]);
+        return (T)round_point(fmaf(d, P.inv_scale[i], -P.feq_scaled[i]));
     }
 };
 
@@ -79,7 +91,7 @@ template <> struct Codec<kF16> {
     }
     static __device__ __forceinline__ T encode(float d, const LatticeParams &P, int i)
     {
-        return (T)fmaf(d, P.inv_scale[i], -P.feq_scaled[i]);
+        return (T)round_point(fmaf(d, P.inv_scale[i], -P.feq_scaled[i]));
     }
 };
 

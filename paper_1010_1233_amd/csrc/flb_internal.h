@@ -127,6 +127,11 @@ hipError_t launch_step(const DeviceView &v, const StepItem *items, int nitems, i
                        int sites, uint32_t step_add, bool nontemporal, bool noise,
                        hipStream_t s);
 bool step_tile_supported(int tw, int r);
+// Two steps per launch: tiles of tile_w x (1024 / tile_w) sites, tile_w 64
+// or 128; items enumerate each lattice's tiles of that shape.
+hipError_t launch_step2(const DeviceView &v, const StepItem *items, int nitems, int tile_w,
+                        uint32_t step_add, bool nontemporal, bool noise, hipStream_t s);
+bool step2_tile_supported(int tw);
 hipError_t launch_advance_step(uint32_t *step, uint32_t n, hipStream_t s);
 hipError_t launch_init(const DeviceView &v, int lattice, int64_t plane, hipStream_t s);
 hipError_t launch_get(const DeviceView &v, int lattice, int nx, int ny, double *out_dev,

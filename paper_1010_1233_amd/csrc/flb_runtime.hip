@@ -89,6 +89,10 @@ struct flb {
     bool nontemporal = false;
     StepItem *d_items = nullptr;
     int nitems = 0;
+    // time blocking: steps per launch (1 or 2) and the two-step kernel's tile
+    int tblock = 1, tile2 = 64;
+    StepItem *d_items2 = nullptr;
+    int nitems2 = 0;
     int64_t t = 0;
 
     // correlators
@@ -268,8 +272,22 @@ int build_step_items(flb_t *h)
     h->nitems = (int)items.size();
     int rc = upload(&h->d_items, items);
     if (rc) return rc;
+    // the two-step kernel's tiles: tile2 x (1024 / tile2) sites
+    std::vector<StepItem> items2;
+    const int TH2 = 1024 / h->tile2;
+    for (size_t l = 0; l < h->params.size(); ++l) {
+        const LatticeParams &P = h->params[l];
+        const int n2 = ((P.nx + h->tile2 - 1) / h->tile2) * ((P.ny + TH2 - 1) / TH2);
+        for (int t = 0; t < n2; ++t) items2.push_back({(int32_t)l, t});
+    }
+    items2 = xcd_order(items2, StepItem{-1, 0});
+    h->nitems2 = (int)items2.size();
+    if ((rc = upload(&h->d_items2, items2))) return rc;
     return upload(&h->d_params, h->params);
 }
+
+// Kernel launches for n steps (the buffer parity flips once per launch).
+int64_t step_launches(const flb_t *h, int64_t n) { return h->tblock == 2 ? n / 2 + n % 2 : n; }
 
 void clear_graphs(flb_t *h)
 {
@@ -560,9 +578,18 @@ int flush_pending(flb_t *h)
 }
 
 // n steps from the device counter value; the counter is advanced afterwards.
+// With time blocking, pairs of steps go through the two-step kernel and an
+// odd last step through the one-step kernel.
 int enqueue_steps(flb_t *h, int64_t n, hipStream_t s)
 {
-    for (int64_t k = 0; k < n; ++k) {
+    int64_t k = 0;
+    if (h->tblock == 2)
+        for (; k + 2 <= n; k += 2) {
+            FLB_HIP(launch_step2(h->view(), h->d_items2, h->nitems2, h->tile2, (uint32_t)k,
+                                 h->nontemporal, h->noise, s));
+            h->cur ^= 1;
+        }
+    for (; k < n; ++k) {
         FLB_HIP(launch_step(h->view(), h->d_items, h->nitems, h->tile_w, h->sites, (uint32_t)k,
                             h->nontemporal, h->noise, s));
         h->cur ^= 1;
@@ -737,7 +764,7 @@ void flb_destroy(flb_t *h)
                     h->d_plans, h->d_tables, h->d_spec, h->d_acc, h->d_rows, h->d_cols,
                     h->d_accum, h->d_cols_a, h->d_cols_b, h->d_fld, h->d_fields,
                     h->d_csum_part, h->d_csum, h->d_cols_a_m, h->d_cols_m, h->d_rows_m,
-                    h->d_rows_blue, h->d_stash, h->d_flush};
+                    h->d_rows_blue, h->d_stash, h->d_flush, h->d_items2};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->ev) (void)hipEventDestroy(h->ev);
@@ -817,7 +844,7 @@ static int run_period_graph(flb_t *h, int every)
         it = h->graphs.emplace(key, ex).first;
     }
     FLB_HIP(hipGraphLaunch(it->second, h->stream));
-    if (every & 1) h->cur ^= 1;
+    if (step_launches(h, every) & 1) h->cur ^= 1;
     if (h->defer) h->pending = !h->pending;
     h->t += every;
     h->nsamples += 1;
@@ -1054,6 +1081,27 @@ int flb_set_step_config(flb_t *h, int tile_w, int sites, int nontemporal)
     return build_step_items(h);
 }
 
+int flb_set_time_blocking(flb_t *h, int steps_per_launch, int tile_w)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (steps_per_launch != 1 && steps_per_launch != 2)
+        return fail(FLB_EINVAL, "steps_per_launch must be 1 or 2");
+    if (!step2_tile_supported(tile_w)) return fail(FLB_EINVAL, "unsupported two-step tile");
+    FLB_HIP(hipStreamSynchronize(h->stream));
+    h->tblock = steps_per_launch;
+    h->tile2 = tile_w;
+    clear_graphs(h);
+    return build_step_items(h);
+}
+
+int flb_get_time_blocking(flb_t *h, int *steps_per_launch, int *tile_w)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (steps_per_launch) *steps_per_launch = h->tblock;
+    if (tile_w) *tile_w = h->tile2;
+    return FLB_OK;
+}
+
 int flb_get_step_config(flb_t *h, int *tile_w, int *sites, int *nontemporal)
 {
     if (check_handle(h)) return FLB_EINVAL;
@@ -1080,15 +1128,18 @@ int flb_autotune(flb_t *h, int nsteps, double *ms_out)
     if (cache) {
         if (FILE *fp = fopen(cache, "r")) {
             char k[160];
-            int tw, sv, nt;
+            int tw, sv, nt, tb, t2;
             double ms;
             int found = 0;
-            while (fscanf(fp, "%159s %d %d %d %lf", k, &tw, &sv, &nt, &ms) == 5)
-                if (strcmp(k, key) == 0 && step_tile_supported(tw, sv)) {
+            while (fscanf(fp, "%159s %d %d %d %d %d %lf", k, &tw, &sv, &nt, &tb, &t2, &ms) == 7)
+                if (strcmp(k, key) == 0 && step_tile_supported(tw, sv) && (tb == 1 || tb == 2) &&
+                    step2_tile_supported(t2)) {
                     found = 1;
                     h->tile_w = tw;
                     h->sites = sv;
                     h->nontemporal = nt != 0;
+                    h->tblock = tb;
+                    h->tile2 = t2;
                     if (ms_out) *ms_out = ms;
                 }
             fclose(fp);
@@ -1120,24 +1171,42 @@ int flb_autotune(flb_t *h, int nsteps, double *ms_out)
     float tbest[3][3][2];
     for (auto &x : tbest)
         for (auto &y : x) y[0] = y[1] = 1e30f;
-    for (int round = 0; round < kRounds && e == hipSuccess && rc == FLB_OK; ++round)
+    // two-step candidates: tile widths 64, 128, streaming or not
+    const int t2s[2] = {64, 128};
+    float t2best[2][2] = {{1e30f, 1e30f}, {1e30f, 1e30f}};
+    const int n2 = nsteps + (nsteps & 1);  // whole pairs
+    auto time_steps = [&](int n, float &best_ms) {
+        if ((rc = build_step_items(h)) != FLB_OK) return;
+        if ((rc = enqueue_steps(h, 2, h->stream)) != FLB_OK) return;
+        e = hipEventRecord(e0, h->stream);
+        if (e == hipSuccess && (rc = enqueue_steps(h, n, h->stream)) != FLB_OK) return;
+        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess) best_ms = std::min(best_ms, ms / n);
+    };
+    const int tb0 = h->tblock, t20 = h->tile2;
+    for (int round = 0; round < kRounds && e == hipSuccess && rc == FLB_OK; ++round) {
+        h->tblock = 1;
         for (int a = 0; a < 3 && e == hipSuccess && rc == FLB_OK; ++a)
             for (int b = 0; b < 3 && e == hipSuccess && rc == FLB_OK; ++b)
                 for (int nt = 0; nt < 2 && e == hipSuccess && rc == FLB_OK; ++nt) {
                     h->tile_w = tws[a];
                     h->sites = svs[b];
                     h->nontemporal = nt != 0;
-                    if ((rc = build_step_items(h)) != FLB_OK) break;
-                    if ((rc = enqueue_steps(h, 2, h->stream)) != FLB_OK) break;
-                    e = hipEventRecord(e0, h->stream);
-                    if (e == hipSuccess && (rc = enqueue_steps(h, nsteps, h->stream)) != FLB_OK)
-                        break;
-                    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-                    if (e == hipSuccess) e = hipEventSynchronize(e1);
-                    float ms = 0;
-                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                    if (e == hipSuccess) tbest[a][b][nt] = std::min(tbest[a][b][nt], ms / nsteps);
+                    time_steps(nsteps, tbest[a][b][nt]);
                 }
+        h->tblock = 2;
+        for (int a = 0; a < 2 && e == hipSuccess && rc == FLB_OK; ++a)
+            for (int nt = 0; nt < 2 && e == hipSuccess && rc == FLB_OK; ++nt) {
+                h->tile2 = t2s[a];
+                h->nontemporal = nt != 0;
+                time_steps(n2, t2best[a][nt]);
+            }
+    }
+    h->tblock = tb0;
+    h->tile2 = t20;
     int best_tw = h->tile_w, best_sv = h->sites;
     bool best_nt = h->nontemporal;
     float best = 1e30f;
@@ -1150,6 +1219,15 @@ int flb_autotune(flb_t *h, int nsteps, double *ms_out)
                     best_sv = svs[b];
                     best_nt = nt != 0;
                 }
+    int best_tb = 1, best_t2 = h->tile2;
+    for (int a = 0; a < 2; ++a)
+        for (int nt = 0; nt < 2; ++nt)
+            if (t2best[a][nt] < best) {
+                best = t2best[a][nt];
+                best_tb = 2;
+                best_t2 = t2s[a];
+                best_nt = nt != 0;
+            }
     // restore the state, the step counter and the buffer parity
     h->cur = cur0;
     if (e == hipSuccess)
@@ -1165,11 +1243,14 @@ int flb_autotune(flb_t *h, int nsteps, double *ms_out)
     h->tile_w = best_tw;
     h->sites = best_sv;
     h->nontemporal = best_nt;
+    h->tblock = best_tb;
+    h->tile2 = best_t2;
     clear_graphs(h);
     if (ms_out) *ms_out = best;
     if (cache)
         if (FILE *fp = fopen(cache, "a")) {
-            fprintf(fp, "%s %d %d %d %.6f\n", key, best_tw, best_sv, best_nt ? 1 : 0, (double)best);
+            fprintf(fp, "%s %d %d %d %d %d %.6f\n", key, best_tw, best_sv, best_nt ? 1 : 0,
+                    best_tb, best_t2, (double)best);
             fclose(fp);
         }
     return build_step_items(h);

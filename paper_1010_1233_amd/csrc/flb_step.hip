@@ -284,6 +284,123 @@ hipError_t launch_step(const DeviceView &v, const StepItem *items, int nitems, i
 }
 
 // ---------------------------------------------------------------------
+// Two steps per launch (time blocking).  A block owns a tile of TW x TH
+// sites.  Phase 1 collides the tile and a one-site halo around it at time t
+// (each site pulled from HBM as in the one-step kernel, the halo recomputed
+// by the neighbouring blocks too) and keeps the post-collision values in LDS
+// in the storage format; phase 2 pulls the tile's values from LDS, collides
+// them at t + 1 and stores them.  Every site goes through the same update
+// function, noise counters and storage rounding as in two one-step launches,
+// so the results are the same; the populations cross HBM once per two steps.
+// ---------------------------------------------------------------------
+constexpr int kStep2Threads = 512;
+
+template <int S, bool NT, bool NOISE, int TW, int TH>
+__global__ __launch_bounds__(kStep2Threads) void step2_kernel(StepArgs g)
+{
+    using T = typename Codec<S>::T;
+    constexpr int RW = TW + 2, RN = RW * (TH + 2);
+    __shared__ T mid[9][RN];
+    const StepItem it = g.items[blockIdx.x];
+    if (it.lattice < 0) return;
+    const LatticeParams &P = g.params[it.lattice];
+    const int nx = P.nx, ny = P.ny;
+    const int tiles_x = (nx + TW - 1) / TW;
+    const int x0 = (it.tile % tiles_x) * TW, y0 = (it.tile / tiles_x) * TH;
+    const T *__restrict__ src = (const T *)g.src + P.base;
+    T *__restrict__ dst = (T *)g.dst + P.base;
+    const uint32_t plane = (uint32_t)P.plane, px = (uint32_t)P.px;
+    const uint32_t t = *g.step + g.step_add;
+
+    for (int r = threadIdx.x; r < RN; r += kStep2Threads) {
+        const int ry = r / RW, rx = r - ry * RW;
+        // region site (wrapped: the tile may be wider than a small lattice)
+        const int x = (x0 - 1 + rx + nx) % nx, y = (y0 - 1 + ry + ny) % ny;
+        const uint32_t xm = x == 0 ? nx - 1 : x - 1, xr = x == nx - 1 ? 0 : x + 1;
+        const uint32_t rc = (uint32_t)y * px, rm = (uint32_t)(y == 0 ? ny - 1 : y - 1) * px;
+        const uint32_t rp = (uint32_t)(y == ny - 1 ? 0 : y + 1) * px;
+        const uint32_t ux = (uint32_t)x;
+        float d[9];
+        d[0] = Codec<S>::decode(*at<T>(src, rc + ux), P, 0);
+        d[1] = Codec<S>::decode(*at<T>(src, 1 * plane + rc + xm), P, 1);
+        d[2] = Codec<S>::decode(*at<T>(src, 2 * plane + rm + ux), P, 2);
+        d[3] = Codec<S>::decode(*at<T>(src, 3 * plane + rc + xr), P, 3);
+        d[4] = Codec<S>::decode(*at<T>(src, 4 * plane + rp + ux), P, 4);
+        d[5] = Codec<S>::decode(*at<T>(src, 5 * plane + rm + xm), P, 5);
+        d[6] = Codec<S>::decode(*at<T>(src, 6 * plane + rm + xr), P, 6);
+        d[7] = Codec<S>::decode(*at<T>(src, 7 * plane + rp + xr), P, 7);
+        d[8] = Codec<S>::decode(*at<T>(src, 8 * plane + rp + xm), P, 8);
+        update_site<NOISE>(d, P, (uint32_t)(y * nx + x), t, g.key0, g.key1);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) mid[i][r] = Codec<S>::encode(d[i], P, i);
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < TW * TH; o += kStep2Threads) {
+        const int oy = o / TW, ox = o - oy * TW;
+        const int x = x0 + ox, y = y0 + oy;
+        if (x >= nx || y >= ny) continue;
+        const int c = (oy + 1) * RW + ox + 1;  // the site in the region
+        float d[9];
+        d[0] = Codec<S>::decode(mid[0][c], P, 0);
+        d[1] = Codec<S>::decode(mid[1][c - 1], P, 1);
+        d[2] = Codec<S>::decode(mid[2][c - RW], P, 2);
+        d[3] = Codec<S>::decode(mid[3][c + 1], P, 3);
+        d[4] = Codec<S>::decode(mid[4][c + RW], P, 4);
+        d[5] = Codec<S>::decode(mid[5][c - RW - 1], P, 5);
+        d[6] = Codec<S>::decode(mid[6][c - RW + 1], P, 6);
+        d[7] = Codec<S>::decode(mid[7][c + RW + 1], P, 7);
+        d[8] = Codec<S>::decode(mid[8][c + RW - 1], P, 8);
+        update_site<NOISE>(d, P, (uint32_t)(y * nx + x), t + 1, g.key0, g.key1);
+        const uint32_t off = (uint32_t)y * px + (uint32_t)x;
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            gstore<NT>(at<T>(dst, i * plane + off), Codec<S>::encode(d[i], P, i));
+    }
+}
+
+template <int S, bool NT, bool NOISE>
+static hipError_t launch_step2_tiles(const StepArgs &a, int nitems, int tw, hipStream_t s)
+{
+    const dim3 grid(nitems), block(kStep2Threads);
+    if (tw == 64)
+        hipLaunchKernelGGL((step2_kernel<S, NT, NOISE, 64, 16>), grid, block, 0, s, a);
+    else if (tw == 128)
+        hipLaunchKernelGGL((step2_kernel<S, NT, NOISE, 128, 8>), grid, block, 0, s, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+bool step2_tile_supported(int tw) { return tw == 64 || tw == 128; }
+
+hipError_t launch_step2(const DeviceView &v, const StepItem *items, int nitems, int tile_w,
+                        uint32_t step_add, bool nontemporal, bool noise, hipStream_t s)
+{
+    StepArgs a;
+    a.src = v.pops[v.cur];
+    a.dst = v.pops[v.cur ^ 1];
+    a.params = v.params;
+    a.items = items;
+    a.step = v.step;
+    a.step_add = step_add;
+    a.key0 = (uint32_t)(v.seed & 0xFFFFFFFFu);
+    a.key1 = (uint32_t)(v.seed >> 32);
+#define FLB_SEL(S_)                                                                              \
+    if (v.storage == S_) {                                                                       \
+        if (nontemporal)                                                                         \
+            return noise ? launch_step2_tiles<S_, true, true>(a, nitems, tile_w, s)              \
+                         : launch_step2_tiles<S_, true, false>(a, nitems, tile_w, s);            \
+        return noise ? launch_step2_tiles<S_, false, true>(a, nitems, tile_w, s)                 \
+                     : launch_step2_tiles<S_, false, false>(a, nitems, tile_w, s);               \
+    }
+    FLB_SEL(kF32)
+    FLB_SEL(kBF16)
+    FLB_SEL(kF16)
+#undef FLB_SEL
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------
 // Step counter
 // ---------------------------------------------------------------------
 __global__ void advance_step_kernel(uint32_t *step, uint32_t n)

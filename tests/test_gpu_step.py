@@ -143,18 +143,21 @@ def test_conservation_flags_nan(flb, oracle_lib):
                                  (256, 2, 1), (64, 4, 0), (128, 4, 1), (256, 4, 0)])
 def test_launch_shape_does_not_change_results(flb, cfg):
     """Every (threads along x, sites per thread, streaming stores) shape gives
-    bit-identical states; 301 columns leave a ragged group at each row end."""
-    nx, ny = 301, 37
-    ref = flb.Lattice(nx, ny, TAU_C1, 1e-3, seed=4)
-    ref.thermalize()
-    ref.step(20)
-    a = ref.get_populations()
-    g = flb.Lattice(nx, ny, TAU_C1, 1e-3, seed=4)
-    g.set_step_config(*cfg)
-    assert g.step_config() == (cfg[0], cfg[1], bool(cfg[2]))
-    g.thermalize()
-    g.step(20)
-    assert np.array_equal(g.get_populations(), a)
+    bit-identical states in every storage format; 301 and 1000 columns leave
+    ragged groups at row ends."""
+    for storage in ("f32", "f16", "bf16"):
+        for nx, ny in ((301, 37), (1000, 7)):
+            ref = flb.Lattice(nx, ny, TAU_C1, 1e-3, u0=(0.03, -0.02), seed=4, storage=storage)
+            ref.set_step_config(256, 1, 0)
+            ref.thermalize()
+            ref.step(20)
+            a = ref.get_populations()
+            g = flb.Lattice(nx, ny, TAU_C1, 1e-3, u0=(0.03, -0.02), seed=4, storage=storage)
+            g.set_step_config(*cfg)
+            assert g.step_config() == (cfg[0], cfg[1], bool(cfg[2]))
+            g.thermalize()
+            g.step(20)
+            assert np.array_equal(g.get_populations(), a), (storage, nx, ny)
 
 
 def test_batch_equals_separate_lattices(flb):
@@ -258,6 +261,7 @@ def test_autotune_keeps_state_and_caches(flb, tmp_path, monkeypatch):
     h = flb.Lattice(257, 130, TAU_C1, 1e-3, seed=1)
     cfg2, ms2 = h.autotune(3)
     assert cfg2 == cfg and abs(ms2 - ms) < 1e-5  # cached with 6 decimals
+    assert h.time_blocking() == g.time_blocking()
     assert len((tmp_path / "tune.txt").read_text().splitlines()) == 1
 
 
@@ -277,3 +281,44 @@ def test_resume_from_saved_state_is_bit_identical(flb):
     assert np.array_equal(g.get_populations(), ref.get_populations())
     with pytest.raises(flb.FlbError):
         g.t = -1
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_time_blocking_equals_one_step_launches(flb, storage):
+    """Pairs of steps per launch (halo recomputed on chip) give exactly the
+    populations of one step per launch: tiny, ragged and tile-sized shapes,
+    both tile widths, an odd number of steps."""
+    for nx, ny in [(2, 2), (3, 5), (37, 23), (64, 16), (130, 17), (257, 3), (5, 300),
+                   (1000, 7)]:
+        note("time blocking", storage, nx, ny)
+        for tile in (64, 128):
+            a = flb.Lattice(nx, ny, TAU_C1, 1e-3, u0=(0.03, -0.02), seed=4, storage=storage)
+            b = flb.Lattice(nx, ny, TAU_C1, 1e-3, u0=(0.03, -0.02), seed=4, storage=storage)
+            b.set_time_blocking(2, tile)
+            assert b.time_blocking() == (2, tile)
+            a.thermalize()
+            b.thermalize()
+            a.step(7)
+            b.step(7)
+            assert a.t == b.t == 7
+            assert np.array_equal(a.get_populations(), b.get_populations()), (nx, ny, tile)
+
+
+def test_time_blocking_batch_and_graph_periods(flb):
+    specs = [dict(nx=70, ny=40, tau=TAU_C1, theta=1e-3, stream_id=0),
+             dict(nx=33, ny=129, tau=TAU_C1, theta=1e-3, u0=(0.05, 0.0), stream_id=1),
+             dict(nx=8, ny=8, tau=TAU_C1, theta=1e-3, stream_id=2)]
+    a = flb.Lattice.batch(specs, seed=6)
+    b = flb.Lattice.batch(specs, seed=6)
+    b.set_time_blocking(2, 128)
+    for h in (a, b):
+        h.thermalize()
+        h.run(103, 10)  # graph periods of ten steps plus a ragged tail
+        h.run(37, 3)    # odd periods started off-phase
+    for i in range(len(specs)):
+        assert np.array_equal(a.get_populations(i), b.get_populations(i))
+        assert np.array_equal(a.read_correlators(i)[0], b.read_correlators(i)[0])
+    with pytest.raises(flb.FlbError):
+        b.set_time_blocking(3, 64)
+    with pytest.raises(flb.FlbError):
+        b.set_time_blocking(2, 256)
