@@ -12,11 +12,13 @@ timed region, inputs resident in HBM.
 
 The JSON line also carries
   roofline      the step kernel (dominant): algorithmic bytes per launch
-                (9 reads + 9 writes per site; the time-blocked kernel does
-                two steps per launch on the same bytes) over its average
-                duration, measured with HIP events on the stream it runs on,
-                within the timed region; HBM traffic from rocprofv3 counters
-                when a summary for the current kernel source is committed;
+                (9 reads + 9 writes per site update, times the updates of
+                one launch: two per site for the time-blocked kernel, which
+                moves the state once for both) over its average duration,
+                measured with HIP events on the stream it runs on, within
+                the timed region; HBM traffic per launch from rocprofv3
+                counters when a summary for the current kernel source is
+                committed, and the rate it implies (measured_GBs);
   cpu_baseline  the FP64 oracle, single thread, on a bounded sample of the
                 same workload;
   forms         step-kernel rates of the other storage formats and of the
@@ -65,12 +67,15 @@ def shape_key(workload, storage, shape, blocking=(1, 64)):
 
 def launch_figures(g, sites, step_ms):
     """The dominant kernel's launch: which kernel, steps per launch, its
-    duration and its algorithmic bytes (one read and one write of the 9
-    populations per site and launch, whatever the steps per launch)."""
+    duration and its algorithmic bytes = 18 values per site update (9 loads
+    + 9 stores) x the site updates of one launch.  The two-step kernel does
+    two updates per site and launch on one read and one write of the state,
+    so its algorithmic rate can exceed what HBM moves (see the measured
+    traffic)."""
     steps, tile2 = g.time_blocking()
     bpv = g.storage_info()[1]
     launch_ms = steps * step_ms
-    algo = 18 * bpv * sites
+    algo = 18 * bpv * sites * steps
     return {"kernel": "step2_kernel" if steps == 2 else STEP_KERNEL,
             "steps_per_launch": steps, "avg_launch_ms": launch_ms,
             "algorithmic_bytes_per_launch": algo,
@@ -330,7 +335,12 @@ def main():
                      "steps_per_launch": launch["steps_per_launch"],
                      "algorithmic_bytes_per_launch": launch["algorithmic_bytes_per_launch"],
                      "avg_launch_ms": launch["avg_launch_ms"],
-                     "launch_shape": list(tuned) + [list(blocking)]},
+                     "launch_shape": list(tuned) + [list(blocking)],
+                     "measured_GBs": (None if traffic is None else
+                                      traffic / (launch["avg_launch_ms"] * 1e-3) / 1e9),
+                     "measured_frac": (None if traffic is None else
+                                       traffic / (launch["avg_launch_ms"] * 1e-3) / 1e9
+                                       / HBM_PEAK_GBS)},
         "step_kernel_glups": V / (step_ms * 1e-3) / 1e9,
         "sample_ms": max(ms_per_step - SAMPLE_EVERY * step_ms, 0.0),
         "mass_drift": drift,
