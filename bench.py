@@ -6,9 +6,12 @@
 One benchmark step is one pass of the whole path on the workload: ten fused
 collide+noise+stream updates of every site and one correlator sample (field
 extraction with the FP64 conservation sums of the sampled state, 2-D
-transforms, FP64 accumulation of the fifteen products).  W untimed steps,
-then K timed steps bracketed by device synchronisation.  `value` is site updates per second (GLUPS) over the
-timed region, inputs resident in HBM.
+transforms, FP64 accumulation of the fifteen products).  The library runs
+each sample beside the next ten updates (on a second stream); the handle's
+synchronise call, which enqueues a sample still waiting for steps, and the
+device synchronisation bracket the timed region, so all K samples run inside
+it.  W untimed steps, then K timed steps.  `value` is site updates per
+second (GLUPS) over the timed region, inputs resident in HBM.
 
 The JSON line also carries
   roofline      the step kernel (dominant): algorithmic bytes per launch
@@ -16,9 +19,13 @@ The JSON line also carries
                 one launch: two per site for the time-blocked kernel, which
                 moves the state once for both) over its average duration,
                 measured with HIP events on the stream it runs on, within
-                the timed region; HBM traffic per launch from rocprofv3
-                counters when a summary for the current kernel source is
-                committed, and the rate it implies (measured_GBs);
+                the timed region (so while the sample shares the device;
+                `isolated` repeats the figures for the kernel alone);
+                HBM traffic per launch from rocprofv3 counters when a
+                summary for the current kernel source is committed, and the
+                rate it implies (measured_GBs); step_kernel_glups_isolated
+                times the step kernel alone after the timed region, and
+                sample_ms is what a period takes beyond ten isolated steps;
   cpu_baseline  the FP64 oracle, single thread, on a bounded sample of the
                 same workload;
   forms         step-kernel rates of the other storage formats and of the
@@ -139,19 +146,23 @@ def time_step_kernel(torch, g, stream, n):
 def batched_form(torch, flb, stream, specs, storage, periods=10):
     """Whole path (graph-replayed periods of SAMPLE_EVERY steps + a sample)
     and step-only rates of one batched handle."""
+    assert periods % 2 == 0  # the timed run then starts where the warm-up did
     b = flb.Lattice.batch(specs, seed=3, storage=storage)
     b.set_stream(stream)
     b.thermalize()
     shape, _ = b.autotune(50)
     sites = sum(s["nx"] * s["ny"] for s in specs)
-    b.run(2 * SAMPLE_EVERY, SAMPLE_EVERY)  # capture the graphs
+    b.run(periods * SAMPLE_EVERY, SAMPLE_EVERY)  # capture the graphs
+    b.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     b.run(periods * SAMPLE_EVERY, SAMPLE_EVERY)
+    b.synchronize()  # enqueues the last sample and waits for it
     e1.record(stream)
     e1.synchronize()
     ms_period = e0.elapsed_time(e1) / periods
-    step_ms = time_step_kernel(torch, b, stream, 20)
+    time_step_kernel(torch, b, stream, 100)  # untimed: leave the idle power state
+    step_ms = time_step_kernel(torch, b, stream, 50)
     lf = launch_figures(b, sites, step_ms)
     shape = list(shape) + [list(b.time_blocking())]
     b.close()
@@ -174,7 +185,7 @@ def velocity_set_form(torch, flb, stream, model, sides, sample=True, periods=5):
     g.set_stream(stream)
     g.thermalize()
     sites = g.sides[0] * g.sides[1] * g.sides[2]
-    g.step(5)
+    g.step(50)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     g.step(20)
@@ -288,12 +299,14 @@ def main():
     with torch.cuda.stream(stream):
         for i in range(args.warmup):
             bench_step(i)
+        g.synchronize()
         torch.cuda.synchronize()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(args.steps)]
         t0 = time.perf_counter()
         for i in range(args.steps):
             bench_step(args.warmup + i, evs[i])
+        g.synchronize()  # enqueues the last sample
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
 
@@ -309,6 +322,14 @@ def main():
     acc, ns = g.read_correlators()
     S = flb.normalize(acc, ns, c["nx"], c["ny"], c["theta"], c["rho0"])
     s_rho_mean = float(S["S_rho"][1:, 1:].mean())
+
+    # the step kernel alone (nothing sampled beside it), after enough
+    # untimed steps that the device has left the power state of the idle
+    # host-side read above
+    with torch.cuda.stream(stream):
+        time_step_kernel(torch, g, stream, 20 * SAMPLE_EVERY)
+        iso_ms = time_step_kernel(torch, g, stream, 10 * SAMPLE_EVERY)
+    iso = launch_figures(g, V, iso_ms)
 
     out = {
         "metric": METRIC,
@@ -340,9 +361,15 @@ def main():
                                       traffic / (launch["avg_launch_ms"] * 1e-3) / 1e9),
                      "measured_frac": (None if traffic is None else
                                        traffic / (launch["avg_launch_ms"] * 1e-3) / 1e9
-                                       / HBM_PEAK_GBS)},
+                                       / HBM_PEAK_GBS),
+                     "isolated": {"avg_launch_ms": iso["avg_launch_ms"],
+                                  "achieved": iso["achieved_GBs"],
+                                  "frac": iso["achieved_GBs"] / HBM_PEAK_GBS,
+                                  "measured_GBs": (None if traffic is None else
+                                                   traffic / (iso["avg_launch_ms"] * 1e-3) / 1e9)}},
         "step_kernel_glups": V / (step_ms * 1e-3) / 1e9,
-        "sample_ms": max(ms_per_step - SAMPLE_EVERY * step_ms, 0.0),
+        "step_kernel_glups_isolated": V / (iso_ms * 1e-3) / 1e9,
+        "sample_ms": max(ms_per_step - SAMPLE_EVERY * iso_ms, 0.0),
         "mass_drift": drift,
         "S_rho_kmean": s_rho_mean,
     }
@@ -372,7 +399,7 @@ def main():
             time_step_kernel(torch, h, stream, 5)
             ms = time_step_kernel(torch, h, stream, 50)
             forms["noise_off_" + args.storage] = {"step_glups": V / (ms * 1e-3) / 1e9}
-            out["noise_overhead"] = step_ms / ms - 1.0
+            out["noise_overhead"] = iso_ms / ms - 1.0
             h.close()
             for name, specs in (("batched_gi_96x512", workloads.gi_sweep_specs()),
                                 ("batched_uneven_64", workloads.uneven_batch_specs())):

@@ -51,15 +51,17 @@ const int kVx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 const int kVy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
 // A captured sampling period: its length, the buffer holding the state at
-// its start and whether a stashed sample is pending (which decides the
-// accumulation mode of its sample).
+// its start, whether the sample of that state is due (it then runs beside
+// the period's steps) and whether a stashed sample is pending (which decides
+// the accumulation mode of the due sample).
 struct GraphKey {
-    int every, parity, pending;
+    int every, parity, pending, due;
     bool operator<(const GraphKey &o) const
     {
         if (every != o.every) return every < o.every;
         if (parity != o.parity) return parity < o.parity;
-        return pending < o.pending;
+        if (pending != o.pending) return pending < o.pending;
+        return due < o.due;
     }
 };
 
@@ -124,6 +126,15 @@ struct flb {
     double *d_csum_part = nullptr, *d_csum = nullptr;
     int rows_lds = 0, cols_lds = 0, cols_cb = 1, cols_a_lds = 0, cols_b_lds = 0;
     int64_t nsamples = 0;
+
+    // A registered sample is due until the next steps are enqueued: it then
+    // runs on `aux` beside them, the second step launch (the first to write
+    // the sampled buffer) waits until it has read the state, and the steps'
+    // stream waits for its end. Every call that reads the sums or changes
+    // the state enqueues a due sample on the work stream first.
+    bool due = false;
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_read = nullptr, ev_done = nullptr;
 
     // streams and graphs
     hipStream_t own = nullptr;
@@ -540,9 +551,14 @@ int setup_correlators(flb_t *h)
     return FLB_OK;
 }
 
-int enqueue_sample(flb_t *h, hipStream_t s)
+// The kernels of one sample of the current state on stream s. When ev_read
+// is given it is recorded once every kernel that reads the populations has
+// been enqueued.
+int enqueue_sample(flb_t *h, hipStream_t s, hipEvent_t ev_read = nullptr)
 {
     const DeviceView v = h->view();
+    // the moment planes first, so that all reads of the state come first
+    if (h->moments) FLB_HIP(launch_corr_moment_fields(v, h->d_fld, h->n_fld, s));
     for (int set = 0; set < (h->moments ? 2 : 1); ++set) {
         // the moment set reuses the spectrum buffer after set 0
         const CorrItem *ca = set ? h->d_cols_a_m : h->d_cols_a;
@@ -552,8 +568,8 @@ int enqueue_sample(flb_t *h, hipStream_t s)
         if (set == 0) {
             FLB_HIP(launch_corr_rows(v, h->d_rows, h->n_rows, h->d_rows_blue, h->n_rows_blue,
                                      h->rows_lds, s));
+            if (ev_read) FLB_HIP(hipEventRecord(ev_read, s));
         } else {
-            FLB_HIP(launch_corr_moment_fields(v, h->d_fld, h->n_fld, s));
             FLB_HIP(launch_corr_moment_rows(v, h->d_rows_m, h->n_rows_m, h->rows_lds, s));
         }
         if (na) FLB_HIP(launch_corr_cols_a(v, ca, na, h->cols_a_lds, s));
@@ -579,22 +595,59 @@ int flush_pending(flb_t *h)
 
 // n steps from the device counter value; the counter is advanced afterwards.
 // With time blocking, pairs of steps go through the two-step kernel and an
-// odd last step through the one-step kernel.
-int enqueue_steps(flb_t *h, int64_t n, hipStream_t s)
+// odd last step through the one-step kernel. When wait_before_second is
+// given, the second launch (the first to write the buffer that held the
+// state at the start) waits for it.
+int enqueue_steps(flb_t *h, int64_t n, hipStream_t s, hipEvent_t wait_before_second = nullptr)
 {
     int64_t k = 0;
+    int launches = 0;
+    auto before_launch = [&]() -> int {
+        if (launches++ == 1 && wait_before_second)
+            FLB_HIP(hipStreamWaitEvent(s, wait_before_second, 0));
+        return FLB_OK;
+    };
+    int rc;
     if (h->tblock == 2)
         for (; k + 2 <= n; k += 2) {
+            if ((rc = before_launch())) return rc;
             FLB_HIP(launch_step2(h->view(), h->d_items2, h->nitems2, h->tile2, (uint32_t)k,
                                  h->nontemporal, h->noise, s));
             h->cur ^= 1;
         }
     for (; k < n; ++k) {
+        if ((rc = before_launch())) return rc;
         FLB_HIP(launch_step(h->view(), h->d_items, h->nitems, h->tile_w, h->sites, (uint32_t)k,
                             h->nontemporal, h->noise, s));
         h->cur ^= 1;
     }
     if (n > 0) FLB_HIP(launch_advance_step(h->d_step, (uint32_t)n, s));
+    return FLB_OK;
+}
+
+// n steps on stream s; a due sample of the state at their start runs on the
+// side stream beside them and s waits for its end.
+int enqueue_steps_overlapped(flb_t *h, int64_t n, hipStream_t s)
+{
+    if (!h->due || n <= 0) return enqueue_steps(h, n, s);
+    FLB_HIP(hipEventRecord(h->ev_fork, s));
+    FLB_HIP(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+    int rc = enqueue_sample(h, h->aux, h->ev_read);
+    if (rc) return rc;
+    h->due = false;
+    FLB_HIP(hipEventRecord(h->ev_done, h->aux));
+    if ((rc = enqueue_steps(h, n, s, h->ev_read))) return rc;
+    FLB_HIP(hipStreamWaitEvent(s, h->ev_done, 0));
+    return FLB_OK;
+}
+
+// Enqueues a due sample on the work stream.
+int settle_due(flb_t *h)
+{
+    if (!h->due) return FLB_OK;
+    int rc = enqueue_sample(h, h->stream);
+    if (rc) return rc;
+    h->due = false;
     return FLB_OK;
 }
 
@@ -666,7 +719,11 @@ flb_t *create_impl(int n, const flb_lattice_spec *specs, uint64_t seed, int stor
         return bail(0);
     }
     if (hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev, hipEventDisableTiming) != hipSuccess) {
+        hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_read, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_done, hipEventDisableTiming) != hipSuccess) {
         fail(FLB_EHIP, "stream creation failed");
         return bail(0);
     }
@@ -759,6 +816,7 @@ void flb_destroy(flb_t *h)
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->own) (void)hipStreamSynchronize(h->own);
+    if (h->aux) (void)hipStreamSynchronize(h->aux);
     clear_graphs(h);
     void *ptrs[] = {h->pops[0], h->d_params, h->d_step, h->d_red, h->d_items,
                     h->d_plans, h->d_tables, h->d_spec, h->d_acc, h->d_rows, h->d_cols,
@@ -767,7 +825,9 @@ void flb_destroy(flb_t *h)
                     h->d_rows_blue, h->d_stash, h->d_flush, h->d_items2};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    if (h->ev) (void)hipEventDestroy(h->ev);
+    for (hipEvent_t e : {h->ev, h->ev_fork, h->ev_read, h->ev_done})
+        if (e) (void)hipEventDestroy(e);
+    if (h->aux) (void)hipStreamDestroy(h->aux);
     if (h->own) (void)hipStreamDestroy(h->own);
     delete h;
 }
@@ -788,6 +848,8 @@ int flb_set_stream(flb_t *h, void *hip_stream)
 int flb_synchronize(flb_t *h)
 {
     if (check_handle(h)) return FLB_EINVAL;
+    int rc = settle_due(h);
+    if (rc) return rc;
     FLB_HIP(hipStreamSynchronize(h->stream));
     return FLB_OK;
 }
@@ -797,19 +859,21 @@ int flb_step(flb_t *h, int64_t nsteps)
     if (check_handle(h)) return FLB_EINVAL;
     int rc = check_time(h, nsteps);
     if (rc) return rc;
-    rc = enqueue_steps(h, nsteps, h->stream);
+    rc = enqueue_steps_overlapped(h, nsteps, h->stream);
     if (rc) return rc;
     h->t += nsteps;
     return FLB_OK;
 }
 
+// Registers a sample of the current state; its kernels are enqueued with
+// the next steps (beside them) or by the next call that needs them.
 int flb_accumulate_correlators(flb_t *h)
 {
     if (check_handle(h)) return FLB_EINVAL;
     int rc = setup_correlators(h);
     if (rc) return rc;
-    rc = enqueue_sample(h, h->stream);
-    if (rc) return rc;
+    if ((rc = settle_due(h))) return rc;  // a second sample of the same state
+    h->due = true;
     h->nsamples += 1;
     return FLB_OK;
 }
@@ -817,20 +881,23 @@ int flb_accumulate_correlators(flb_t *h)
 // One period of `every` steps followed by a sample, from a captured graph.
 static int run_period_graph(flb_t *h, int every)
 {
-    const GraphKey key{every, h->cur, h->pending ? 1 : 0};
+    const bool due0 = h->due;
+    const GraphKey key{every, h->cur, h->pending ? 1 : 0, due0 ? 1 : 0};
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
         // capture on the handle's own stream (capturing the legacy default
-        // stream is not allowed), then launch on the current stream
+        // stream is not allowed), then launch on the current stream; a due
+        // sample forks onto the side stream inside the capture and joins
+        // before its end
         const int cur0 = h->cur;
         const bool pending0 = h->pending;
         FLB_HIP(hipStreamBeginCapture(h->own, hipStreamCaptureModeRelaxed));
-        int rc = enqueue_steps(h, every, h->own);
-        if (!rc) rc = enqueue_sample(h, h->own);
+        int rc = enqueue_steps_overlapped(h, every, h->own);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(h->own, &g);
         h->cur = cur0;
         h->pending = pending0;
+        h->due = due0;
         if (rc) {
             if (g) (void)hipGraphDestroy(g);
             return rc;
@@ -845,9 +912,10 @@ static int run_period_graph(flb_t *h, int every)
     }
     FLB_HIP(hipGraphLaunch(it->second, h->stream));
     if (step_launches(h, every) & 1) h->cur ^= 1;
-    if (h->defer) h->pending = !h->pending;
+    if (due0 && h->defer) h->pending = !h->pending;
     h->t += every;
     h->nsamples += 1;
+    h->due = true;  // the period's own sample runs beside the next steps
     return FLB_OK;
 }
 
@@ -890,7 +958,7 @@ int flb_read_correlators(flb_t *h, int lattice, double *out, size_t n_doubles, i
     const LatticeParams &P = h->params[lattice];
     const size_t need = (size_t)h->nkinds * P.ny * P.nkx;
     if (n_doubles < need) return fail(FLB_ESIZE, "output buffer too small for the correlators");
-    if ((rc = flush_pending(h))) return rc;
+    if ((rc = settle_due(h)) || (rc = flush_pending(h))) return rc;
     FLB_HIP(hipStreamSynchronize(h->stream));
     // device rows have pitch kxp >= nkx
     FLB_HIP(hipMemcpy2D(out, (size_t)P.nkx * sizeof(double), h->d_acc + P.acc_base,
@@ -907,7 +975,8 @@ int flb_reset_correlators(flb_t *h)
     if (rc) return rc;
     FLB_HIP(launch_fill(h->d_acc, (size_t)h->acc_elems, h->stream));
     h->nsamples = 0;
-    h->pending = false;  // a stashed sample is dropped with the sums
+    h->pending = false;  // a stashed or due sample is dropped with the sums
+    h->due = false;
     return FLB_OK;
 }
 
@@ -935,6 +1004,8 @@ int flb_set_populations(flb_t *h, int lattice, const double *in, size_t n)
     const LatticeParams &P = h->params[lattice];
     const size_t need = 9 * (size_t)P.nx * (size_t)P.ny;
     if (n < need) return fail(FLB_ESIZE, "input buffer smaller than 9*nx*ny");
+    int rc = settle_due(h);
+    if (rc) return rc;
     double *d = nullptr;
     FLB_HIP(hipMalloc((void **)&d, need * sizeof(double)));
     hipError_t e = hipStreamSynchronize(h->stream);
@@ -966,6 +1037,8 @@ int flb_sample_conservation(flb_t *h, int lattice, double out[5])
     if (!out) return fail(FLB_EINVAL, "out must not be NULL");
     if (!h->corr_ready || h->nsamples == 0)
         return fail(FLB_ESTATE, "no correlator sample taken since the last reset");
+    int rc = settle_due(h);
+    if (rc) return rc;
     FLB_HIP(hipStreamSynchronize(h->stream));
     FLB_HIP(hipMemcpy(out, h->d_csum + 5 * (size_t)lattice, 5 * sizeof(double),
                       hipMemcpyDeviceToHost));
@@ -986,6 +1059,8 @@ int flb_conservation_dev(flb_t *h, int lattice, double *out_dev)
 int flb_thermalize(flb_t *h)
 {
     if (check_handle(h)) return FLB_EINVAL;
+    int rc = settle_due(h);
+    if (rc) return rc;
     for (size_t l = 0; l < h->params.size(); ++l) {
         const LatticeParams &P = h->params[l];
         const int nb = (int)std::min<int64_t>(h->red_blocks,
@@ -1150,7 +1225,8 @@ int flb_autotune(flb_t *h, int nsteps, double *ms_out)
         }
     }
 
-    // save the state: the candidates advance it
+    // save the state: the candidates advance it (a due sample reads it first)
+    if (int rc0 = settle_due(h)) return rc0;
     FLB_HIP(hipStreamSynchronize(h->stream));
     const size_t bytes = (size_t)h->total_elems * h->elem_bytes;
     void *saved = nullptr;
