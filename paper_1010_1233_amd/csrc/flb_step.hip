@@ -285,22 +285,53 @@ hipError_t launch_step(const DeviceView &v, const StepItem *items, int nitems, i
 
 // ---------------------------------------------------------------------
 // Two steps per launch (time blocking).  A block owns a tile of TW x TH
-// sites.  Phase 1 collides the tile and a one-site halo around it at time t
-// (each site pulled from HBM as in the one-step kernel, the halo recomputed
-// by the neighbouring blocks too) and keeps the post-collision values in LDS
-// in the storage format; phase 2 pulls the tile's values from LDS, collides
-// them at t + 1 and stores them.  Every site goes through the same update
-// function, noise counters and storage rounding as in two one-step launches,
-// so the results are the same; the populations cross HBM once per two steps.
+// sites.  Phase 1 collides the tile and the one-site ring around it at time
+// t (each site pulled from HBM as in the one-step kernel, the ring
+// recomputed by the neighbouring blocks too) and keeps the post-collision
+// values in LDS in the storage format; phase 2 pulls the tile's values from
+// LDS, collides them at t + 1 and stores them.  Every site goes through the
+// same update function, noise counters and storage rounding as in two
+// one-step launches, so the results are the same; the populations cross HBM
+// once per two steps.
+//
+// Each thread collides the same tile sites in both phases (and one ring
+// site in phase 1), so the rest population, which streams from the site
+// itself, stays in a register: LDS holds planes 1..8 only (38 KB for a
+// 64 x 16 tile, four blocks per CU).  All of a thread's phase-1 loads are
+// issued before its first collision.
 // ---------------------------------------------------------------------
 constexpr int kStep2Threads = 512;
+
+// region coordinates of the h-th site of the one-site ring around a tile
+template <int TW, int TH>
+__device__ __forceinline__ void ring_site(int h, int &rx, int &ry)
+{
+    constexpr int RW = TW + 2;
+    if (h < RW) {
+        ry = 0;
+        rx = h;
+    } else if (h < 2 * RW) {
+        ry = TH + 1;
+        rx = h - RW;
+    } else if (h < 2 * RW + TH) {
+        ry = h - 2 * RW + 1;
+        rx = 0;
+    } else {
+        ry = h - 2 * RW - TH + 1;
+        rx = RW - 1;
+    }
+}
 
 template <int S, bool NT, bool NOISE, int TW, int TH>
 __global__ __launch_bounds__(kStep2Threads) void step2_kernel(StepArgs g)
 {
     using T = typename Codec<S>::T;
     constexpr int RW = TW + 2, RN = RW * (TH + 2);
-    __shared__ T mid[9][RN];
+    constexpr int NTILE = TW * TH, NRING = RN - NTILE;
+    constexpr int KT = NTILE / kStep2Threads;  // tile sites per thread
+    constexpr int K = KT + 1;                  // phase-1 sites per thread: tile sites, then a ring site
+    static_assert(NTILE % kStep2Threads == 0 && NRING <= kStep2Threads, "tile shape");
+    __shared__ T mid[8][RN];  // planes 1..8 after phase 1
     const StepItem it = g.items[blockIdx.x];
     if (it.lattice < 0) return;
     const LatticeParams &P = g.params[it.lattice];
@@ -311,50 +342,95 @@ __global__ __launch_bounds__(kStep2Threads) void step2_kernel(StepArgs g)
     T *__restrict__ dst = (T *)g.dst + P.base;
     const uint32_t plane = (uint32_t)P.plane, px = (uint32_t)P.px;
     const uint32_t t = *g.step + g.step_add;
+    const int tid = threadIdx.x;
 
-    for (int r = threadIdx.x; r < RN; r += kStep2Threads) {
-        const int ry = r / RW, rx = r - ry * RW;
-        // region site (wrapped: the tile may be wider than a small lattice)
-        const int x = (x0 - 1 + rx + nx) % nx, y = (y0 - 1 + ry + ny) % ny;
-        const uint32_t xm = x == 0 ? nx - 1 : x - 1, xr = x == nx - 1 ? 0 : x + 1;
-        const uint32_t rc = (uint32_t)y * px, rm = (uint32_t)(y == 0 ? ny - 1 : y - 1) * px;
-        const uint32_t rp = (uint32_t)(y == ny - 1 ? 0 : y + 1) * px;
-        const uint32_t ux = (uint32_t)x;
-        float d[9];
-        d[0] = Codec<S>::decode(*at<T>(src, rc + ux), P, 0);
-        d[1] = Codec<S>::decode(*at<T>(src, 1 * plane + rc + xm), P, 1);
-        d[2] = Codec<S>::decode(*at<T>(src, 2 * plane + rm + ux), P, 2);
-        d[3] = Codec<S>::decode(*at<T>(src, 3 * plane + rc + xr), P, 3);
-        d[4] = Codec<S>::decode(*at<T>(src, 4 * plane + rp + ux), P, 4);
-        d[5] = Codec<S>::decode(*at<T>(src, 5 * plane + rm + xm), P, 5);
-        d[6] = Codec<S>::decode(*at<T>(src, 6 * plane + rm + xr), P, 6);
-        d[7] = Codec<S>::decode(*at<T>(src, 7 * plane + rp + xr), P, 7);
-        d[8] = Codec<S>::decode(*at<T>(src, 8 * plane + rp + xm), P, 8);
-        update_site<NOISE>(d, P, (uint32_t)(y * nx + x), t, g.key0, g.key1);
+    // phase-1 sites: region index and (wrapped) lattice coordinates
+    int xs[K], ys[K], rs[K];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) mid[i][r] = Codec<S>::encode(d[i], P, i);
+    for (int k = 0; k < K; ++k) {
+        int rx, ry;
+        if (k < KT) {
+            const int o = tid + k * kStep2Threads;
+            ry = o / TW + 1;
+            rx = o % TW + 1;
+        } else {
+            ring_site<TW, TH>(tid < NRING ? tid : 0, rx, ry);
+        }
+        rs[k] = ry * RW + rx;
+        // wrap (x >= -1): at most one subtraction unless the lattice is
+        // smaller than a tile
+        int x = x0 - 1 + rx, y = y0 - 1 + ry;
+        x = x < 0 ? x + nx : x;
+        y = y < 0 ? y + ny : y;
+        while (x >= nx) x -= nx;
+        while (y >= ny) y -= ny;
+        xs[k] = x;
+        ys[k] = y;
+    }
+    // per-plane bases (wave-uniform) and byte offsets within a plane
+    const char *sp[9];
+    char *dp[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        sp[i] = reinterpret_cast<const char *>(src) + (size_t)i * plane * sizeof(T);
+        dp[i] = reinterpret_cast<char *>(dst) + (size_t)i * plane * sizeof(T);
+    }
+    constexpr uint32_t E = sizeof(T);
+    T raw[K][9];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (k == KT && tid >= NRING) break;
+        const int x = xs[k], y = ys[k];
+        const uint32_t ux = (uint32_t)x * E;
+        const uint32_t xm = (uint32_t)(x == 0 ? nx - 1 : x - 1) * E;
+        const uint32_t xr = (uint32_t)(x == nx - 1 ? 0 : x + 1) * E;
+        const uint32_t rc = (uint32_t)y * px * E, rm = (uint32_t)(y == 0 ? ny - 1 : y - 1) * px * E;
+        const uint32_t rp = (uint32_t)(y == ny - 1 ? 0 : y + 1) * px * E;
+        raw[k][0] = *reinterpret_cast<const T *>(sp[0] + (rc + ux));
+        raw[k][1] = *reinterpret_cast<const T *>(sp[1] + (rc + xm));
+        raw[k][2] = *reinterpret_cast<const T *>(sp[2] + (rm + ux));
+        raw[k][3] = *reinterpret_cast<const T *>(sp[3] + (rc + xr));
+        raw[k][4] = *reinterpret_cast<const T *>(sp[4] + (rp + ux));
+        raw[k][5] = *reinterpret_cast<const T *>(sp[5] + (rm + xm));
+        raw[k][6] = *reinterpret_cast<const T *>(sp[6] + (rm + xr));
+        raw[k][7] = *reinterpret_cast<const T *>(sp[7] + (rp + xr));
+        raw[k][8] = *reinterpret_cast<const T *>(sp[8] + (rp + xm));
+    }
+    T own[KT];  // plane 0 of the tile sites after phase 1, in the storage format
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (k == KT && tid >= NRING) break;
+        float d[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] = Codec<S>::decode(raw[k][i], P, i);
+        update_site<NOISE>(d, P, (uint32_t)(ys[k] * nx + xs[k]), t, g.key0, g.key1);
+        if (k < KT) own[k] = Codec<S>::encode(d[0], P, 0);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) mid[i - 1][rs[k]] = Codec<S>::encode(d[i], P, i);
     }
     __syncthreads();
-    for (int o = threadIdx.x; o < TW * TH; o += kStep2Threads) {
-        const int oy = o / TW, ox = o - oy * TW;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+        const int o = tid + k * kStep2Threads;
+        const int oy = o / TW, ox = o % TW;
         const int x = x0 + ox, y = y0 + oy;
         if (x >= nx || y >= ny) continue;
-        const int c = (oy + 1) * RW + ox + 1;  // the site in the region
+        const int c = rs[k];
         float d[9];
-        d[0] = Codec<S>::decode(mid[0][c], P, 0);
-        d[1] = Codec<S>::decode(mid[1][c - 1], P, 1);
-        d[2] = Codec<S>::decode(mid[2][c - RW], P, 2);
-        d[3] = Codec<S>::decode(mid[3][c + 1], P, 3);
-        d[4] = Codec<S>::decode(mid[4][c + RW], P, 4);
-        d[5] = Codec<S>::decode(mid[5][c - RW - 1], P, 5);
-        d[6] = Codec<S>::decode(mid[6][c - RW + 1], P, 6);
-        d[7] = Codec<S>::decode(mid[7][c + RW + 1], P, 7);
-        d[8] = Codec<S>::decode(mid[8][c + RW - 1], P, 8);
+        d[0] = Codec<S>::decode(own[k], P, 0);
+        d[1] = Codec<S>::decode(mid[0][c - 1], P, 1);
+        d[2] = Codec<S>::decode(mid[1][c - RW], P, 2);
+        d[3] = Codec<S>::decode(mid[2][c + 1], P, 3);
+        d[4] = Codec<S>::decode(mid[3][c + RW], P, 4);
+        d[5] = Codec<S>::decode(mid[4][c - RW - 1], P, 5);
+        d[6] = Codec<S>::decode(mid[5][c - RW + 1], P, 6);
+        d[7] = Codec<S>::decode(mid[6][c + RW + 1], P, 7);
+        d[8] = Codec<S>::decode(mid[7][c + RW - 1], P, 8);
         update_site<NOISE>(d, P, (uint32_t)(y * nx + x), t + 1, g.key0, g.key1);
-        const uint32_t off = (uint32_t)y * px + (uint32_t)x;
+        const uint32_t off = ((uint32_t)y * px + (uint32_t)x) * E;
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            gstore<NT>(at<T>(dst, i * plane + off), Codec<S>::encode(d[i], P, i));
+            gstore<NT>(reinterpret_cast<T *>(dp[i] + off), Codec<S>::encode(d[i], P, i));
     }
 }
 

@@ -5,6 +5,7 @@ the accumulated sums agree element by element to a small relative tolerance;
 statistical runs check S_k = 1 and vanishing cross correlators at u0 = 0 on
 the GPU alone (Eq. 7), with the abstract's "< 0.5 %" on the cross correlators.
 """
+import os
 import sys
 
 import numpy as np
@@ -271,3 +272,55 @@ def test_reads_between_paired_samples(flb, oracle_lib):
     o.acc[...] = 0
     o.sample()
     _compare(a.read_correlators()[0], o.acc, 2e-4)
+
+
+@pytest.mark.parametrize("side", [
+    2048,
+    pytest.param(4096, marks=pytest.mark.skipif(
+        os.environ.get("FLB_FULL_SIZE") != "1",
+        reason="two minutes of oracle time; set FLB_FULL_SIZE=1 to run")),
+])
+def test_storage_formats_against_oracle(flb, oracle_lib, side):
+    """The 4096^2 workload's parameters (u_x = 0.05, tau_s = 0.6, kT = 1e-4),
+    at 2048^2 and (opt-in) 4096^2: thermal start, ten steps and one sample
+    in each storage format against the oracle's FP64 run of the same
+    trajectory.  Per kind, the error of the sums over k relative to their
+    size (cross kinds relative to the geometric mean of the two fields' auto
+    sums) measures what the storage format costs the correlators."""
+    c = workloads.CONFIGS["c5_4096"]
+    nx = ny = side
+    note(f"{side}^2 oracle run")
+    o = oracle_lib.Lattice(nx, ny, c["tau"], c["theta"], u0=c["u0"], seed=c["seed"])
+    o.thermalize()
+    o.step(10)
+    o.sample()
+    ref = o.acc.copy()
+    del o
+    ref[:, 0, 0] = 0
+    auto = np.sqrt((ref[:5] ** 2).reshape(5, -1).sum(axis=1))
+    # fields of each product kind (rho, jx, jy, ux, uy = 0..4)
+    pairs = {5: (3, 4), 6: (3, 4), 7: (0, 1), 8: (0, 1), 9: (0, 2), 10: (0, 2),
+             11: (0, 3), 12: (0, 3), 13: (0, 4), 14: (0, 4)}
+    # measured at 2048^2: worst kind 5e-7, 3.7e-4, 2.9e-3
+    bounds = {"f32": 3e-6, "f16": 2e-3, "bf16": 1.5e-2}
+    for storage, bound in bounds.items():
+        note(f"{side}^2", storage)
+        g = flb.Lattice(nx, ny, c["tau"], c["theta"], u0=c["u0"], seed=c["seed"],
+                        storage=storage)
+        g.thermalize()
+        g.step(10)
+        g.accumulate()
+        acc, ns = g.read_correlators()
+        g.close()
+        assert ns == 1
+        rel = []
+        for q in range(15):
+            err = np.sqrt(((acc[q] - ref[q]) ** 2).sum())
+            if q < 5:
+                scale = auto[q]
+            else:
+                a, b = pairs[q]
+                scale = np.sqrt(auto[a] * auto[b])
+            rel.append(err / scale)
+        note(f"  {storage}: relative error per kind", " ".join(f"{r:.2e}" for r in rel))
+        assert max(rel) < bound, (storage, rel)
