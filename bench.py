@@ -18,9 +18,10 @@ The JSON line also carries
                 (9 reads + 9 writes per site update, times the updates of
                 one launch: two per site for the time-blocked kernel, which
                 moves the state once for both) over its average duration,
-                measured with HIP events on the stream it runs on, within
-                the timed region (so while the sample shares the device;
-                `isolated` repeats the figures for the kernel alone);
+                measured with a HIP event pair around every launch on the
+                stream it runs on, within the timed region (so while the
+                sample shares the device; `isolated` repeats the figures
+                for the kernel alone);
                 HBM traffic per launch from rocprofv3 counters when a
                 summary for the current kernel source is committed, and the
                 rate it implies (measured_GBs); step_kernel_glups_isolated
@@ -288,29 +289,29 @@ def main():
           flush=True)
     cons0 = g.conservation()
 
-    def bench_step(i, ev=None):
-        if ev is not None:
-            ev[0].record(stream)
+    def bench_step():
         g.step(SAMPLE_EVERY)
-        if ev is not None:
-            ev[1].record(stream)
         g.accumulate()
 
     with torch.cuda.stream(stream):
         for i in range(args.warmup):
-            bench_step(i)
+            bench_step()
         g.synchronize()
         torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
+        # HIP event pairs around every step-kernel launch of the timed region
+        g.set_launch_timing(True)
         t0 = time.perf_counter()
         for i in range(args.steps):
-            bench_step(args.warmup + i, evs[i])
+            bench_step()
         g.synchronize()  # enqueues the last sample
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        g.set_launch_timing(False)
+        n_launches, launch_total_ms = g.launch_timing()
 
-    step_ms = sum(a.elapsed_time(b) for a, b in evs) / (args.steps * SAMPLE_EVERY)
+    steps_per_launch = g.time_blocking()[0]
+    assert n_launches * steps_per_launch == args.steps * SAMPLE_EVERY, n_launches
+    step_ms = launch_total_ms / n_launches / steps_per_launch
     ms_per_step = elapsed * 1e3 / args.steps
     value = args.steps * SAMPLE_EVERY * V / elapsed / 1e9
     launch = launch_figures(g, V, step_ms)

@@ -43,15 +43,16 @@
  * synchronise the handle's stream; flb_step, flb_run and
  * flb_accumulate_correlators only enqueue work.
  *
- * Sample overlap: a sample registered by flb_accumulate_correlators (or by
- * flb_run at the end of a period) is enqueued with the next steps, on an
- * internal second stream beside them; the step that would overwrite the
- * sampled state waits until the sample has read it, and the work stream
- * waits for the sample's end before the step call's work is complete.
- * Results are identical to enqueueing the sample at once.  flb_synchronize,
- * flb_read_correlators, flb_sample_conservation, flb_set_populations,
- * flb_thermalize and flb_autotune enqueue a sample still waiting on the
- * work stream first; flb_reset_correlators drops it with the sums.
+ * Sample overlap (flb_set_sample_overlap): a sample registered by
+ * flb_accumulate_correlators (or by flb_run at the end of a period) is
+ * enqueued with the next steps, on an internal second stream beside them;
+ * the step that would overwrite the sampled state waits until the sample has
+ * read it, and the work stream waits for the sample's end before the step
+ * call's work is complete.  Results are identical to enqueueing the sample
+ * at once.  flb_synchronize, flb_read_correlators, flb_sample_conservation,
+ * flb_set_populations, flb_thermalize and flb_autotune enqueue a sample
+ * still waiting on the work stream first; flb_reset_correlators drops it with
+ * the sums.  Without overlap every sample is enqueued at once.
  *
  * Errors: calls return FLB_OK (0) or a negative FLB_E* code and leave a
  * message for flb_last_error() (per thread).  Creation calls return NULL on
@@ -156,6 +157,22 @@ int flb_set_stream(flb_t *h, void *hip_stream);
  * work enqueued by the handle has finished. */
 int flb_synchronize(flb_t *h);
 
+/* Sample overlap on (1, the default) or off (0), see above.  A sample
+ * waiting for steps is enqueued first.  flb_get_sample_overlap returns the
+ * setting (or a negative FLB_E* code). */
+int flb_set_sample_overlap(flb_t *h, int on);
+int flb_get_sample_overlap(flb_t *h);
+
+/* Launch timing: while on, every step-kernel launch that flb_step or
+ * flb_run enqueues outside a captured graph is bracketed by a pair of HIP
+ * events on the work stream, recorded after any wait on the sample, so the
+ * pair measures that kernel's execution.  flb_get_launch_timing
+ * synchronises the work stream and writes the number of timed launches and
+ * the sum of their durations (ms) since the previous call, then starts a new
+ * count.  Graph-replayed periods are not timed. */
+int flb_set_launch_timing(flb_t *h, int on);
+int flb_get_launch_timing(flb_t *h, int64_t *launches, double *total_ms);
+
 /* Advances every lattice of the handle by nsteps >= 0 steps of Eq. (5) with
  * streaming (Eq. 1).  Enqueues only. */
 int flb_step(flb_t *h, int64_t nsteps);
@@ -163,9 +180,9 @@ int flb_step(flb_t *h, int64_t nsteps);
 /* Advances by nsteps and, after every step that reaches a time t with
  * t % sample_every == 0, adds a correlator sample (sample_every = 0: no
  * samples).  Whole periods of sample_every steps plus their sample are
- * replayed from a captured HIP graph, each with the previous period's sample
- * beside its steps.  Enqueues only; the last sample waits for the next steps
- * or flb_synchronize (sample overlap, above). */
+ * replayed from a captured HIP graph (with sample overlap, each with the
+ * previous period's sample beside its steps).  Enqueues only; with sample
+ * overlap the last sample waits for the next steps or flb_synchronize. */
 int flb_run(flb_t *h, int64_t nsteps, int sample_every);
 
 /* Adds one sample of the current state of every lattice to its FP64
@@ -173,8 +190,9 @@ int flb_run(flb_t *h, int64_t nsteps, int sample_every);
  * kx = 0..nx/2, ky = 0..ny-1; the k = 0 entry is left unchanged (the mean is
  * removed, Sec. 3).  FLB_ESIZE for sides beyond FLB_MAX_FFT_SIDE (powers
  * of two) or FLB_MAX_FFT_SIDE / 2 (other lengths).
- * Registers the sample (counted at once); its kernels are enqueued with the
- * next steps, or by the next call that needs them (sample overlap, above). */
+ * Registers the sample (counted at once); with sample overlap (above) its
+ * kernels are enqueued with the next steps, or by the next call that needs
+ * them, otherwise at once. */
 int flb_accumulate_correlators(flb_t *h);
 
 /* Copies lattice `lattice`'s raw FP64 sums to out[kind][ky][kx] (host), with

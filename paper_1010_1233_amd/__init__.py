@@ -66,6 +66,11 @@ SIGNATURES = {
     "flb_last_error": (ctypes.c_char_p, []),
     "flb_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "flb_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
+    "flb_set_sample_overlap": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "flb_get_sample_overlap": (ctypes.c_int, [ctypes.c_void_p]),
+    "flb_set_launch_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "flb_get_launch_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(ctypes.c_double)]),
     "flb_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
     "flb_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int]),
     "flb_accumulate_correlators": (ctypes.c_int, [ctypes.c_void_p]),
@@ -238,6 +243,28 @@ class Lattice:
 
     def synchronize(self):
         _check(lib().flb_synchronize(self._h))
+
+    def set_sample_overlap(self, on):
+        """Run each correlator sample beside the following steps (True) or
+        enqueue it at once (False); results are the same."""
+        _check(lib().flb_set_sample_overlap(self._h, int(bool(on))))
+
+    def sample_overlap(self):
+        v = lib().flb_get_sample_overlap(self._h)
+        _check(min(v, 0))
+        return bool(v)
+
+    def set_launch_timing(self, on):
+        """Bracket every step-kernel launch enqueued outside a graph with a
+        pair of HIP events (see ``launch_timing``)."""
+        _check(lib().flb_set_launch_timing(self._h, int(bool(on))))
+
+    def launch_timing(self):
+        """(launches, total ms) of the step-kernel launches timed since the
+        previous call; synchronises the work stream."""
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        _check(lib().flb_get_launch_timing(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
 
     def step(self, n=1):
         _check(lib().flb_step(self._h, int(n)))

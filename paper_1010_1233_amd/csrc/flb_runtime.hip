@@ -16,6 +16,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/flb.h"
@@ -133,8 +134,15 @@ struct flb {
     // stream waits for its end. Every call that reads the sums or changes
     // the state enqueues a due sample on the work stream first.
     bool due = false;
+    bool overlap = true;  // flb_set_sample_overlap
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_read = nullptr, ev_done = nullptr;
+
+    // launch timing (flb_set_launch_timing): an event pair around every step
+    // launch enqueued outside a graph capture, recorded after any wait so
+    // that it brackets the kernel alone
+    bool timing = false, capturing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare_events;
 
     // streams and graphs
     hipStream_t own = nullptr;
@@ -602,9 +610,31 @@ int enqueue_steps(flb_t *h, int64_t n, hipStream_t s, hipEvent_t wait_before_sec
 {
     int64_t k = 0;
     int launches = 0;
+    const bool timing = h->timing && !h->capturing;
+    hipEvent_t stop = nullptr;
     auto before_launch = [&]() -> int {
         if (launches++ == 1 && wait_before_second)
             FLB_HIP(hipStreamWaitEvent(s, wait_before_second, 0));
+        if (timing) {
+            std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+            if (!h->spare_events.empty()) {
+                ev = h->spare_events.back();
+                h->spare_events.pop_back();
+            } else {
+                FLB_HIP(hipEventCreate(&ev.first));
+                if (hipEventCreate(&ev.second) != hipSuccess) {
+                    (void)hipEventDestroy(ev.first);
+                    return fail(FLB_EHIP, "timing event creation failed");
+                }
+            }
+            h->timed.push_back(ev);
+            FLB_HIP(hipEventRecord(ev.first, s));
+            stop = ev.second;
+        }
+        return FLB_OK;
+    };
+    auto after_launch = [&]() -> int {
+        if (timing) FLB_HIP(hipEventRecord(stop, s));
         return FLB_OK;
     };
     int rc;
@@ -613,12 +643,14 @@ int enqueue_steps(flb_t *h, int64_t n, hipStream_t s, hipEvent_t wait_before_sec
             if ((rc = before_launch())) return rc;
             FLB_HIP(launch_step2(h->view(), h->d_items2, h->nitems2, h->tile2, (uint32_t)k,
                                  h->nontemporal, h->noise, s));
+            if ((rc = after_launch())) return rc;
             h->cur ^= 1;
         }
     for (; k < n; ++k) {
         if ((rc = before_launch())) return rc;
         FLB_HIP(launch_step(h->view(), h->d_items, h->nitems, h->tile_w, h->sites, (uint32_t)k,
                             h->nontemporal, h->noise, s));
+        if ((rc = after_launch())) return rc;
         h->cur ^= 1;
     }
     if (n > 0) FLB_HIP(launch_advance_step(h->d_step, (uint32_t)n, s));
@@ -827,6 +859,11 @@ void flb_destroy(flb_t *h)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : {h->ev, h->ev_fork, h->ev_read, h->ev_done})
         if (e) (void)hipEventDestroy(e);
+    for (auto *v : {&h->timed, &h->spare_events})
+        for (auto &pr : *v) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
     if (h->aux) (void)hipStreamDestroy(h->aux);
     if (h->own) (void)hipStreamDestroy(h->own);
     delete h;
@@ -865,8 +902,9 @@ int flb_step(flb_t *h, int64_t nsteps)
     return FLB_OK;
 }
 
-// Registers a sample of the current state; its kernels are enqueued with
-// the next steps (beside them) or by the next call that needs them.
+// Registers a sample of the current state; with sample overlap its kernels
+// are enqueued with the next steps (beside them) or by the next call that
+// needs them, otherwise at once.
 int flb_accumulate_correlators(flb_t *h)
 {
     if (check_handle(h)) return FLB_EINVAL;
@@ -875,6 +913,50 @@ int flb_accumulate_correlators(flb_t *h)
     if ((rc = settle_due(h))) return rc;  // a second sample of the same state
     h->due = true;
     h->nsamples += 1;
+    if (!h->overlap) return settle_due(h);
+    return FLB_OK;
+}
+
+int flb_set_sample_overlap(flb_t *h, int on)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    int rc = settle_due(h);
+    if (rc) return rc;
+    if (h->overlap != (on != 0)) {
+        h->overlap = on != 0;
+        clear_graphs(h);
+    }
+    return FLB_OK;
+}
+
+int flb_get_sample_overlap(flb_t *h)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    return h->overlap ? 1 : 0;
+}
+
+int flb_set_launch_timing(flb_t *h, int on)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    h->timing = on != 0;
+    return FLB_OK;
+}
+
+int flb_get_launch_timing(flb_t *h, int64_t *launches, double *total_ms)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (!launches || !total_ms) return fail(FLB_EINVAL, "launches and total_ms must not be NULL");
+    FLB_HIP(hipStreamSynchronize(h->stream));
+    double sum = 0.0;
+    for (auto &pr : h->timed) {
+        float ms = 0.0f;
+        FLB_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+        sum += ms;
+    }
+    *launches = (int64_t)h->timed.size();
+    *total_ms = sum;
+    h->spare_events.insert(h->spare_events.end(), h->timed.begin(), h->timed.end());
+    h->timed.clear();
     return FLB_OK;
 }
 
@@ -892,7 +974,10 @@ static int run_period_graph(flb_t *h, int every)
         const int cur0 = h->cur;
         const bool pending0 = h->pending;
         FLB_HIP(hipStreamBeginCapture(h->own, hipStreamCaptureModeRelaxed));
+        h->capturing = true;
         int rc = enqueue_steps_overlapped(h, every, h->own);
+        if (!rc && !h->overlap) rc = enqueue_sample(h, h->own);  // the period's own sample
+        h->capturing = false;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(h->own, &g);
         h->cur = cur0;
@@ -912,10 +997,12 @@ static int run_period_graph(flb_t *h, int every)
     }
     FLB_HIP(hipGraphLaunch(it->second, h->stream));
     if (step_launches(h, every) & 1) h->cur ^= 1;
-    if (due0 && h->defer) h->pending = !h->pending;
+    // samples the graph enqueued: the due one, and without overlap its own
+    const int enqueued = (due0 ? 1 : 0) + (h->overlap ? 0 : 1);
+    if (h->defer && (enqueued & 1)) h->pending = !h->pending;
     h->t += every;
     h->nsamples += 1;
-    h->due = true;  // the period's own sample runs beside the next steps
+    h->due = h->overlap;  // with overlap the period's sample runs beside the next steps
     return FLB_OK;
 }
 

@@ -106,6 +106,11 @@ def test_null_handle_calls_fail_cleanly(flb):
     assert L.flb_num_lattices(None) == -1
     assert L.flb_num_kinds(None) == flb.EINVAL
     assert L.flb_set_step(None, 0) == flb.EINVAL
+    assert L.flb_set_sample_overlap(None, 1) == flb.EINVAL
+    assert L.flb_get_sample_overlap(None) == flb.EINVAL
+    assert L.flb_set_launch_timing(None, 1) == flb.EINVAL
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    assert L.flb_get_launch_timing(None, ctypes.byref(n), ctypes.byref(ms)) == flb.EINVAL
     assert "NULL" in flb.last_error()
     L.flb_destroy(None)
 

@@ -155,3 +155,38 @@ def test_overlapped_sequence_matches_oracle(flb, oracle_lib):
     for q in range(15):
         d = np.abs(acc[q] - o.acc[q]).max()
         assert d <= 2e-4 * max(scale[q], scale[:5].max() * 1e-3), (q, d, scale[q])
+
+
+def test_overlap_switch_and_launch_timing(flb):
+    """Samples enqueued at once (overlap off) give the same bits as the
+    overlapped order, through plain calls and graph periods; launch timing
+    counts the step launches enqueued outside graphs."""
+    note("overlap switch, launch timing")
+    a, b = _pair(flb, 512, 256, blocking=2)
+    assert a.sample_overlap() and b.sample_overlap()
+    b.set_sample_overlap(False)
+    assert not b.sample_overlap()
+    for g in (a, b):
+        g.run(45, 10)
+        for n in (3, 4):
+            g.step(n)
+            g.accumulate()
+        g.run(20, 10)
+    assert np.array_equal(a.read_correlators()[0], b.read_correlators()[0])
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    a.set_launch_timing(True)
+    assert a.launch_timing() == (0, 0.0)
+    assert a.t == 72
+    a.step(7)  # three two-step launches and one one-step launch
+    n, ms = a.launch_timing()
+    assert n == 4 and ms > 0
+    a.step(1)
+    a.launch_timing()
+    a.run(20, 10)  # from t = 80: two graph periods, not timed
+    a.accumulate()
+    a.step(2)
+    n, ms = a.launch_timing()
+    assert n == 1 and ms > 0
+    a.set_launch_timing(False)
+    a.step(2)
+    assert a.launch_timing() == (0, 0.0)
