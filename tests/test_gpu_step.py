@@ -322,3 +322,72 @@ def test_time_blocking_batch_and_graph_periods(flb):
         b.set_time_blocking(3, 64)
     with pytest.raises(flb.FlbError):
         b.set_time_blocking(2, 256)
+
+
+VX = (0, 1, 0, -1, 0, 1, -1, -1, 1)
+VY = (0, 0, 1, 0, -1, 1, 1, -1, -1)
+
+
+def _oracle_site(oracle_lib, f, x, y, t, nx, tau, sigma, seed, stream_id=0):
+    """Post-collision values of site (x, y) at time t from the pulled
+    populations f[:, y, x] (one site of the oracle's step)."""
+    z = oracle_lib.normals_from_words(
+        oracle_lib.noise_words(seed, stream_id, t, y * nx + x, 0))
+    return oracle_lib.collide_site(np.ascontiguousarray(f[:, y, x]), tau, sigma, z)
+
+
+@pytest.mark.parametrize("nx,ny", [(4096, 4096), (10900, 10900)])
+def test_sampled_sites_at_full_and_maximum_size(flb, oracle_lib, nx, ny):
+    """The 4096^2 workload and a lattice at the size limit (populations of
+    4.28 GB, just under the 4 GiB reach of the 32-bit offsets), in the launch
+    shape the benchmark times: 2000 sampled sites (the corners among them)
+    after one step of the one-step kernel and after two steps of the
+    two-step kernel, each against the oracle's collision of that site (for
+    two steps, of its nine upstream neighbours at t, then of the site at
+    t + 1); the two kernels' states after two steps are the same bits."""
+    c = workloads.CONFIGS["c5_4096"]
+    tau, theta, seed = c["tau"], c["theta"], c["seed"]
+    sigma = oracle_lib.noise_amplitudes(tau, theta, 1.0)
+    note(f"{nx}x{ny} sampled sites")
+    kw = dict(u0=c["u0"], seed=seed)
+    a = flb.Lattice(nx, ny, tau, theta, **kw)
+    a.set_step_config(256, 1, 1)
+    a.set_time_blocking(2, 64)
+    a.thermalize()
+    a.step(4)
+    t = a.t
+    f0 = a.get_populations()  # f_i(x, t): the pulled values at every site
+    b = flb.Lattice(nx, ny, tau, theta, **kw)
+    b.set_step_config(256, 1, 1)
+    b.set_populations(f0)
+    b.t = t
+    b.set_time_blocking(1, 64)
+    b.step(1)
+    f1 = b.get_populations()
+    rng = np.random.default_rng(7)
+    xs = np.concatenate([[0, nx - 1, 0, nx - 1], rng.integers(0, nx, 1996)])
+    ys = np.concatenate([[0, 0, ny - 1, ny - 1], rng.integers(0, ny, 1996)])
+    err1 = 0.0
+    for x, y in zip(xs.tolist(), ys.tolist()):
+        fo = _oracle_site(oracle_lib, f0, x, y, t, nx, tau, sigma, seed)
+        got = [f1[i, (y + VY[i]) % ny, (x + VX[i]) % nx] for i in range(9)]
+        err1 = max(err1, float(np.abs(np.array(got) - fo).max()))
+    del f1
+    note("  one step: max |df|", err1)
+    assert err1 < 1e-6
+    a.step(2)  # one launch of the two-step kernel
+    f2 = a.get_populations()
+    err2 = 0.0
+    for x, y in zip(xs[:500].tolist(), ys[:500].tolist()):
+        pulled = np.empty((9, 1, 1))
+        for i in range(9):
+            xu, yu = (x - VX[i]) % nx, (y - VY[i]) % ny
+            pulled[i, 0, 0] = _oracle_site(oracle_lib, f0, xu, yu, t, nx, tau, sigma, seed)[i]
+        z = oracle_lib.normals_from_words(oracle_lib.noise_words(seed, 0, t + 1, y * nx + x, 0))
+        fo = oracle_lib.collide_site(np.ascontiguousarray(pulled[:, 0, 0]), tau, sigma, z)
+        got = [f2[i, (y + VY[i]) % ny, (x + VX[i]) % nx] for i in range(9)]
+        err2 = max(err2, float(np.abs(np.array(got) - fo).max()))
+    note("  two steps: max |df|", err2)
+    assert err2 < 2e-6
+    b.step(1)  # second step through the one-step kernel
+    assert np.array_equal(b.get_populations(), f2)
