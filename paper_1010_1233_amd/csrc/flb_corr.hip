@@ -33,7 +33,9 @@ struct CorrArgs {
     const float2 *tables;
     const CorrItem *items;
     float2 *spec;
-    float2 *stash;  // spectra of a sample whose products are not yet added
+    float2 *stash;  // spectra of samples whose products are not yet added
+    int64_t stash_stride;  // elements per stash slot
+    int arg;        // stash slot (stash mode) or number of slots (pair mode, flush)
     double *acc;
     float *fields;
     double *csum_part;
@@ -383,14 +385,32 @@ __device__ __forceinline__ void accumulate_k(double *a, int64_t kstride, const f
 
 // Adds the products of two samples at one k to the sums in one
 // read-modify-write of the FP64 sums.
-__device__ __forceinline__ void accumulate_pair_k(double *a, int64_t kstride,
-                                                  const float2 (&X)[5], const float2 (&Y)[5])
+// The products of X (when WITH_X) and of the n stashed samples at st (slot
+// j at st + j * sstride, field f at + f * kstride), summed in that order and
+// added to the sums in one read-modify-write.
+template <bool WITH_X>
+__device__ __forceinline__ void accumulate_stashed_k(double *a, int64_t kstride,
+                                                     const float2 (&X)[5], const float2 *st,
+                                                     int64_t sstride, int n)
 {
-    double u[kKinds], w[kKinds];
-    products_k(u, X);
-    products_k(w, Y);
+    double u[kKinds];
+    if constexpr (WITH_X) {
+        products_k(u, X);
+    } else {
 #pragma unroll
-    for (int q = 0; q < kKinds; ++q) a[q * kstride] += u[q] + w[q];
+        for (int q = 0; q < kKinds; ++q) u[q] = 0.0;
+    }
+    for (int j = 0; j < n; ++j) {
+        float2 Y[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) Y[f] = st[j * sstride + f * kstride];
+        double w[kKinds];
+        products_k(w, Y);
+#pragma unroll
+        for (int q = 0; q < kKinds; ++q) u[q] += w[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kKinds; ++q) a[q * kstride] += u[q];
 }
 
 // Squared moduli of the six moment spectra at one k, added to kinds
@@ -417,10 +437,11 @@ __device__ __forceinline__ void accumulate_set(double *a, int64_t kstride, const
 // Power-of-two ny, pass B with accumulation.  item: lattice, first column, k1.
 // LDS [q][f][c]: the Q rows Q*k1 .. Q*k1+Q-1 of all fields of the set, 16
 // columns.  MODE (field set 0): kAccDirect adds this sample's products;
-// kAccStash keeps its spectra in the stash instead; kAccPair adds the
-// products of this sample and of the stashed one in one read-modify-write
-// of the FP64 sums (the sums are the same, the HBM traffic for them is
-// halved over a pair of samples).
+// kAccStash keeps its spectra in stash slot g.arg instead; kAccPair adds the
+// products of this sample and of the g.arg stashed ones in one
+// read-modify-write of the FP64 sums (the sums are the same up to FP64
+// rounding order; the HBM traffic for them is divided by the samples per
+// read-modify-write).
 template <int SET, int MODE>
 __global__ __launch_bounds__(kFftThreads) void corr_cols_b_kernel(CorrArgs g)
 {
@@ -462,13 +483,11 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_b_kernel(CorrArgs g)
 #pragma unroll
         for (int f = 0; f < NF; ++f) X[f] = lds[k2 * NL + f * 16 + c];
         if constexpr (MODE == kAccStash) {
+            float2 *slot = stash + (int64_t)g.arg * g.stash_stride;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) stash[f * fstride + o] = X[f];
+            for (int f = 0; f < NF; ++f) slot[f * fstride + o] = X[f];
         } else if constexpr (MODE == kAccPair) {
-            float2 Y[NF];
-#pragma unroll
-            for (int f = 0; f < NF; ++f) Y[f] = stash[f * fstride + o];
-            accumulate_pair_k(acc + o, fstride, X, Y);
+            accumulate_stashed_k<true>(acc + o, fstride, X, stash + o, g.stash_stride, g.arg);
         } else {
             accumulate_set<SET, NF>(acc + o, fstride, X);
         }
@@ -527,6 +546,26 @@ __global__ __launch_bounds__(kThreads) void corr_accum_kernel(CorrArgs g)
     accumulate_set<SET, NF>(g.acc + P.acc_base + o, fstride, X);
 }
 
+// Reads a sample's stashed spectra back: the products of the first g.arg
+// stash slots added to the sums (the layout and items of
+// corr_accum_kernel<0>).
+__global__ __launch_bounds__(kThreads) void corr_flush_kernel(CorrArgs g)
+{
+    const CorrItem it = g.items[blockIdx.x];
+    if (it.lattice < 0) return;
+    const LatticeParams &P = g.params[it.lattice];
+    const int nkx = P.nkx, kxp = P.kxp;
+    const int64_t nk = (int64_t)P.ny * nkx;
+    const int64_t k = (int64_t)it.a + threadIdx.x;
+    if (k >= nk || k == 0) return;
+    const int ky = (int)(k / nkx), kx = (int)(k - (int64_t)ky * nkx);
+    const int64_t o = (int64_t)ky * kxp + kx;
+    const int64_t fstride = (int64_t)P.ny * kxp;
+    const float2 X[5] = {};
+    accumulate_stashed_k<false>(g.acc + P.acc_base + o, fstride, X,
+                                g.stash + P.spec_base + o, g.stash_stride, g.arg);
+}
+
 static CorrArgs make_args(const DeviceView &v, const CorrItem *items, int set)
 {
     CorrArgs g;
@@ -537,6 +576,8 @@ static CorrArgs make_args(const DeviceView &v, const CorrItem *items, int set)
     g.items = items;
     g.spec = v.spec;
     g.stash = v.stash;
+    g.stash_stride = v.stash_stride;
+    g.arg = 0;
     g.acc = v.acc;
     g.fields = v.fields;
     g.csum_part = v.csum_part;
@@ -608,9 +649,10 @@ hipError_t launch_corr_cols_a(const DeviceView &v, const CorrItem *items, int ni
 }
 
 hipError_t launch_corr_cols_b(const DeviceView &v, const CorrItem *items, int nitems, int set,
-                              int mode, int lds_bytes, hipStream_t s)
+                              int mode, int arg, int lds_bytes, hipStream_t s)
 {
-    const CorrArgs g = make_args(v, items, set);
+    CorrArgs g = make_args(v, items, set);
+    g.arg = arg;
     const dim3 grid(nitems), block(kFftThreads);
     if (set == 1)
         hipLaunchKernelGGL((corr_cols_b_kernel<1, kAccDirect>), grid, block, lds_bytes, s, g);
@@ -623,13 +665,12 @@ hipError_t launch_corr_cols_b(const DeviceView &v, const CorrItem *items, int ni
     return hipGetLastError();
 }
 
-hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nitems,
+hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nitems, int nslots,
                              hipStream_t s)
 {
-    // the stash has the layout of the spectra: accumulate it as a sample
     CorrArgs g = make_args(v, items, 0);
-    g.spec = v.stash;
-    hipLaunchKernelGGL(corr_accum_kernel<0>, dim3(nitems), dim3(kThreads), 0, s, g);
+    g.arg = nslots;
+    hipLaunchKernelGGL(corr_flush_kernel, dim3(nitems), dim3(kThreads), 0, s, g);
     return hipGetLastError();
 }
 

@@ -111,7 +111,8 @@ struct DeviceView {
     const uint32_t *step;             // device step counter
     uint32_t *step_rw;
     float2 *spec;
-    float2 *stash;                    // spectra awaiting accumulation (layout of spec)
+    float2 *stash;                    // slots of spectra awaiting accumulation (layout of spec)
+    int64_t stash_stride;             // elements per stash slot
     double *acc;
     float *fields;                    // [6][ny][nx] FP32 moment planes per lattice
     double *csum_part;                // field-kernel partial sums
@@ -160,12 +161,16 @@ hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nite
                             int lds_bytes, hipStream_t s);
 hipError_t launch_corr_cols_a(const DeviceView &v, const CorrItem *items, int nitems,
                               int lds_bytes, hipStream_t s);
-// Accumulation modes of column pass B for field set 0 (power-of-two ny).
+// Accumulation modes of column pass B for field set 0 (power-of-two ny):
+// add this sample's products; keep its spectra in stash slot `arg`; add its
+// products and those of the first `arg` stash slots in one read-modify-write.
 enum AccMode : int { kAccDirect = 0, kAccStash = 1, kAccPair = 2 };
+// samples per read-modify-write of the FP64 sums (kDeferK - 1 stash slots)
+constexpr int kDeferK = 8;
 hipError_t launch_corr_cols_b(const DeviceView &v, const CorrItem *items, int nitems, int set,
-                              int mode, int lds_bytes, hipStream_t s);
-// Adds the products of the stashed spectra to the sums (field set 0).
-hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nitems,
+                              int mode, int arg, int lds_bytes, hipStream_t s);
+// Adds the products of the first nslots stash slots to the sums (field set 0).
+hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nitems, int nslots,
                              hipStream_t s);
 hipError_t launch_corr_accum(const DeviceView &v, const CorrItem *items, int nitems, int set,
                              hipStream_t s);

@@ -53,8 +53,8 @@ const int kVy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
 // A captured sampling period: its length, the buffer holding the state at
 // its start, whether the sample of that state is due (it then runs beside
-// the period's steps) and whether a stashed sample is pending (which decides
-// the accumulation mode of the due sample).
+// the period's steps) and how many stashed samples are pending (which
+// decides the accumulation modes of the period's samples).
 struct GraphKey {
     int every, parity, pending, due;
     bool operator<(const GraphKey &o) const
@@ -117,9 +117,11 @@ struct flb {
     int n_cols_a_m = 0, n_cols_m = 0, n_rows_m = 0;
     CorrItem *d_rows_blue = nullptr;  // rows of lattices with Bluestein row transforms
     int n_rows_blue = 0;
-    // deferred accumulation (power-of-two ny): every other sample stashes its
-    // spectra and the next one adds both samples' products at once
-    bool defer = false, pending = false;
+    // deferred accumulation (power-of-two ny): samples stash their spectra in
+    // kDeferK - 1 slots and every kDeferK-th one adds the products of all of
+    // them at once; `pending` counts the stashed samples
+    bool defer = false;
+    int pending = 0;
     float2 *d_stash = nullptr;
     CorrItem *d_flush = nullptr;
     int n_flush = 0;
@@ -161,6 +163,7 @@ struct flb {
         v.step_rw = d_step;
         v.spec = d_spec;
         v.stash = d_stash;
+        v.stash_stride = spec_elems;
         v.acc = d_acc;
         v.fields = d_fields;
         v.csum_part = d_csum_part;
@@ -528,7 +531,7 @@ int setup_correlators(flb_t *h)
     h->n_rows_m = (int)rows_m.size();
     h->n_flush = (int)flush.size();
     h->defer = !cols_b.empty();
-    h->pending = false;
+    h->pending = 0;
     h->n_rows = (int)rows.size();
     h->n_cols = (int)cols.size();
     h->n_accum = (int)accum.size();
@@ -548,7 +551,8 @@ int setup_correlators(flb_t *h)
     FLB_HIP(hipMalloc((void **)&h->d_spec, spec * sizeof(float2)));
     FLB_HIP(hipMalloc((void **)&h->d_acc, acc * sizeof(double)));
     if (fld > 0) FLB_HIP(hipMalloc((void **)&h->d_fields, fld * sizeof(float)));
-    if (h->defer) FLB_HIP(hipMalloc((void **)&h->d_stash, spec * sizeof(float2)));
+    if (h->defer)
+        FLB_HIP(hipMalloc((void **)&h->d_stash, (size_t)(kDeferK - 1) * spec * sizeof(float2)));
     FLB_HIP(hipMalloc((void **)&h->d_csum_part, (size_t)nparts * 5 * sizeof(double)));
     FLB_HIP(hipMalloc((void **)&h->d_csum, h->params.size() * 5 * sizeof(double)));
     FLB_HIP(launch_fill(h->d_csum, h->params.size() * 5, h->stream));
@@ -582,13 +586,15 @@ int enqueue_sample(flb_t *h, hipStream_t s, hipEvent_t ev_read = nullptr)
         }
         if (na) FLB_HIP(launch_corr_cols_a(v, ca, na, h->cols_a_lds, s));
         if (h->n_cols_b) {
-            const int mode = (set || !h->defer) ? kAccDirect : h->pending ? kAccPair : kAccStash;
-            FLB_HIP(launch_corr_cols_b(v, h->d_cols_b, h->n_cols_b, set, mode, h->cols_b_lds, s));
+            const int mode = (set || !h->defer) ? kAccDirect
+                             : h->pending == kDeferK - 1 ? kAccPair : kAccStash;
+            FLB_HIP(launch_corr_cols_b(v, h->d_cols_b, h->n_cols_b, set, mode, h->pending,
+                                       h->cols_b_lds, s));
         }
         if (ng) FLB_HIP(launch_corr_cols(v, cg, ng, h->cols_cb, h->cols_lds, s));
         if (h->n_accum) FLB_HIP(launch_corr_accum(v, h->d_accum, h->n_accum, set, s));
     }
-    if (h->defer) h->pending = !h->pending;
+    if (h->defer) h->pending = (h->pending + 1) % kDeferK;
     return FLB_OK;
 }
 
@@ -596,8 +602,8 @@ int enqueue_sample(flb_t *h, hipStream_t s, hipEvent_t ev_read = nullptr)
 int flush_pending(flb_t *h)
 {
     if (!h->pending) return FLB_OK;
-    FLB_HIP(launch_corr_flush(h->view(), h->d_flush, h->n_flush, h->stream));
-    h->pending = false;
+    FLB_HIP(launch_corr_flush(h->view(), h->d_flush, h->n_flush, h->pending, h->stream));
+    h->pending = 0;
     return FLB_OK;
 }
 
@@ -964,7 +970,7 @@ int flb_get_launch_timing(flb_t *h, int64_t *launches, double *total_ms)
 static int run_period_graph(flb_t *h, int every)
 {
     const bool due0 = h->due;
-    const GraphKey key{every, h->cur, h->pending ? 1 : 0, due0 ? 1 : 0};
+    const GraphKey key{every, h->cur, h->pending, due0 ? 1 : 0};
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
         // capture on the handle's own stream (capturing the legacy default
@@ -972,7 +978,7 @@ static int run_period_graph(flb_t *h, int every)
         // sample forks onto the side stream inside the capture and joins
         // before its end
         const int cur0 = h->cur;
-        const bool pending0 = h->pending;
+        const int pending0 = h->pending;
         FLB_HIP(hipStreamBeginCapture(h->own, hipStreamCaptureModeRelaxed));
         h->capturing = true;
         int rc = enqueue_steps_overlapped(h, every, h->own);
@@ -999,7 +1005,7 @@ static int run_period_graph(flb_t *h, int every)
     if (step_launches(h, every) & 1) h->cur ^= 1;
     // samples the graph enqueued: the due one, and without overlap its own
     const int enqueued = (due0 ? 1 : 0) + (h->overlap ? 0 : 1);
-    if (h->defer && (enqueued & 1)) h->pending = !h->pending;
+    if (h->defer) h->pending = (h->pending + enqueued) % kDeferK;
     h->t += every;
     h->nsamples += 1;
     h->due = h->overlap;  // with overlap the period's sample runs beside the next steps
@@ -1062,7 +1068,7 @@ int flb_reset_correlators(flb_t *h)
     if (rc) return rc;
     FLB_HIP(launch_fill(h->d_acc, (size_t)h->acc_elems, h->stream));
     h->nsamples = 0;
-    h->pending = false;  // a stashed or due sample is dropped with the sums
+    h->pending = 0;  // stashed and due samples are dropped with the sums
     h->due = false;
     return FLB_OK;
 }
