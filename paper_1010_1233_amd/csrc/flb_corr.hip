@@ -148,8 +148,12 @@ __device__ __forceinline__ void store_row_spectra(const float2 *lds, const Latti
 // cases are separate instantiations so that the power-of-two one carries no
 // chirp state in registers.
 // item: lattice, first row, rows, index of the block's partial.
+// At most 80 VGPRs (six waves per SIMD, three blocks per CU) at the cost of a
+// few spilled values: the kernel is bound by the latency of its transforms,
+// and the third block hides more of it (measured 2 % faster than 93 VGPRs
+// and two blocks).
 template <int S, bool BLUE>
-__global__ __launch_bounds__(kFftThreads) void corr_rows_kernel(CorrArgs g)
+__global__ __launch_bounds__(kFftThreads, 6) void corr_rows_kernel(CorrArgs g)
 {
     using T = typename Codec<S>::T;
     constexpr int E = 4096 / kFftThreads;  // line elements per thread
