@@ -169,7 +169,8 @@ int flb_get_sample_overlap(flb_t *h);
  * pair measures that kernel's execution.  flb_get_launch_timing
  * synchronises the work stream and writes the number of timed launches and
  * the sum of their durations (ms) since the previous call, then starts a new
- * count.  Graph-replayed periods are not timed. */
+ * count.  Graph-replayed periods and flb_autotune's candidates are not
+ * timed; each timed launch keeps its event pair until it is read. */
 int flb_set_launch_timing(flb_t *h, int on);
 int flb_get_launch_timing(flb_t *h, int64_t *launches, double *total_ms);
 

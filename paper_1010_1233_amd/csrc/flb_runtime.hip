@@ -1356,6 +1356,8 @@ int flb_autotune(flb_t *h, int nsteps, double *ms_out)
         if (e == hipSuccess) best_ms = std::min(best_ms, ms / n);
     };
     const int tb0 = h->tblock, t20 = h->tile2;
+    const bool timing0 = h->timing;  // the candidates' launches are not the caller's
+    h->timing = false;
     for (int round = 0; round < kRounds && e == hipSuccess && rc == FLB_OK; ++round) {
         h->tblock = 1;
         for (int a = 0; a < 3 && e == hipSuccess && rc == FLB_OK; ++a)
@@ -1376,6 +1378,7 @@ int flb_autotune(flb_t *h, int nsteps, double *ms_out)
     }
     h->tblock = tb0;
     h->tile2 = t20;
+    h->timing = timing0;
     int best_tw = h->tile_w, best_sv = h->sites;
     bool best_nt = h->nontemporal;
     float best = 1e30f;
