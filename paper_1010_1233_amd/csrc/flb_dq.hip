@@ -457,6 +457,66 @@ __global__ __launch_bounds__(kFftThreads) void dq_lines_kernel(DqCorrArgs g, int
     }
 }
 
+// Kind index of field f's auto-correlation: the two u_x u_y* kinds come
+// just before the first non-conserved moment (D >= 2).
+__device__ __forceinline__ int dq_auto_kind(int f, int D)
+{
+    return (D >= 2 && f >= 1 + 2 * D) ? f + 2 : f;
+}
+
+// Last transform axis with the accumulation fused in: one block per (field
+// group, position along the other axis, group of cb adjacent kx), the
+// groups being every field alone except u_x, u_y, which are transformed
+// together for their cross kinds; the spectra are added to the FP64 sums as
+// they leave LDS, never written back.
+__global__ __launch_bounds__(kFftThreads) void dq_last_kernel(DqCorrArgs g, int axis, int cb)
+{
+    extern __shared__ float2 lds[];
+    const int D = g.D, ny = g.n[1], nz = g.n[2];
+    const int n = axis == 1 ? ny : nz, nouter = axis == 1 ? nz : ny;
+    const size_t stride = axis == 1 ? (size_t)g.kxp : (size_t)ny * g.kxp;
+    const size_t ostride = axis == 1 ? (size_t)ny * g.kxp : (size_t)g.kxp;
+    const int ncg = (g.nkx + cb - 1) / cb;
+    int b = (int)blockIdx.x;
+    const int cgi = b % ncg;
+    b /= ncg;
+    const int o = b % nouter, grp = b / nouter;
+    const bool upair = D >= 2 && grp == 1 + D;
+    const int f0 = (D >= 2 && grp > 1 + D) ? grp + 1 : grp, nfg = upair ? 2 : 1;
+    const int c0 = cgi * cb, ncol = min(cb, g.nkx - c0);
+    const LinePlan &L = g.plans[axis == 1 ? g.line_y : g.line_z];
+    const float2 *chirp = g.tables + L.chirp_off;
+    const size_t fstride = (size_t)ny * nz * g.kxp;
+    const size_t base = (size_t)o * ostride + c0;
+    const int nl = nfg * cb;  // interleaved lines: field q, column c at q * cb + c
+    for (int idx = threadIdx.x; idx < L.m * nl; idx += kFftThreads) {
+        const int j = idx / nl, r = idx - j * nl, q = r / cb, c = r - q * cb;
+        float2 v = make_float2(0.f, 0.f);
+        if (j < n && c < ncol) {
+            v = g.spec[(size_t)(f0 + q) * fstride + base + (size_t)j * stride + c];
+            if (L.bluestein) v = cmul(v, chirp[j]);
+        }
+        lds[bitrev(j, L.log2m) * nl + r] = v;
+    }
+    __syncthreads();
+    lds_line_dft<false>(lds, L, nl, 1, nl, g.tables);
+    for (int idx = threadIdx.x; idx < n * cb; idx += kFftThreads) {
+        const int j = idx / cb, c = idx - j * cb;
+        if (c >= ncol || (j == 0 && o == 0 && c0 + c == 0)) continue;  // k = 0
+        const size_t off = base + (size_t)j * stride + c;
+        const float2 X = lds[j * nl + c];
+        const double xr = X.x, xi = X.y;
+        g.acc[(size_t)dq_auto_kind(f0, D) * fstride + off] += xr * xr + xi * xi;
+        if (upair) {
+            const float2 Y = lds[j * nl + cb + c];
+            const double yr = Y.x, yi = Y.y;
+            g.acc[(size_t)dq_auto_kind(f0 + 1, D) * fstride + off] += yr * yr + yi * yi;
+            g.acc[(size_t)(1 + 2 * D) * fstride + off] += xr * yr + xi * yi;
+            g.acc[(size_t)(2 + 2 * D) * fstride + off] += xi * yr - xr * yi;
+        }
+    }
+}
+
 // FP64 accumulation of the kinds of flb_dq.h at every k of the half space.
 __global__ __launch_bounds__(kDqThreads) void dq_accum_kernel(DqCorrArgs g)
 {
@@ -519,6 +579,7 @@ struct flb_dq {
     double *d_acc = nullptr;
     int line[3] = {0, 0, 0};
     int rows_lds = 0, lines_lds = 0, rb = 1, cb = 1;
+    int last_cb = 0, last_lds = 0;  // fused last pass (0: a separate accumulation)
     int64_t nsamples = 0;
 };
 
@@ -653,6 +714,17 @@ int setup_corr(flb_dq *h)
         if (h->n[a] > 1) my = std::max(my, lt.plans[h->line[a]].m);
     h->cb = std::max(1, std::min(16, 8192 / my));
     h->lines_lds = my * h->cb * (int)sizeof(float2);
+    // the last axis carries the accumulation when two fields of cb >= 4
+    // columns fit 32 KB of LDS
+    h->last_cb = 0;
+    if (h->D >= 2) {
+        const int ml = lt.plans[h->line[h->D - 1]].m;
+        const int cbl = std::min(16, 32768 / (2 * ml * (int)sizeof(float2)));
+        if (cbl >= 4) {
+            h->last_cb = cbl;
+            h->last_lds = 2 * ml * cbl * (int)sizeof(float2);
+        }
+    }
     const int nkx = h->n[0] / 2 + 1, kxp = (nkx + 15) / 16 * 16;
     h->P.nkx = nkx;
     h->P.kxp = kxp;
@@ -709,17 +781,27 @@ int enqueue_sample(flb_dq *h)
                        h->stream, g, h->rb);
     DQ_HIP(hipGetLastError());
     const int ncg = (h->P.nkx + h->cb - 1) / h->cb;
+    const int last = h->D - 1;  // the last transformed axis (D >= 2)
     for (int axis = 1; axis < 3; ++axis) {
         if (h->n[axis] < 2) continue;
         const int nouter = axis == 1 ? h->n[2] : h->n[1];
-        hipLaunchKernelGGL(dq_lines_kernel, dim3(h->nf * nouter * ncg), dim3(kFftThreads),
-                           h->lines_lds, h->stream, g, axis, h->cb);
+        if (axis == last && h->last_cb) {
+            const int ncgl = (h->P.nkx + h->last_cb - 1) / h->last_cb;
+            const int ngroups = h->nf - 1;  // u_x and u_y together
+            hipLaunchKernelGGL(dq_last_kernel, dim3(ngroups * nouter * ncgl), dim3(kFftThreads),
+                               h->last_lds, h->stream, g, axis, h->last_cb);
+        } else {
+            hipLaunchKernelGGL(dq_lines_kernel, dim3(h->nf * nouter * ncg), dim3(kFftThreads),
+                               h->lines_lds, h->stream, g, axis, h->cb);
+        }
         DQ_HIP(hipGetLastError());
     }
-    const int64_t nk = (int64_t)nrows * h->P.nkx;
-    hipLaunchKernelGGL(dq_accum_kernel, dim3((unsigned)((nk + kDqThreads - 1) / kDqThreads)),
-                       dim3(kDqThreads), 0, h->stream, g);
-    DQ_HIP(hipGetLastError());
+    if (!h->last_cb) {
+        const int64_t nk = (int64_t)nrows * h->P.nkx;
+        hipLaunchKernelGGL(dq_accum_kernel, dim3((unsigned)((nk + kDqThreads - 1) / kDqThreads)),
+                           dim3(kDqThreads), 0, h->stream, g);
+        DQ_HIP(hipGetLastError());
+    }
     h->nsamples += 1;
     return FLB_OK;
 }
