@@ -244,9 +244,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the method's lattices are "
-              "independent; sharding across GPUs is described, not built). Use --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (independent "
+              "lattices would shard across GPUs with one final all-reduce of the FP64 sums). "
+              "Use --gpus 1.", file=sys.stderr)
         return 2
 
     import torch
