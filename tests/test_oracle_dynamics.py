@@ -110,7 +110,7 @@ def test_sound_wave_frequency_and_damping(oracle_lib, L_side, tau):
     assert abs(arg / h_arg - 1) < 0.1 * k * k
 
 
-def test_survey_eigenvalues():
+def test_exact_linear_eigenvalues_at_the_first_mode():
     """Exact linear eigenvalues at k = 2 pi / 32 x, tau_s = tau_b = 0.8 (a
     number computed once, independently, by a numpy linearisation)."""
     sh, mod, arg = lyapunov.exact_rates(2 * np.pi / 32, workloads.tau_vector(0.8, 0.8, 1.0))
