@@ -238,6 +238,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--sweep-shapes", action="store_true",
                     help="only run every step-kernel launch shape briefly (for counter runs)")
+    ap.add_argument("--velocity-sets", action="store_true",
+                    help="only time the other velocity sets (D3Q15 at 256^3 with its "
+                         "correlators, D1Q3 at 2^26 sites) and print their figures")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 603,979,776 bytes device to device three times "
                          "(the known-size reference for HBM byte counters)")
@@ -275,6 +278,15 @@ def main():
         return 0
     if args.sweep_shapes:
         sweep_shapes(flb, workloads, args.workload, args.storage)
+        return 0
+    if args.velocity_sets:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            out = {"d3q15_256x256x256": velocity_set_form(torch, flb, stream, "D3Q15",
+                                                          (256, 256, 256)),
+                   "d1q3_67108864": velocity_set_form(torch, flb, stream, "D1Q3", (1 << 26,),
+                                                      sample=False)}
+        print(json.dumps(out), flush=True)
         return 0
     stream = torch.cuda.Stream()
     g, c = make_lattice(flb, workloads, args.workload, args.storage)

@@ -464,12 +464,13 @@ __device__ __forceinline__ int dq_auto_kind(int f, int D)
     return (D >= 2 && f >= 1 + 2 * D) ? f + 2 : f;
 }
 
-// Last transform axis with the accumulation fused in: one block per (field
-// group, position along the other axis, group of cb adjacent kx), the
-// groups being every field alone except u_x, u_y, which are transformed
-// together for their cross kinds; the spectra are added to the FP64 sums as
-// they leave LDS, never written back.
-__global__ __launch_bounds__(kFftThreads) void dq_last_kernel(DqCorrArgs g, int axis, int cb)
+// Last transform axis with the accumulation fused in: one block per (field,
+// position along the other axis, group of cb adjacent kx), every field alone
+// except u_x, u_y, which are transformed together for their cross kinds
+// (upair: one launch of that pair alone); the spectra are added to the FP64
+// sums as they leave LDS, never written back.
+__global__ __launch_bounds__(kFftThreads) void dq_last_kernel(DqCorrArgs g, int axis, int cb,
+                                                              int upair)
 {
     extern __shared__ float2 lds[];
     const int D = g.D, ny = g.n[1], nz = g.n[2];
@@ -481,8 +482,8 @@ __global__ __launch_bounds__(kFftThreads) void dq_last_kernel(DqCorrArgs g, int 
     const int cgi = b % ncg;
     b /= ncg;
     const int o = b % nouter, grp = b / nouter;
-    const bool upair = D >= 2 && grp == 1 + D;
-    const int f0 = (D >= 2 && grp > 1 + D) ? grp + 1 : grp, nfg = upair ? 2 : 1;
+    // single fields skip u_x, u_y (fields 1 + D, 2 + D)
+    const int f0 = upair ? 1 + D : (grp < 1 + D ? grp : grp + 2), nfg = upair ? 2 : 1;
     const int c0 = cgi * cb, ncol = min(cb, g.nkx - c0);
     const LinePlan &L = g.plans[axis == 1 ? g.line_y : g.line_z];
     const float2 *chirp = g.tables + L.chirp_off;
@@ -579,7 +580,9 @@ struct flb_dq {
     double *d_acc = nullptr;
     int line[3] = {0, 0, 0};
     int rows_lds = 0, lines_lds = 0, rb = 1, cb = 1;
-    int last_cb = 0, last_lds = 0;  // fused last pass (0: a separate accumulation)
+    // fused last pass: columns per block for single fields and for the u
+    // pair (0: a separate accumulation)
+    int last_cb = 0, last_cb_pair = 0, last_lds = 0;
     int64_t nsamples = 0;
 };
 
@@ -714,15 +717,17 @@ int setup_corr(flb_dq *h)
         if (h->n[a] > 1) my = std::max(my, lt.plans[h->line[a]].m);
     h->cb = std::max(1, std::min(16, 8192 / my));
     h->lines_lds = my * h->cb * (int)sizeof(float2);
-    // the last axis carries the accumulation when two fields of cb >= 4
-    // columns fit 32 KB of LDS
-    h->last_cb = 0;
+    // the last axis carries the accumulation when the two u fields of cb >= 4
+    // columns fit 32 KB of LDS; single fields take up to 16 columns (whole
+    // 128-byte lines of the spectra and the sums) in the same 32 KB
+    h->last_cb = h->last_cb_pair = 0;
     if (h->D >= 2) {
         const int ml = lt.plans[h->line[h->D - 1]].m;
-        const int cbl = std::min(16, 32768 / (2 * ml * (int)sizeof(float2)));
-        if (cbl >= 4) {
-            h->last_cb = cbl;
-            h->last_lds = 2 * ml * cbl * (int)sizeof(float2);
+        const int cbp = std::min(16, 32768 / (2 * ml * (int)sizeof(float2)));
+        if (cbp >= 4) {
+            h->last_cb_pair = cbp;
+            h->last_cb = std::min(16, 2 * cbp);
+            h->last_lds = 32768;
         }
     }
     const int nkx = h->n[0] / 2 + 1, kxp = (nkx + 15) / 16 * 16;
@@ -787,9 +792,12 @@ int enqueue_sample(flb_dq *h)
         const int nouter = axis == 1 ? h->n[2] : h->n[1];
         if (axis == last && h->last_cb) {
             const int ncgl = (h->P.nkx + h->last_cb - 1) / h->last_cb;
-            const int ngroups = h->nf - 1;  // u_x and u_y together
-            hipLaunchKernelGGL(dq_last_kernel, dim3(ngroups * nouter * ncgl), dim3(kFftThreads),
-                               h->last_lds, h->stream, g, axis, h->last_cb);
+            const int ncgp = (h->P.nkx + h->last_cb_pair - 1) / h->last_cb_pair;
+            hipLaunchKernelGGL(dq_last_kernel, dim3((h->nf - 2) * nouter * ncgl),
+                               dim3(kFftThreads), h->last_lds, h->stream, g, axis, h->last_cb, 0);
+            DQ_HIP(hipGetLastError());
+            hipLaunchKernelGGL(dq_last_kernel, dim3(nouter * ncgp), dim3(kFftThreads),
+                               h->last_lds, h->stream, g, axis, h->last_cb_pair, 1);
         } else {
             hipLaunchKernelGGL(dq_lines_kernel, dim3(h->nf * nouter * ncg), dim3(kFftThreads),
                                h->lines_lds, h->stream, g, axis, h->cb);
