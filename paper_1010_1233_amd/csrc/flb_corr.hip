@@ -510,6 +510,10 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g, int 
     const int f = it.a, c0 = it.b;
     const int ncol = min(cb, nkx - c0);
     float2 *col = g.spec + P.spec_base + (int64_t)f * ny * kxp + c0;
+    // the transformed column goes back in place, or to stash slot g.arg >= 0
+    float2 *out = g.arg < 0 ? col
+                            : g.stash + (int64_t)g.arg * g.stash_stride + P.spec_base +
+                                  (int64_t)f * ny * kxp + c0;
     const float2 *chirp = g.tables + L.chirp_off;
     for (int idx = threadIdx.x; idx < L.m * cb; idx += kFftThreads) {
         const int j = idx / cb, c = idx - j * cb;
@@ -524,7 +528,7 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g, int 
     lds_line_dft<false>(lds, L, cb, 1, cb, g.tables);
     for (int idx = threadIdx.x; idx < ny * cb; idx += kFftThreads) {
         const int j = idx / cb, c = idx - j * cb;
-        if (c < ncol) col[(int64_t)j * kxp + c] = lds[idx];
+        if (c < ncol) out[(int64_t)j * kxp + c] = lds[idx];
     }
 }
 
@@ -547,6 +551,14 @@ __global__ __launch_bounds__(kThreads) void corr_accum_kernel(CorrArgs g)
     float2 X[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) X[f] = sp[f * fstride + o];
+    if constexpr (SET == 0) {
+        // g.arg > 0: with the products of that many stashed samples
+        if (g.arg > 0) {
+            accumulate_stashed_k<true>(g.acc + P.acc_base + o, fstride, X,
+                                       g.stash + P.spec_base + o, g.stash_stride, g.arg);
+            return;
+        }
+    }
     accumulate_set<SET, NF>(g.acc + P.acc_base + o, fstride, X);
 }
 
@@ -679,17 +691,19 @@ hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nit
 }
 
 hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int cb,
-                            int lds_bytes, hipStream_t s)
+                            int slot, int lds_bytes, hipStream_t s)
 {
-    const CorrArgs g = make_args(v, items, 0);
+    CorrArgs g = make_args(v, items, 0);
+    g.arg = slot;
     hipLaunchKernelGGL(corr_cols_kernel, dim3(nitems), dim3(kFftThreads), lds_bytes, s, g, cb);
     return hipGetLastError();
 }
 
 hipError_t launch_corr_accum(const DeviceView &v, const CorrItem *items, int nitems, int set,
-                             hipStream_t s)
+                             int nslots, hipStream_t s)
 {
-    const CorrArgs g = make_args(v, items, set);
+    CorrArgs g = make_args(v, items, set);
+    g.arg = nslots;
     if (set == 1)
         hipLaunchKernelGGL(corr_accum_kernel<1>, dim3(nitems), dim3(kThreads), 0, s, g);
     else

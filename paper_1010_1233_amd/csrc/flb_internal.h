@@ -157,8 +157,11 @@ hipError_t launch_corr_moment_fields(const DeviceView &v, const CorrItem *items,
 hipError_t launch_corr_moment_rows(const DeviceView &v, const CorrItem *items, int nitems,
                                    int lds_bytes, hipStream_t s);
 // Column passes and accumulation; set selects the fields and kinds as above.
+// Other ny: the column transform writes back in place, or to stash slot
+// `slot` >= 0; the accumulation adds this sample's products and, for
+// nslots > 0 (field set 0), those of the first nslots stash slots.
 hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int cb,
-                            int lds_bytes, hipStream_t s);
+                            int slot, int lds_bytes, hipStream_t s);
 hipError_t launch_corr_cols_a(const DeviceView &v, const CorrItem *items, int nitems,
                               int lds_bytes, hipStream_t s);
 // Accumulation modes of column pass B for field set 0 (power-of-two ny):
@@ -173,7 +176,7 @@ hipError_t launch_corr_cols_b(const DeviceView &v, const CorrItem *items, int ni
 hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nitems, int nslots,
                              hipStream_t s);
 hipError_t launch_corr_accum(const DeviceView &v, const CorrItem *items, int nitems, int set,
-                             hipStream_t s);
+                             int nslots, hipStream_t s);
 hipError_t launch_fill(double *p, size_t n, hipStream_t s);
 
 // ---------------------------------------------------------------------

@@ -117,9 +117,10 @@ struct flb {
     int n_cols_a_m = 0, n_cols_m = 0, n_rows_m = 0;
     CorrItem *d_rows_blue = nullptr;  // rows of lattices with Bluestein row transforms
     int n_rows_blue = 0;
-    // deferred accumulation (power-of-two ny): samples stash their spectra in
-    // kDeferK - 1 slots and every kDeferK-th one adds the products of all of
-    // them at once; `pending` counts the stashed samples
+    // deferred accumulation: samples stash their spectra in kDeferK - 1 slots
+    // (pass B for power-of-two ny, the column transform's output otherwise)
+    // and every kDeferK-th one adds the products of all of them at once;
+    // `pending` counts the stashed samples
     bool defer = false;
     int pending = 0;
     float2 *d_stash = nullptr;
@@ -506,8 +507,10 @@ int setup_correlators(flb_t *h)
                     cols_m.push_back({(int32_t)l, f, c0, 0});
                 }
             const int64_t nk = (int64_t)P.ny * P.nkx;
-            for (int64_t k0 = 0; k0 < nk; k0 += kThreads)
+            for (int64_t k0 = 0; k0 < nk; k0 += kThreads) {
                 accum.push_back({(int32_t)l, (int32_t)k0, 0, 0});
+                flush.push_back({(int32_t)l, (int32_t)k0, 0, 0});
+            }
         }
     }
     const CorrItem idle{-1, 0, 0, 0};
@@ -530,7 +533,7 @@ int setup_correlators(flb_t *h)
     h->n_cols_m = (int)cols_m.size();
     h->n_rows_m = (int)rows_m.size();
     h->n_flush = (int)flush.size();
-    h->defer = !cols_b.empty();
+    h->defer = !cols_b.empty() || !cols.empty();
     h->pending = 0;
     h->n_rows = (int)rows.size();
     h->n_cols = (int)cols.size();
@@ -591,8 +594,14 @@ int enqueue_sample(flb_t *h, hipStream_t s, hipEvent_t ev_read = nullptr)
             FLB_HIP(launch_corr_cols_b(v, h->d_cols_b, h->n_cols_b, set, mode, h->pending,
                                        h->cols_b_lds, s));
         }
-        if (ng) FLB_HIP(launch_corr_cols(v, cg, ng, h->cols_cb, h->cols_lds, s));
-        if (h->n_accum) FLB_HIP(launch_corr_accum(v, h->d_accum, h->n_accum, set, s));
+        // other ny (field set 0): stash the column transform's output, or add
+        // this sample's products with the stashed ones
+        const bool stash = !set && h->defer && h->pending < kDeferK - 1;
+        if (ng)
+            FLB_HIP(launch_corr_cols(v, cg, ng, h->cols_cb, stash ? h->pending : -1, h->cols_lds, s));
+        if (h->n_accum && !stash)
+            FLB_HIP(launch_corr_accum(v, h->d_accum, h->n_accum, set,
+                                      (!set && h->defer) ? h->pending : 0, s));
     }
     if (h->defer) h->pending = (h->pending + 1) % kDeferK;
     return FLB_OK;
