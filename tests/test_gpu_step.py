@@ -391,3 +391,26 @@ def test_sampled_sites_at_full_and_maximum_size(flb, oracle_lib, nx, ny):
     assert err2 < 2e-6
     b.step(1)  # second step through the one-step kernel
     assert np.array_equal(b.get_populations(), f2)
+
+
+def test_empty_calls_change_nothing(flb):
+    """Zero steps, a run of zero steps, a run without samples, and reading
+    the sums before any sample: nothing moves, nothing is counted."""
+    a = flb.Lattice(40, 24, TAU_C1, 1e-4, u0=(0.03, 0.0), seed=11)
+    a.thermalize()
+    f0 = a.get_populations()
+    a.step(0)
+    a.run(0, 10)
+    assert a.t == 0 and np.array_equal(a.get_populations(), f0)
+    acc, ns = a.read_correlators()
+    assert ns == 0 and not acc.any()
+    a.run(25, 0)  # steps only
+    b = flb.Lattice(40, 24, TAU_C1, 1e-4, u0=(0.03, 0.0), seed=11)
+    b.thermalize()
+    b.step(25)
+    assert a.t == b.t == 25 and np.array_equal(a.get_populations(), b.get_populations())
+    assert a.read_correlators()[1] == 0
+    a.accumulate()
+    a.step(0)  # a waiting sample stays waiting through no steps
+    acc, ns = a.read_correlators()
+    assert ns == 1 and acc.any()
