@@ -148,14 +148,15 @@ __device__ __forceinline__ void store_row_spectra(const float2 *lds, const Latti
 // cases are separate instantiations so that the power-of-two one carries no
 // chirp state in registers.
 // item: lattice, first row, rows, index of the block's partial.
-// At most 64 VGPRs (eight waves per SIMD, four blocks per CU) at the cost of
-// spilled values: the kernel is bound by the latency of its transforms and
-// shares the CUs with the step kernel.  Measured at 4096^2: 93 VGPRs (two
-// blocks) 0.79 ms per sample alone, 80 (three blocks) 0.77 ms, 64 (four
-// blocks, 28 values spilled) 0.80 ms alone but the whole path, sample beside
-// the steps, 0.8 % faster than at 80.
+// At most 80 VGPRs (six waves per SIMD, three blocks per CU): the kernel is
+// bound by the latency of its transforms, and the third block hides more of
+// it.  Measured at 4096^2 (sample alone, whole path, row-kernel HBM bytes
+// over the algorithmic ones): 93 VGPRs 0.79 ms, 82.5 GLUPS, 1.00; 80 VGPRs
+// (6 values spilled) 0.77 ms, 83.4 GLUPS, 1.17; 64 VGPRs (28 spilled)
+// 0.80 ms, 84.1 GLUPS, 1.64, the spills' scratch traffic not worth the last
+// percent.
 template <int S, bool BLUE>
-__global__ __launch_bounds__(kFftThreads, 8) void corr_rows_kernel(CorrArgs g)
+__global__ __launch_bounds__(kFftThreads, 6) void corr_rows_kernel(CorrArgs g)
 {
     using T = typename Codec<S>::T;
     constexpr int E = 4096 / kFftThreads;  // line elements per thread
