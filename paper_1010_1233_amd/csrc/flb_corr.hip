@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kFftThreads, 6) void corr_rows_kernel(CorrArgs g)
                 }
                 if (BLUE) v = cmul(v, chirp[x]);
             }
-            lds[lds_slot<true>(l * m + bitrev(x, lg))] = v;
+            lds[lds_slot<true>(l * m + (BLUE ? x : bitrev(x, lg)))] = v;
         }
         __syncthreads();
         if (BLUE) lds_line_dft<true>(lds, L, nl, m, 1, g.tables);
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kFftThreads) void corr_moment_rows_kernel(CorrArgs 
             if (e >= ne) break;
             float2 v = make_float2(va[j], vb[j]);
             if (L.bluestein && x < nx) v = cmul(v, chirp[x]);
-            lds[lds_slot<true>(l * m + bitrev(x, lg))] = v;
+            lds[lds_slot<true>(l * m + line_in_pos(L, x))] = v;
         }
     }
     __syncthreads();
@@ -501,8 +501,10 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_b_kernel(CorrArgs g)
     }
 }
 
-// Other ny: whole columns, in place.  item: lattice, field, first column.
-__global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g, int cb)
+// Other ny: whole columns.  item: lattice, field, first column, log2 of the
+// columns per block (16 for work lengths up to 512, fewer for longer ones, so
+// that a block's lines take at most 8192 LDS elements).  LDS [j][c].
+__global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g)
 {
     extern __shared__ float2 lds[];
     const CorrItem it = g.items[blockIdx.x];
@@ -510,7 +512,7 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g, int 
     const LatticeParams &P = g.params[it.lattice];
     const LinePlan &L = g.plans[P.line_y];
     const int ny = P.ny, nkx = P.nkx, kxp = P.kxp;
-    const int f = it.a, c0 = it.b;
+    const int f = it.a, c0 = it.b, lgc = it.c, cb = 1 << lgc;
     const int ncol = min(cb, nkx - c0);
     float2 *col = g.spec + P.spec_base + (int64_t)f * ny * kxp + c0;
     // the transformed column goes back in place, or to stash slot g.arg >= 0
@@ -518,19 +520,28 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g, int 
                             : g.stash + (int64_t)g.arg * g.stash_stride + P.spec_base +
                                   (int64_t)f * ny * kxp + c0;
     const float2 *chirp = g.tables + L.chirp_off;
-    for (int idx = threadIdx.x; idx < L.m * cb; idx += kFftThreads) {
-        const int j = idx / cb, c = idx - j * cb;
-        float2 v = make_float2(0.f, 0.f);
-        if (j < ny && c < ncol) {
-            v = col[(int64_t)j * kxp + c];
-            if (L.bluestein) v = cmul(v, chirp[j]);
+    // the work length's zero padding, rows ny .. m-1
+    for (int idx = ny * cb + (int)threadIdx.x; idx < L.m * cb; idx += kFftThreads)
+        lds[line_in_pos(L, idx >> lgc) * cb + (idx & (cb - 1))] = make_float2(0.f, 0.f);
+    const int ne = ny * cb;
+    for (int i0 = threadIdx.x; i0 < ne; i0 += kBatch * kFftThreads) {
+        float2 v[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int idx = i0 + b * kFftThreads, j = idx >> lgc, c = idx & (cb - 1);
+            v[b] = make_float2(0.f, 0.f);
+            if (idx < ne && c < ncol) v[b] = col[(int64_t)j * kxp + c];
         }
-        lds[bitrev(j, L.log2m) * cb + c] = v;
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int idx = i0 + b * kFftThreads, j = idx >> lgc, c = idx & (cb - 1);
+            if (idx < ne) lds[line_in_pos(L, j) * cb + c] = L.bluestein ? cmul(v[b], chirp[j]) : v[b];
+        }
     }
     __syncthreads();
     lds_line_dft<false>(lds, L, cb, 1, cb, g.tables);
-    for (int idx = threadIdx.x; idx < ny * cb; idx += kFftThreads) {
-        const int j = idx / cb, c = idx - j * cb;
+    for (int idx = threadIdx.x; idx < ne; idx += kFftThreads) {
+        const int j = idx >> lgc, c = idx & (cb - 1);
         if (c < ncol) out[(int64_t)j * kxp + c] = lds[idx];
     }
 }
@@ -693,12 +704,12 @@ hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nit
     return hipGetLastError();
 }
 
-hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int cb,
-                            int slot, int lds_bytes, hipStream_t s)
+hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int slot,
+                            int lds_bytes, hipStream_t s)
 {
     CorrArgs g = make_args(v, items, 0);
     g.arg = slot;
-    hipLaunchKernelGGL(corr_cols_kernel, dim3(nitems), dim3(kFftThreads), lds_bytes, s, g, cb);
+    hipLaunchKernelGGL(corr_cols_kernel, dim3(nitems), dim3(kFftThreads), lds_bytes, s, g);
     return hipGetLastError();
 }
 

@@ -397,7 +397,7 @@ __global__ __launch_bounds__(kFftThreads) void dq_rows_kernel(DqCorrArgs g, int 
             if (pair) v.y = B[o];
             if (L.bluestein) v = cmul(v, chirp[x]);
         }
-        lds[lds_slot<true>(l * m + bitrev(x, lg))] = v;
+        lds[lds_slot<true>(l * m + line_in_pos(L, x))] = v;
     }
     __syncthreads();
     lds_line_dft<true>(lds, L, nl, m, 1, g.tables);
@@ -447,7 +447,7 @@ __global__ __launch_bounds__(kFftThreads) void dq_lines_kernel(DqCorrArgs g, int
             v = col[(size_t)j * stride + c];
             if (L.bluestein) v = cmul(v, chirp[j]);
         }
-        lds[bitrev(j, L.log2m) * cb + c] = v;
+        lds[line_in_pos(L, j) * cb + c] = v;
     }
     __syncthreads();
     lds_line_dft<false>(lds, L, cb, 1, cb, g.tables);
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(kFftThreads) void dq_last_kernel(DqCorrArgs g, int 
             v = g.spec[(size_t)(f0 + q) * fstride + base + (size_t)j * stride + c];
             if (L.bluestein) v = cmul(v, chirp[j]);
         }
-        lds[bitrev(j, L.log2m) * nl + r] = v;
+        lds[line_in_pos(L, j) * nl + r] = v;
     }
     __syncthreads();
     lds_line_dft<false>(lds, L, nl, 1, nl, g.tables);

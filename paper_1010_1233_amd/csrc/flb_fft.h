@@ -1,10 +1,15 @@
 // flb_fft.h -- LDS line transforms shared by the correlator kernels.
 //
-// The LDS transforms are in-place decimation in time with radix-2 stages
-// fused three at a time (radix 8): a thread loads eight elements, runs three
-// butterfly stages in registers and stores them back, so a 4096-point line
-// takes four passes and four barriers.  Lines of other lengths use
-// Bluestein's chirp-z convolution with a power-of-two work length.
+// The LDS transforms are in-place radix-2 transforms with stages fused three
+// at a time (radix 8): a thread loads eight elements, runs three butterfly
+// stages in registers and stores them back, so a 4096-point line takes four
+// passes and four barriers.  Power-of-two lines are transformed by
+// decimation in time (bit-reversed input, natural output).  Lines of other
+// lengths use Bluestein's chirp-z convolution with a power-of-two work
+// length: a forward decimation-in-frequency transform (natural input,
+// bit-reversed output) whose last pass multiplies by the transformed chirp
+// kernel, then an inverse decimation-in-time transform back to natural
+// order, so that no pass only permutes.
 #pragma once
 
 #include "flb_device.h"
@@ -60,14 +65,21 @@ __device__ __forceinline__ float2 rotate(float2 w)
     return r;
 }
 
-// One pass of R fused radix-2 stages s .. s+R-1 (1-based) over `nlines`
-// lines of length 2^lg; element e of line l at slot(l * ls + e * es).  The
-// pass needs twiddles exp(-2 pi i (k + m h) / (h 2^(u+1))) for sub-stage u;
-// all are w^(2^(R-1-u)) times a fixed 2^(u+1)-th root of unity, with
+// One pass of R fused radix-2 stages s .. s+R-1 (1-based; stage s pairs
+// elements h = 2^(s-1) apart) over `nlines` lines of length 2^lg; element e
+// of line l at slot(l * ls + e * es).  A thread takes the 2^R elements
+// b + k + j h (j < 2^R) of one group.  Sub-stage u pairs j and j + 2^u with
+// twiddle exp(-2 pi i (k + m h) / (h 2^(u+1))), m = j mod 2^u; all are
+// w^(2^(R-1-u)) times a fixed 2^(u+1)-th root of unity, with
 // w = exp(-2 pi i k / (h 2^R)) the one value read from the table.
-template <int R, bool PAD, bool INV>
+// Decimation in time (DIF false) runs u = 0 .. R-1 and multiplies the
+// second operand by the twiddle before the sum and difference; decimation
+// in frequency (DIF true) runs u = R-1 .. 0 and multiplies the difference.
+// With `post`, every output of the pass is multiplied by post[e] (e the
+// element's index in its line).
+template <int R, bool PAD, bool INV, bool DIF = false>
 __device__ __forceinline__ void dit_pass(float2 *buf, int lg, int s, int nlines, int ls, int es,
-                                         const float2 *tw)
+                                         const float2 *tw, const float2 *post = nullptr)
 {
     constexpr int G = 1 << R;
     const int h = 1 << (s - 1);
@@ -112,7 +124,8 @@ __device__ __forceinline__ void dit_pass(float2 *buf, int lg, int s, int nlines,
         if constexpr (R >= 2) base[R - 2] = cmul(w, w);
         if constexpr (R >= 3) base[0] = cmul(base[1], base[1]);
 #pragma unroll
-        for (int u = 0; u < R; ++u) {
+        for (int uu = 0; uu < R; ++uu) {
+            const int u = DIF ? R - 1 - uu : uu;
             const int half = 1 << u;
 #pragma unroll
             for (int j = 0; j < G; ++j) {
@@ -123,10 +136,20 @@ __device__ __forceinline__ void dit_pass(float2 *buf, int lg, int s, int nlines,
                 else if (u == 1) t = m ? rotate<1, 1, INV>(base[1]) : base[1];
                 else t = m == 0 ? base[2] : m == 1 ? rotate<2, 1, INV>(base[2])
                        : m == 2 ? rotate<2, 2, INV>(base[2]) : rotate<2, 3, INV>(base[2]);
-                const float2 x = cmul(t, v[j + half]);
-                v[j + half] = make_float2(v[j].x - x.x, v[j].y - x.y);
-                v[j] = make_float2(v[j].x + x.x, v[j].y + x.y);
+                if constexpr (DIF) {
+                    const float2 a = v[j], c = v[j + half];
+                    v[j] = make_float2(a.x + c.x, a.y + c.y);
+                    v[j + half] = cmul(t, make_float2(a.x - c.x, a.y - c.y));
+                } else {
+                    const float2 x = cmul(t, v[j + half]);
+                    v[j + half] = make_float2(v[j].x - x.x, v[j].y - x.y);
+                    v[j] = make_float2(v[j].x + x.x, v[j].y + x.y);
+                }
             }
+        }
+        if (post) {
+#pragma unroll
+            for (int j = 0; j < G; ++j) v[j] = cmul(v[j], post[b + k + j * h]);
         }
 #pragma unroll
         for (int j = 0; j < G; ++j) buf[slot[j]] = v[j];
@@ -154,41 +177,47 @@ __device__ __forceinline__ void lds_fft_dit(float2 *buf, int lg, int nlines, int
     }
 }
 
+// In-place forward transform of lines given in natural order; bit-reversed
+// order out, each output (at line element e) multiplied by post[e].  The
+// widest stages go first, the radix-2 or radix-4 remainder last.
 template <bool PAD>
-__device__ __forceinline__ void lds_bitrev(float2 *buf, int lg, int nlines, int ls, int es)
+__device__ __forceinline__ void lds_fft_dif(float2 *buf, int lg, int nlines, int ls, int es,
+                                            const float2 *tw, const float2 *post)
 {
-    const int m = 1 << lg;
-    for (int idx = threadIdx.x; idx < nlines * m; idx += blockDim.x) {
-        const int l = idx >> lg, j = idx & (m - 1);
-        const int r = bitrev(j, lg);
-        if (j < r) {
-            const int a = lds_slot<PAD>(l * ls + j * es), b = lds_slot<PAD>(l * ls + r * es);
-            const float2 t = buf[a];
-            buf[a] = buf[b];
-            buf[b] = t;
-        }
+    int top = lg;  // stages 1 .. top are left
+    while (top >= 1) {
+        const int r = top >= 3 ? 3 : top;
+        const int s = top - r + 1;
+        const float2 *p = s == 1 ? post : nullptr;
+        if (r == 3) dit_pass<3, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
+        else if (r == 2) dit_pass<2, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
+        else dit_pass<1, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
+        top -= r;
+        __syncthreads();
     }
-    __syncthreads();
 }
 
-// Length-n DFT of lines whose inputs were written at bit-reversed positions
+// Where lds_line_dft expects element x of a line: bit-reversed for
+// power-of-two lengths, natural order for Bluestein work lengths.
+__device__ __forceinline__ int line_in_pos(const LinePlan &L, int x)
+{
+    return L.bluestein ? x : bitrev(x, L.log2m);
+}
+
+// Length-n DFT of lines whose element x was written at line_in_pos(L, x)
 // (already multiplied by the chirp for Bluestein lengths), in place; on exit
-// element k < n holds X_k in natural order.
+// element k < n holds X_k in natural order.  The transformed chirp kernel is
+// stored in bit-reversed order, the order of the forward transform's output.
 template <bool PAD>
 __device__ __forceinline__ void lds_line_dft(float2 *buf, const LinePlan &L, int nlines, int ls, int es,
                              const float2 *tables)
 {
     const float2 *tw = tables;
-    lds_fft_dit<PAD, false>(buf, L.log2m, nlines, ls, es, tw);
-    if (!L.bluestein) return;
-    const float2 *K = tables + L.kernel_off;
-    for (int idx = threadIdx.x; idx < nlines * L.m; idx += blockDim.x) {
-        const int l = idx >> L.log2m, j = idx & (L.m - 1);
-        float2 *p = buf + lds_slot<PAD>(l * ls + j * es);
-        *p = cmul(*p, K[j]);
+    if (!L.bluestein) {
+        lds_fft_dit<PAD, false>(buf, L.log2m, nlines, ls, es, tw);
+        return;
     }
-    __syncthreads();
-    lds_bitrev<PAD>(buf, L.log2m, nlines, ls, es);
+    lds_fft_dif<PAD>(buf, L.log2m, nlines, ls, es, tw, tables + L.kernel_off);
     lds_fft_dit<PAD, true>(buf, L.log2m, nlines, ls, es, tw);
     const float2 *C = tables + L.chirp_off;
     for (int idx = threadIdx.x; idx < nlines * L.n; idx += blockDim.x) {

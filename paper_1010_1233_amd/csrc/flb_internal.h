@@ -62,6 +62,7 @@ struct alignas(16) LatticeParams {
     int32_t col_lgp;          // P = ny / Q
     int32_t col_lgn;          // log2 ny
     int32_t col_nq;           // q values per pass-A block
+    int32_t col_lgcb;         // other ny: log2 of the columns per column-kernel block
     int32_t fld_tiles_x;      // field-kernel tiles (256 sites) per row band
     int64_t fld_base;         // float offset of this lattice's five field planes
     int32_t fld_part0;        // first conservation partial of this lattice
@@ -160,8 +161,8 @@ hipError_t launch_corr_moment_rows(const DeviceView &v, const CorrItem *items, i
 // Other ny: the column transform writes back in place, or to stash slot
 // `slot` >= 0; the accumulation adds this sample's products and, for
 // nslots > 0 (field set 0), those of the first nslots stash slots.
-hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int cb,
-                            int slot, int lds_bytes, hipStream_t s);
+hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int slot,
+                            int lds_bytes, hipStream_t s);
 hipError_t launch_corr_cols_a(const DeviceView &v, const CorrItem *items, int nitems,
                               int lds_bytes, hipStream_t s);
 // Accumulation modes of column pass B for field set 0 (power-of-two ny):

@@ -128,7 +128,7 @@ struct flb {
     int n_flush = 0;
     float *d_fields = nullptr;
     double *d_csum_part = nullptr, *d_csum = nullptr;
-    int rows_lds = 0, cols_lds = 0, cols_cb = 1, cols_a_lds = 0, cols_b_lds = 0;
+    int rows_lds = 0, cols_lds = 0, cols_a_lds = 0, cols_b_lds = 0;
     int64_t nsamples = 0;
 
     // A registered sample is due until the next steps are enqueued: it then
@@ -392,8 +392,13 @@ int flbdev::LineTables::plan_for(int n)
             if (j > 0) b[L.m - j] = std::conj(c[j]);
         }
         host_fft(b);
+        // bit-reversed order, the order in which the device's forward
+        // transform leaves its output
         L.kernel_off = (int64_t)tables.size();
-        for (int j = 0; j < L.m; ++j) {
+        const int lgm = log2i(L.m);
+        for (int p = 0; p < L.m; ++p) {
+            int j = 0;
+            for (int bit = 0; bit < lgm; ++bit) j |= ((p >> bit) & 1) << (lgm - 1 - bit);
             const auto v = b[j] / (double)L.m;  // inverse transform's 1/m folded in
             tables.push_back(make_float2((float)v.real(), (float)v.imag()));
         }
@@ -423,7 +428,6 @@ int setup_correlators(flb_t *h)
 
     int64_t spec = 0, acc = 0, fld = 0;
     int nparts = 0;
-    int max_my_general = 1;
     h->rows_lds = h->cols_a_lds = h->cols_b_lds = h->cols_lds = 0;
     for (auto &P : h->params) {
         P.line_x = plan_for(P.nx);
@@ -442,7 +446,11 @@ int setup_correlators(flb_t *h)
             h->cols_b_lds =
                 std::max(h->cols_b_lds, P.col_q * 16 * h->nfld * (int)sizeof(float2));
         } else {
-            max_my_general = std::max(max_my_general, lt.plans[P.line_y].m);
+            // columns per block of the general column kernel: its lines fill
+            // at most 8192 LDS elements
+            const int my = lt.plans[P.line_y].m;
+            P.col_lgcb = log2i(std::max(1, std::min(16, 8192 / my)));
+            h->cols_lds = std::max(h->cols_lds, (my << P.col_lgcb) * (int)sizeof(float2));
         }
         P.spec_base = spec;
         P.acc_base = acc;
@@ -461,8 +469,6 @@ int setup_correlators(flb_t *h)
     }
     h->spec_elems = spec;
     h->acc_elems = acc;
-    h->cols_cb = std::max(1, std::min(16, 8192 / max_my_general));
-    h->cols_lds = max_my_general * h->cols_cb * (int)sizeof(float2);
 
     h->plans = lt.plans;
     std::vector<CorrItem> rows, cols, accum, cols_a, cols_b, flds, cols_a_m, cols_m, rows_m;
@@ -502,9 +508,9 @@ int setup_correlators(flb_t *h)
                 flush.push_back({(int32_t)l, (int32_t)k0, 0, 0});
         } else {
             for (int f = 0; f < h->nfld; ++f)
-                for (int c0 = 0; c0 < P.nkx; c0 += h->cols_cb) {
-                    if (f < kFields) cols.push_back({(int32_t)l, f, c0, 0});
-                    cols_m.push_back({(int32_t)l, f, c0, 0});
+                for (int c0 = 0; c0 < P.nkx; c0 += 1 << P.col_lgcb) {
+                    if (f < kFields) cols.push_back({(int32_t)l, f, c0, P.col_lgcb});
+                    cols_m.push_back({(int32_t)l, f, c0, P.col_lgcb});
                 }
             const int64_t nk = (int64_t)P.ny * P.nkx;
             for (int64_t k0 = 0; k0 < nk; k0 += kThreads) {
@@ -598,7 +604,7 @@ int enqueue_sample(flb_t *h, hipStream_t s, hipEvent_t ev_read = nullptr)
         // this sample's products with the stashed ones
         const bool stash = !set && h->defer && h->pending < kDeferK - 1;
         if (ng)
-            FLB_HIP(launch_corr_cols(v, cg, ng, h->cols_cb, stash ? h->pending : -1, h->cols_lds, s));
+            FLB_HIP(launch_corr_cols(v, cg, ng, stash ? h->pending : -1, h->cols_lds, s));
         if (h->n_accum && !stash)
             FLB_HIP(launch_corr_accum(v, h->d_accum, h->n_accum, set,
                                       (!set && h->defer) ? h->pending : 0, s));
