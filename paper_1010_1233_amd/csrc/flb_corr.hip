@@ -110,10 +110,11 @@ __device__ __forceinline__ void site_moments(const typename Codec<S>::T *p,
 // pair z = a + i b of two real sequences, a_k = (z_k + conj z_{-k}) / 2 and
 // b_k = (z_k - conj z_{-k}) / (2i) go to fields fa and fa + 1; a single real
 // sequence (pair false) goes to field fa as is.  kx = 0..nx/2, padding
-// columns up to kxp zeroed.
+// columns up to kxp zeroed.  With `chirp`, line element k is first
+// multiplied by chirp[k] (a Bluestein line left without its output chirp).
 __device__ __forceinline__ void store_row_spectra(const float2 *lds, const LatticeParams &P,
                                                   float2 *spec, int y0, int nl, int m, int fa,
-                                                  bool pair)
+                                                  bool pair, const float2 *chirp = nullptr)
 {
     const int nx = P.nx, nkx = P.nkx, kxp = P.kxp;
     const int64_t fstride = (int64_t)P.ny * kxp;
@@ -126,11 +127,14 @@ __device__ __forceinline__ void store_row_spectra(const float2 *lds, const Latti
             if (pair) sb[row] = make_float2(0.f, 0.f);
             continue;
         }
-        const float2 zk = lds[lds_slot<true>(l * m + k)];
+        float2 zk = lds[lds_slot<true>(l * m + k)];
+        if (chirp) zk = cmul(zk, chirp[k]);
         if (!pair) {
             sa[row] = zk;
         } else {
-            const float2 zm = lds[lds_slot<true>(l * m + (k == 0 ? 0 : nx - k))];
+            const int km = k == 0 ? 0 : nx - k;
+            float2 zm = lds[lds_slot<true>(l * m + km)];
+            if (chirp) zm = cmul(zm, chirp[km]);
             sa[row] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
             sb[row] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
         }
@@ -223,10 +227,11 @@ __global__ __launch_bounds__(kFftThreads, 6) void corr_rows_kernel(CorrArgs g)
             lds[lds_slot<true>(l * m + (BLUE ? x : bitrev(x, lg)))] = v;
         }
         __syncthreads();
-        if (BLUE) lds_line_dft<true>(lds, L, nl, m, 1, g.tables);
+        if (BLUE) lds_line_dft<true, false>(lds, L, nl, m, 1, g.tables);
         else lds_fft_dit<true, false>(lds, lg, nl, m, 1, g.tables);
         // spectra: 1, 2 = jx, jy; 3, 4 = ux, uy; 0 = rho
-        store_row_spectra(lds, P, spec, y0, nl, m, sig == 0 ? 1 : sig == 1 ? 3 : 0, sig != 2);
+        store_row_spectra(lds, P, spec, y0, nl, m, sig == 0 ? 1 : sig == 1 ? 3 : 0, sig != 2,
+                          BLUE ? chirp : nullptr);
     }
 }
 
@@ -503,7 +508,9 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_b_kernel(CorrArgs g)
 
 // Other ny: whole columns.  item: lattice, field, first column, log2 of the
 // columns per block (16 for work lengths up to 512, fewer for longer ones, so
-// that a block's lines take at most 8192 LDS elements).  LDS [j][c].
+// that a block's lines take at most 8192 LDS elements).  LDS [j][c], padded
+// (the small-stride passes of a few interleaved lines would otherwise
+// share banks); the output chirp is applied as the result is stored.
 __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g)
 {
     extern __shared__ float2 lds[];
@@ -522,7 +529,8 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g)
     const float2 *chirp = g.tables + L.chirp_off;
     // the work length's zero padding, rows ny .. m-1
     for (int idx = ny * cb + (int)threadIdx.x; idx < L.m * cb; idx += kFftThreads)
-        lds[line_in_pos(L, idx >> lgc) * cb + (idx & (cb - 1))] = make_float2(0.f, 0.f);
+        lds[lds_slot<true>(line_in_pos(L, idx >> lgc) * cb + (idx & (cb - 1)))] =
+            make_float2(0.f, 0.f);
     const int ne = ny * cb;
     for (int i0 = threadIdx.x; i0 < ne; i0 += kBatch * kFftThreads) {
         float2 v[kBatch];
@@ -535,14 +543,18 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g)
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
             const int idx = i0 + b * kFftThreads, j = idx >> lgc, c = idx & (cb - 1);
-            if (idx < ne) lds[line_in_pos(L, j) * cb + c] = L.bluestein ? cmul(v[b], chirp[j]) : v[b];
+            if (idx < ne)
+                lds[lds_slot<true>(line_in_pos(L, j) * cb + c)] =
+                    L.bluestein ? cmul(v[b], chirp[j]) : v[b];
         }
     }
     __syncthreads();
-    lds_line_dft<false>(lds, L, cb, 1, cb, g.tables);
+    lds_line_dft<true, false>(lds, L, cb, 1, cb, g.tables);
     for (int idx = threadIdx.x; idx < ne; idx += kFftThreads) {
         const int j = idx >> lgc, c = idx & (cb - 1);
-        if (c < ncol) out[(int64_t)j * kxp + c] = lds[idx];
+        if (c >= ncol) continue;
+        const float2 v = lds[lds_slot<true>(idx)];
+        out[(int64_t)j * kxp + c] = L.bluestein ? cmul(v, chirp[j]) : v;
     }
 }
 

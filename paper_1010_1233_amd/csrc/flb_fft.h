@@ -208,7 +208,9 @@ __device__ __forceinline__ int line_in_pos(const LinePlan &L, int x)
 // (already multiplied by the chirp for Bluestein lengths), in place; on exit
 // element k < n holds X_k in natural order.  The transformed chirp kernel is
 // stored in bit-reversed order, the order of the forward transform's output.
-template <bool PAD>
+// With CHIRP false a Bluestein line is left without its final chirp factor:
+// the caller multiplies element k by the chirp's k-th value as it reads it.
+template <bool PAD, bool CHIRP = true>
 __device__ __forceinline__ void lds_line_dft(float2 *buf, const LinePlan &L, int nlines, int ls, int es,
                              const float2 *tables)
 {
@@ -219,6 +221,7 @@ __device__ __forceinline__ void lds_line_dft(float2 *buf, const LinePlan &L, int
     }
     lds_fft_dif<PAD>(buf, L.log2m, nlines, ls, es, tw, tables + L.kernel_off);
     lds_fft_dit<PAD, true>(buf, L.log2m, nlines, ls, es, tw);
+    if constexpr (!CHIRP) return;
     const float2 *C = tables + L.chirp_off;
     for (int idx = threadIdx.x; idx < nlines * L.n; idx += blockDim.x) {
         const int l = idx / L.n, j = idx - l * L.n;

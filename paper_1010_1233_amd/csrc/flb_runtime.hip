@@ -450,7 +450,9 @@ int setup_correlators(flb_t *h)
             // at most 8192 LDS elements
             const int my = lt.plans[P.line_y].m;
             P.col_lgcb = log2i(std::max(1, std::min(16, 8192 / my)));
-            h->cols_lds = std::max(h->cols_lds, (my << P.col_lgcb) * (int)sizeof(float2));
+            const int e = my << P.col_lgcb;  // padded like the row kernels' lines
+            h->cols_lds = std::max(h->cols_lds,
+                                   (e + (e >> 4) + (e >> 8) + 1) * (int)sizeof(float2));
         }
         P.spec_base = spec;
         P.acc_base = acc;
