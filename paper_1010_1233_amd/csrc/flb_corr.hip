@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kFftThreads, 6) void corr_rows_kernel(CorrArgs g)
             lds[lds_slot<true>(l * m + (BLUE ? x : bitrev(x, lg)))] = v;
         }
         __syncthreads();
-        if (BLUE) lds_line_dft<true, false>(lds, L, nl, m, 1, g.tables);
+        if (BLUE) lds_bluestein_dft<true, false>(lds, L, nl, m, 1, g.tables);
         else lds_fft_dit<true, false>(lds, lg, nl, m, 1, g.tables);
         // spectra: 1, 2 = jx, jy; 3, 4 = ux, uy; 0 = rho
         store_row_spectra(lds, P, spec, y0, nl, m, sig == 0 ? 1 : sig == 1 ? 3 : 0, sig != 2,
@@ -506,7 +506,8 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_b_kernel(CorrArgs g)
     }
 }
 
-// Other ny: whole columns.  item: lattice, field, first column, log2 of the
+// Other ny (Bluestein lengths): whole columns.  item: lattice, field, first
+// column, log2 of the
 // columns per block (16 for work lengths up to 512, fewer for longer ones, so
 // that a block's lines take at most 8192 LDS elements).  LDS [j][c], padded
 // (the small-stride passes of a few interleaved lines would otherwise
@@ -529,8 +530,7 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g)
     const float2 *chirp = g.tables + L.chirp_off;
     // the work length's zero padding, rows ny .. m-1
     for (int idx = ny * cb + (int)threadIdx.x; idx < L.m * cb; idx += kFftThreads)
-        lds[lds_slot<true>(line_in_pos(L, idx >> lgc) * cb + (idx & (cb - 1)))] =
-            make_float2(0.f, 0.f);
+        lds[lds_slot<true>(idx)] = make_float2(0.f, 0.f);
     const int ne = ny * cb;
     for (int i0 = threadIdx.x; i0 < ne; i0 += kBatch * kFftThreads) {
         float2 v[kBatch];
@@ -542,19 +542,15 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g)
         }
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
-            const int idx = i0 + b * kFftThreads, j = idx >> lgc, c = idx & (cb - 1);
-            if (idx < ne)
-                lds[lds_slot<true>(line_in_pos(L, j) * cb + c)] =
-                    L.bluestein ? cmul(v[b], chirp[j]) : v[b];
+            const int idx = i0 + b * kFftThreads;
+            if (idx < ne) lds[lds_slot<true>(idx)] = cmul(v[b], chirp[idx >> lgc]);
         }
     }
     __syncthreads();
-    lds_line_dft<true, false>(lds, L, cb, 1, cb, g.tables);
+    lds_bluestein_dft<true, false>(lds, L, cb, 1, cb, g.tables);
     for (int idx = threadIdx.x; idx < ne; idx += kFftThreads) {
         const int j = idx >> lgc, c = idx & (cb - 1);
-        if (c >= ncol) continue;
-        const float2 v = lds[lds_slot<true>(idx)];
-        out[(int64_t)j * kxp + c] = L.bluestein ? cmul(v, chirp[j]) : v;
+        if (c < ncol) out[(int64_t)j * kxp + c] = cmul(lds[lds_slot<true>(idx)], chirp[j]);
     }
 }
 

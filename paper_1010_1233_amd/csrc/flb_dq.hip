@@ -371,9 +371,14 @@ struct DqCorrArgs {
     int D;
 };
 
+// The transform kernels below are instantiated for power-of-two lines
+// (BLUE false) and for Bluestein lines (BLUE true); the host picks the one
+// that matches the axis's line plan.
+
 // Transforms along x: one block per (field pair, group of rows); pair p packs
 // fields 2p + i (2p+1) (the last field alone if nf is odd) and writes the
 // half spectra kx = 0..nx/2 of both, rows of pitch kxp.
+template <bool BLUE>
 __global__ __launch_bounds__(kFftThreads) void dq_rows_kernel(DqCorrArgs g, int rb)
 {
     extern __shared__ float2 lds[];
@@ -395,12 +400,13 @@ __global__ __launch_bounds__(kFftThreads) void dq_rows_kernel(DqCorrArgs g, int 
             const size_t o = (size_t)(r0 + l) * nx + x;
             v.x = A[o];
             if (pair) v.y = B[o];
-            if (L.bluestein) v = cmul(v, chirp[x]);
+            if (BLUE) v = cmul(v, chirp[x]);
         }
-        lds[lds_slot<true>(l * m + line_in_pos(L, x))] = v;
+        lds[lds_slot<true>(l * m + (BLUE ? x : bitrev(x, lg)))] = v;
     }
     __syncthreads();
-    lds_line_dft<true>(lds, L, nl, m, 1, g.tables);
+    if (BLUE) lds_bluestein_dft<true>(lds, L, nl, m, 1, g.tables);
+    else lds_fft_dit<true, false>(lds, lg, nl, m, 1, g.tables);
     const size_t fstride = (size_t)nrows * g.kxp;
     float2 *sa = g.spec + (size_t)fa * fstride, *sb = sa + fstride;
     for (int e = threadIdx.x; e < nl * g.kxp; e += kFftThreads) {
@@ -424,6 +430,7 @@ __global__ __launch_bounds__(kFftThreads) void dq_rows_kernel(DqCorrArgs g, int 
 
 // Transforms along y (axis 1) or z (axis 2), in place: one block per
 // (field, position along the other axis, group of cb adjacent kx).
+template <bool BLUE>
 __global__ __launch_bounds__(kFftThreads) void dq_lines_kernel(DqCorrArgs g, int axis, int cb)
 {
     extern __shared__ float2 lds[];
@@ -445,12 +452,13 @@ __global__ __launch_bounds__(kFftThreads) void dq_lines_kernel(DqCorrArgs g, int
         float2 v = make_float2(0.f, 0.f);
         if (j < n && c < ncol) {
             v = col[(size_t)j * stride + c];
-            if (L.bluestein) v = cmul(v, chirp[j]);
+            if (BLUE) v = cmul(v, chirp[j]);
         }
-        lds[line_in_pos(L, j) * cb + c] = v;
+        lds[(BLUE ? j : bitrev(j, L.log2m)) * cb + c] = v;
     }
     __syncthreads();
-    lds_line_dft<false>(lds, L, cb, 1, cb, g.tables);
+    if (BLUE) lds_bluestein_dft<false>(lds, L, cb, 1, cb, g.tables);
+    else lds_fft_dit<false, false>(lds, L.log2m, cb, 1, cb, g.tables);
     for (int idx = threadIdx.x; idx < n * cb; idx += kFftThreads) {
         const int j = idx / cb, c = idx - j * cb;
         if (c < ncol) col[(size_t)j * stride + c] = lds[idx];
@@ -469,6 +477,7 @@ __device__ __forceinline__ int dq_auto_kind(int f, int D)
 // except u_x, u_y, which are transformed together for their cross kinds
 // (upair: one launch of that pair alone); the spectra are added to the FP64
 // sums as they leave LDS, never written back.
+template <bool BLUE>
 __global__ __launch_bounds__(kFftThreads) void dq_last_kernel(DqCorrArgs g, int axis, int cb,
                                                               int upair)
 {
@@ -495,12 +504,13 @@ __global__ __launch_bounds__(kFftThreads) void dq_last_kernel(DqCorrArgs g, int 
         float2 v = make_float2(0.f, 0.f);
         if (j < n && c < ncol) {
             v = g.spec[(size_t)(f0 + q) * fstride + base + (size_t)j * stride + c];
-            if (L.bluestein) v = cmul(v, chirp[j]);
+            if (BLUE) v = cmul(v, chirp[j]);
         }
-        lds[line_in_pos(L, j) * nl + r] = v;
+        lds[(BLUE ? j : bitrev(j, L.log2m)) * nl + r] = v;
     }
     __syncthreads();
-    lds_line_dft<false>(lds, L, nl, 1, nl, g.tables);
+    if (BLUE) lds_bluestein_dft<false>(lds, L, nl, 1, nl, g.tables);
+    else lds_fft_dit<false, false>(lds, L.log2m, nl, 1, nl, g.tables);
     for (int idx = threadIdx.x; idx < n * cb; idx += kFftThreads) {
         const int j = idx / cb, c = idx - j * cb;
         if (c >= ncol || (j == 0 && o == 0 && c0 + c == 0)) continue;  // k = 0
@@ -579,6 +589,7 @@ struct flb_dq {
     float2 *d_spec = nullptr;
     double *d_acc = nullptr;
     int line[3] = {0, 0, 0};
+    bool blue[3] = {false, false, false};  // the axis's line plan is a Bluestein one
     int rows_lds = 0, lines_lds = 0, rb = 1, cb = 1;
     // fused last pass: columns per block for single fields and for the u
     // pair (0: a separate accumulation)
@@ -708,7 +719,10 @@ int setup_corr(flb_dq *h)
                                       "other sides up to 2048");
     DQ_HIP(hipStreamSynchronize(h->stream));
     LineTables lt;
-    for (int a = 0; a < 3; ++a) h->line[a] = lt.plan_for(h->n[a] > 1 ? h->n[a] : 2);
+    for (int a = 0; a < 3; ++a) {
+        h->line[a] = lt.plan_for(h->n[a] > 1 ? h->n[a] : 2);
+        h->blue[a] = lt.plans[h->line[a]].bluestein != 0;
+    }
     const int mx = lt.plans[h->line[0]].m;
     h->rb = std::max(1, std::min(h->n[1] * h->n[2], 4096 / mx));
     h->rows_lds = lds_padded_elems(h->rb * mx) * (int)sizeof(float2);
@@ -782,8 +796,12 @@ int enqueue_sample(flb_dq *h)
     const int nrows = h->n[1] * h->n[2];
     const int ngroups = (nrows + h->rb - 1) / h->rb;
     const int npairs = (h->nf + 1) / 2;
-    hipLaunchKernelGGL(dq_rows_kernel, dim3(npairs * ngroups), dim3(kFftThreads), h->rows_lds,
-                       h->stream, g, h->rb);
+    if (h->blue[0])
+        hipLaunchKernelGGL(dq_rows_kernel<true>, dim3(npairs * ngroups), dim3(kFftThreads),
+                           h->rows_lds, h->stream, g, h->rb);
+    else
+        hipLaunchKernelGGL(dq_rows_kernel<false>, dim3(npairs * ngroups), dim3(kFftThreads),
+                           h->rows_lds, h->stream, g, h->rb);
     DQ_HIP(hipGetLastError());
     const int ncg = (h->P.nkx + h->cb - 1) / h->cb;
     const int last = h->D - 1;  // the last transformed axis (D >= 2)
@@ -793,13 +811,15 @@ int enqueue_sample(flb_dq *h)
         if (axis == last && h->last_cb) {
             const int ncgl = (h->P.nkx + h->last_cb - 1) / h->last_cb;
             const int ncgp = (h->P.nkx + h->last_cb_pair - 1) / h->last_cb_pair;
-            hipLaunchKernelGGL(dq_last_kernel, dim3((h->nf - 2) * nouter * ncgl),
-                               dim3(kFftThreads), h->last_lds, h->stream, g, axis, h->last_cb, 0);
+            auto lastk = h->blue[axis] ? dq_last_kernel<true> : dq_last_kernel<false>;
+            hipLaunchKernelGGL(lastk, dim3((h->nf - 2) * nouter * ncgl), dim3(kFftThreads),
+                               h->last_lds, h->stream, g, axis, h->last_cb, 0);
             DQ_HIP(hipGetLastError());
-            hipLaunchKernelGGL(dq_last_kernel, dim3(nouter * ncgp), dim3(kFftThreads),
-                               h->last_lds, h->stream, g, axis, h->last_cb_pair, 1);
+            hipLaunchKernelGGL(lastk, dim3(nouter * ncgp), dim3(kFftThreads), h->last_lds,
+                               h->stream, g, axis, h->last_cb_pair, 1);
         } else {
-            hipLaunchKernelGGL(dq_lines_kernel, dim3(h->nf * nouter * ncg), dim3(kFftThreads),
+            auto lines = h->blue[axis] ? dq_lines_kernel<true> : dq_lines_kernel<false>;
+            hipLaunchKernelGGL(lines, dim3(h->nf * nouter * ncg), dim3(kFftThreads),
                                h->lines_lds, h->stream, g, axis, h->cb);
         }
         DQ_HIP(hipGetLastError());

@@ -197,28 +197,27 @@ __device__ __forceinline__ void lds_fft_dif(float2 *buf, int lg, int nlines, int
     }
 }
 
-// Where lds_line_dft expects element x of a line: bit-reversed for
-// power-of-two lengths, natural order for Bluestein work lengths.
+// Where a line transform expects element x of a line: bit-reversed for
+// power-of-two lengths (lds_fft_dit), natural order for Bluestein work
+// lengths (lds_bluestein_dft).
 __device__ __forceinline__ int line_in_pos(const LinePlan &L, int x)
 {
     return L.bluestein ? x : bitrev(x, L.log2m);
 }
 
-// Length-n DFT of lines whose element x was written at line_in_pos(L, x)
-// (already multiplied by the chirp for Bluestein lengths), in place; on exit
+// Length-n DFT of Bluestein lines (L.bluestein) whose element x was written
+// in natural order, already multiplied by the chirp, in place; on exit
 // element k < n holds X_k in natural order.  The transformed chirp kernel is
 // stored in bit-reversed order, the order of the forward transform's output.
-// With CHIRP false a Bluestein line is left without its final chirp factor:
-// the caller multiplies element k by the chirp's k-th value as it reads it.
+// With CHIRP false the lines are left without their final chirp factor: the
+// caller multiplies element k by the chirp's k-th value as it reads it.
+// Kernels that know a plan's kind at compile time call this or lds_fft_dit
+// directly, so that a power-of-two instantiation carries no Bluestein code.
 template <bool PAD, bool CHIRP = true>
-__device__ __forceinline__ void lds_line_dft(float2 *buf, const LinePlan &L, int nlines, int ls, int es,
-                             const float2 *tables)
+__device__ __forceinline__ void lds_bluestein_dft(float2 *buf, const LinePlan &L, int nlines,
+                                                  int ls, int es, const float2 *tables)
 {
     const float2 *tw = tables;
-    if (!L.bluestein) {
-        lds_fft_dit<PAD, false>(buf, L.log2m, nlines, ls, es, tw);
-        return;
-    }
     lds_fft_dif<PAD>(buf, L.log2m, nlines, ls, es, tw, tables + L.kernel_off);
     lds_fft_dit<PAD, true>(buf, L.log2m, nlines, ls, es, tw);
     if constexpr (!CHIRP) return;
@@ -229,6 +228,16 @@ __device__ __forceinline__ void lds_line_dft(float2 *buf, const LinePlan &L, int
         *p = cmul(*p, C[j]);
     }
     __syncthreads();
+}
+
+// Either kind of plan, chosen at run time: lines whose element x was written
+// at line_in_pos(L, x).
+template <bool PAD>
+__device__ __forceinline__ void lds_line_dft(float2 *buf, const LinePlan &L, int nlines, int ls,
+                                             int es, const float2 *tables)
+{
+    if (L.bluestein) lds_bluestein_dft<PAD>(buf, L, nlines, ls, es, tables);
+    else lds_fft_dit<PAD, false>(buf, L.log2m, nlines, ls, es, tables);
 }
 
 constexpr int kFftThreads = 512;  // threads of the transform kernels
