@@ -33,7 +33,8 @@ def _compare(acc_g, acc_o, rtol):
 
 
 @pytest.mark.parametrize("nx,ny", [(32, 32), (20, 20), (24, 18), (37, 23), (64, 8), (2, 2),
-                                   (128, 96), (3, 256), (40, 600), (1000, 5)])
+                                   (128, 96), (3, 256), (40, 600), (1000, 5), (300, 7),
+                                   (1500, 3)])
 def test_single_sample_matches_oracle(flb, oracle_lib, nx, ny):
     note("sample", nx, ny)
     g = flb.Lattice(nx, ny, TAU_C1, 1e-4, u0=(0.04, -0.01), seed=3)

@@ -132,13 +132,15 @@ def test_waiting_sample_precedes_state_changes(flb, oracle_lib):
     assert ns == 0 and not acc.any()
 
 
-def test_overlapped_sequence_matches_oracle(flb, oracle_lib):
+@pytest.mark.parametrize("nx,ny", [(96, 64), (70, 45)])
+def test_overlapped_sequence_matches_oracle(flb, oracle_lib, nx, ny):
     """Irregular step counts between samples, overlapped on the GPU, against
-    the oracle's samples of the same trajectory."""
-    note("overlap oracle")
+    the oracle's samples of the same trajectory (70 x 45: Bluestein rows and
+    columns, whose spectra go through the stash)."""
+    note("overlap oracle", nx, ny)
     kw = dict(u0=(0.03, -0.01), seed=21)
-    g = flb.Lattice(96, 64, TAU, 1e-4, **kw)
-    o = oracle_lib.Lattice(96, 64, TAU, 1e-4, **kw)
+    g = flb.Lattice(nx, ny, TAU, 1e-4, **kw)
+    o = oracle_lib.Lattice(nx, ny, TAU, 1e-4, **kw)
     g.set_time_blocking(1, 64)
     g.thermalize()
     o.thermalize()
