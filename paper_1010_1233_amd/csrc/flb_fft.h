@@ -78,7 +78,7 @@ __device__ __forceinline__ float2 rotate(float2 w)
 // With `post`, every output of the pass is multiplied by post[e] (e the
 // element's index in its line).
 template <int R, bool PAD, bool INV, bool DIF = false>
-__device__ __forceinline__ void dit_pass(float2 *buf, int lg, int s, int nlines, int ls, int es,
+__device__ __forceinline__ void fused_pass(float2 *buf, int lg, int s, int nlines, int ls, int es,
                                          const float2 *tw, const float2 *post = nullptr)
 {
     constexpr int G = 1 << R;
@@ -164,13 +164,13 @@ __device__ __forceinline__ void lds_fft_dit(float2 *buf, int lg, int nlines, int
     while (s <= lg) {
         const int r = lg - s + 1;
         if (r >= 3) {
-            dit_pass<3, PAD, INV>(buf, lg, s, nlines, ls, es, tw);
+            fused_pass<3, PAD, INV>(buf, lg, s, nlines, ls, es, tw);
             s += 3;
         } else if (r == 2) {
-            dit_pass<2, PAD, INV>(buf, lg, s, nlines, ls, es, tw);
+            fused_pass<2, PAD, INV>(buf, lg, s, nlines, ls, es, tw);
             s += 2;
         } else {
-            dit_pass<1, PAD, INV>(buf, lg, s, nlines, ls, es, tw);
+            fused_pass<1, PAD, INV>(buf, lg, s, nlines, ls, es, tw);
             s += 1;
         }
         __syncthreads();
@@ -189,9 +189,9 @@ __device__ __forceinline__ void lds_fft_dif(float2 *buf, int lg, int nlines, int
         const int r = top >= 3 ? 3 : top;
         const int s = top - r + 1;
         const float2 *p = s == 1 ? post : nullptr;
-        if (r == 3) dit_pass<3, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
-        else if (r == 2) dit_pass<2, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
-        else dit_pass<1, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
+        if (r == 3) fused_pass<3, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
+        else if (r == 2) fused_pass<2, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
+        else fused_pass<1, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
         top -= r;
         __syncthreads();
     }
