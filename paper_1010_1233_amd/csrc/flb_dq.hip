@@ -393,16 +393,28 @@ __global__ __launch_bounds__(kFftThreads) void dq_rows_kernel(DqCorrArgs g, int 
     const size_t V = (size_t)nx * nrows;
     const float *A = g.fld + (size_t)fa * V, *B = A + V;
     const float2 *chirp = g.tables + L.chirp_off;
-    for (int e = threadIdx.x; e < nl * m; e += kFftThreads) {
-        const int l = e >> lg, x = e & (m - 1);
-        float2 v = make_float2(0.f, 0.f);
-        if (x < nx) {
-            const size_t o = (size_t)(r0 + l) * nx + x;
-            v.x = A[o];
-            if (pair) v.y = B[o];
-            if (BLUE) v = cmul(v, chirp[x]);
+    // loads kBatch per thread in flight before any is stored to LDS
+    const int ne = nl * m;
+    for (int e0 = threadIdx.x; e0 < ne; e0 += kBatch * kFftThreads) {
+        float va[kBatch], vb[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const int e = e0 + i * kFftThreads, l = e >> lg, x = e & (m - 1);
+            va[i] = vb[i] = 0.f;
+            if (e < ne && x < nx) {
+                const size_t o = (size_t)(r0 + l) * nx + x;
+                va[i] = A[o];
+                if (pair) vb[i] = B[o];
+            }
         }
-        lds[lds_slot<true>(l * m + (BLUE ? x : bitrev(x, lg)))] = v;
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const int e = e0 + i * kFftThreads, l = e >> lg, x = e & (m - 1);
+            if (e >= ne) break;
+            float2 v = make_float2(va[i], vb[i]);
+            if (BLUE && x < nx) v = cmul(v, chirp[x]);
+            lds[lds_slot<true>(l * m + (BLUE ? x : bitrev(x, lg)))] = v;
+        }
     }
     __syncthreads();
     if (BLUE) lds_bluestein_dft<true>(lds, L, nl, m, 1, g.tables);
@@ -447,14 +459,22 @@ __global__ __launch_bounds__(kFftThreads) void dq_lines_kernel(DqCorrArgs g, int
     const LinePlan &L = g.plans[axis == 1 ? g.line_y : g.line_z];
     const float2 *chirp = g.tables + L.chirp_off;
     float2 *col = g.spec + (size_t)f * ((size_t)nz * ny * g.kxp) + (size_t)o * ostride + c0;
-    for (int idx = threadIdx.x; idx < L.m * cb; idx += kFftThreads) {
-        const int j = idx / cb, c = idx - j * cb;
-        float2 v = make_float2(0.f, 0.f);
-        if (j < n && c < ncol) {
-            v = col[(size_t)j * stride + c];
-            if (BLUE) v = cmul(v, chirp[j]);
+    const int ne = L.m * cb;
+    for (int i0 = threadIdx.x; i0 < ne; i0 += kBatch * kFftThreads) {
+        float2 v[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const int idx = i0 + i * kFftThreads, j = idx / cb, c = idx - j * cb;
+            v[i] = make_float2(0.f, 0.f);
+            if (idx < ne && j < n && c < ncol) v[i] = col[(size_t)j * stride + c];
         }
-        lds[(BLUE ? j : bitrev(j, L.log2m)) * cb + c] = v;
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const int idx = i0 + i * kFftThreads, j = idx / cb, c = idx - j * cb;
+            if (idx >= ne) break;
+            if (BLUE && j < n) v[i] = cmul(v[i], chirp[j]);
+            lds[(BLUE ? j : bitrev(j, L.log2m)) * cb + c] = v[i];
+        }
     }
     __syncthreads();
     if (BLUE) lds_bluestein_dft<false>(lds, L, cb, 1, cb, g.tables);
@@ -499,14 +519,24 @@ __global__ __launch_bounds__(kFftThreads) void dq_last_kernel(DqCorrArgs g, int 
     const size_t fstride = (size_t)ny * nz * g.kxp;
     const size_t base = (size_t)o * ostride + c0;
     const int nl = nfg * cb;  // interleaved lines: field q, column c at q * cb + c
-    for (int idx = threadIdx.x; idx < L.m * nl; idx += kFftThreads) {
-        const int j = idx / nl, r = idx - j * nl, q = r / cb, c = r - q * cb;
-        float2 v = make_float2(0.f, 0.f);
-        if (j < n && c < ncol) {
-            v = g.spec[(size_t)(f0 + q) * fstride + base + (size_t)j * stride + c];
-            if (BLUE) v = cmul(v, chirp[j]);
+    const int ne = L.m * nl;
+    for (int i0 = threadIdx.x; i0 < ne; i0 += kBatch * kFftThreads) {
+        float2 v[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const int idx = i0 + i * kFftThreads, j = idx / nl, r = idx - j * nl, q = r / cb,
+                      c = r - q * cb;
+            v[i] = make_float2(0.f, 0.f);
+            if (idx < ne && j < n && c < ncol)
+                v[i] = g.spec[(size_t)(f0 + q) * fstride + base + (size_t)j * stride + c];
         }
-        lds[(BLUE ? j : bitrev(j, L.log2m)) * nl + r] = v;
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const int idx = i0 + i * kFftThreads, j = idx / nl, r = idx - j * nl;
+            if (idx >= ne) break;
+            if (BLUE && j < n) v[i] = cmul(v[i], chirp[j]);
+            lds[(BLUE ? j : bitrev(j, L.log2m)) * nl + r] = v[i];
+        }
     }
     __syncthreads();
     if (BLUE) lds_bluestein_dft<false>(lds, L, nl, 1, nl, g.tables);
