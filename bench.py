@@ -28,7 +28,8 @@ The JSON line also carries
                 times the step kernel alone after the timed region, and
                 sample_ms is what a period takes beyond ten isolated steps;
   cpu_baseline  the FP64 oracle, single thread, on a bounded sample of the
-                same workload;
+                same workload, with the host's CPU model and the number of
+                CPUs the process may use;
   forms         step-kernel rates of the other storage formats and of the
                 noise-free step (the paper's ghost-noise overhead), and the
                 batched forms (96 x 512^2 Galilean-invariance sweep, 64
@@ -44,6 +45,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -228,7 +230,26 @@ def cpu_baseline(workloads, name, max_side=2048):
     V = nx * ny
     return {"value": SAMPLE_EVERY * V / dt / 1e9, "unit": "GLUPS", "cores": 1, "kind": "oracle",
             "sample": f"{SAMPLE_EVERY} steps + 1 correlator sample of a {nx}x{ny} lattice with "
-                      f"the workload's parameters ({dt:.1f} s, FP64, one thread)"}
+                      f"the workload's parameters ({dt:.1f} s, FP64, one thread)",
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """The host's CPU model and the number of CPUs this process may use."""
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        ncpu = os.cpu_count()
+    return {"model": model, "cpus_available": ncpu}
 
 
 def main():
