@@ -547,7 +547,7 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g)
         }
     }
     __syncthreads();
-    lds_bluestein_dft<true, false>(lds, L, cb, 1, cb, g.tables);
+    lds_bluestein_dft<true, false, 4>(lds, L, cb, 1, cb, g.tables);
     for (int idx = threadIdx.x; idx < ne; idx += kFftThreads) {
         const int j = idx >> lgc, c = idx & (cb - 1);
         if (c < ncol) out[(int64_t)j * kxp + c] = cmul(lds[lds_slot<true>(idx)], chirp[j]);

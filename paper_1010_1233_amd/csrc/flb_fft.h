@@ -48,21 +48,34 @@ template <bool PAD> __device__ __forceinline__ int lds_slot(int i)
 
 __host__ __device__ constexpr int lds_padded_elems(int n) { return n + (n >> 4) + (n >> 8) + 1; }
 
-// w * exp(-/+ 2 pi i m / 2^(u+1)) for the compile-time root index (u, m):
-// multiplications by 1 and -i are free, by exp(-i pi/4) two multiplies.
+// w * exp(-/+ 2 pi i m / 2^(u+1)) for the compile-time root index (u, m),
+// u <= 3: multiplications by 1 and -i are free, by exp(-i pi/4) two
+// multiplies; an odd multiple of pi/8 (u = 3) first takes one general
+// complex multiply by exp(-/+ i pi/8).
 template <int U, int M, bool INV>
 __device__ __forceinline__ float2 rotate(float2 w)
 {
-    constexpr int q = (M << (2 - U)) & 7;  // the root as a multiple of pi/4
-    constexpr float c = 0.70710678118654752f;
-    float2 r = w;
-    if constexpr (q & 1) {  // exp(-i pi/4) (forward) or exp(+i pi/4) (inverse)
-        r = INV ? make_float2(c * (w.x - w.y), c * (w.x + w.y))
-                : make_float2(c * (w.x + w.y), c * (w.y - w.x));
+    if constexpr (U == 3) {
+        if constexpr (M % 2 == 0) {
+            return rotate<2, M / 2, INV>(w);
+        } else {
+            constexpr float c = 0.92387953251128674f, s = 0.38268343236508977f;  // pi/8
+            const float2 r = INV ? make_float2(c * w.x - s * w.y, c * w.y + s * w.x)
+                                 : make_float2(c * w.x + s * w.y, c * w.y - s * w.x);
+            return rotate<2, M / 2, INV>(r);
+        }
+    } else {
+        constexpr int q = (M << (2 - U)) & 7;  // the root as a multiple of pi/4
+        constexpr float c = 0.70710678118654752f;
+        float2 r = w;
+        if constexpr (q & 1) {  // exp(-i pi/4) (forward) or exp(+i pi/4) (inverse)
+            r = INV ? make_float2(c * (w.x - w.y), c * (w.x + w.y))
+                    : make_float2(c * (w.x + w.y), c * (w.y - w.x));
+        }
+        if constexpr (q & 2) r = INV ? make_float2(-r.y, r.x) : make_float2(r.y, -r.x);  // -/+ i
+        if constexpr (q & 4) r = make_float2(-r.x, -r.y);
+        return r;
     }
-    if constexpr (q & 2) r = INV ? make_float2(-r.y, r.x) : make_float2(r.y, -r.x);  // -/+ i
-    if constexpr (q & 4) r = make_float2(-r.x, -r.y);
-    return r;
 }
 
 // One pass of R fused radix-2 stages s .. s+R-1 (1-based; stage s pairs
@@ -119,10 +132,17 @@ __device__ __forceinline__ void fused_pass(float2 *buf, int lg, int s, int nline
         for (int j = 0; j < G; ++j) v[j] = buf[slot[j]];
         float2 w = tw[k << (kTwLog - (s + R - 1))];
         if (INV) w.y = -w.y;
-        float2 base[3];
-        base[R - 1] = w;
-        if constexpr (R >= 2) base[R - 2] = cmul(w, w);
-        if constexpr (R >= 3) base[0] = cmul(base[1], base[1]);
+        float2 base[4];
+        if constexpr (R == 4) {
+            base[3] = w;
+            base[2] = cmul(w, w);
+            base[1] = cmul(base[2], base[2]);
+            base[0] = cmul(base[1], base[1]);
+        } else {
+            base[R - 1] = w;
+            if constexpr (R >= 2) base[R - 2] = cmul(w, w);
+            if constexpr (R >= 3) base[0] = cmul(base[1], base[1]);
+        }
 #pragma unroll
         for (int uu = 0; uu < R; ++uu) {
             const int u = DIF ? R - 1 - uu : uu;
@@ -134,8 +154,14 @@ __device__ __forceinline__ void fused_pass(float2 *buf, int lg, int s, int nline
                 float2 t;
                 if (u == 0) t = base[0];
                 else if (u == 1) t = m ? rotate<1, 1, INV>(base[1]) : base[1];
-                else t = m == 0 ? base[2] : m == 1 ? rotate<2, 1, INV>(base[2])
-                       : m == 2 ? rotate<2, 2, INV>(base[2]) : rotate<2, 3, INV>(base[2]);
+                else if (u == 2)
+                    t = m == 0 ? base[2] : m == 1 ? rotate<2, 1, INV>(base[2])
+                      : m == 2 ? rotate<2, 2, INV>(base[2]) : rotate<2, 3, INV>(base[2]);
+                else
+                    t = m == 0 ? base[3] : m == 1 ? rotate<3, 1, INV>(base[3])
+                      : m == 2 ? rotate<3, 2, INV>(base[3]) : m == 3 ? rotate<3, 3, INV>(base[3])
+                      : m == 4 ? rotate<3, 4, INV>(base[3]) : m == 5 ? rotate<3, 5, INV>(base[3])
+                      : m == 6 ? rotate<3, 6, INV>(base[3]) : rotate<3, 7, INV>(base[3]);
                 if constexpr (DIF) {
                     const float2 a = v[j], c = v[j + half];
                     v[j] = make_float2(a.x + c.x, a.y + c.y);
@@ -157,12 +183,22 @@ __device__ __forceinline__ void fused_pass(float2 *buf, int lg, int s, int nline
 }
 
 // In-place transform of lines given in bit-reversed order; natural order out.
-template <bool PAD, bool INV>
+// RMAX: at most that many stages per pass (3, or 4 for kernels with the
+// registers to hold sixteen elements per thread).
+template <bool PAD, bool INV, int RMAX = 3>
 __device__ __forceinline__ void lds_fft_dit(float2 *buf, int lg, int nlines, int ls, int es, const float2 *tw)
 {
     int s = 1;
     while (s <= lg) {
         const int r = lg - s + 1;
+        if constexpr (RMAX >= 4) {
+            if (r >= 4) {
+                fused_pass<4, PAD, INV>(buf, lg, s, nlines, ls, es, tw);
+                s += 4;
+                __syncthreads();
+                continue;
+            }
+        }
         if (r >= 3) {
             fused_pass<3, PAD, INV>(buf, lg, s, nlines, ls, es, tw);
             s += 3;
@@ -180,15 +216,23 @@ __device__ __forceinline__ void lds_fft_dit(float2 *buf, int lg, int nlines, int
 // In-place forward transform of lines given in natural order; bit-reversed
 // order out, each output (at line element e) multiplied by post[e].  The
 // widest stages go first, the radix-2 or radix-4 remainder last.
-template <bool PAD>
+template <bool PAD, int RMAX = 3>
 __device__ __forceinline__ void lds_fft_dif(float2 *buf, int lg, int nlines, int ls, int es,
                                             const float2 *tw, const float2 *post)
 {
     int top = lg;  // stages 1 .. top are left
     while (top >= 1) {
-        const int r = top >= 3 ? 3 : top;
+        const int r = top >= RMAX ? RMAX : top;
         const int s = top - r + 1;
         const float2 *p = s == 1 ? post : nullptr;
+        if constexpr (RMAX >= 4) {
+            if (r == 4) {
+                fused_pass<4, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
+                top -= 4;
+                __syncthreads();
+                continue;
+            }
+        }
         if (r == 3) fused_pass<3, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
         else if (r == 2) fused_pass<2, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
         else fused_pass<1, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
@@ -213,13 +257,13 @@ __device__ __forceinline__ int line_in_pos(const LinePlan &L, int x)
 // caller multiplies element k by the chirp's k-th value as it reads it.
 // Kernels that know a plan's kind at compile time call this or lds_fft_dit
 // directly, so that a power-of-two instantiation carries no Bluestein code.
-template <bool PAD, bool CHIRP = true>
+template <bool PAD, bool CHIRP = true, int RMAX = 3>
 __device__ __forceinline__ void lds_bluestein_dft(float2 *buf, const LinePlan &L, int nlines,
                                                   int ls, int es, const float2 *tables)
 {
     const float2 *tw = tables;
-    lds_fft_dif<PAD>(buf, L.log2m, nlines, ls, es, tw, tables + L.kernel_off);
-    lds_fft_dit<PAD, true>(buf, L.log2m, nlines, ls, es, tw);
+    lds_fft_dif<PAD, RMAX>(buf, L.log2m, nlines, ls, es, tw, tables + L.kernel_off);
+    lds_fft_dit<PAD, true, RMAX>(buf, L.log2m, nlines, ls, es, tw);
     if constexpr (!CHIRP) return;
     const float2 *C = tables + L.chirp_off;
     for (int idx = threadIdx.x; idx < nlines * L.n; idx += blockDim.x) {
