@@ -19,3 +19,13 @@ def test_world_size_above_one_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")], capture_output=True,
                        text=True, timeout=120, env=env)
     assert r.returncode == 2 and "Use --gpus 1" in r.stderr
+
+
+def test_cpu_baseline_host_record():
+    """The CPU baseline names the host it ran on: a CPU model string and the
+    number of CPUs the process may use (at least one)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    h = bench.host_cpu()
+    assert isinstance(h["model"], str)
+    assert isinstance(h["cpus_available"], int) and h["cpus_available"] >= 1
