@@ -325,3 +325,36 @@ def test_storage_formats_against_oracle(flb, oracle_lib, side):
             rel.append(err / scale)
         note(f"  {storage}: relative error per kind", " ".join(f"{r:.2e}" for r in rel))
         assert max(rel) < bound, (storage, rel)
+
+
+def test_batch_of_column_block_widths_equals_separate_lattices(flb, oracle_lib):
+    """Column work lengths 2048, 1024 and 256 (Bluestein, 4, 8 and 16
+    columns per block) and a power-of-two side in one batch: over ten samples
+    (across an eight-sample accumulation cycle, with graph-replayed periods)
+    every lattice's sums are the bits of the same lattice run alone, and the
+    longest columns' sums match the oracle."""
+    specs = [dict(nx=40, ny=600, tau=TAU_C1, theta=1e-4, stream_id=0),
+             dict(nx=30, ny=300, tau=TAU_C1, theta=1e-4, u0=(0.03, 0.0), stream_id=1),
+             dict(nx=50, ny=100, tau=TAU_C1, theta=1e-4, stream_id=2),
+             dict(nx=24, ny=64, tau=TAU_C1, theta=1e-4, u0=(0.0, 0.02), stream_id=3)]
+    note("column block widths batch")
+    b = flb.Lattice.batch(specs, seed=8)
+    b.thermalize()
+    b.run(40, 4)
+    for i, s in enumerate(specs):
+        one = flb.Lattice(s["nx"], s["ny"], s["tau"], s["theta"], u0=s.get("u0", (0, 0)),
+                          seed=8, stream_id=s["stream_id"])
+        one.thermalize()
+        one.run(40, 4)
+        acc, ns = b.read_correlators(i)
+        ref, nr = one.read_correlators()
+        assert ns == nr == 10
+        assert np.array_equal(acc, ref), i
+        one.close()
+    s = specs[0]
+    o = oracle_lib.Lattice(s["nx"], s["ny"], s["tau"], s["theta"], seed=8,
+                           stream_id=s["stream_id"])
+    o.thermalize()
+    o.run(40, 4)
+    assert o.nsamples == 10
+    _compare(b.read_correlators(0)[0], o.acc, 1e-3)
