@@ -507,11 +507,13 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_b_kernel(CorrArgs g)
 }
 
 // Other ny (Bluestein lengths): whole columns.  item: lattice, field, first
-// column, log2 of the
-// columns per block (16 for work lengths up to 512, fewer for longer ones, so
-// that a block's lines take at most 8192 LDS elements).  LDS [j][c], padded
-// (the small-stride passes of a few interleaved lines would otherwise
-// share banks); the output chirp is applied as the result is stored.
+// column, log2 of the columns per block (16 for work lengths up to 512,
+// fewer for longer ones, so that a block's lines take at most 8192 LDS
+// elements).  LDS [j][c], padded (the small-stride passes of a few
+// interleaved lines would otherwise share banks).  The transforms fuse four
+// radix-2 stages per pass, sixteen elements per thread: the registers that
+// takes are free at the two blocks per CU the LDS allows.  The output chirp
+// is applied as the result is stored.
 __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g)
 {
     extern __shared__ float2 lds[];
