@@ -319,7 +319,9 @@ __global__ __launch_bounds__(kFftThreads) void corr_moment_rows_kernel(CorrArgs 
     store_row_spectra(lds, P, g.spec + P.spec_base, y0, nl, m, fa, true);
 }
 
-// Power-of-two ny = P*Q, pass A.  item: lattice, field, first column, first q.
+// Power-of-two ny = P*Q above 2048 (the runtime's kColsWholeMax; shorter
+// columns go whole through corr_cols_kernel), pass A.  item: lattice, field,
+// first column, first q.
 // LDS [p][ql][c], 16 columns, nq q-values per block.
 __global__ __launch_bounds__(kFftThreads) void corr_cols_a_kernel(CorrArgs g)
 {
@@ -446,7 +448,8 @@ __device__ __forceinline__ void accumulate_set(double *a, int64_t kstride, const
         accumulate_moments_k(a, kstride, X);
 }
 
-// Power-of-two ny, pass B with accumulation.  item: lattice, first column, k1.
+// Power-of-two ny above 2048, pass B with accumulation.  item: lattice, first
+// column, k1.
 // LDS [q][f][c]: the Q rows Q*k1 .. Q*k1+Q-1 of all fields of the set, 16
 // columns.  MODE (field set 0): kAccDirect adds this sample's products;
 // kAccStash keeps its spectra in stash slot g.arg instead; kAccPair adds the
@@ -506,14 +509,15 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_b_kernel(CorrArgs g)
     }
 }
 
-// Other ny (Bluestein lengths): whole columns.  item: lattice, field, first
-// column, log2 of the columns per block (16 for work lengths up to 512,
-// fewer for longer ones, so that a block's lines take at most 8192 LDS
-// elements).  LDS [j][c], padded (the small-stride passes of a few
-// interleaved lines would otherwise share banks).  The transforms fuse four
-// radix-2 stages per pass, sixteen elements per thread: the registers that
-// takes are free at the two blocks per CU the LDS allows.  The output chirp
-// is applied as the result is stored.
+// Whole columns: Bluestein lengths and power-of-two ny up to 2048 (the
+// runtime's kColsWholeMax).  item: lattice, field, first column, log2 of the columns
+// per block (16 for work lengths up to 512, fewer for longer ones, so that a
+// block's lines take at most 8192 LDS elements).  LDS [j][c], padded (the
+// small-stride passes of a few interleaved lines would otherwise share
+// banks).  The transforms fuse four radix-2 stages per pass, sixteen
+// elements per thread: the registers that takes are free at the two blocks
+// per CU the LDS allows.  A Bluestein line's output chirp is applied as the
+// result is stored.
 __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g)
 {
     extern __shared__ float2 lds[];
@@ -530,7 +534,8 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g)
                             : g.stash + (int64_t)g.arg * g.stash_stride + P.spec_base +
                                   (int64_t)f * ny * kxp + c0;
     const float2 *chirp = g.tables + L.chirp_off;
-    // the work length's zero padding, rows ny .. m-1
+    const bool blue = L.bluestein != 0;
+    // a Bluestein work length's zero padding, rows ny .. m-1
     for (int idx = ny * cb + (int)threadIdx.x; idx < L.m * cb; idx += kFftThreads)
         lds[lds_slot<true>(idx)] = make_float2(0.f, 0.f);
     const int ne = ny * cb;
@@ -544,15 +549,20 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g)
         }
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
-            const int idx = i0 + b * kFftThreads;
-            if (idx < ne) lds[lds_slot<true>(idx)] = cmul(v[b], chirp[idx >> lgc]);
+            const int idx = i0 + b * kFftThreads, j = idx >> lgc, c = idx & (cb - 1);
+            if (idx >= ne) continue;
+            if (blue) lds[lds_slot<true>(idx)] = cmul(v[b], chirp[j]);
+            else lds[lds_slot<true>((bitrev(j, L.log2m) << lgc) + c)] = v[b];
         }
     }
     __syncthreads();
-    lds_bluestein_dft<true, false, 4>(lds, L, cb, 1, cb, g.tables);
+    if (blue) lds_bluestein_dft<true, false, 4>(lds, L, cb, 1, cb, g.tables);
+    else lds_fft_dit<true, false, 4>(lds, L.log2m, cb, 1, cb, g.tables);
     for (int idx = threadIdx.x; idx < ne; idx += kFftThreads) {
         const int j = idx >> lgc, c = idx & (cb - 1);
-        if (c < ncol) out[(int64_t)j * kxp + c] = cmul(lds[lds_slot<true>(idx)], chirp[j]);
+        if (c >= ncol) continue;
+        const float2 x = lds[lds_slot<true>(idx)];
+        out[(int64_t)j * kxp + c] = blue ? cmul(x, chirp[j]) : x;
     }
 }
 

@@ -57,7 +57,7 @@ struct alignas(16) LatticeParams {
     int32_t line_x;           // index of the x-direction line plan
     int32_t line_y;           // index of the y-direction line plan
     int32_t kxp;              // row pitch of spectra and sums: nkx rounded up to 16
-    int32_t col_pow2;         // ny is a power of two: columns by the P*Q split
+    int32_t col_pow2;         // ny a power of two above 2048: columns by the P*Q split
     int32_t col_q, col_lgq;   // Q = min(ny, 64) consecutive rows per pass-B block
     int32_t col_lgp;          // P = ny / Q
     int32_t col_lgn;          // log2 ny

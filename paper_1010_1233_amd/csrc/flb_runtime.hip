@@ -412,6 +412,14 @@ int flbdev::LineTables::plan_for(int n)
 
 namespace {
 
+// Longest power-of-two column transformed whole by the general column kernel
+// (16 columns per block up to 512, 8 at 1024, 4 at 2048): one pass instead
+// of the P*Q split's two. Measured whole against split (whole path, GLUPS):
+// 96 x 512^2 93.1 against 88.5, 16 x 1024^2 87.9 against 83.9, 4 x 2048^2
+// 85.9 against 84.7; at 4096 (two columns per block, 16-byte runs) 80.0
+// against 82.5, so longer columns keep the split.
+constexpr int kColsWholeMax = 2048;
+
 int setup_correlators(flb_t *h)
 {
     if (h->corr_ready) return FLB_OK;
@@ -433,7 +441,9 @@ int setup_correlators(flb_t *h)
         P.line_x = plan_for(P.nx);
         P.line_y = plan_for(P.ny);
         P.kxp = (P.nkx + 15) / 16 * 16;
-        P.col_pow2 = is_pow2(P.ny);
+        // power-of-two columns up to kColsWholeMax are transformed whole, in
+        // one pass, like the other lengths; longer ones by the P*Q split
+        P.col_pow2 = is_pow2(P.ny) && P.ny > kColsWholeMax;
         if (P.col_pow2) {
             P.col_lgn = log2i(P.ny);
             P.col_q = std::min(P.ny, 64);

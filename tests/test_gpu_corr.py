@@ -34,7 +34,7 @@ def _compare(acc_g, acc_o, rtol):
 
 @pytest.mark.parametrize("nx,ny", [(32, 32), (20, 20), (24, 18), (37, 23), (64, 8), (2, 2),
                                    (128, 96), (3, 256), (40, 600), (1000, 5), (300, 7),
-                                   (1500, 3)])
+                                   (1500, 3), (12, 1024), (10, 2048), (6, 4096)])
 def test_single_sample_matches_oracle(flb, oracle_lib, nx, ny):
     note("sample", nx, ny)
     g = flb.Lattice(nx, ny, TAU_C1, 1e-4, u0=(0.04, -0.01), seed=3)
@@ -358,3 +358,33 @@ def test_batch_of_column_block_widths_equals_separate_lattices(flb, oracle_lib):
     o.run(40, 4)
     assert o.nsamples == 10
     _compare(b.read_correlators(0)[0], o.acc, 1e-3)
+
+
+def test_split_column_path_over_sample_cycles(flb, oracle_lib):
+    """ny = 4096 takes the P*Q column split (pass A, then pass B, which
+    stashes seven samples of eight and adds the eighth's products with
+    them): ten samples, overlapped beside the steps, with reads after the
+    third and ninth (a read adds the stashed samples first), against
+    samples enqueued at once (same bits) and against the oracle."""
+    kw = dict(u0=(0.03, -0.01), seed=17)
+    a = flb.Lattice(8, 4096, TAU_C1, 1e-4, **kw)
+    b = flb.Lattice(8, 4096, TAU_C1, 1e-4, **kw)
+    o = oracle_lib.Lattice(8, 4096, TAU_C1, 1e-4, **kw)
+    b.set_sample_overlap(False)
+    for L in (a, b, o):
+        L.thermalize()
+    for i in range(10):
+        for L in (a, b, o):
+            L.step(3)
+        a.accumulate()
+        b.accumulate()
+        o.sample()
+        if i in (2, 8):
+            ra, na = a.read_correlators()
+            assert na == i + 1
+            assert np.array_equal(ra, b.read_correlators()[0])
+            _compare(ra, o.acc, 2e-4)
+    ra, na = a.read_correlators()
+    assert na == o.nsamples == 10
+    assert np.array_equal(ra, b.read_correlators()[0])
+    _compare(ra, o.acc, 2e-4)
