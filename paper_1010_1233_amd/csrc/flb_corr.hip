@@ -15,12 +15,11 @@
 //          fields and the FP64 conservation partials of its rows.  (The
 //          optional moment set goes through FP32 field planes and a separate
 //          row kernel.)
-//   columns, power-of-two ny = P*Q (Q <= 64): pass A transforms the P-long
-//          strided columns (rows q, q+Q, ...) and applies the twiddles;
-//          pass B transforms Q consecutive rows of all five fields and adds
-//          the fifteen products to the FP64 sums straight from LDS.
-//   columns, other ny: one kernel transforms whole columns (Bluestein), a
-//          second one accumulates.
+//   columns: one kernel transforms whole columns in LDS (Bluestein's
+//          convolution for lengths that are not powers of two) and keeps
+//          the spectra in a stash slot; with every eighth sample a second
+//          kernel adds the fifteen products of that sample and the seven
+//          stashed ones to the FP64 sums, one thread per k.
 // The line transforms themselves are in flb_fft.h.
 #include "flb_fft.h"
 
@@ -319,53 +318,6 @@ __global__ __launch_bounds__(kFftThreads) void corr_moment_rows_kernel(CorrArgs 
     store_row_spectra(lds, P, g.spec + P.spec_base, y0, nl, m, fa, true);
 }
 
-// Power-of-two ny = P*Q above 2048 (the runtime's kColsWholeMax; shorter
-// columns go whole through corr_cols_kernel), pass A.  item: lattice, field,
-// first column, first q.
-// LDS [p][ql][c], 16 columns, nq q-values per block.
-__global__ __launch_bounds__(kFftThreads) void corr_cols_a_kernel(CorrArgs g)
-{
-    extern __shared__ float2 lds[];
-    const CorrItem it = g.items[blockIdx.x];
-    if (it.lattice < 0) return;
-    const LatticeParams &P = g.params[it.lattice];
-    const int f = it.a, c0 = it.b, q0 = it.c;
-    const int lgP = P.col_lgp, Pn = 1 << lgP, Q = P.col_q, kxp = P.kxp;
-    const int NL = P.col_nq * 16;
-    float2 *col = g.spec + P.spec_base + (int64_t)f * P.ny * kxp + c0;
-    const int ne = Pn * NL;
-    for (int i0 = threadIdx.x; i0 < ne; i0 += kBatch * kFftThreads) {
-        float2 v[kBatch];
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-            const int idx = i0 + j * kFftThreads, pp = idx / NL, r = idx - pp * NL;
-            if (idx < ne) v[j] = col[(int64_t)(q0 + (r >> 4) + Q * pp) * kxp + (r & 15)];
-        }
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-            const int idx = i0 + j * kFftThreads, pp = idx / NL, r = idx - pp * NL;
-            if (idx < ne) lds[bitrev(pp, lgP) * NL + r] = v[j];
-        }
-    }
-    __syncthreads();
-    lds_fft_dit<false, false>(lds, lgP, NL, 1, NL, g.tables);
-    const int lgN = P.col_lgn;
-    for (int i0 = threadIdx.x; i0 < ne; i0 += kBatch * kFftThreads) {
-        float2 w[kBatch];
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-            const int idx = i0 + j * kFftThreads, k1 = idx / NL, r = idx - k1 * NL;
-            if (idx < ne) w[j] = twiddle(g.tables, ((q0 + (r >> 4)) * k1) & ((1 << lgN) - 1), lgN);
-        }
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-            const int idx = i0 + j * kFftThreads, k1 = idx / NL, r = idx - k1 * NL;
-            if (idx < ne)
-                col[(int64_t)(q0 + (r >> 4) + Q * k1) * kxp + (r & 15)] = cmul(lds[idx], w[j]);
-        }
-    }
-}
-
 // Fifteen products of the five spectra at one k, in FP64.
 __device__ __forceinline__ void products_k(double (&val)[kKinds], const float2 (&X)[5])
 {
@@ -448,77 +400,22 @@ __device__ __forceinline__ void accumulate_set(double *a, int64_t kstride, const
         accumulate_moments_k(a, kstride, X);
 }
 
-// Power-of-two ny above 2048, pass B with accumulation.  item: lattice, first
-// column, k1.
-// LDS [q][f][c]: the Q rows Q*k1 .. Q*k1+Q-1 of all fields of the set, 16
-// columns.  MODE (field set 0): kAccDirect adds this sample's products;
-// kAccStash keeps its spectra in stash slot g.arg instead; kAccPair adds the
-// products of this sample and of the g.arg stashed ones in one
-// read-modify-write of the FP64 sums (the sums are the same up to FP64
-// rounding order; the HBM traffic for them is divided by the samples per
-// read-modify-write).
-template <int SET, int MODE>
-__global__ __launch_bounds__(kFftThreads) void corr_cols_b_kernel(CorrArgs g)
-{
-    constexpr int NF = SET ? 6 : 5;
-    extern __shared__ float2 lds[];
-    const CorrItem it = g.items[blockIdx.x];
-    if (it.lattice < 0) return;
-    const LatticeParams &P = g.params[it.lattice];
-    const int c0 = it.a, k1 = it.b;
-    const int Q = P.col_q, lgQ = P.col_lgq, Pn = 1 << P.col_lgp;
-    const int ny = P.ny, nkx = P.nkx, kxp = P.kxp;
-    constexpr int NL = NF * 16;
-    const float2 *spec = g.spec + P.spec_base + c0;
-    const int64_t fstride = (int64_t)ny * kxp;
-    const int ne = Q * NL;
-    for (int i0 = threadIdx.x; i0 < ne; i0 += kBatch * kFftThreads) {
-        float2 v[kBatch];
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-            const int idx = i0 + j * kFftThreads, q = idx / NL, r = idx - q * NL;
-            if (idx < ne) v[j] = spec[(r >> 4) * fstride + (int64_t)(Q * k1 + q) * kxp + (r & 15)];
-        }
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-            const int idx = i0 + j * kFftThreads, q = idx / NL, r = idx - q * NL;
-            if (idx < ne) lds[bitrev(q, lgQ) * NL + r] = v[j];
-        }
-    }
-    __syncthreads();
-    lds_fft_dit<false, false>(lds, lgQ, NL, 1, NL, g.tables);
-    double *acc = g.acc + P.acc_base;
-    float2 *stash = g.stash + P.spec_base;
-    for (int idx = threadIdx.x; idx < Q * 16; idx += kFftThreads) {
-        const int k2 = idx >> 4, c = idx & 15;
-        const int kx = c0 + c, ky = k1 + Pn * k2;
-        if (kx >= nkx || (kx == 0 && ky == 0)) continue;
-        const int64_t o = (int64_t)ky * kxp + kx;
-        float2 X[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) X[f] = lds[k2 * NL + f * 16 + c];
-        if constexpr (MODE == kAccStash) {
-            float2 *slot = stash + (int64_t)g.arg * g.stash_stride;
-#pragma unroll
-            for (int f = 0; f < NF; ++f) slot[f * fstride + o] = X[f];
-        } else if constexpr (MODE == kAccPair) {
-            accumulate_stashed_k<true>(acc + o, fstride, X, stash + o, g.stash_stride, g.arg);
-        } else {
-            accumulate_set<SET, NF>(acc + o, fstride, X);
-        }
-    }
-}
-
-// Whole columns: Bluestein lengths and power-of-two ny up to 2048 (the
-// runtime's kColsWholeMax).  item: lattice, field, first column, log2 of the columns
-// per block (16 for work lengths up to 512, fewer for longer ones, so that a
-// block's lines take at most 8192 LDS elements).  LDS [j][c], padded (the
-// small-stride passes of a few interleaved lines would otherwise share
-// banks).  The transforms fuse four radix-2 stages per pass, sixteen
-// elements per thread: the registers that takes are free at the two blocks
-// per CU the LDS allows.  A Bluestein line's output chirp is applied as the
-// result is stored.
-__global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g)
+// Column transforms, whole columns in LDS: Bluestein's convolution for
+// lengths that are not powers of two, the plain transform otherwise.  item:
+// lattice, field, first column, log2 of the columns per block (at most 16,
+// so that a block's lines take at most kColsElems LDS elements, or
+// kColsLargeElems in the large blocks of NT = kColsLargeThreads threads that
+// power-of-two lengths from 1024 on take).  LDS [j][c], padded (the small-stride
+// passes of a few interleaved lines would otherwise share banks).  The
+// transforms fuse four radix-2 stages per pass, sixteen elements per thread:
+// the registers that takes are free at the occupancy the LDS allows.  A
+// Bluestein line's output chirp is applied as the result is stored.
+// Whole 4096-point columns in blocks of four (1024 threads, one block per
+// CU) against a two-pass split into 64 x 64 points (16 columns per pass, an
+// HBM round trip of the spectra between the passes), 4096^2 whole path:
+// 87.3 against 83.4 GLUPS; in blocks of two (512 threads): 80.0.
+template <int NT>
+__global__ __launch_bounds__(NT) void corr_cols_kernel(CorrArgs g)
 {
     extern __shared__ float2 lds[];
     const CorrItem it = g.items[blockIdx.x];
@@ -536,20 +433,20 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g)
     const float2 *chirp = g.tables + L.chirp_off;
     const bool blue = L.bluestein != 0;
     // a Bluestein work length's zero padding, rows ny .. m-1
-    for (int idx = ny * cb + (int)threadIdx.x; idx < L.m * cb; idx += kFftThreads)
+    for (int idx = ny * cb + (int)threadIdx.x; idx < L.m * cb; idx += NT)
         lds[lds_slot<true>(idx)] = make_float2(0.f, 0.f);
     const int ne = ny * cb;
-    for (int i0 = threadIdx.x; i0 < ne; i0 += kBatch * kFftThreads) {
+    for (int i0 = threadIdx.x; i0 < ne; i0 += kBatch * NT) {
         float2 v[kBatch];
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
-            const int idx = i0 + b * kFftThreads, j = idx >> lgc, c = idx & (cb - 1);
+            const int idx = i0 + b * NT, j = idx >> lgc, c = idx & (cb - 1);
             v[b] = make_float2(0.f, 0.f);
             if (idx < ne && c < ncol) v[b] = col[(int64_t)j * kxp + c];
         }
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
-            const int idx = i0 + b * kFftThreads, j = idx >> lgc, c = idx & (cb - 1);
+            const int idx = i0 + b * NT, j = idx >> lgc, c = idx & (cb - 1);
             if (idx >= ne) continue;
             if (blue) lds[lds_slot<true>(idx)] = cmul(v[b], chirp[j]);
             else lds[lds_slot<true>((bitrev(j, L.log2m) << lgc) + c)] = v[b];
@@ -558,7 +455,7 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g)
     __syncthreads();
     if (blue) lds_bluestein_dft<true, false, 4>(lds, L, cb, 1, cb, g.tables);
     else lds_fft_dit<true, false, 4>(lds, L.log2m, cb, 1, cb, g.tables);
-    for (int idx = threadIdx.x; idx < ne; idx += kFftThreads) {
+    for (int idx = threadIdx.x; idx < ne; idx += NT) {
         const int j = idx >> lgc, c = idx & (cb - 1);
         if (c >= ncol) continue;
         const float2 x = lds[lds_slot<true>(idx)];
@@ -566,7 +463,7 @@ __global__ __launch_bounds__(kFftThreads) void corr_cols_kernel(CorrArgs g)
     }
 }
 
-// Other ny: accumulation.  item: lattice, first k of the (ny, nkx) plane.
+// Accumulation.  item: lattice, first k of the (ny, nkx) plane.
 template <int SET>
 __global__ __launch_bounds__(kThreads) void corr_accum_kernel(CorrArgs g)
 {
@@ -690,31 +587,6 @@ hipError_t launch_corr_moment_rows(const DeviceView &v, const CorrItem *items, i
     return hipGetLastError();
 }
 
-hipError_t launch_corr_cols_a(const DeviceView &v, const CorrItem *items, int nitems,
-                              int lds_bytes, hipStream_t s)
-{
-    const CorrArgs g = make_args(v, items, 0);
-    hipLaunchKernelGGL(corr_cols_a_kernel, dim3(nitems), dim3(kFftThreads), lds_bytes, s, g);
-    return hipGetLastError();
-}
-
-hipError_t launch_corr_cols_b(const DeviceView &v, const CorrItem *items, int nitems, int set,
-                              int mode, int arg, int lds_bytes, hipStream_t s)
-{
-    CorrArgs g = make_args(v, items, set);
-    g.arg = arg;
-    const dim3 grid(nitems), block(kFftThreads);
-    if (set == 1)
-        hipLaunchKernelGGL((corr_cols_b_kernel<1, kAccDirect>), grid, block, lds_bytes, s, g);
-    else if (mode == kAccStash)
-        hipLaunchKernelGGL((corr_cols_b_kernel<0, kAccStash>), grid, block, lds_bytes, s, g);
-    else if (mode == kAccPair)
-        hipLaunchKernelGGL((corr_cols_b_kernel<0, kAccPair>), grid, block, lds_bytes, s, g);
-    else
-        hipLaunchKernelGGL((corr_cols_b_kernel<0, kAccDirect>), grid, block, lds_bytes, s, g);
-    return hipGetLastError();
-}
-
 hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nitems, int nslots,
                              hipStream_t s)
 {
@@ -725,11 +597,16 @@ hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nit
 }
 
 hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int slot,
-                            int lds_bytes, hipStream_t s)
+                            bool large, int lds_bytes, hipStream_t s)
 {
     CorrArgs g = make_args(v, items, 0);
     g.arg = slot;
-    hipLaunchKernelGGL(corr_cols_kernel, dim3(nitems), dim3(kFftThreads), lds_bytes, s, g);
+    if (large)
+        hipLaunchKernelGGL(corr_cols_kernel<kColsLargeThreads>, dim3(nitems),
+                           dim3(kColsLargeThreads), lds_bytes, s, g);
+    else
+        hipLaunchKernelGGL(corr_cols_kernel<kFftThreads>, dim3(nitems), dim3(kFftThreads),
+                           lds_bytes, s, g);
     return hipGetLastError();
 }
 

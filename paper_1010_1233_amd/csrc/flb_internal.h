@@ -57,12 +57,8 @@ struct alignas(16) LatticeParams {
     int32_t line_x;           // index of the x-direction line plan
     int32_t line_y;           // index of the y-direction line plan
     int32_t kxp;              // row pitch of spectra and sums: nkx rounded up to 16
-    int32_t col_pow2;         // ny a power of two above 2048: columns by the P*Q split
-    int32_t col_q, col_lgq;   // Q = min(ny, 64) consecutive rows per pass-B block
-    int32_t col_lgp;          // P = ny / Q
-    int32_t col_lgn;          // log2 ny
-    int32_t col_nq;           // q values per pass-A block
-    int32_t col_lgcb;         // other ny: log2 of the columns per column-kernel block
+    int32_t col_large;        // columns in the column kernel's large blocks
+    int32_t col_lgcb;         // log2 of the columns per column-kernel block
     int32_t fld_tiles_x;      // field-kernel tiles (256 sites) per row band
     int64_t fld_base;         // float offset of this lattice's five field planes
     int32_t fld_part0;        // first conservation partial of this lattice
@@ -157,22 +153,19 @@ hipError_t launch_corr_moment_fields(const DeviceView &v, const CorrItem *items,
                                      hipStream_t s);
 hipError_t launch_corr_moment_rows(const DeviceView &v, const CorrItem *items, int nitems,
                                    int lds_bytes, hipStream_t s);
-// Column passes and accumulation; set selects the fields and kinds as above.
-// Other ny: the column transform writes back in place, or to stash slot
-// `slot` >= 0; the accumulation adds this sample's products and, for
-// nslots > 0 (field set 0), those of the first nslots stash slots.
+// Column transforms and accumulation; set selects the fields and kinds as
+// above.  The column transform writes back in place, or to stash slot
+// `slot` >= 0; `large` picks the large blocks (kColsLargeElems elements,
+// kColsLargeThreads threads) over the kColsElems-element ones.  The
+// accumulation adds this sample's products and, for nslots > 0 (field set
+// 0), those of the first nslots stash slots.
+constexpr int kColsElems = 8192;
+constexpr int kColsLargeElems = 16384;
+constexpr int kColsLargeThreads = 1024;
 hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int slot,
-                            int lds_bytes, hipStream_t s);
-hipError_t launch_corr_cols_a(const DeviceView &v, const CorrItem *items, int nitems,
-                              int lds_bytes, hipStream_t s);
-// Accumulation modes of column pass B for field set 0 (power-of-two ny):
-// add this sample's products; keep its spectra in stash slot `arg`; add its
-// products and those of the first `arg` stash slots in one read-modify-write.
-enum AccMode : int { kAccDirect = 0, kAccStash = 1, kAccPair = 2 };
+                            bool large, int lds_bytes, hipStream_t s);
 // samples per read-modify-write of the FP64 sums (kDeferK - 1 stash slots)
 constexpr int kDeferK = 8;
-hipError_t launch_corr_cols_b(const DeviceView &v, const CorrItem *items, int nitems, int set,
-                              int mode, int arg, int lds_bytes, hipStream_t s);
 // Adds the products of the first nslots stash slots to the sums (field set 0).
 hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nitems, int nslots,
                              hipStream_t s);

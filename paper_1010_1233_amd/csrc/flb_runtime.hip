@@ -106,21 +106,23 @@ struct flb {
     float2 *d_spec = nullptr;
     double *d_acc = nullptr;
     int64_t spec_elems = 0, acc_elems = 0;
-    CorrItem *d_rows = nullptr, *d_cols = nullptr, *d_accum = nullptr;
-    CorrItem *d_cols_a = nullptr, *d_cols_b = nullptr, *d_fld = nullptr;
-    int n_rows = 0, n_cols = 0, n_accum = 0, n_cols_a = 0, n_cols_b = 0, n_fld = 0;
+    // column items of the two block sizes of the column kernel (the large
+    // ones for the longest work lengths)
+    CorrItem *d_rows = nullptr, *d_cols = nullptr, *d_cols_l = nullptr, *d_accum = nullptr;
+    CorrItem *d_fld = nullptr;
+    int n_rows = 0, n_cols = 0, n_cols_l = 0, n_accum = 0, n_fld = 0;
     // moment spectra (FLB_FLAG_MOMENT_SPECTRA): a second field set of six
     // moments through the same transforms, into kinds kKinds .. kKinds + 5
     bool moments = false;
     int nkinds = kKinds, nfld = kFields;
-    CorrItem *d_cols_a_m = nullptr, *d_cols_m = nullptr, *d_rows_m = nullptr;
-    int n_cols_a_m = 0, n_cols_m = 0, n_rows_m = 0;
+    CorrItem *d_cols_m = nullptr, *d_cols_lm = nullptr, *d_rows_m = nullptr;
+    int n_cols_m = 0, n_cols_lm = 0, n_rows_m = 0;
     CorrItem *d_rows_blue = nullptr;  // rows of lattices with Bluestein row transforms
     int n_rows_blue = 0;
-    // deferred accumulation: samples stash their spectra in kDeferK - 1 slots
-    // (pass B for power-of-two ny, the column transform's output otherwise)
-    // and every kDeferK-th one adds the products of all of them at once;
-    // `pending` counts the stashed samples
+    // deferred accumulation: samples stash their spectra (the column
+    // transform's output) in kDeferK - 1 slots and every kDeferK-th one adds
+    // the products of all of them at once; `pending` counts the stashed
+    // samples
     bool defer = false;
     int pending = 0;
     float2 *d_stash = nullptr;
@@ -128,7 +130,7 @@ struct flb {
     int n_flush = 0;
     float *d_fields = nullptr;
     double *d_csum_part = nullptr, *d_csum = nullptr;
-    int rows_lds = 0, cols_lds = 0, cols_a_lds = 0, cols_b_lds = 0;
+    int rows_lds = 0, cols_lds = 0, cols_l_lds = 0;
     int64_t nsamples = 0;
 
     // A registered sample is due until the next steps are enqueued: it then
@@ -412,13 +414,15 @@ int flbdev::LineTables::plan_for(int n)
 
 namespace {
 
-// Longest power-of-two column transformed whole by the general column kernel
-// (16 columns per block up to 512, 8 at 1024, 4 at 2048): one pass instead
-// of the P*Q split's two. Measured whole against split (whole path, GLUPS):
-// 96 x 512^2 93.1 against 88.5, 16 x 1024^2 87.9 against 83.9, 4 x 2048^2
-// 85.9 against 84.7; at 4096 (two columns per block, 16-byte runs) 80.0
-// against 82.5, so longer columns keep the split.
-constexpr int kColsWholeMax = 2048;
+// Power-of-two column lengths from which the column kernel takes its large
+// blocks (kColsLargeElems elements, kColsLargeThreads threads: 16, 8 and 4
+// columns of 1024, 2048 and 4096 points) instead of the kColsElems-element
+// ones.  Whole path, large against small blocks: 16 x 1024^2 88.2 against
+// 87.0 GLUPS, 4 x 2048^2 89.0 against 86.2, 4096^2 87.3 against 80.0 (two
+// columns per block leave 16-byte runs).  Bluestein work lengths keep the
+// small blocks: large ones from 1024 or 2048 on made the 64 uneven
+// lattices' path 56.2 or 56.6 against 57.5.
+constexpr int kColsLargeMin = 1024;
 
 int setup_correlators(flb_t *h)
 {
@@ -436,34 +440,21 @@ int setup_correlators(flb_t *h)
 
     int64_t spec = 0, acc = 0, fld = 0;
     int nparts = 0;
-    h->rows_lds = h->cols_a_lds = h->cols_b_lds = h->cols_lds = 0;
+    h->rows_lds = h->cols_lds = h->cols_l_lds = 0;
     for (auto &P : h->params) {
         P.line_x = plan_for(P.nx);
         P.line_y = plan_for(P.ny);
         P.kxp = (P.nkx + 15) / 16 * 16;
-        // power-of-two columns up to kColsWholeMax are transformed whole, in
-        // one pass, like the other lengths; longer ones by the P*Q split
-        P.col_pow2 = is_pow2(P.ny) && P.ny > kColsWholeMax;
-        if (P.col_pow2) {
-            P.col_lgn = log2i(P.ny);
-            P.col_q = std::min(P.ny, 64);
-            P.col_lgq = log2i(P.col_q);
-            P.col_lgp = P.col_lgn - P.col_lgq;
-            const int Pn = 1 << P.col_lgp;
-            P.col_nq = std::min(P.col_q, std::max(1, 256 / Pn));
-            if (Pn > 1)
-                h->cols_a_lds = std::max(h->cols_a_lds, Pn * P.col_nq * 16 * (int)sizeof(float2));
-            h->cols_b_lds =
-                std::max(h->cols_b_lds, P.col_q * 16 * h->nfld * (int)sizeof(float2));
-        } else {
-            // columns per block of the general column kernel: its lines fill
-            // at most 8192 LDS elements
-            const int my = lt.plans[P.line_y].m;
-            P.col_lgcb = log2i(std::max(1, std::min(16, 8192 / my)));
-            const int e = my << P.col_lgcb;  // padded like the row kernels' lines
-            h->cols_lds = std::max(h->cols_lds,
-                                   (e + (e >> 4) + (e >> 8) + 1) * (int)sizeof(float2));
-        }
+        // columns per block of the column kernel: at most 16, lines of at most
+        // kColsElems LDS elements per block (kColsLargeElems for power-of-two
+        // lengths from kColsLargeMin on, which take the large blocks)
+        const int my = lt.plans[P.line_y].m;
+        P.col_large = !lt.plans[P.line_y].bluestein && my >= kColsLargeMin;
+        P.col_lgcb =
+            log2i(std::max(1, std::min(16, (P.col_large ? kColsLargeElems : kColsElems) / my)));
+        const int e = my << P.col_lgcb;  // padded like the row kernels' lines
+        int &lds = P.col_large ? h->cols_l_lds : h->cols_lds;
+        lds = std::max(lds, (e + (e >> 4) + (e >> 8) + 1) * (int)sizeof(float2));
         P.spec_base = spec;
         P.acc_base = acc;
         spec += (int64_t)h->nfld * P.ny * P.kxp;
@@ -483,7 +474,7 @@ int setup_correlators(flb_t *h)
     h->acc_elems = acc;
 
     h->plans = lt.plans;
-    std::vector<CorrItem> rows, cols, accum, cols_a, cols_b, flds, cols_a_m, cols_m, rows_m;
+    std::vector<CorrItem> rows, cols, cols_l, accum, flds, cols_m, cols_lm, rows_m;
     std::vector<CorrItem> rows_blue, flush;
     for (size_t l = 0; l < h->params.size(); ++l) {
         const LatticeParams &P = h->params[l];
@@ -504,31 +495,15 @@ int setup_correlators(flb_t *h)
             if (h->moments)
                 for (int sig = 0; sig < 3; ++sig) rows_m.push_back({(int32_t)l, y, rb, sig});
         }
-        if (P.col_pow2) {
-            const int Pn = 1 << P.col_lgp;
-            if (Pn > 1)
-                for (int f = 0; f < h->nfld; ++f)
-                    for (int c0 = 0; c0 < P.kxp; c0 += 16)
-                        for (int q0 = 0; q0 < P.col_q; q0 += P.col_nq) {
-                            if (f < kFields) cols_a.push_back({(int32_t)l, f, c0, q0});
-                            cols_a_m.push_back({(int32_t)l, f, c0, q0});
-                        }
-            for (int c0 = 0; c0 < P.kxp; c0 += 16)
-                for (int k1 = 0; k1 < Pn; ++k1) cols_b.push_back({(int32_t)l, c0, k1, 0});
-            const int64_t nk = (int64_t)P.ny * P.nkx;
-            for (int64_t k0 = 0; k0 < nk; k0 += kThreads)
-                flush.push_back({(int32_t)l, (int32_t)k0, 0, 0});
-        } else {
-            for (int f = 0; f < h->nfld; ++f)
-                for (int c0 = 0; c0 < P.nkx; c0 += 1 << P.col_lgcb) {
-                    if (f < kFields) cols.push_back({(int32_t)l, f, c0, P.col_lgcb});
-                    cols_m.push_back({(int32_t)l, f, c0, P.col_lgcb});
-                }
-            const int64_t nk = (int64_t)P.ny * P.nkx;
-            for (int64_t k0 = 0; k0 < nk; k0 += kThreads) {
-                accum.push_back({(int32_t)l, (int32_t)k0, 0, 0});
-                flush.push_back({(int32_t)l, (int32_t)k0, 0, 0});
+        for (int f = 0; f < h->nfld; ++f)
+            for (int c0 = 0; c0 < P.nkx; c0 += 1 << P.col_lgcb) {
+                if (f < kFields) (P.col_large ? cols_l : cols).push_back({(int32_t)l, f, c0, P.col_lgcb});
+                (P.col_large ? cols_lm : cols_m).push_back({(int32_t)l, f, c0, P.col_lgcb});
             }
+        const int64_t nk = (int64_t)P.ny * P.nkx;
+        for (int64_t k0 = 0; k0 < nk; k0 += kThreads) {
+            accum.push_back({(int32_t)l, (int32_t)k0, 0, 0});
+            flush.push_back({(int32_t)l, (int32_t)k0, 0, 0});
         }
     }
     const CorrItem idle{-1, 0, 0, 0};
@@ -536,34 +511,31 @@ int setup_correlators(flb_t *h)
     rows = xcd_order(rows, idle);
     rows_blue = xcd_order(rows_blue, idle);
     h->n_rows_blue = (int)rows_blue.size();
-    cols_a = xcd_order(cols_a, idle);
-    cols_b = xcd_order(cols_b, idle);
     cols = xcd_order(cols, idle);
+    cols_l = xcd_order(cols_l, idle);
     if (h->moments) {
-        cols_a_m = xcd_order(cols_a_m, idle);
         cols_m = xcd_order(cols_m, idle);
+        cols_lm = xcd_order(cols_lm, idle);
         rows_m = xcd_order(rows_m, idle);
     } else {
-        cols_a_m.clear();
         cols_m.clear();
+        cols_lm.clear();
     }
-    h->n_cols_a_m = (int)cols_a_m.size();
     h->n_cols_m = (int)cols_m.size();
+    h->n_cols_lm = (int)cols_lm.size();
     h->n_rows_m = (int)rows_m.size();
     h->n_flush = (int)flush.size();
-    h->defer = !cols_b.empty() || !cols.empty();
+    h->defer = !cols.empty() || !cols_l.empty();
     h->pending = 0;
     h->n_rows = (int)rows.size();
     h->n_cols = (int)cols.size();
+    h->n_cols_l = (int)cols_l.size();
     h->n_accum = (int)accum.size();
-    h->n_cols_a = (int)cols_a.size();
-    h->n_cols_b = (int)cols_b.size();
     h->n_fld = (int)flds.size();
     int rc;
     if ((rc = upload(&h->d_fld, flds)) || (rc = upload(&h->d_rows, rows)) ||
-        (rc = upload(&h->d_cols, cols)) ||
-        (rc = upload(&h->d_accum, accum)) || (rc = upload(&h->d_cols_a, cols_a)) ||
-        (rc = upload(&h->d_cols_b, cols_b)) || (rc = upload(&h->d_cols_a_m, cols_a_m)) ||
+        (rc = upload(&h->d_cols, cols)) || (rc = upload(&h->d_cols_l, cols_l)) ||
+        (rc = upload(&h->d_accum, accum)) || (rc = upload(&h->d_cols_lm, cols_lm)) ||
         (rc = upload(&h->d_cols_m, cols_m)) || (rc = upload(&h->d_rows_m, rows_m)) ||
         (rc = upload(&h->d_rows_blue, rows_blue)) || (rc = upload(&h->d_flush, flush)) ||
         (rc = upload(&h->d_plans, h->plans)) ||
@@ -594,10 +566,10 @@ int enqueue_sample(flb_t *h, hipStream_t s, hipEvent_t ev_read = nullptr)
     if (h->moments) FLB_HIP(launch_corr_moment_fields(v, h->d_fld, h->n_fld, s));
     for (int set = 0; set < (h->moments ? 2 : 1); ++set) {
         // the moment set reuses the spectrum buffer after set 0
-        const CorrItem *ca = set ? h->d_cols_a_m : h->d_cols_a;
         const CorrItem *cg = set ? h->d_cols_m : h->d_cols;
-        const int na = set ? h->n_cols_a_m : h->n_cols_a;
+        const CorrItem *cl = set ? h->d_cols_lm : h->d_cols_l;
         const int ng = set ? h->n_cols_m : h->n_cols;
+        const int nl = set ? h->n_cols_lm : h->n_cols_l;
         if (set == 0) {
             FLB_HIP(launch_corr_rows(v, h->d_rows, h->n_rows, h->d_rows_blue, h->n_rows_blue,
                                      h->rows_lds, s));
@@ -605,18 +577,12 @@ int enqueue_sample(flb_t *h, hipStream_t s, hipEvent_t ev_read = nullptr)
         } else {
             FLB_HIP(launch_corr_moment_rows(v, h->d_rows_m, h->n_rows_m, h->rows_lds, s));
         }
-        if (na) FLB_HIP(launch_corr_cols_a(v, ca, na, h->cols_a_lds, s));
-        if (h->n_cols_b) {
-            const int mode = (set || !h->defer) ? kAccDirect
-                             : h->pending == kDeferK - 1 ? kAccPair : kAccStash;
-            FLB_HIP(launch_corr_cols_b(v, h->d_cols_b, h->n_cols_b, set, mode, h->pending,
-                                       h->cols_b_lds, s));
-        }
-        // other ny (field set 0): stash the column transform's output, or add
-        // this sample's products with the stashed ones
+        // field set 0: stash the column transform's output, or (every
+        // kDeferK-th sample) add this sample's products with the stashed ones
         const bool stash = !set && h->defer && h->pending < kDeferK - 1;
-        if (ng)
-            FLB_HIP(launch_corr_cols(v, cg, ng, stash ? h->pending : -1, h->cols_lds, s));
+        const int slot = stash ? h->pending : -1;
+        if (ng) FLB_HIP(launch_corr_cols(v, cg, ng, slot, false, h->cols_lds, s));
+        if (nl) FLB_HIP(launch_corr_cols(v, cl, nl, slot, true, h->cols_l_lds, s));
         if (h->n_accum && !stash)
             FLB_HIP(launch_corr_accum(v, h->d_accum, h->n_accum, set,
                                       (!set && h->defer) ? h->pending : 0, s));
@@ -885,8 +851,8 @@ void flb_destroy(flb_t *h)
     clear_graphs(h);
     void *ptrs[] = {h->pops[0], h->d_params, h->d_step, h->d_red, h->d_items,
                     h->d_plans, h->d_tables, h->d_spec, h->d_acc, h->d_rows, h->d_cols,
-                    h->d_accum, h->d_cols_a, h->d_cols_b, h->d_fld, h->d_fields,
-                    h->d_csum_part, h->d_csum, h->d_cols_a_m, h->d_cols_m, h->d_rows_m,
+                    h->d_accum, h->d_cols_l, h->d_fld, h->d_fields,
+                    h->d_csum_part, h->d_csum, h->d_cols_lm, h->d_cols_m, h->d_rows_m,
                     h->d_rows_blue, h->d_stash, h->d_flush, h->d_items2};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);

@@ -243,9 +243,10 @@ def test_moment_spectra_paired_run_and_batch(flb, oracle_lib):
 
 
 def test_reads_between_paired_samples(flb, oracle_lib):
-    """Power-of-two sides add the products of two samples at a time; a read
-    with one sample outstanding adds it first.  Reading after every sample,
-    twice in a row, or only at the end all give the oracle's sums."""
+    """Samples stash their spectra and every eighth adds the products of all
+    eight; a read with samples outstanding adds them first.  Reading after
+    every sample, twice in a row, or only at the end all give the oracle's
+    sums."""
     kw = dict(u0=(0.02, 0.0), seed=12)
     a = flb.Lattice(64, 32, TAU_C1, 1e-4, **kw)
     b = flb.Lattice(64, 32, TAU_C1, 1e-4, **kw)
@@ -360,12 +361,12 @@ def test_batch_of_column_block_widths_equals_separate_lattices(flb, oracle_lib):
     _compare(b.read_correlators(0)[0], o.acc, 1e-3)
 
 
-def test_split_column_path_over_sample_cycles(flb, oracle_lib):
-    """ny = 4096 takes the P*Q column split (pass A, then pass B, which
-    stashes seven samples of eight and adds the eighth's products with
-    them): ten samples, overlapped beside the steps, with reads after the
-    third and ninth (a read adds the stashed samples first), against
-    samples enqueued at once (same bits) and against the oracle."""
+def test_large_column_blocks_over_sample_cycles(flb, oracle_lib):
+    """ny = 4096 takes the column kernel's large blocks (1024 threads, four
+    whole columns): ten samples, which stash seven of eight and add the
+    eighth's products with them, overlapped beside the steps, with reads
+    after the third and ninth (a read adds the stashed samples first),
+    against samples enqueued at once (same bits) and against the oracle."""
     kw = dict(u0=(0.03, -0.01), seed=17)
     a = flb.Lattice(8, 4096, TAU_C1, 1e-4, **kw)
     b = flb.Lattice(8, 4096, TAU_C1, 1e-4, **kw)
