@@ -150,10 +150,10 @@ def batched_form(torch, flb, stream, specs, storage, periods=16):
     """Whole path (graph-replayed periods of SAMPLE_EVERY steps + a sample)
     and step-only rates of one batched handle."""
     # the captured periods depend on the buffer parity and on how many of the
-    # eight samples of an accumulation cycle are stashed: a multiple of 8
+    # sixteen samples of an accumulation cycle are stashed: a multiple of 16
     # periods starts the timed run where the warm-up started, so that it
     # replays graphs the warm-up captured
-    assert periods % 8 == 0
+    assert periods % 16 == 0
     b = flb.Lattice.batch(specs, seed=3, storage=storage)
     b.set_stream(stream)
     b.thermalize()

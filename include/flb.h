@@ -200,8 +200,8 @@ int flb_accumulate_correlators(flb_t *h);
  * kind < flb_num_kinds(h), ky < ny, kx < nx/2+1, and writes the number of
  * samples taken to *nsamples (may be NULL).  n_doubles must be at least
  * flb_num_kinds(h)*ny*(nx/2+1), else FLB_ESIZE.  Synchronises.  The library
- * adds the FP64 products of eight samples in one pass over the sums and keeps
- * the FP32 spectra of up to seven samples until then; a read adds those
+ * adds the FP64 products of sixteen samples in one pass over the sums and
+ * keeps the FP32 spectra of up to fifteen samples until then; a read adds those
  * first, so the sums are those of adding every sample, up to FP64 rounding
  * order. */
 int flb_read_correlators(flb_t *h, int lattice, double *out, size_t n_doubles,

@@ -17,9 +17,9 @@
 //          row kernel.)
 //   columns: one kernel transforms whole columns in LDS (Bluestein's
 //          convolution for lengths that are not powers of two) and keeps
-//          the spectra in a stash slot; with every eighth sample a second
-//          kernel adds the fifteen products of that sample and the seven
-//          stashed ones to the FP64 sums, one thread per k.
+//          the spectra in a stash slot; with every kDeferK-th (sixteenth)
+//          sample a second kernel adds the fifteen products of that sample
+//          and of the stashed ones to the FP64 sums, one thread per k.
 // The line transforms themselves are in flb_fft.h.
 #include "flb_fft.h"
 

@@ -164,8 +164,11 @@ constexpr int kColsLargeElems = 16384;
 constexpr int kColsLargeThreads = 1024;
 hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int slot,
                             bool large, int lds_bytes, hipStream_t s);
-// samples per read-modify-write of the FP64 sums (kDeferK - 1 stash slots)
-constexpr int kDeferK = 8;
+// samples per read-modify-write of the FP64 sums (kDeferK - 1 stash slots,
+// each the size of the spectra: 5 GB at 4096^2).  4096^2 whole path: 87.5
+// GLUPS with 16 against 86.4 with 8, the sums' read-modify-write being most
+// of the accumulation's bytes.
+constexpr int kDeferK = 16;
 // Adds the products of the first nslots stash slots to the sums (field set 0).
 hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nitems, int nslots,
                              hipStream_t s);

@@ -243,8 +243,8 @@ def test_moment_spectra_paired_run_and_batch(flb, oracle_lib):
 
 
 def test_reads_between_paired_samples(flb, oracle_lib):
-    """Samples stash their spectra and every eighth adds the products of all
-    eight; a read with samples outstanding adds them first.  Reading after
+    """Samples stash their spectra and every sixteenth adds the products of
+    all sixteen; a read with samples outstanding adds them first.  Reading after
     every sample, twice in a row, or only at the end all give the oracle's
     sums."""
     kw = dict(u0=(0.02, 0.0), seed=12)
@@ -330,8 +330,8 @@ def test_storage_formats_against_oracle(flb, oracle_lib, side):
 
 def test_batch_of_column_block_widths_equals_separate_lattices(flb, oracle_lib):
     """Column work lengths 2048, 1024 and 256 (Bluestein, 4, 8 and 16
-    columns per block) and a power-of-two side in one batch: over ten samples
-    (across an eight-sample accumulation cycle, with graph-replayed periods)
+    columns per block) and a power-of-two side in one batch: over twenty samples
+    (across a sixteen-sample accumulation cycle, with graph-replayed periods)
     every lattice's sums are the bits of the same lattice run alone, and the
     longest columns' sums match the oracle."""
     specs = [dict(nx=40, ny=600, tau=TAU_C1, theta=1e-4, stream_id=0),
@@ -341,32 +341,33 @@ def test_batch_of_column_block_widths_equals_separate_lattices(flb, oracle_lib):
     note("column block widths batch")
     b = flb.Lattice.batch(specs, seed=8)
     b.thermalize()
-    b.run(40, 4)
+    b.run(80, 4)
     for i, s in enumerate(specs):
         one = flb.Lattice(s["nx"], s["ny"], s["tau"], s["theta"], u0=s.get("u0", (0, 0)),
                           seed=8, stream_id=s["stream_id"])
         one.thermalize()
-        one.run(40, 4)
+        one.run(80, 4)
         acc, ns = b.read_correlators(i)
         ref, nr = one.read_correlators()
-        assert ns == nr == 10
+        assert ns == nr == 20
         assert np.array_equal(acc, ref), i
         one.close()
     s = specs[0]
     o = oracle_lib.Lattice(s["nx"], s["ny"], s["tau"], s["theta"], seed=8,
                            stream_id=s["stream_id"])
     o.thermalize()
-    o.run(40, 4)
-    assert o.nsamples == 10
+    o.run(80, 4)
+    assert o.nsamples == 20
     _compare(b.read_correlators(0)[0], o.acc, 1e-3)
 
 
 def test_large_column_blocks_over_sample_cycles(flb, oracle_lib):
     """ny = 4096 takes the column kernel's large blocks (1024 threads, four
-    whole columns): ten samples, which stash seven of eight and add the
-    eighth's products with them, overlapped beside the steps, with reads
-    after the third and ninth (a read adds the stashed samples first),
-    against samples enqueued at once (same bits) and against the oracle."""
+    whole columns): twenty samples, which stash fifteen of sixteen and add
+    the sixteenth's products with them, overlapped beside the steps, with
+    reads after the third and seventeenth (a read adds the stashed samples
+    first), against samples enqueued at once (same bits) and against the
+    oracle."""
     kw = dict(u0=(0.03, -0.01), seed=17)
     a = flb.Lattice(8, 4096, TAU_C1, 1e-4, **kw)
     b = flb.Lattice(8, 4096, TAU_C1, 1e-4, **kw)
@@ -374,18 +375,18 @@ def test_large_column_blocks_over_sample_cycles(flb, oracle_lib):
     b.set_sample_overlap(False)
     for L in (a, b, o):
         L.thermalize()
-    for i in range(10):
+    for i in range(20):
         for L in (a, b, o):
             L.step(3)
         a.accumulate()
         b.accumulate()
         o.sample()
-        if i in (2, 8):
+        if i in (2, 16):
             ra, na = a.read_correlators()
             assert na == i + 1
             assert np.array_equal(ra, b.read_correlators()[0])
             _compare(ra, o.acc, 2e-4)
     ra, na = a.read_correlators()
-    assert na == o.nsamples == 10
+    assert na == o.nsamples == 20
     assert np.array_equal(ra, b.read_correlators()[0])
     _compare(ra, o.acc, 2e-4)
