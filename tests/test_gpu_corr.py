@@ -188,7 +188,8 @@ def test_sample_records_conservation_sums(flb, oracle_lib):
     assert np.abs(cs - o.conservation()).max() < 1e-5
 
 
-@pytest.mark.parametrize("nx,ny", [(32, 32), (24, 18), (37, 23), (128, 96), (256, 128), (2, 2)])
+@pytest.mark.parametrize("nx,ny", [(32, 32), (24, 18), (37, 23), (128, 96), (256, 128), (2, 2),
+                                   (8, 1024)])
 def test_moment_spectra_match_oracle(flb, oracle_lib, nx, ny):
     """Kinds 15..20 (|M^a_k|^2, a = 3..8) of one sample against the oracle;
     the first fifteen kinds are unchanged by the extra field set."""
