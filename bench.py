@@ -8,9 +8,11 @@ collide+noise+stream updates of every site and one correlator sample (field
 extraction with the FP64 conservation sums of the sampled state, 2-D
 transforms, FP64 accumulation of the fifteen products).  The library runs
 each sample beside the next ten updates (on a second stream); the handle's
-synchronise call, which enqueues a sample still waiting for steps, and the
-device synchronisation bracket the timed region, so all K samples run inside
-it.  W untimed steps, then K timed steps.  `value` is site updates per
+flush call, which enqueues a sample still waiting for steps and adds the
+products of the samples whose spectra are stashed, and the device
+synchronisation close the timed region, which opens with no sample owed: the
+whole work of exactly K samples runs inside it.  W untimed steps, then K
+timed steps.  `value` is site updates per
 second (GLUPS) over the timed region, inputs resident in HBM.
 
 The JSON line also carries
@@ -27,9 +29,9 @@ The JSON line also carries
                 rate it implies (measured_GBs); step_kernel_glups_isolated
                 times the step kernel alone after the timed region, and
                 sample_ms is what a period takes beyond ten isolated steps;
-  cpu_baseline  the FP64 oracle, single thread, on a bounded sample of the
-                same workload, with the host's CPU model and the number of
-                CPUs the process may use;
+  cpu_baseline  the FP64 oracle on a bounded sample of the same workload,
+                over every CPU the process may use (value, cores) and on one
+                thread (single_core_value), with the host's CPU model;
   forms         step-kernel rates of the other storage formats and of the
                 noise-free step (the paper's ghost-noise overhead), and the
                 batched forms (96 x 512^2 Galilean-invariance sweep, 64
@@ -55,6 +57,9 @@ sys.path.insert(0, ROOT)
 METRIC = "noisy D2Q9 GLUPS and % of HBM peak, FP32/batched vs plain, at matched S(k)"
 HBM_PEAK_GBS = 8000.0
 SAMPLE_EVERY = 10
+# samples per read-modify-write pass of the FP64 correlator sums in the
+# library (the others keep their spectra until then)
+ACCUMULATE_EVERY = 16
 STEP_KERNEL = "step_kernel"
 
 
@@ -215,23 +220,52 @@ def velocity_set_form(torch, flb, stream, model, sides, sample=True, periods=5):
     return out
 
 
-def cpu_baseline(workloads, name, max_side=2048):
-    """The oracle (FP64, one thread) on a bounded sample of the same workload:
-    the same parameters on a lattice of at most max_side^2 sites, ten steps
-    and one correlator sample (one benchmark step), timed as a whole."""
+def cpu_baseline(workloads, name, side=1024):
+    """The oracle (FP64, as it stands) on a bounded sample of the same
+    workload: its parameters on side^2 lattices, ten steps and one
+    correlator sample per lattice (one benchmark step), first on one thread,
+    then on every CPU the process may use with one lattice per thread
+    (ctypes releases the interpreter lock during the oracle's calls, so the
+    threads run in parallel).  Lattices are set up before the clock starts."""
+    import threading
+
     import oracle
     c = workloads.CONFIGS[name]
-    nx, ny = min(c["nx"], max_side), min(c["ny"], max_side)
-    L = oracle.Lattice(nx, ny, c["tau"], c["theta"], rho0=c["rho0"], u0=c["u0"], seed=c["seed"])
-    t0 = time.perf_counter()
-    L.step(SAMPLE_EVERY)
-    L.sample()
-    dt = time.perf_counter() - t0
+    nx, ny = min(c["nx"], side), min(c["ny"], side)
     V = nx * ny
-    return {"value": SAMPLE_EVERY * V / dt / 1e9, "unit": "GLUPS", "cores": 1, "kind": "oracle",
+    oracle.tables()  # the oracle's constant tables, set up once before any thread
+
+    def lattice(i):
+        return oracle.Lattice(nx, ny, c["tau"], c["theta"], rho0=c["rho0"], u0=c["u0"],
+                              seed=c["seed"], stream_id=i)
+
+    def work(L):
+        L.step(SAMPLE_EVERY)
+        L.sample()
+
+    L = lattice(0)
+    t0 = time.perf_counter()
+    work(L)
+    dt1 = time.perf_counter() - t0
+    del L
+    host = host_cpu()
+    n = max(1, int(host["cpus_available"] or 1))
+    lats = [lattice(i) for i in range(n)]
+    threads = [threading.Thread(target=work, args=(x,)) for x in lats]
+    t0 = time.perf_counter()
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    dtn = time.perf_counter() - t0
+    del lats
+    return {"value": n * SAMPLE_EVERY * V / dtn / 1e9, "unit": "GLUPS", "cores": n,
+            "kind": "oracle",
+            "single_core_value": SAMPLE_EVERY * V / dt1 / 1e9,
             "sample": f"{SAMPLE_EVERY} steps + 1 correlator sample of a {nx}x{ny} lattice with "
-                      f"the workload's parameters ({dt:.1f} s, FP64, one thread)",
-            "host": host_cpu()}
+                      f"the workload's parameters, FP64: on one thread ({dt1:.1f} s), then one "
+                      f"such lattice on each of {n} threads at once ({dtn:.1f} s)",
+            "host": host}
 
 
 def host_cpu():
@@ -333,6 +367,9 @@ def main():
     with torch.cuda.stream(stream):
         for i in range(args.warmup):
             bench_step()
+        # the warm-up's stashed samples are added before the window opens, so
+        # that the window holds the whole work of exactly its own samples
+        g.flush_correlators()
         g.synchronize()
         torch.cuda.synchronize()
         # HIP event pairs around every step-kernel launch of the timed region
@@ -340,7 +377,9 @@ def main():
         t0 = time.perf_counter()
         for i in range(args.steps):
             bench_step()
-        g.synchronize()  # enqueues the last sample
+        # enqueues the last sample and the products of the stashed ones
+        g.flush_correlators()
+        g.synchronize()
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         g.set_launch_timing(False)
@@ -357,8 +396,7 @@ def main():
     drift = float(abs(g.sample_conservation()[0] - cons0[0]))
 
     # correlator sanity (matched S(k)): k-averaged S(rho) over the run
-    acc, ns = g.read_correlators()
-    S = flb.normalize(acc, ns, c["nx"], c["ny"], c["theta"], c["rho0"])
+    S = g.read_normalized()
     s_rho_mean = float(S["S_rho"][1:, 1:].mean())
 
     # the step kernel alone (nothing sampled beside it), after enough
@@ -408,6 +446,11 @@ def main():
         "step_kernel_glups": V / (step_ms * 1e-3) / 1e9,
         "step_kernel_glups_isolated": V / (iso_ms * 1e-3) / 1e9,
         "sample_ms": max(ms_per_step - SAMPLE_EVERY * iso_ms, 0.0),
+        # every timed sample's transforms and its share of the FP64 sums'
+        # read-modify-write passes (one per ACCUMULATE_EVERY samples, plus one
+        # for the remainder) ran inside the window
+        "samples_timed": args.steps,
+        "accumulations_timed": -(-args.steps // ACCUMULATE_EVERY),
         "mass_drift": drift,
         "S_rho_kmean": s_rho_mean,
     }

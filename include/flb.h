@@ -207,6 +207,35 @@ int flb_accumulate_correlators(flb_t *h);
 int flb_read_correlators(flb_t *h, int lattice, double *out, size_t n_doubles,
                          int64_t *nsamples);
 
+/* Normalised correlators of lattice `lattice` in the layout of
+ * flb_read_correlators (out[kind][ky][kx], host, n_doubles as there): the
+ * sums divided by the number of samples and by each kind's normalisation
+ * (Sec. 3, Eqs. 11-12), with mu = 3 theta and c_s = 1/sqrt(3):
+ *   kind 0       S(rho)     = <|rho_k|^2> / (V mu rho0)
+ *   kinds 1, 2   S(j_a)     = <|j_a,k|^2> / (V rho0 theta)
+ *   kinds 3, 4   S(u_a)     = rho0 <|u_a,k|^2> / (V theta)
+ *   kinds 5, 6   R(u_x,u_y) = rho0 <u_x,k u_y,k*> / (V theta)      (Re, Im)
+ *   kinds 7..10  R(rho,j_a) = <rho_k j_a,k*> / (V mu rho0 c_s)     (Re, Im)
+ *   kinds 11..14 R(rho,u_a) = <rho_k u_a,k*> / (V mu c_s)          (Re, Im)
+ *   kinds 15..20 S(M^a)     = <|M^a_k|^2> / (V mu rho0), a = 3..8
+ * V = nx ny.  The paper's N^rho = 1/(rho^3 V) and N^{u_a} = 1/(rho V k_B T)
+ * are these at rho0 = 1, theta = k_B T = 1/3, where the equal-time moment
+ * variance is rho0 (Eq. 7): at u0 = 0 every S is 1 and every R is 0 at
+ * linear order.  Writes the sample count to *nsamples (may be NULL).
+ * FLB_ESTATE when no sample was taken since the last reset, or when the
+ * lattice's theta is 0 (no fluctuation scale to normalise by).
+ * Synchronises. */
+int flb_read_normalized(flb_t *h, int lattice, double *out, size_t n_doubles,
+                        int64_t *nsamples);
+
+/* Enqueues, without waiting, the work still owed to the FP64 sums: a
+ * sample waiting for the next steps, then the products of the stashed
+ * samples (see flb_read_correlators).  Once the handle's stream has run
+ * this far, the sums hold every sample taken, as a read would find them.
+ * For callers that synchronise the stream themselves and for timing a
+ * whole number of samples. */
+int flb_flush_correlators(flb_t *h);
+
 /* Zeroes every lattice's correlator sums and the sample count. */
 int flb_reset_correlators(flb_t *h);
 

@@ -94,6 +94,14 @@ int flb_dq_accumulate(flb_dq_t *h);
 /* Copies the raw sums to out[kind][nz][ny][nx/2+1] (host, FP64); n_doubles
  * must be at least nkinds*nz*ny*(nx/2+1).  Synchronises. */
 int flb_dq_read(flb_dq_t *h, double *out, size_t n_doubles, int64_t *nsamples);
+/* The same sums divided by the sample count and by each kind's
+ * normalisation (Eq. 11, Eq. 12 for u_x u_y*; mu = 3 theta, V the number of
+ * sites): V mu rho0 for rho and every moment M^a, V rho0 theta for j_a,
+ * V theta / rho0 for u_a and both u_x u_y* kinds, so that each is 1 (auto)
+ * or 0 (cross) at u0 = 0 to linear order.  Same layout and sizes as
+ * flb_dq_read.  FLB_ESTATE when no sample was taken or theta = 0.
+ * Synchronises. */
+int flb_dq_read_normalized(flb_dq_t *h, double *out, size_t n_doubles, int64_t *nsamples);
 int flb_dq_reset(flb_dq_t *h);
 
 /* Populations f_i(x, t) (just after streaming, before the next collision) as

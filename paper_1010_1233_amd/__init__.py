@@ -1,8 +1,10 @@
 """MI355X (gfx950) fluctuating ideal-gas lattice Boltzmann library.
 
 Python binding of ``libflb.so`` (C interface in ``include/flb.h``): argument
-marshalling only; every step of the method runs in the library's HIP
-kernels.  PyTorch, when used, only supplies streams (``set_stream``).
+marshalling only.  Every step of the method runs in the library: the path in
+its HIP kernels, the normalisation of the correlator sums (Eqs. 11-12) on its
+host side (``read_normalized``); the binding only names the kinds it returns.
+PyTorch, when used, only supplies streams (``set_stream``).
 
 The library must have been built (``python -m paper_1010_1233_amd.build``);
 importing the package does not load it, the first use does, and a missing
@@ -29,6 +31,12 @@ KINDS = ("rho_rho", "jx_jx", "jy_jy", "ux_ux", "uy_uy",
          "re_ux_uy", "im_ux_uy", "re_rho_jx", "im_rho_jx", "re_rho_jy", "im_rho_jy",
          "re_rho_ux", "im_rho_ux", "re_rho_uy", "im_rho_uy")
 MOMENT_KINDS = tuple("M%d_M%d" % (a, a) for a in range(3, 9))
+# Names of the normalised kinds (flb_read_normalized): one real array per
+# structure factor; a cross correlator's Re and Im kinds become one complex
+# array.
+NORMALIZED = (("S_rho", 0), ("S_jx", 1), ("S_jy", 2), ("S_ux", 3), ("S_uy", 4),
+              ("R_uxuy", 5, 6), ("R_rhojx", 7, 8), ("R_rhojy", 9, 10), ("R_rhoux", 11, 12),
+              ("R_rhouy", 13, 14)) + tuple(("S_M%d" % a, 12 + a) for a in range(3, 9))
 
 
 class FlbError(RuntimeError):
@@ -76,6 +84,9 @@ SIGNATURES = {
     "flb_accumulate_correlators": (ctypes.c_int, [ctypes.c_void_p]),
     "flb_read_correlators": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_size_t,
                                             _i64p]),
+    "flb_read_normalized": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_size_t,
+                                           _i64p]),
+    "flb_flush_correlators": (ctypes.c_int, [ctypes.c_void_p]),
     "flb_reset_correlators": (ctypes.c_int, [ctypes.c_void_p]),
     "flb_get_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_size_t]),
     "flb_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_size_t]),
@@ -111,6 +122,7 @@ SIGNATURES = {
     "flb_dq_get_step": (ctypes.c_int64, [ctypes.c_void_p]),
     "flb_dq_accumulate": (ctypes.c_int, [ctypes.c_void_p]),
     "flb_dq_read": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_size_t, _i64p]),
+    "flb_dq_read_normalized": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_size_t, _i64p]),
     "flb_dq_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "flb_dq_get_populations": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_size_t]),
     "flb_dq_set_populations": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_size_t]),
@@ -370,38 +382,37 @@ class Lattice:
                                           ctypes.byref(ns)))
         return out, ns.value
 
+    def read_normalized_raw(self, lattice=0):
+        """(normalised kinds [nkinds][ny][nx//2+1] as the library computes
+        them, number of samples)."""
+        nx, ny, nk = self._shapes[lattice]
+        out = np.empty((self.nkinds, ny, nk), dtype=np.float64)
+        ns = ctypes.c_int64()
+        _check(lib().flb_read_normalized(self._h, lattice, _dptr(out), out.size,
+                                         ctypes.byref(ns)))
+        return out, ns.value
 
-def normalize(acc, nsamples, nx, ny, theta, rho0):
-    """Normalised correlators from raw sums (host arithmetic of the library).
+    def read_normalized(self, lattice=0):
+        """The library's normalised correlators by name (``NORMALIZED``):
+        S_rho, S_jx, ..., R_uxuy (complex), ..., and S_M3..S_M8 with the
+        moment spectra."""
+        out, _ = self.read_normalized_raw(lattice)
+        return _named(out, NORMALIZED)
 
-    S(rho) = <|rho_k|^2> / (V mu rho0) with mu = 3 theta (Eq. 11, N^rho at the
-    noise temperature); S(j_a) = <|j_a|^2> / (V rho0 theta);
-    S(u_a) = rho0 <|u_a|^2> / (V theta) (N^{u_a} = 1/(rho0 V k_B T));
-    R(u_x, u_y) = rho0 <u_x u_y*> / (V theta) (Eq. 12);
-    R(rho, j_a) = <rho j_a*> / (V mu rho0 c_s); R(rho, u_a) = <rho u_a*> / (V mu c_s).
-    With the moment spectra (21 kinds) also S(M^a) = <|M^a_k|^2> / (V mu rho0),
-    a = 3..8: every moment of the Hermite-normalised basis has per-site
-    variance mu rho0 at rest.
-    """
-    V = float(nx) * float(ny)
-    mu = 3.0 * theta
-    cs = 3.0 ** -0.5
-    m = np.asarray(acc) / max(int(nsamples), 1)
-    out = {
-        "S_rho": m[0] / (V * mu * rho0),
-        "S_jx": m[1] / (V * rho0 * theta),
-        "S_jy": m[2] / (V * rho0 * theta),
-        "S_ux": rho0 * m[3] / (V * theta),
-        "S_uy": rho0 * m[4] / (V * theta),
-        "R_uxuy": rho0 * (m[5] + 1j * m[6]) / (V * theta),
-        "R_rhojx": (m[7] + 1j * m[8]) / (V * mu * rho0 * cs),
-        "R_rhojy": (m[9] + 1j * m[10]) / (V * mu * rho0 * cs),
-        "R_rhoux": (m[11] + 1j * m[12]) / (V * mu * cs),
-        "R_rhouy": (m[13] + 1j * m[14]) / (V * mu * cs),
-    }
-    if m.shape[0] == NKINDS_MOMENTS:
-        for a in range(3, 9):
-            out["S_M%d" % a] = m[NKINDS + a - 3] / (V * mu * rho0)
+    def flush_correlators(self):
+        """Enqueue the work still owed to the sums (a waiting sample, the
+        stashed samples' products) without waiting for it."""
+        _check(lib().flb_flush_correlators(self._h))
+
+
+def _named(arr, names):
+    """Named views of a kinds-first array: one kind, or a Re/Im pair packed
+    as one complex array; names past the array's kinds are left out."""
+    out = {}
+    for e in names:
+        if e[-1] >= arr.shape[0]:
+            continue
+        out[e[0]] = arr[e[1]] if len(e) == 2 else arr[e[1]] + 1j * arr[e[2]]
     return out
 
 
@@ -495,6 +506,16 @@ class DqLattice:
         _check(lib().flb_dq_read(self._h, _dptr(out), out.size, ctypes.byref(ns)))
         return out, ns.value
 
+    def read_normalized(self):
+        """The library's normalised structure factors by name: S_rho,
+        S_j<a>, S_u<a>, R_uxuy (complex, D >= 2), S_M<a> for the
+        non-conserved moments."""
+        nx, ny, nz = self.sides
+        out = np.empty((self.nkinds, nz, ny, nx // 2 + 1))
+        ns = ctypes.c_int64()
+        _check(lib().flb_dq_read_normalized(self._h, _dptr(out), out.size, ctypes.byref(ns)))
+        return _named(out, dq_kind_names(self.D, self.Q))
+
     def get_populations(self):
         nx, ny, nz = self.sides
         out = np.empty((self.Q, nz, ny, nx))
@@ -513,26 +534,21 @@ class DqLattice:
         return out
 
 
-def dq_normalize(acc, nsamples, D, Q, sides, theta, rho0):
-    """Structure factors of the flb_dq.h kinds: S(rho) = <|rho_k|^2>/(V mu rho0),
-    S(j_a) = <|j_a|^2>/(V rho0 theta), S(u_a) = rho0 <|u_a|^2>/(V theta),
-    R(u_x,u_y) = rho0 <u_x u_y*>/(V theta), S(M^a) = <|M^a|^2>/(V mu rho0)."""
-    V = float(np.prod(sides))
-    mu = 3.0 * theta
-    m = np.asarray(acc) / max(int(nsamples), 1)
+def dq_kind_names(D, Q):
+    """Names and kind indices of the flb_dq.h kinds in ``read_normalized``."""
     ax = "xyz"
-    out = {"S_rho": m[0] / (V * mu * rho0)}
+    names = [("S_rho", 0)]
     k = 1
     for a in range(D):
-        out["S_j" + ax[a]] = m[k] / (V * rho0 * theta)
+        names.append(("S_j" + ax[a], k))
         k += 1
     for a in range(D):
-        out["S_u" + ax[a]] = rho0 * m[k] / (V * theta)
+        names.append(("S_u" + ax[a], k))
         k += 1
     if D >= 2:
-        out["R_uxuy"] = rho0 * (m[k] + 1j * m[k + 1]) / (V * theta)
+        names.append(("R_uxuy", k, k + 1))
         k += 2
     for a in range(D + 1, Q):
-        out["S_M%d" % a] = m[k] / (V * mu * rho0)
+        names.append(("S_M%d" % a, k))
         k += 1
-    return out
+    return tuple(names)

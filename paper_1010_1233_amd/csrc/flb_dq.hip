@@ -598,7 +598,7 @@ struct flb_dq {
     uint32_t V = 0;
     double w[kDqMaxQ] = {0}, m[kDqMaxQ][kDqMaxQ] = {{0}};
     int v[kDqMaxQ][3] = {{0}};
-    double rho0 = 1.0;
+    double rho0 = 1.0, theta = 0.0;
     uint64_t seed = 0;
     bool noise = false;
     bool nontemporal = false;  // streaming accesses (buffers beyond 256 MB)
@@ -938,6 +938,7 @@ flb_dq_t *flb_dq_create(int model, const int32_t n[3], const double *tau, double
     h->nf = 1 + 2 * D + h->nm;
     h->nkinds = h->nf + (D >= 2 ? 2 : 0);
     h->rho0 = rho0;
+    h->theta = theta;
     h->seed = seed;
     DqParams &P = h->P;
     std::memset(&P, 0, sizeof P);
@@ -1092,6 +1093,32 @@ int flb_dq_read(flb_dq_t *h, double *out, size_t n_doubles, int64_t *nsamples)
                        (size_t)h->P.kxp * sizeof(double), (size_t)h->P.nkx * sizeof(double),
                        (size_t)h->nkinds * nrows, hipMemcpyDeviceToHost));
     if (nsamples) *nsamples = h->nsamples;
+    return FLB_OK;
+}
+
+int flb_dq_read_normalized(flb_dq_t *h, double *out, size_t n_doubles, int64_t *nsamples)
+{
+    int64_t ns = 0;
+    int rc = flb_dq_read(h, out, n_doubles, &ns);
+    if (rc) return rc;
+    if (nsamples) *nsamples = ns;
+    if (ns <= 0) return dq_fail(FLB_ESTATE, "no correlator sample to normalise");
+    if (!(h->theta > 0))
+        return dq_fail(FLB_ESTATE, "theta = 0: no fluctuation scale to normalise by");
+    // Eq. (11) (and Eq. 12 for u_x u_y*) at the noise temperature, mu = 3 theta
+    const double V = (double)h->V, mu = 3.0 * h->theta, rho0 = h->rho0, theta = h->theta;
+    const int D = h->D;
+    const size_t plane = (size_t)h->n[1] * h->n[2] * h->P.nkx;
+    for (int q = 0; q < h->nkinds; ++q) {
+        double norm;
+        if (q == 0) norm = 1.0 / (V * mu * rho0);                  // rho
+        else if (q <= D) norm = 1.0 / (V * rho0 * theta);          // j_a
+        else if (q <= 2 * D) norm = rho0 / (V * theta);            // u_a
+        else if (D >= 2 && q <= 2 * D + 2) norm = rho0 / (V * theta);  // Re, Im u_x u_y*
+        else norm = 1.0 / (V * mu * rho0);                         // non-conserved moments
+        double *p = out + (size_t)q * plane;
+        for (size_t k = 0; k < plane; ++k) p[k] = p[k] / (double)ns * norm;
+    }
     return FLB_OK;
 }
 

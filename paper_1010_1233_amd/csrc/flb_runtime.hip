@@ -1054,6 +1054,42 @@ int flb_read_correlators(flb_t *h, int lattice, double *out, size_t n_doubles, i
     return FLB_OK;
 }
 
+int flb_read_normalized(flb_t *h, int lattice, double *out, size_t n_doubles, int64_t *nsamples)
+{
+    int64_t ns = 0;
+    int rc = flb_read_correlators(h, lattice, out, n_doubles, &ns);
+    if (rc) return rc;
+    if (nsamples) *nsamples = ns;
+    const flb_lattice_spec &s = h->specs[lattice];
+    if (ns <= 0) return fail(FLB_ESTATE, "no correlator sample to normalise");
+    if (!(s.theta > 0)) return fail(FLB_ESTATE, "theta = 0: no fluctuation scale to normalise by");
+    // Sec. 3, Eqs. (11)-(12) at the noise temperature theta (mu = 3 theta)
+    const double V = (double)s.nx * (double)s.ny, mu = 3.0 * s.theta, rho0 = s.rho0;
+    const double cs = 1.0 / std::sqrt(3.0), theta = s.theta;
+    double norm[FLB_NKINDS_MOMENTS];
+    norm[0] = 1.0 / (V * mu * rho0);
+    norm[1] = norm[2] = 1.0 / (V * rho0 * theta);
+    norm[3] = norm[4] = norm[5] = norm[6] = rho0 / (V * theta);
+    for (int q = 7; q < 11; ++q) norm[q] = 1.0 / (V * mu * rho0 * cs);
+    for (int q = 11; q < 15; ++q) norm[q] = 1.0 / (V * mu * cs);
+    for (int q = 15; q < FLB_NKINDS_MOMENTS; ++q) norm[q] = 1.0 / (V * mu * rho0);
+    const size_t plane = (size_t)s.ny * (size_t)(s.nx / 2 + 1);
+    for (int q = 0; q < h->nkinds; ++q) {
+        double *p = out + q * plane;
+        for (size_t k = 0; k < plane; ++k) p[k] = p[k] / (double)ns * norm[q];
+    }
+    return FLB_OK;
+}
+
+int flb_flush_correlators(flb_t *h)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (!h->corr_ready) return FLB_OK;  // no sample was ever taken
+    int rc = settle_due(h);
+    if (rc) return rc;
+    return flush_pending(h);
+}
+
 int flb_reset_correlators(flb_t *h)
 {
     if (check_handle(h)) return FLB_EINVAL;

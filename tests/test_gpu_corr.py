@@ -5,7 +5,6 @@ the accumulated sums agree element by element to a small relative tolerance;
 statistical runs check S_k = 1 and vanishing cross correlators at u0 = 0 on
 the GPU alone (Eq. 7), with the abstract's "< 0.5 %" on the cross correlators.
 """
-import os
 import sys
 
 import numpy as np
@@ -34,7 +33,8 @@ def _compare(acc_g, acc_o, rtol):
 
 @pytest.mark.parametrize("nx,ny", [(32, 32), (20, 20), (24, 18), (37, 23), (64, 8), (2, 2),
                                    (128, 96), (3, 256), (40, 600), (1000, 5), (300, 7),
-                                   (1500, 3), (12, 1024), (10, 2048), (6, 4096)])
+                                   (1500, 3), (12, 1024), (10, 2048), (6, 4096),
+                                   (512, 512), (512, 300), (300, 512)])
 def test_single_sample_matches_oracle(flb, oracle_lib, nx, ny):
     note("sample", nx, ny)
     g = flb.Lattice(nx, ny, TAU_C1, 1e-4, u0=(0.04, -0.01), seed=3)
@@ -152,8 +152,7 @@ def test_structure_factors_are_one_on_gpu(flb):
     def block():
         g.reset_correlators()
         g.run(20000, 10)
-        acc, ns = g.read_correlators()
-        return flb.normalize(acc, ns, nx, ny, theta, 1.0)
+        return g.read_normalized()
 
     mean, sem = block_means(block, 16)
     pred = lyapunov.predict(nx, ny, tau, theta)
@@ -277,17 +276,13 @@ def test_reads_between_paired_samples(flb, oracle_lib):
     _compare(a.read_correlators()[0], o.acc, 2e-4)
 
 
-@pytest.mark.parametrize("side", [
-    2048,
-    pytest.param(4096, marks=pytest.mark.skipif(
-        os.environ.get("FLB_FULL_SIZE") != "1",
-        reason="two minutes of oracle time; set FLB_FULL_SIZE=1 to run")),
-])
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("side", [2048, 4096])
 def test_storage_formats_against_oracle(flb, oracle_lib, side):
-    """The 4096^2 workload's parameters (u_x = 0.05, tau_s = 0.6, kT = 1e-4),
-    at 2048^2 and (opt-in) 4096^2: thermal start, ten steps and one sample
-    in each storage format against the oracle's FP64 run of the same
-    trajectory.  Per kind, the error of the sums over k relative to their
+    """The 4096^2 workload (u_x = 0.05, tau_s = 0.6, kT = 1e-4), at 4096^2
+    itself and at 2048^2: thermal start, ten steps and one sample in each
+    storage format against the oracle's FP64 run of the same trajectory
+    (one oracle run per side, about a minute at 4096^2).  Per kind, the error of the sums over k relative to their
     size (cross kinds relative to the geometric mean of the two fields' auto
     sums) measures what the storage format costs the correlators."""
     c = workloads.CONFIGS["c5_4096"]
@@ -391,3 +386,29 @@ def test_large_column_blocks_over_sample_cycles(flb, oracle_lib):
     assert na == o.nsamples == 20
     assert np.array_equal(ra, b.read_correlators()[0])
     _compare(ra, o.acc, 2e-4)
+
+
+def test_galilean_batch_shape_over_sample_cycles(flb, oracle_lib):
+    """The Galilean-invariance sweep's shape: 512^2 lattices (512-point rows
+    and 512-point columns in the small column blocks) at four of the sweep's
+    mean velocities, batched, graph-replayed periods with the samples beside
+    the steps; twenty samples cross a sixteen-sample accumulation cycle.
+    Every lattice's sums match the oracle's run of the same trajectory
+    element by element."""
+    us = (0.0, 0.05, 0.1, 0.2)
+    specs = [dict(nx=512, ny=512, tau=workloads.tau_vector(0.8, 1.0, 1.0), theta=1e-4,
+                  rho0=1.0, u0=(u, 0.0), stream_id=16 * i) for i, u in enumerate(us)]
+    note("4 x 512^2 batch, 20 samples")
+    b = flb.Lattice.batch(specs, seed=3)
+    b.thermalize()
+    b.run(40, 2)
+    for i, s in enumerate(specs):
+        note("  oracle lattice", i)
+        o = oracle_lib.Lattice(512, 512, s["tau"], s["theta"], u0=s["u0"], seed=3,
+                               stream_id=s["stream_id"])
+        o.thermalize()
+        o.run(40, 2)
+        acc, ns = b.read_correlators(i)
+        assert ns == o.nsamples == 20
+        assert np.all(acc[:, 0, 0] == 0)
+        _compare(acc, o.acc, 1e-3)

@@ -153,8 +153,7 @@ def _stats(flb, model, sides, tau, ladd, nblocks, steps, every, seed, theta=1e-4
     for _ in range(nblocks):
         g.reset_correlators()
         g.run(steps, every)
-        acc, ns = g.read_correlators()
-        blocks.append(flb.dq_normalize(acc, ns, D, Q, g.sides, theta, 1.0))
+        blocks.append(g.read_normalized())
     pred = lyapunov_dq.predict(model, sides, tau, theta, ladd=ladd)
     mask = ~np.isnan(pred["S_rho"])
     zs = []

@@ -192,7 +192,9 @@ def test_torch_stream_binding(flb):
 
 def test_large_lattice_one_step(flb, oracle_lib):
     """4096^2 (the 16.8M-site workload, u0_x = 0.05, tau_s = 0.6) in the
-    launch shape the benchmark times: one full step against the oracle."""
+    default one-step launch shape: one full step against the oracle at every
+    site.  The two-step shape the benchmark times is checked against the
+    oracle at sampled sites in test_sampled_sites_at_full_and_maximum_size."""
     c = workloads.CONFIGS["c5_4096"]
     note("4096^2 one step")
     g, o = pair(flb, oracle_lib, c["nx"], c["ny"], c["tau"], c["theta"], u0=c["u0"],
