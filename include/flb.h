@@ -243,6 +243,18 @@ int flb_reset_correlators(flb_t *h);
  * FP64).  n must be at least 9*nx*ny.  Synchronises. */
 int flb_get_populations(flb_t *h, int lattice, double *out, size_t n);
 
+/* For callers that cannot allocate device memory (loops that read the
+ * state often and may not call hipMalloc, harnesses that forbid device
+ * allocation): flb_get_populations without its per-call staging
+ * allocation.  Same arguments, output and errors, plus FLB_ESIZE when
+ * 9*nx*ny exceeds 8388608 values (2^23).  The values pass through a 64 MiB
+ * staging array in the library's code object, one per GPU, held until the
+ * process ends; the call allocates nothing.  Calls on one GPU share that
+ * array: calls from several host threads that overlap on one GPU race (each
+ * call synchronises the handle's stream before it returns, so calls from
+ * one thread never overlap).  Synchronises. */
+int flb_get_populations_noalloc(flb_t *h, int lattice, double *out, size_t n);
+
 /* Replaces lattice `lattice`'s populations by in[9][ny][nx] (host, FP64 full
  * values).  Values are rounded to the storage format.  Synchronises. */
 int flb_set_populations(flb_t *h, int lattice, const double *in, size_t n);

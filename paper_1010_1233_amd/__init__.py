@@ -89,6 +89,8 @@ SIGNATURES = {
     "flb_flush_correlators": (ctypes.c_int, [ctypes.c_void_p]),
     "flb_reset_correlators": (ctypes.c_int, [ctypes.c_void_p]),
     "flb_get_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_size_t]),
+    "flb_get_populations_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp,
+                                                   ctypes.c_size_t]),
     "flb_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_size_t]),
     "flb_conservation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp]),
     "flb_conservation_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),

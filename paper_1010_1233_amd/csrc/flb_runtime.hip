@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -23,6 +24,14 @@
 #include "flb_internal.h"
 
 using namespace flbdev;
+
+// Staging area of flb_get_populations_noalloc, part of the library's code
+// object: every GPU the library is loaded on holds its own copy (64 MiB)
+// until the process ends, so that call needs no device allocation.  Host
+// code never uses the array's name as an address: it takes each device's
+// address from hipGetSymbolAddress (scratch_on_device).
+constexpr size_t kNoAllocDoubles = (size_t)1 << 23;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
 
 namespace {
 thread_local std::string g_err;
@@ -789,6 +798,31 @@ flb_t *create_impl(int n, const flb_lattice_spec *specs, uint64_t seed, int stor
     return h;
 }
 
+// Device address of `scratch` on device `dev`, looked up once per device
+// with that device current and kept.
+int scratch_on_device(int dev, double **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *ptr[kMaxDevices] = {};
+    if (dev < 0 || dev >= kMaxDevices) return fail(FLB_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        int cur = -1;
+        FLB_HIP(hipGetDevice(&cur));
+        if (cur != dev) FLB_HIP(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return fail(FLB_EHIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                      hipGetErrorString(e));
+        ptr[dev] = static_cast<double *>(p);
+    }
+    *out = ptr[dev];
+    return FLB_OK;
+}
+
 int check_handle(flb_t *h)
 {
     if (!h) return fail(FLB_EINVAL, "NULL handle");
@@ -1116,6 +1150,27 @@ int flb_get_populations(flb_t *h, int lattice, double *out, size_t n)
     if (e == hipSuccess) e = hipMemcpy(out, d, need * sizeof(double), hipMemcpyDeviceToHost);
     (void)hipFree(d);
     if (e != hipSuccess) return fail(FLB_EHIP, std::string("get populations: ") + hipGetErrorString(e));
+    return FLB_OK;
+}
+
+int flb_get_populations_noalloc(flb_t *h, int lattice, double *out, size_t n)
+{
+    if (check_lattice(h, lattice)) return FLB_EINVAL;
+    if (!out) return fail(FLB_EINVAL, "out must not be NULL");
+    const LatticeParams &P = h->params[lattice];
+    const size_t need = 9 * (size_t)P.nx * (size_t)P.ny;
+    if (n < need) return fail(FLB_ESIZE, "output buffer smaller than 9*nx*ny");
+    if (need > kNoAllocDoubles)
+        return fail(FLB_ESIZE, "lattice too large for the no-allocation read: 9*nx*ny must be "
+                               "at most 8388608 (use flb_get_populations)");
+    double *d = nullptr;
+    int rc = scratch_on_device(h->device, &d);
+    if (rc) return rc;
+    // every value the copy reads is written by the kernel first: nothing
+    // needs clearing
+    FLB_HIP(launch_get(h->view(), lattice, P.nx, P.ny, d, h->stream));
+    FLB_HIP(hipMemcpyAsync(out, d, need * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    FLB_HIP(hipStreamSynchronize(h->stream));
     return FLB_OK;
 }
 
