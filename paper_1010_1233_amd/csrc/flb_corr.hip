@@ -21,6 +21,9 @@
 //          sample a second kernel adds the fifteen products of that sample
 //          and of the stashed ones to the FP64 sums, one thread per k.
 // The line transforms themselves are in flb_fft.h.
+#include <algorithm>
+#include <type_traits>
+
 #include "flb_fft.h"
 
 namespace flbdev {
@@ -340,20 +343,35 @@ __device__ __forceinline__ void products_k(double (&val)[kKinds], const float2 (
     for (int q = 0; q < kKinds; ++q) val[q] = p[q];
 }
 
+// One read-modify-write of NK FP64 sums at one k (stride kstride): every
+// old value is read before any is written, so the reads are in flight
+// together (read and write addresses are the same, so the compiler may not
+// reorder a later read before an earlier write on its own).
+template <int NK>
+__device__ __forceinline__ void add_to_sums(double *a, int64_t kstride, const double (&u)[NK])
+{
+    double old[NK];
+#pragma unroll
+    for (int q = 0; q < NK; ++q) old[q] = a[q * kstride];
+#pragma unroll
+    for (int q = 0; q < NK; ++q) a[q * kstride] = old[q] + u[q];
+}
+
 // Adds the products of one sample at one k to the sums.
 __device__ __forceinline__ void accumulate_k(double *a, int64_t kstride, const float2 (&X)[5])
 {
     double val[kKinds];
     products_k(val, X);
-#pragma unroll
-    for (int q = 0; q < kKinds; ++q) a[q * kstride] += val[q];
+    add_to_sums(a, kstride, val);
 }
 
-// Adds the products of two samples at one k to the sums in one
-// read-modify-write of the FP64 sums.
-// The products of X (when WITH_X) and of the n stashed samples at st (slot
-// j at st + j * sstride, field f at + f * kstride), summed in that order and
-// added to the sums in one read-modify-write.
+// Stash slots read per batch: fifteen slots (a cycle of sixteen samples) are
+// three batches, each with all its reads in flight at once.
+constexpr int kSlotBatch = 5;
+
+// The products of X (when WITH_X) and of the n >= 1 stashed samples at st
+// (slot j at st + j * sstride, field f at + f * kstride), summed in that
+// order and added to the sums in one read-modify-write.
 template <bool WITH_X>
 __device__ __forceinline__ void accumulate_stashed_k(double *a, int64_t kstride,
                                                      const float2 (&X)[5], const float2 *st,
@@ -366,17 +384,27 @@ __device__ __forceinline__ void accumulate_stashed_k(double *a, int64_t kstride,
 #pragma unroll
         for (int q = 0; q < kKinds; ++q) u[q] = 0.0;
     }
-    for (int j = 0; j < n; ++j) {
-        float2 Y[5];
+    for (int j0 = 0; j0 < n; j0 += kSlotBatch) {
+        // slots past the last are read again (in bounds) and not added
+        float2 Y[kSlotBatch][5];
 #pragma unroll
-        for (int f = 0; f < 5; ++f) Y[f] = st[j * sstride + f * kstride];
-        double w[kKinds];
-        products_k(w, Y);
+        for (int b = 0; b < kSlotBatch; ++b) {
+            const int j = min(j0 + b, n - 1);
 #pragma unroll
-        for (int q = 0; q < kKinds; ++q) u[q] += w[q];
+            for (int f = 0; f < 5; ++f) Y[b][f] = st[j * sstride + f * kstride];
+        }
+        // (a select, not a branch: the reads of a batch must not be sunk
+        // into per-slot branches, which would serialise them again)
+#pragma unroll
+        for (int b = 0; b < kSlotBatch; ++b) {
+            const bool on = j0 + b < n;
+            double w[kKinds];
+            products_k(w, Y[b]);
+#pragma unroll
+            for (int q = 0; q < kKinds; ++q) u[q] += on ? w[q] : 0.0;
+        }
     }
-#pragma unroll
-    for (int q = 0; q < kKinds; ++q) a[q * kstride] += u[q];
+    add_to_sums(a, kstride, u);
 }
 
 // Squared moduli of the six moment spectra at one k, added to kinds
@@ -384,11 +412,13 @@ __device__ __forceinline__ void accumulate_stashed_k(double *a, int64_t kstride,
 __device__ __forceinline__ void accumulate_moments_k(double *a, int64_t kstride,
                                                      const float2 (&X)[6])
 {
+    double u[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         const double re = X[f].x, im = X[f].y;
-        a[(kKinds + f) * kstride] += re * re + im * im;
+        u[f] = re * re + im * im;
     }
+    add_to_sums<6>(a + kKinds * kstride, kstride, u);
 }
 
 template <int SET, int NF>
@@ -460,6 +490,168 @@ __global__ __launch_bounds__(NT) void corr_cols_kernel(CorrArgs g)
         if (c >= ncol) continue;
         const float2 x = lds[lds_slot<true>(idx)];
         out[(int64_t)j * kxp + c] = blue ? cmul(x, chirp[j]) : x;
+    }
+}
+
+// Column transforms of power-of-two lengths N = 2^LG, 512 <= N <= 4096, in
+// persistent blocks of NT threads.  A group is CB = 16384 / N (at most 16)
+// adjacent columns of one field of one lattice (item: lattice, field, first
+// column, log2 CB); each block works through the groups the host scheduled
+// for it (sched[it * gridDim.x + blockIdx.x], it < niter, lattice -1 =
+// none), and issues the global loads of its next group as soon as the
+// current one has left its registers, so that they run under the current
+// group's LDS passes and stores.
+// The transform is the in-place decimation in time of lds_fft_dit with
+// passes of R1, R2, R3 fused radix-2 stages, but its first pass works on the
+// registers the global loads fill (first-pass group g of a column holds rows
+// bitrev(g) + r N / 2^R1 at position bitrev(r), the bit-reversed input
+// order) and its last pass stores the natural-order result straight to
+// global memory, so only the middle pass reads and writes LDS in between.
+// LDS [element][column] interleaved, padded as the other column layouts.
+// 1024 to 4096 points take 512 threads, each with two groups per pass:
+// with 1024 threads a radix-16 pass alone fills the 128 registers a thread
+// may hold, and the prefetched group did not fit beside it.
+
+// bit reversal of r < 2^bits at compile time (register array indices)
+__host__ __device__ constexpr int rev_bits(int r, int bits)
+{
+    int o = 0;
+    for (int b = 0; b < bits; ++b) o |= ((r >> b) & 1) << (bits - 1 - b);
+    return o;
+}
+
+// a[0] <- a[1] <- ... <- a[n-1] <- a[0]: a register array cycled with
+// static indices only
+template <int NA> __device__ __forceinline__ void rotate_left(float2 (&a)[NA])
+{
+    const float2 t = a[0];
+#pragma unroll
+    for (int i = 0; i + 1 < NA; ++i) a[i] = a[i + 1];
+    a[NA - 1] = t;
+}
+
+__host__ __device__ constexpr int cols_pipe_threads(int lg) { return lg >= 10 ? 512 : 1024; }
+
+template <int LG, int R1, int R2, int R3>
+__global__ __launch_bounds__(cols_pipe_threads(LG)) void corr_cols_pipe_kernel(
+    CorrArgs g, const PipeItem *__restrict__ sched, int niter)
+{
+    static_assert(R1 + R2 + R3 == LG && R1 <= 4 && R2 <= 4 && R3 <= 4, "pass plan");
+    constexpr int NT = cols_pipe_threads(LG);
+    constexpr int N = 1 << LG;
+    constexpr int G1 = 1 << R1, G2 = 1 << R2, G3 = 1 << R3;
+    constexpr int CB = (16384 >> LG) < 16 ? (16384 >> LG) : 16;  // columns per group
+    constexpr int LGC = (CB == 16) ? 4 : (CB == 8) ? 3 : (CB == 4) ? 2 : (CB == 2) ? 1 : 0;
+    static_assert((1 << LGC) == CB, "columns per group");
+    // groups of the first, middle and last pass per thread
+    constexpr int NG1 = (CB << (LG - R1)) / NT, NG2 = (CB << (LG - R2)) / NT;
+    constexpr int NG3 = (CB << (LG - R3)) / NT;
+    static_assert(NG1 >= 1 && NG1 * NT == (CB << (LG - R1)) && NG2 * NT == (CB << (LG - R2)) &&
+                  NG3 * NT == (CB << (LG - R3)) && NT % CB == 0, "passes");
+    constexpr int S2 = R1 + 1, H2 = 1 << (S2 - 1);  // the middle pass's first stage, distance
+    constexpr int H3 = N >> R3;                     // element distance of the last pass
+    extern __shared__ float2 lds[];
+    const int tid = threadIdx.x;
+    const int c = tid & (CB - 1);                   // this thread's column in its group
+
+    // The twiddles of the middle and last passes depend on the thread alone:
+    // read once, before any load whose completion the loop waits for (the
+    // vector memory counter is in order, so a twiddle read behind the
+    // prefetched loads would wait for them).
+    float2 tw2[NG2], tw3[NG3];
+#pragma unroll
+    for (int i = 0; i < NG2; ++i)
+        tw2[i] = g.tables[((tid + i * NT) >> LGC & (H2 - 1)) << (kTwLog - (S2 + R2 - 1))];
+#pragma unroll
+    for (int i = 0; i < NG3; ++i) tw3[i] = g.tables[((tid + i * NT) >> LGC) << (kTwLog - LG)];
+    // vmcnt(0), other counters untouched: the twiddles have arrived before
+    // the first prefetch is issued, so no wait inside the loop is held up by
+    // them (otherwise the wait analysis, not telling the first iteration
+    // from later ones, orders them behind the prefetched loads)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+
+    float2 v[NG1][G1];
+    // global loads of rows r0 .. r1-1 (of the G1 of each first-pass group the
+    // thread takes) of one group of columns into v, bit-reversed order within
+    // a first-pass group; a wave-uniform base and 32-bit offsets (a field's
+    // spectra are far below 2^32 elements).  Threads past the group's last
+    // column read that column again and store nothing.
+    auto load = [&](const PipeItem &it, auto r0, auto r1) {
+        const float2 *col = g.spec + it.off;
+        const uint32_t kxp = (uint32_t)it.kxp, cl = (uint32_t)min(c, it.ncol - 1);
+#pragma unroll
+        for (int q = 0; q < NG1; ++q) {
+            const int g1 = (tid + q * NT) >> LGC;
+            const uint32_t o0 = (uint32_t)bitrev(g1, LG - R1) * kxp + cl;
+#pragma unroll
+            for (int r = decltype(r0)::value; r < decltype(r1)::value; ++r)
+                v[q][rev_bits(r, R1)] = col[o0 + ((uint32_t)r << (LG - R1)) * kxp];
+        }
+    };
+    using Zero = std::integral_constant<int, 0>;
+    using Half = std::integral_constant<int, G1 / 2>;
+    using All = std::integral_constant<int, G1>;
+
+    PipeItem cur = sched[blockIdx.x];
+    if (cur.ncol <= 0) return;
+    load(cur, Zero{}, All{});
+    for (int it = 0;; ++it) {
+        __syncthreads();  // the previous item's last pass has read LDS
+        // first pass: stages 1 .. R1 (h = 1, so every twiddle is a fixed root)
+#pragma unroll
+        for (int q = 0; q < NG1; ++q) {
+            const int g1 = (tid + q * NT) >> LGC;
+            group_butterflies<R1, false, false>(v[q], make_float2(1.f, 0.f));
+#pragma unroll
+            for (int j = 0; j < G1; ++j) lds[lds_slot<true>((((g1 << R1) + j) << LGC) + c)] = v[q][j];
+        }
+        const PipeItem next = it + 1 < niter ? sched[(it + 1) * gridDim.x + blockIdx.x]
+                                             : PipeItem{0, 0, 0};
+        // the next item's loads, half before the middle pass and half after
+        // it
+        if (next.ncol > 0) load(next, Zero{}, Half{});
+        __syncthreads();
+        // middle pass: stages S2 .. S2 + R2 - 1, as fused_pass on the
+        // interleaved layout
+        // (one group at a time: interleaving two would need twice the
+        // registers; the twiddles rotate so that the one in use is tw2[0])
+#pragma unroll 1
+        for (int i = 0; i < NG2; ++i) {
+            const int idx = tid + i * NT, gg = idx >> LGC, l = idx & (CB - 1);
+            const int k = gg & (H2 - 1);
+            const int e0 = ((((gg >> (S2 - 1)) << (S2 - 1 + R2)) + k) << LGC) + l;
+            float2 x[G2];
+#pragma unroll
+            for (int j = 0; j < G2; ++j) x[j] = lds[lds_slot<true>(e0 + ((j * H2) << LGC))];
+            group_butterflies<R2, false, false>(x, tw2[0]);
+#pragma unroll
+            for (int j = 0; j < G2; ++j) lds[lds_slot<true>(e0 + ((j * H2) << LGC))] = x[j];
+            rotate_left(tw2);
+        }
+        if (next.ncol > 0) load(next, Half{}, All{});
+        __syncthreads();
+        // last pass: stages LG - R3 + 1 .. LG, groups k < H3 of elements
+        // k + j H3, which are in natural order when they leave it
+        {
+            float2 *out = (g.arg < 0 ? g.spec : g.stash + (int64_t)g.arg * g.stash_stride) + cur.off;
+            const uint32_t kxp = (uint32_t)cur.kxp;
+#pragma unroll 1
+            for (int i = 0; i < NG3; ++i) {
+                const int idx = tid + i * NT, k = idx >> LGC, cc = idx & (CB - 1);
+                float2 x[G3];
+#pragma unroll
+                for (int j = 0; j < G3; ++j) x[j] = lds[lds_slot<true>(((k + j * H3) << LGC) + cc)];
+                group_butterflies<R3, false, false>(x, tw3[0]);
+                rotate_left(tw3);
+                if (cc < cur.ncol) {
+                    const uint32_t o0 = (uint32_t)k * kxp + (uint32_t)cc;
+#pragma unroll
+                    for (int j = 0; j < G3; ++j) out[o0 + (uint32_t)(j * H3) * kxp] = x[j];
+                }
+            }
+        }
+        if (next.ncol <= 0) break;
+        cur = next;
     }
 }
 
@@ -607,6 +799,40 @@ hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nite
     else
         hipLaunchKernelGGL(corr_cols_kernel<kFftThreads>, dim3(nitems), dim3(kFftThreads),
                            lds_bytes, s, g);
+    return hipGetLastError();
+}
+
+bool corr_cols_pipe_supported(int lg) { return lg >= 9 && lg <= 12; }
+
+int corr_cols_pipe_lds_bytes(int lg)
+{
+    const int n = 1 << lg, cb = std::min(16, 16384 / n);
+    return (lds_slot<true>(n * cb - 1) + 1) * (int)sizeof(float2);
+}
+
+hipError_t launch_corr_cols_pipe(const DeviceView &v, const PipeItem *sched, int niter, int grid,
+                                 int lg, int slot, hipStream_t s)
+{
+    CorrArgs g = make_args(v, nullptr, 0);
+    g.arg = slot;
+    const int lds = corr_cols_pipe_lds_bytes(lg);
+    const dim3 gr(grid), bl(cols_pipe_threads(lg));
+    switch (lg) {
+    case 9:
+        hipLaunchKernelGGL((corr_cols_pipe_kernel<9, 3, 3, 3>), gr, bl, lds, s, g, sched, niter);
+        break;
+    case 10:
+        hipLaunchKernelGGL((corr_cols_pipe_kernel<10, 4, 3, 3>), gr, bl, lds, s, g, sched, niter);
+        break;
+    case 11:
+        hipLaunchKernelGGL((corr_cols_pipe_kernel<11, 4, 4, 3>), gr, bl, lds, s, g, sched, niter);
+        break;
+    case 12:
+        hipLaunchKernelGGL((corr_cols_pipe_kernel<12, 4, 4, 4>), gr, bl, lds, s, g, sched, niter);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

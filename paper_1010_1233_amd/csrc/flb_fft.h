@@ -41,7 +41,7 @@ __device__ __forceinline__ float2 twiddle(const float2 *tw, int e, int lgn)
 // few banks; one pad slot every 16 and every 256 elements spreads every
 // access pattern of the row kernel over all banks (two-way at most for
 // 8-byte elements).  Column layouts interleave lines and need no padding.
-template <bool PAD> __device__ __forceinline__ int lds_slot(int i)
+template <bool PAD> __host__ __device__ __forceinline__ int lds_slot(int i)
 {
     return PAD ? i + (i >> 4) + (i >> 8) : i;
 }
@@ -78,18 +78,68 @@ __device__ __forceinline__ float2 rotate(float2 w)
     }
 }
 
+// The butterflies of one group of 2^R elements of a pass of R fused radix-2
+// stages (below), in registers.  Sub-stage u pairs j and j + 2^u with twiddle
+// exp(-2 pi i (k + m h) / (h 2^(u+1))), m = j mod 2^u; all are w^(2^(R-1-u))
+// times a fixed 2^(u+1)-th root of unity, with w = exp(-/+ 2 pi i k / (h 2^R))
+// (the sign of the inverse transform already applied).  Decimation in time
+// (DIF false) runs u = 0 .. R-1 and multiplies the second operand by the
+// twiddle before the sum and difference; decimation in frequency (DIF true)
+// runs u = R-1 .. 0 and multiplies the difference.
+template <int R, bool INV, bool DIF>
+__device__ __forceinline__ void group_butterflies(float2 (&v)[1 << R], float2 w)
+{
+    constexpr int G = 1 << R;
+    float2 base[4];
+    if constexpr (R == 4) {
+        base[3] = w;
+        base[2] = cmul(w, w);
+        base[1] = cmul(base[2], base[2]);
+        base[0] = cmul(base[1], base[1]);
+    } else {
+        base[R - 1] = w;
+        if constexpr (R >= 2) base[R - 2] = cmul(w, w);
+        if constexpr (R >= 3) base[0] = cmul(base[1], base[1]);
+    }
+#pragma unroll
+    for (int uu = 0; uu < R; ++uu) {
+        const int u = DIF ? R - 1 - uu : uu;
+        const int half = 1 << u;
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            if (j & half) continue;
+            const int m = j & (half - 1);
+            float2 t;
+            if (u == 0) t = base[0];
+            else if (u == 1) t = m ? rotate<1, 1, INV>(base[1]) : base[1];
+            else if (u == 2)
+                t = m == 0 ? base[2] : m == 1 ? rotate<2, 1, INV>(base[2])
+                  : m == 2 ? rotate<2, 2, INV>(base[2]) : rotate<2, 3, INV>(base[2]);
+            else
+                t = m == 0 ? base[3] : m == 1 ? rotate<3, 1, INV>(base[3])
+                  : m == 2 ? rotate<3, 2, INV>(base[3]) : m == 3 ? rotate<3, 3, INV>(base[3])
+                  : m == 4 ? rotate<3, 4, INV>(base[3]) : m == 5 ? rotate<3, 5, INV>(base[3])
+                  : m == 6 ? rotate<3, 6, INV>(base[3]) : rotate<3, 7, INV>(base[3]);
+            if constexpr (DIF) {
+                const float2 a = v[j], c = v[j + half];
+                v[j] = make_float2(a.x + c.x, a.y + c.y);
+                v[j + half] = cmul(t, make_float2(a.x - c.x, a.y - c.y));
+            } else {
+                const float2 x = cmul(t, v[j + half]);
+                v[j + half] = make_float2(v[j].x - x.x, v[j].y - x.y);
+                v[j] = make_float2(v[j].x + x.x, v[j].y + x.y);
+            }
+        }
+    }
+}
+
 // One pass of R fused radix-2 stages s .. s+R-1 (1-based; stage s pairs
 // elements h = 2^(s-1) apart) over `nlines` lines of length 2^lg; element e
 // of line l at slot(l * ls + e * es).  A thread takes the 2^R elements
-// b + k + j h (j < 2^R) of one group.  Sub-stage u pairs j and j + 2^u with
-// twiddle exp(-2 pi i (k + m h) / (h 2^(u+1))), m = j mod 2^u; all are
-// w^(2^(R-1-u)) times a fixed 2^(u+1)-th root of unity, with
-// w = exp(-2 pi i k / (h 2^R)) the one value read from the table.
-// Decimation in time (DIF false) runs u = 0 .. R-1 and multiplies the
-// second operand by the twiddle before the sum and difference; decimation
-// in frequency (DIF true) runs u = R-1 .. 0 and multiplies the difference.
-// With `post`, every output of the pass is multiplied by post[e] (e the
-// element's index in its line).
+// b + k + j h (j < 2^R) of one group and runs group_butterflies on them with
+// w = exp(-2 pi i k / (h 2^R)), the one value read from the table.  With
+// `post`, every output of the pass is multiplied by post[e] (e the element's
+// index in its line).
 template <int R, bool PAD, bool INV, bool DIF = false>
 __device__ __forceinline__ void fused_pass(float2 *buf, int lg, int s, int nlines, int ls, int es,
                                          const float2 *tw, const float2 *post = nullptr)
@@ -132,47 +182,7 @@ __device__ __forceinline__ void fused_pass(float2 *buf, int lg, int s, int nline
         for (int j = 0; j < G; ++j) v[j] = buf[slot[j]];
         float2 w = tw[k << (kTwLog - (s + R - 1))];
         if (INV) w.y = -w.y;
-        float2 base[4];
-        if constexpr (R == 4) {
-            base[3] = w;
-            base[2] = cmul(w, w);
-            base[1] = cmul(base[2], base[2]);
-            base[0] = cmul(base[1], base[1]);
-        } else {
-            base[R - 1] = w;
-            if constexpr (R >= 2) base[R - 2] = cmul(w, w);
-            if constexpr (R >= 3) base[0] = cmul(base[1], base[1]);
-        }
-#pragma unroll
-        for (int uu = 0; uu < R; ++uu) {
-            const int u = DIF ? R - 1 - uu : uu;
-            const int half = 1 << u;
-#pragma unroll
-            for (int j = 0; j < G; ++j) {
-                if (j & half) continue;
-                const int m = j & (half - 1);
-                float2 t;
-                if (u == 0) t = base[0];
-                else if (u == 1) t = m ? rotate<1, 1, INV>(base[1]) : base[1];
-                else if (u == 2)
-                    t = m == 0 ? base[2] : m == 1 ? rotate<2, 1, INV>(base[2])
-                      : m == 2 ? rotate<2, 2, INV>(base[2]) : rotate<2, 3, INV>(base[2]);
-                else
-                    t = m == 0 ? base[3] : m == 1 ? rotate<3, 1, INV>(base[3])
-                      : m == 2 ? rotate<3, 2, INV>(base[3]) : m == 3 ? rotate<3, 3, INV>(base[3])
-                      : m == 4 ? rotate<3, 4, INV>(base[3]) : m == 5 ? rotate<3, 5, INV>(base[3])
-                      : m == 6 ? rotate<3, 6, INV>(base[3]) : rotate<3, 7, INV>(base[3]);
-                if constexpr (DIF) {
-                    const float2 a = v[j], c = v[j + half];
-                    v[j] = make_float2(a.x + c.x, a.y + c.y);
-                    v[j + half] = cmul(t, make_float2(a.x - c.x, a.y - c.y));
-                } else {
-                    const float2 x = cmul(t, v[j + half]);
-                    v[j + half] = make_float2(v[j].x - x.x, v[j].y - x.y);
-                    v[j] = make_float2(v[j].x + x.x, v[j].y + x.y);
-                }
-            }
-        }
+        group_butterflies<R, INV, DIF>(v, w);
         if (post) {
 #pragma unroll
             for (int j = 0; j < G; ++j) v[j] = cmul(v[j], post[b + k + j * h]);

@@ -164,6 +164,21 @@ constexpr int kColsLargeElems = 16384;
 constexpr int kColsLargeThreads = 1024;
 hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int slot,
                             bool large, int lds_bytes, hipStream_t s);
+// Column transforms of power-of-two lengths 2^lg, 9 <= lg <= 12, in
+// persistent blocks: sched holds niter x grid groups of columns (the group
+// of block b in round it at it * grid + b), each of 16384 / 2^lg (at most
+// 16) adjacent columns of one field: the complex offset of its first
+// column in the spectra (and in a stash slot), the row pitch kxp, and the
+// number of columns it has (0: no group).  `slot` as for launch_corr_cols.
+struct PipeItem {
+    int64_t off;
+    int32_t kxp;
+    int32_t ncol;
+};
+bool corr_cols_pipe_supported(int lg);
+int corr_cols_pipe_lds_bytes(int lg);
+hipError_t launch_corr_cols_pipe(const DeviceView &v, const PipeItem *sched, int niter, int grid,
+                                 int lg, int slot, hipStream_t s);
 // samples per read-modify-write of the FP64 sums (kDeferK - 1 stash slots,
 // each the size of the spectra: 5 GB at 4096^2).  4096^2 whole path: 87.5
 // GLUPS with 16 against 86.4 with 8, the sums' read-modify-write being most

@@ -128,6 +128,14 @@ struct flb {
     int n_cols_m = 0, n_cols_lm = 0, n_rows_m = 0;
     CorrItem *d_rows_blue = nullptr;  // rows of lattices with Bluestein row transforms
     int n_rows_blue = 0;
+    // power-of-two columns of 512..4096 points: persistent launches of the
+    // pipelined column kernel, one per work length and field set, each with
+    // its host-made schedule
+    struct PipeLaunch {
+        int lg = 0, grid = 0, niter = 0;
+        PipeItem *d_sched = nullptr;
+    };
+    std::vector<PipeLaunch> pipe[2];
     // deferred accumulation: samples stash their spectra (the column
     // transform's output) in kDeferK - 1 slots and every kDeferK-th one adds
     // the products of all of them at once; `pending` counts the stashed
@@ -433,6 +441,43 @@ namespace {
 // lattices' path 56.2 or 56.6 against 57.5.
 constexpr int kColsLargeMin = 1024;
 
+// Schedule of a persistent launch of `grid` blocks (a multiple of 8) over
+// `items`, whole groups first and partial ones (fewer columns) last: each
+// block takes items round after round, sched[it * grid + b].  Block b runs
+// on XCD b % 8, so every XCD gets a contiguous run of the whole groups
+// (neighbouring columns share cache lines in its L2) and every block the
+// same number of them; the remainder, the partial groups where possible,
+// goes one per block into a last round.
+std::vector<CorrItem> persistent_schedule(const std::vector<CorrItem> &items, int grid,
+                                          int &niter)
+{
+    const int F = (int)items.size(), nslot = grid / 8;
+    const int q = F / grid, rem = F - q * grid;
+    niter = q + (rem > 0 ? 1 : 0);
+    std::vector<CorrItem> sched((size_t)niter * grid, CorrItem{-1, 0, 0, 0});
+    for (int x = 0; x < 8; ++x)
+        for (int j = 0; j < q * nslot; ++j)
+            sched[(size_t)(j / nslot) * grid + x + 8 * (j % nslot)] = items[(size_t)x * q * nslot + j];
+    for (int r = 0; r < rem; ++r) sched[(size_t)q * grid + r] = items[(size_t)q * grid + r];
+    return sched;
+}
+
+// The pipelined column kernel's form of scheduled column groups: offset of
+// the first column in the spectra, row pitch and number of columns.
+std::vector<PipeItem> pipe_items(const flb_t *h, const std::vector<CorrItem> &sched)
+{
+    std::vector<PipeItem> out(sched.size(), PipeItem{0, 0, 0});
+    for (size_t i = 0; i < sched.size(); ++i) {
+        const CorrItem &it = sched[i];
+        if (it.lattice < 0) continue;
+        const LatticeParams &P = h->params[it.lattice];
+        out[i].off = P.spec_base + (int64_t)it.a * P.ny * P.kxp + it.b;
+        out[i].kxp = P.kxp;
+        out[i].ncol = std::min(1 << it.c, P.nkx - it.b);
+    }
+    return out;
+}
+
 int setup_correlators(flb_t *h)
 {
     if (h->corr_ready) return FLB_OK;
@@ -485,6 +530,7 @@ int setup_correlators(flb_t *h)
     h->plans = lt.plans;
     std::vector<CorrItem> rows, cols, cols_l, accum, flds, cols_m, cols_lm, rows_m;
     std::vector<CorrItem> rows_blue, flush;
+    std::map<int, std::vector<CorrItem>> pipe_full[2], pipe_part[2];  // per field set and lg
     for (size_t l = 0; l < h->params.size(); ++l) {
         const LatticeParams &P = h->params[l];
         if (h->moments) {
@@ -504,11 +550,24 @@ int setup_correlators(flb_t *h)
             if (h->moments)
                 for (int sig = 0; sig < 3; ++sig) rows_m.push_back({(int32_t)l, y, rb, sig});
         }
-        for (int f = 0; f < h->nfld; ++f)
-            for (int c0 = 0; c0 < P.nkx; c0 += 1 << P.col_lgcb) {
-                if (f < kFields) (P.col_large ? cols_l : cols).push_back({(int32_t)l, f, c0, P.col_lgcb});
-                (P.col_large ? cols_lm : cols_m).push_back({(int32_t)l, f, c0, P.col_lgcb});
-            }
+        const LinePlan &Ly = lt.plans[P.line_y];
+        if (!Ly.bluestein && corr_cols_pipe_supported(Ly.log2m)) {
+            // whole groups and the partial last group of each field apart
+            const int cb = std::min(16, 16384 / Ly.m), lgc = log2i(cb);
+            for (int f = 0; f < h->nfld; ++f)
+                for (int c0 = 0; c0 < P.nkx; c0 += cb) {
+                    const CorrItem it{(int32_t)l, f, c0, lgc};
+                    const bool whole = c0 + cb <= P.nkx;
+                    if (f < kFields) (whole ? pipe_full[0] : pipe_part[0])[Ly.log2m].push_back(it);
+                    (whole ? pipe_full[1] : pipe_part[1])[Ly.log2m].push_back(it);
+                }
+        } else {
+            for (int f = 0; f < h->nfld; ++f)
+                for (int c0 = 0; c0 < P.nkx; c0 += 1 << P.col_lgcb) {
+                    if (f < kFields) (P.col_large ? cols_l : cols).push_back({(int32_t)l, f, c0, P.col_lgcb});
+                    (P.col_large ? cols_lm : cols_m).push_back({(int32_t)l, f, c0, P.col_lgcb});
+                }
+        }
         const int64_t nk = (int64_t)P.ny * P.nkx;
         for (int64_t k0 = 0; k0 < nk; k0 += kThreads) {
             accum.push_back({(int32_t)l, (int32_t)k0, 0, 0});
@@ -534,7 +593,41 @@ int setup_correlators(flb_t *h)
     h->n_cols_lm = (int)cols_lm.size();
     h->n_rows_m = (int)rows_m.size();
     h->n_flush = (int)flush.size();
-    h->defer = !cols.empty() || !cols_l.empty();
+    int ncu = 0;
+    FLB_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
+    for (int set = 0; set < 2; ++set) {
+        for (auto &pl : h->pipe[set])
+            if (pl.d_sched) (void)hipFree(pl.d_sched);
+        h->pipe[set].clear();
+        if (set == 1 && !h->moments) continue;
+        for (auto &kv : pipe_full[set]) {
+            std::vector<CorrItem> items = kv.second;
+            const auto &part = pipe_part[set][kv.first];
+            items.insert(items.end(), part.begin(), part.end());
+            // one block resident per CU: 140 KB of LDS from 1024 points on,
+            // the registers of 1024 threads at 512 points
+            int grid = std::max(8, ncu / 8 * 8);
+            grid = std::min(grid, ((int)items.size() + 7) / 8 * 8);
+            flb_t::PipeLaunch pl;
+            pl.lg = kv.first;
+            pl.grid = grid;
+            int rc0 = upload(&pl.d_sched, pipe_items(h, persistent_schedule(items, grid, pl.niter)));
+            if (rc0) return rc0;
+            h->pipe[set].push_back(pl);
+        }
+        for (auto &kv : pipe_part[set])  // lengths with partial groups only
+            if (!pipe_full[set].count(kv.first)) {
+                const std::vector<CorrItem> &items = kv.second;
+                flb_t::PipeLaunch pl;
+                pl.lg = kv.first;
+                pl.grid = ((int)items.size() + 7) / 8 * 8;
+                int rc0 = upload(&pl.d_sched,
+                                 pipe_items(h, persistent_schedule(items, pl.grid, pl.niter)));
+                if (rc0) return rc0;
+                h->pipe[set].push_back(pl);
+            }
+    }
+    h->defer = !cols.empty() || !cols_l.empty() || !h->pipe[0].empty();
     h->pending = 0;
     h->n_rows = (int)rows.size();
     h->n_cols = (int)cols.size();
@@ -592,6 +685,8 @@ int enqueue_sample(flb_t *h, hipStream_t s, hipEvent_t ev_read = nullptr)
         const int slot = stash ? h->pending : -1;
         if (ng) FLB_HIP(launch_corr_cols(v, cg, ng, slot, false, h->cols_lds, s));
         if (nl) FLB_HIP(launch_corr_cols(v, cl, nl, slot, true, h->cols_l_lds, s));
+        for (const auto &pl : h->pipe[set])
+            FLB_HIP(launch_corr_cols_pipe(v, pl.d_sched, pl.niter, pl.grid, pl.lg, slot, s));
         if (h->n_accum && !stash)
             FLB_HIP(launch_corr_accum(v, h->d_accum, h->n_accum, set,
                                       (!set && h->defer) ? h->pending : 0, s));
@@ -890,6 +985,9 @@ void flb_destroy(flb_t *h)
                     h->d_rows_blue, h->d_stash, h->d_flush, h->d_items2};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (auto &set : h->pipe)
+        for (auto &pl : set)
+            if (pl.d_sched) (void)hipFree(pl.d_sched);
     for (hipEvent_t e : {h->ev, h->ev_fork, h->ev_read, h->ev_done})
         if (e) (void)hipEventDestroy(e);
     for (auto *v : {&h->timed, &h->spare_events})
