@@ -121,8 +121,12 @@ __device__ __forceinline__ void store_row_spectra(const float2 *lds, const Latti
     const int nx = P.nx, nkx = P.nkx, kxp = P.kxp;
     const int64_t fstride = (int64_t)P.ny * kxp;
     float2 *sa = spec + fa * fstride, *sb = sa + fstride;
+    // line l = e / kxp by a float reciprocal: (e + 1/2) / kxp stays at least
+    // 1/(2 kxp) away from an integer, far beyond the rounding of the product
+    // (e < 8192, kxp < 4096)
+    const float rkxp = 1.0f / (float)kxp;
     for (int e = threadIdx.x; e < nl * kxp; e += kFftThreads) {
-        const int l = e / kxp, k = e - l * kxp;
+        const int l = (int)(((float)e + 0.5f) * rkxp), k = e - l * kxp;
         const int64_t row = (int64_t)(y0 + l) * kxp + k;
         if (k >= nkx) {  // padding columns: keep them finite
             sa[row] = make_float2(0.f, 0.f);
@@ -200,7 +204,8 @@ __global__ __launch_bounds__(kFftThreads, 6) void corr_rows_kernel(CorrArgs g)
 
     const float2 *chirp = g.tables + L.chirp_off;
     float2 *spec = g.spec + P.spec_base;
-    const float jx0 = P.rho0 * P.u0x, jy0 = P.rho0 * P.u0y;
+    const float rho0 = P.rho0, u0x = P.u0x, u0y = P.u0y;
+    const float jx0 = rho0 * u0x, jy0 = rho0 * u0y;
 #pragma unroll 1
     for (int sig = 0; sig < 3; ++sig) {
         // (the block sum and every earlier signal's reads of LDS are behind a
@@ -210,23 +215,24 @@ __global__ __launch_bounds__(kFftThreads, 6) void corr_rows_kernel(CorrArgs g)
         // in registers through the transforms
         int tid = (int)threadIdx.x;
         asm volatile("" : "+v"(tid));
+        // (no branch per element: sites past a row's end, where the line
+        // is zero padding, are set to zero by a select)
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const int e = tid + j * kFftThreads, l = e >> lg, x = e & (m - 1);
-            if (e >= ne) break;
-            float2 v = make_float2(0.f, 0.f);
-            if (x < nx) {
-                if (sig == 0) {
-                    v = make_float2(jx[j] - jx0, jy[j] - jy0);
-                } else if (sig == 1) {
-                    const float ir = 1.0f / (P.rho0 + r[j]);
-                    v = make_float2(jx[j] * ir - P.u0x, jy[j] * ir - P.u0y);
-                } else {
-                    v.x = r[j];
-                }
-                if (BLUE) v = cmul(v, chirp[x]);
+            float2 v;
+            if (sig == 0) {
+                v = make_float2(jx[j] - jx0, jy[j] - jy0);
+            } else if (sig == 1) {
+                // u = j / rho with the hardware reciprocal (1 ulp)
+                const float ir = __builtin_amdgcn_rcpf(rho0 + r[j]);
+                v = make_float2(fmaf(jx[j], ir, -u0x), fmaf(jy[j], ir, -u0y));
+            } else {
+                v = make_float2(r[j], 0.f);
             }
-            lds[lds_slot<true>(l * m + (BLUE ? x : bitrev(x, lg)))] = v;
+            if (BLUE) v = cmul(v, chirp[x < nx ? x : 0]);
+            if (x >= nx) v = make_float2(0.f, 0.f);
+            if (e < ne) lds[lds_slot<true>(l * m + (BLUE ? x : bitrev(x, lg)))] = v;
         }
         __syncthreads();
         if (BLUE) lds_bluestein_dft<true, false>(lds, L, nl, m, 1, g.tables);
@@ -601,7 +607,7 @@ __global__ __launch_bounds__(cols_pipe_threads(LG)) void corr_cols_pipe_kernel(
 #pragma unroll
         for (int q = 0; q < NG1; ++q) {
             const int g1 = (tid + q * NT) >> LGC;
-            group_butterflies<R1, false, false>(v[q], make_float2(1.f, 0.f));
+            group_butterflies<R1, false, false, true>(v[q], make_float2(1.f, 0.f));
 #pragma unroll
             for (int j = 0; j < G1; ++j) lds[lds_slot<true>((((g1 << R1) + j) << LGC) + c)] = v[q][j];
         }

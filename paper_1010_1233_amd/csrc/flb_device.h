@@ -7,9 +7,16 @@
 
 namespace flbdev {
 
+// a ^ b ^ c in one instruction: gfx950's three-input bit operation with the
+// truth table of a three-way xor (bit abc of 0x96 is a ^ b ^ c)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, SC'11).  The key
 // is wave-uniform, so its schedule lives in scalar registers; each round is
-// two 32x32->64 multiplies and two three-way xors.
+// two 32x32->64 multiplies and two three-way xors (one instruction each).
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
@@ -18,7 +25,7 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
         const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
         const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        c = make_uint4(xor3(hi1, c.y, k0), lo1, xor3(hi0, c.w, k1), lo0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }

@@ -86,10 +86,48 @@ __device__ __forceinline__ float2 rotate(float2 w)
 // (DIF false) runs u = 0 .. R-1 and multiplies the second operand by the
 // twiddle before the sum and difference; decimation in frequency (DIF true)
 // runs u = R-1 .. 0 and multiplies the difference.
-template <int R, bool INV, bool DIF>
+// UNIT: w = 1 (the first pass of a decimation in time, the last of a
+// decimation in frequency, k = 0): every twiddle is a fixed root of unity and
+// is applied to the operand directly by rotate (multiplications by 1 and -i
+// cost nothing, by the eighth roots two multiplies).
+template <int R, bool INV, bool DIF, bool UNIT = false>
 __device__ __forceinline__ void group_butterflies(float2 (&v)[1 << R], float2 w)
 {
     constexpr int G = 1 << R;
+    if constexpr (UNIT) {
+        (void)w;
+#pragma unroll
+        for (int uu = 0; uu < R; ++uu) {
+            const int u = DIF ? R - 1 - uu : uu;
+            const int half = 1 << u;
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                if (j & half) continue;
+                const int m = j & (half - 1);
+                auto rot = [&](float2 x) -> float2 {
+                    if (m == 0) return x;
+                    if (u == 1) return rotate<1, 1, INV>(x);
+                    if (u == 2)
+                        return m == 1 ? rotate<2, 1, INV>(x) : m == 2 ? rotate<2, 2, INV>(x)
+                                                                     : rotate<2, 3, INV>(x);
+                    return m == 1 ? rotate<3, 1, INV>(x) : m == 2 ? rotate<3, 2, INV>(x)
+                         : m == 3 ? rotate<3, 3, INV>(x) : m == 4 ? rotate<3, 4, INV>(x)
+                         : m == 5 ? rotate<3, 5, INV>(x) : m == 6 ? rotate<3, 6, INV>(x)
+                                                                 : rotate<3, 7, INV>(x);
+                };
+                if constexpr (DIF) {
+                    const float2 a = v[j], c = v[j + half];
+                    v[j] = make_float2(a.x + c.x, a.y + c.y);
+                    v[j + half] = rot(make_float2(a.x - c.x, a.y - c.y));
+                } else {
+                    const float2 x = rot(v[j + half]);
+                    v[j + half] = make_float2(v[j].x - x.x, v[j].y - x.y);
+                    v[j] = make_float2(v[j].x + x.x, v[j].y + x.y);
+                }
+            }
+        }
+        return;
+    }
     float2 base[4];
     if constexpr (R == 4) {
         base[3] = w;
@@ -140,7 +178,7 @@ __device__ __forceinline__ void group_butterflies(float2 (&v)[1 << R], float2 w)
 // w = exp(-2 pi i k / (h 2^R)), the one value read from the table.  With
 // `post`, every output of the pass is multiplied by post[e] (e the element's
 // index in its line).
-template <int R, bool PAD, bool INV, bool DIF = false>
+template <int R, bool PAD, bool INV, bool DIF = false, bool UNIT = false>
 __device__ __forceinline__ void fused_pass(float2 *buf, int lg, int s, int nlines, int ls, int es,
                                          const float2 *tw, const float2 *post = nullptr)
 {
@@ -180,9 +218,12 @@ __device__ __forceinline__ void fused_pass(float2 *buf, int lg, int s, int nline
         float2 v[G];
 #pragma unroll
         for (int j = 0; j < G; ++j) v[j] = buf[slot[j]];
-        float2 w = tw[k << (kTwLog - (s + R - 1))];
-        if (INV) w.y = -w.y;
-        group_butterflies<R, INV, DIF>(v, w);
+        float2 w = make_float2(1.f, 0.f);
+        if constexpr (!UNIT) {
+            w = tw[k << (kTwLog - (s + R - 1))];
+            if (INV) w.y = -w.y;
+        }
+        group_butterflies<R, INV, DIF, UNIT>(v, w);
         if (post) {
 #pragma unroll
             for (int j = 0; j < G; ++j) v[j] = cmul(v[j], post[b + k + j * h]);
@@ -198,7 +239,18 @@ __device__ __forceinline__ void fused_pass(float2 *buf, int lg, int s, int nline
 template <bool PAD, bool INV, int RMAX = 3>
 __device__ __forceinline__ void lds_fft_dit(float2 *buf, int lg, int nlines, int ls, int es, const float2 *tw)
 {
+    if (lg < 1) return;
+    // the first pass (stages 1 .. r, k = 0) has fixed twiddles only
     int s = 1;
+    {
+        const int r = lg < RMAX ? lg : RMAX;
+        if (RMAX >= 4 && r >= 4) fused_pass<(RMAX >= 4 ? 4 : 3), PAD, INV, false, true>(buf, lg, 1, nlines, ls, es, tw);
+        else if (r == 3) fused_pass<3, PAD, INV, false, true>(buf, lg, 1, nlines, ls, es, tw);
+        else if (r == 2) fused_pass<2, PAD, INV, false, true>(buf, lg, 1, nlines, ls, es, tw);
+        else fused_pass<1, PAD, INV, false, true>(buf, lg, 1, nlines, ls, es, tw);
+        s += r;
+        __syncthreads();
+    }
     while (s <= lg) {
         const int r = lg - s + 1;
         if constexpr (RMAX >= 4) {
@@ -234,18 +286,26 @@ __device__ __forceinline__ void lds_fft_dif(float2 *buf, int lg, int nlines, int
     while (top >= 1) {
         const int r = top >= RMAX ? RMAX : top;
         const int s = top - r + 1;
-        const float2 *p = s == 1 ? post : nullptr;
+        if (s == 1) {  // the last pass: k = 0, fixed twiddles only
+            if (RMAX >= 4 && r == 4)
+                fused_pass<(RMAX >= 4 ? 4 : 3), PAD, false, true, true>(buf, lg, 1, nlines, ls, es, tw, post);
+            else if (r == 3) fused_pass<3, PAD, false, true, true>(buf, lg, 1, nlines, ls, es, tw, post);
+            else if (r == 2) fused_pass<2, PAD, false, true, true>(buf, lg, 1, nlines, ls, es, tw, post);
+            else fused_pass<1, PAD, false, true, true>(buf, lg, 1, nlines, ls, es, tw, post);
+            __syncthreads();
+            break;
+        }
         if constexpr (RMAX >= 4) {
             if (r == 4) {
-                fused_pass<4, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
+                fused_pass<4, PAD, false, true>(buf, lg, s, nlines, ls, es, tw);
                 top -= 4;
                 __syncthreads();
                 continue;
             }
         }
-        if (r == 3) fused_pass<3, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
-        else if (r == 2) fused_pass<2, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
-        else fused_pass<1, PAD, false, true>(buf, lg, s, nlines, ls, es, tw, p);
+        if (r == 3) fused_pass<3, PAD, false, true>(buf, lg, s, nlines, ls, es, tw);
+        else if (r == 2) fused_pass<2, PAD, false, true>(buf, lg, s, nlines, ls, es, tw);
+        else fused_pass<1, PAD, false, true>(buf, lg, s, nlines, ls, es, tw);
         top -= r;
         __syncthreads();
     }
