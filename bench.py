@@ -151,6 +151,14 @@ def time_step_kernel(torch, g, stream, n):
     return e0.elapsed_time(e1) / n
 
 
+def steady_step_ms(torch, g, stream, n=50, warm=100, reps=3):
+    """Step time (ms) of a handle alone: `warm` untimed steps (the device
+    leaves the power state of whatever ran before), then the fastest of
+    `reps` runs of n steps."""
+    time_step_kernel(torch, g, stream, warm)
+    return min(time_step_kernel(torch, g, stream, n) for _ in range(reps))
+
+
 def batched_form(torch, flb, stream, specs, storage, periods=16):
     """Whole path (graph-replayed periods of SAMPLE_EVERY steps + a sample)
     and step-only rates of one batched handle."""
@@ -173,8 +181,7 @@ def batched_form(torch, flb, stream, specs, storage, periods=16):
     e1.record(stream)
     e1.synchronize()
     ms_period = e0.elapsed_time(e1) / periods
-    time_step_kernel(torch, b, stream, 100)  # untimed: leave the idle power state
-    step_ms = time_step_kernel(torch, b, stream, 50)
+    step_ms = steady_step_ms(torch, b, stream)
     lf = launch_figures(b, sites, step_ms)
     shape = list(shape) + [list(b.time_blocking())]
     b.close()
@@ -403,8 +410,7 @@ def main():
     # untimed steps that the device has left the power state of the idle
     # host-side read above
     with torch.cuda.stream(stream):
-        time_step_kernel(torch, g, stream, 20 * SAMPLE_EVERY)
-        iso_ms = time_step_kernel(torch, g, stream, 10 * SAMPLE_EVERY)
+        iso_ms = steady_step_ms(torch, g, stream, n=10 * SAMPLE_EVERY, warm=20 * SAMPLE_EVERY)
     iso = launch_figures(g, V, iso_ms)
 
     out = {
@@ -464,21 +470,20 @@ def main():
                 h, _ = make_lattice(flb, workloads, args.workload, st)
                 h.set_stream(stream)
                 h.thermalize()
-                h.autotune(50)
-                time_step_kernel(torch, h, stream, 6)
-                ms = time_step_kernel(torch, h, stream, 50)
+                shape, _ = h.autotune(50)
+                ms = steady_step_ms(torch, h, stream)
                 lf = launch_figures(h, V, ms)
                 forms[st] = {"step_glups": V / (ms * 1e-3) / 1e9,
                              "steps_per_launch": lf["steps_per_launch"],
-                             "achieved_GBs": lf["achieved_GBs"]}
+                             "achieved_GBs": lf["achieved_GBs"],
+                             "launch_shape": list(shape) + [list(h.time_blocking())]}
                 h.close()
             cq = dict(workloads.CONFIGS[args.workload])
             h = flb.Lattice(cq["nx"], cq["ny"], cq["tau"], 0.0, rho0=cq["rho0"], u0=cq["u0"],
                             seed=cq["seed"], storage=args.storage)
             h.set_stream(stream)
             h.autotune(50)
-            time_step_kernel(torch, h, stream, 5)
-            ms = time_step_kernel(torch, h, stream, 50)
+            ms = steady_step_ms(torch, h, stream)
             forms["noise_off_" + args.storage] = {"step_glups": V / (ms * 1e-3) / 1e9}
             out["noise_overhead"] = iso_ms / ms - 1.0
             h.close()

@@ -53,6 +53,13 @@ struct alignas(16) LatticeParams {
     float inv_scale[9];
     float feq_scaled[9];      // feq * inv_scale
     float therm_amp[9];       // sqrt(mu rho0 w_i) for the thermal start
+    // 16-bit steps collide the stored scaled deviations q directly
+    // (d = s q + feq): class scales folded into the moment coefficients,
+    // the reference state's moments as offsets, w_i / s_i for the back
+    // transform (see collide_q)
+    float qcoef[11];
+    float qoff[9];
+    float qback[3];
     uint32_t stream_id;
     int32_t line_x;           // index of the x-direction line plan
     int32_t line_y;           // index of the y-direction line plan

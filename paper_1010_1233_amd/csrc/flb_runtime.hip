@@ -264,6 +264,31 @@ LatticeParams make_params(const flb_lattice_spec &s, uint32_t flags)
         P.feq_scaled[i] = P.feq[i] * P.inv_scale[i];
         P.therm_amp[i] = (float)std::sqrt(mu * s.rho0 * kW[i]);
     }
+    // collide_q's constants, from the FP32 values the codec uses:
+    // d_i = s_i q_i + F_i with s = scale, F = feq
+    {
+        double F[9];
+        for (int i = 0; i < 9; ++i) F[i] = P.feq[i];
+        const double s0 = P.scale[0], s1 = P.scale[1], s5 = P.scale[5];
+        const double Fa = F[1] + F[3], Fb = F[2] + F[4], Fc = F[5] + F[7], Fe = F[6] + F[8];
+        const double Fx = F[1] - F[3], Fy = F[2] - F[4], Fp = F[5] - F[7], Fm = F[6] - F[8];
+        const double coef[11] = {s0, s1, s5, 2.25 * s1, 9.0 * s5, 0.5 * s1, 2.0 * s5,
+                                 3.0 * s5, 1.5 * s1, 0.5 * s0, 0.0};
+        for (int k = 0; k < 11; ++k) P.qcoef[k] = (float)coef[k];
+        const double off[9] = {F[0] + Fa + Fb + Fc + Fe,                 // sum of F: delta rho
+                               Fx + Fp - Fm,                              // j_x
+                               Fy + Fp + Fm,                              // j_y
+                               2.25 * (Fa - Fb),                          // s3 = 3/2 M3
+                               9.0 * (Fc - Fe),                           // s4 = 3 M4
+                               0.5 * (Fa + Fb) + 2.0 * (Fc + Fe) - F[0],  // s5 = M5
+                               1.5 * (2.0 * (Fp - Fm) - Fx),              // s6
+                               1.5 * (2.0 * (Fp + Fm) - Fy),              // s7
+                               0.5 * F[0] + 2.0 * (Fc + Fe) - (Fa + Fb)}; // s8 = M8
+        for (int k = 0; k < 9; ++k) P.qoff[k] = (float)off[k];
+        P.qback[0] = (float)(kW[0] / s0);
+        P.qback[1] = (float)(kW[1] / s1);
+        P.qback[2] = (float)(kW[5] / s5);
+    }
     P.stream_id = s.stream_id;
     return P;
 }

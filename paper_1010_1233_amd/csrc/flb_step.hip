@@ -80,6 +80,85 @@ __device__ __forceinline__ void collide(float (&d)[9], const LatticeParams &P, c
     d[8] = fmaf(w5, (B - t4) + (P6 - Q7), d[8]);
 }
 
+// The same collision for the 16-bit formats, on the stored scaled
+// deviations q_i = (d_i - F_i) / s_i themselves (F the deviation of the
+// reference state f^0(rho0, u0), s_i = sqrt(mu rho0 w_i) one scale per
+// velocity class): every moment above is a linear function of the d_i, so
+// it is the class-scaled sum of the q_i plus the moment of F, and the
+// change of d_i, w_i sum_a m_i^a dM^a, is a change of q_i by w_i / s_i times
+// that sum.  No value is decoded to d or encoded back one by one.
+template <bool NOISE>
+__device__ __forceinline__ void collide_q(float (&q)[9], const LatticeParams &P,
+                                          const float (&z)[6])
+{
+    const float *C = P.qcoef, *K = P.qoff;
+    const float qa = q[1] + q[3], qb = q[2] + q[4];
+    const float qc = q[5] + q[7], qe = q[6] + q[8];
+    const float qab = qa + qb, qce = qc + qe;
+    const float qx = q[1] - q[3], qy = q[2] - q[4];
+    const float qp = q[5] - q[7], qm = q[6] - q[8];
+    const float pmm = qp - qm, ppm = qp + qm;
+    // C: s0, s1, s5, 9/4 s1, 9 s5, s1/2, 2 s5, 3 s5, 3/2 s1, s0/2
+    const float drho = fmaf(C[0], q[0], fmaf(C[1], qab, fmaf(C[2], qce, K[0])));
+    const float jx = fmaf(C[1], qx, fmaf(C[2], pmm, K[1]));
+    const float jy = fmaf(C[1], qy, fmaf(C[2], ppm, K[2]));
+    const float s3 = fmaf(C[3], qa - qb, K[3]);
+    const float s4 = fmaf(C[4], qc - qe, K[4]);
+    const float s5 = fmaf(C[5], qab, fmaf(C[6], qce, fmaf(-C[0], q[0], K[5])));
+    const float s6 = fmaf(C[7], pmm, fmaf(-C[8], qx, K[6]));
+    const float s7 = fmaf(C[7], ppm, fmaf(-C[8], qy, K[7]));
+    const float s8 = fmaf(C[9], q[0], fmaf(C[6], qce, fmaf(-C[1], qab, K[8])));
+
+    // Eq. (10), relaxation and noise exactly as in collide()
+    const float ir = __builtin_amdgcn_rcpf(P.rho0 + drho);
+    const float jxx = jx * jx, jyy = jy * jy;
+    const float e3 = 2.25f * (jxx - jyy) * ir;
+    const float e4 = 9.0f * (jx * jy) * ir;
+    const float e5 = 1.5f * (jxx + jyy) * ir;
+    float t3 = P.omega[0] * (e3 - s3);
+    float t4 = P.omega[1] * (e4 - s4);
+    float t5 = P.omega[2] * (e5 - s5);
+    float t6 = -P.omega[3] * s6;
+    float t7 = -P.omega[4] * s7;
+    float t8 = -P.omega[5] * s8;
+    if constexpr (NOISE) {
+        t3 = fmaf(P.amp[0], z[0], t3);
+        t4 = fmaf(P.amp[1], z[1], t4);
+        t5 = fmaf(P.amp[2], z[2], t5);
+        t6 = fmaf(P.amp[3], z[3], t6);
+        t7 = fmaf(P.amp[4], z[4], t7);
+        t8 = fmaf(P.amp[5], z[5], t8);
+    }
+    // q*_i = q_i + (w_i / s_i) sum_{a>=3} m_i^a dM^a
+    const float A = fmaf(0.5f, t5, -t8);
+    const float B = 2.0f * (t5 + t8);
+    const float P6 = 2.0f * t6, Q7 = 2.0f * t7;
+    const float w0 = P.qback[0], w1 = P.qback[1], w5 = P.qback[2];
+    q[0] = fmaf(w0, fmaf(0.5f, t8, -t5), q[0]);
+    q[1] = fmaf(w1, (A + t3) - t6, q[1]);
+    q[3] = fmaf(w1, (A + t3) + t6, q[3]);
+    q[2] = fmaf(w1, (A - t3) - t7, q[2]);
+    q[4] = fmaf(w1, (A - t3) + t7, q[4]);
+    q[5] = fmaf(w5, (B + t4) + (P6 + Q7), q[5]);
+    q[6] = fmaf(w5, (B - t4) - (P6 - Q7), q[6]);
+    q[7] = fmaf(w5, (B + t4) - (P6 + Q7), q[7]);
+    q[8] = fmaf(w5, (B - t4) + (P6 - Q7), q[8]);
+}
+
+// The step kernels' working value of a stored population: the FP32
+// deviation itself, or for the 16-bit formats the stored scaled deviation
+// (collide_q works on it); `out` rounds a working value to the storage
+// format (materialised in FP32 first: see round_point).
+template <int S> struct Work {
+    using T = typename Codec<S>::T;
+    static __device__ __forceinline__ float in(T v) { return (float)v; }
+    static __device__ __forceinline__ T out(float x)
+    {
+        if constexpr (S == kF32) return x;
+        else return (T)round_point(x);
+    }
+};
+
 struct StepArgs {
     const void *src;
     void *dst;
@@ -90,14 +169,16 @@ struct StepArgs {
     uint32_t key0, key1;
 };
 
-// Collision of one site, including its noise draw.
-template <bool NOISE>
+// Collision of one site, including its noise draw, on working values
+// (Work<S>).
+template <bool NOISE, int S>
 __device__ __forceinline__ void update_site(float (&d)[9], const LatticeParams &P, uint32_t site,
                                             uint32_t t, uint32_t key0, uint32_t key1)
 {
     float z[6] = {0, 0, 0, 0, 0, 0};
     if constexpr (NOISE) normals6(philox4x32_10(make_uint4(site, t, P.stream_id, 0u), key0, key1), z);
-    collide<NOISE>(d, P, z);
+    if constexpr (S == kF32) collide<NOISE>(d, P, z);
+    else collide_q<NOISE>(d, P, z);
 }
 
 // V consecutive values of one storage row, as one vector access.
@@ -184,18 +265,18 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs g)
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             float d[9];
-            d[0] = Codec<S>::decode(lane<T, V>(a0, k), P, 0);
-            d[2] = Codec<S>::decode(lane<T, V>(a2, k), P, 2);
-            d[4] = Codec<S>::decode(lane<T, V>(a4, k), P, 4);
-            d[1] = Codec<S>::decode(k > 0 ? lane<T, V>(a1, k - 1) : e1, P, 1);
-            d[5] = Codec<S>::decode(k > 0 ? lane<T, V>(a5, k - 1) : e5, P, 5);
-            d[8] = Codec<S>::decode(k > 0 ? lane<T, V>(a8, k - 1) : e8, P, 8);
-            d[3] = Codec<S>::decode(k < V - 1 ? lane<T, V>(a3, k + 1) : e3, P, 3);
-            d[6] = Codec<S>::decode(k < V - 1 ? lane<T, V>(a6, k + 1) : e6, P, 6);
-            d[7] = Codec<S>::decode(k < V - 1 ? lane<T, V>(a7, k + 1) : e7, P, 7);
-            update_site<NOISE>(d, P, site0 + (uint32_t)k, t, g.key0, g.key1);
+            d[0] = Work<S>::in(lane<T, V>(a0, k));
+            d[2] = Work<S>::in(lane<T, V>(a2, k));
+            d[4] = Work<S>::in(lane<T, V>(a4, k));
+            d[1] = Work<S>::in(k > 0 ? lane<T, V>(a1, k - 1) : e1);
+            d[5] = Work<S>::in(k > 0 ? lane<T, V>(a5, k - 1) : e5);
+            d[8] = Work<S>::in(k > 0 ? lane<T, V>(a8, k - 1) : e8);
+            d[3] = Work<S>::in(k < V - 1 ? lane<T, V>(a3, k + 1) : e3);
+            d[6] = Work<S>::in(k < V - 1 ? lane<T, V>(a6, k + 1) : e6);
+            d[7] = Work<S>::in(k < V - 1 ? lane<T, V>(a7, k + 1) : e7);
+            update_site<NOISE, S>(d, P, site0 + (uint32_t)k, t, g.key0, g.key1);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) o[i][k] = Codec<S>::encode(d[i], P, i);
+            for (int i = 0; i < 9; ++i) o[i][k] = Work<S>::out(d[i]);
         }
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -213,18 +294,18 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs g)
             const uint32_t ux = (uint32_t)x;
             const uint32_t xl = (x == 0) ? nx - 1 : x - 1, xr = (x == nx - 1) ? 0 : x + 1;
             float d[9];
-            d[0] = Codec<S>::decode(*at<T>(src, rc + ux), P, 0);
-            d[1] = Codec<S>::decode(*at<T>(src, 1 * plane + rc + xl), P, 1);
-            d[2] = Codec<S>::decode(*at<T>(src, 2 * plane + rm + ux), P, 2);
-            d[3] = Codec<S>::decode(*at<T>(src, 3 * plane + rc + xr), P, 3);
-            d[4] = Codec<S>::decode(*at<T>(src, 4 * plane + rp + ux), P, 4);
-            d[5] = Codec<S>::decode(*at<T>(src, 5 * plane + rm + xl), P, 5);
-            d[6] = Codec<S>::decode(*at<T>(src, 6 * plane + rm + xr), P, 6);
-            d[7] = Codec<S>::decode(*at<T>(src, 7 * plane + rp + xr), P, 7);
-            d[8] = Codec<S>::decode(*at<T>(src, 8 * plane + rp + xl), P, 8);
-            update_site<NOISE>(d, P, (uint32_t)(y * nx + x), t, g.key0, g.key1);
+            d[0] = Work<S>::in(*at<T>(src, rc + ux));
+            d[1] = Work<S>::in(*at<T>(src, 1 * plane + rc + xl));
+            d[2] = Work<S>::in(*at<T>(src, 2 * plane + rm + ux));
+            d[3] = Work<S>::in(*at<T>(src, 3 * plane + rc + xr));
+            d[4] = Work<S>::in(*at<T>(src, 4 * plane + rp + ux));
+            d[5] = Work<S>::in(*at<T>(src, 5 * plane + rm + xl));
+            d[6] = Work<S>::in(*at<T>(src, 6 * plane + rm + xr));
+            d[7] = Work<S>::in(*at<T>(src, 7 * plane + rp + xr));
+            d[8] = Work<S>::in(*at<T>(src, 8 * plane + rp + xl));
+            update_site<NOISE, S>(d, P, (uint32_t)(y * nx + x), t, g.key0, g.key1);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) gstore<NT>(at<T>(dst, i * plane + rc + ux), Codec<S>::encode(d[i], P, i));
+            for (int i = 0; i < 9; ++i) gstore<NT>(at<T>(dst, i * plane + rc + ux), Work<S>::out(d[i]));
         }
     }
 }
@@ -402,11 +483,11 @@ __global__ __launch_bounds__(kStep2Threads) void step2_kernel(StepArgs g)
         if (k == KT && tid >= NRING) break;
         float d[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) d[i] = Codec<S>::decode(raw[k][i], P, i);
-        update_site<NOISE>(d, P, (uint32_t)(ys[k] * nx + xs[k]), t, g.key0, g.key1);
-        if (k < KT) own[k] = Codec<S>::encode(d[0], P, 0);
+        for (int i = 0; i < 9; ++i) d[i] = Work<S>::in(raw[k][i]);
+        update_site<NOISE, S>(d, P, (uint32_t)(ys[k] * nx + xs[k]), t, g.key0, g.key1);
+        if (k < KT) own[k] = Work<S>::out(d[0]);
 #pragma unroll
-        for (int i = 1; i < 9; ++i) mid[i - 1][rs[k]] = Codec<S>::encode(d[i], P, i);
+        for (int i = 1; i < 9; ++i) mid[i - 1][rs[k]] = Work<S>::out(d[i]);
     }
     __syncthreads();
 #pragma unroll
@@ -417,20 +498,20 @@ __global__ __launch_bounds__(kStep2Threads) void step2_kernel(StepArgs g)
         if (x >= nx || y >= ny) continue;
         const int c = rs[k];
         float d[9];
-        d[0] = Codec<S>::decode(own[k], P, 0);
-        d[1] = Codec<S>::decode(mid[0][c - 1], P, 1);
-        d[2] = Codec<S>::decode(mid[1][c - RW], P, 2);
-        d[3] = Codec<S>::decode(mid[2][c + 1], P, 3);
-        d[4] = Codec<S>::decode(mid[3][c + RW], P, 4);
-        d[5] = Codec<S>::decode(mid[4][c - RW - 1], P, 5);
-        d[6] = Codec<S>::decode(mid[5][c - RW + 1], P, 6);
-        d[7] = Codec<S>::decode(mid[6][c + RW + 1], P, 7);
-        d[8] = Codec<S>::decode(mid[7][c + RW - 1], P, 8);
-        update_site<NOISE>(d, P, (uint32_t)(y * nx + x), t + 1, g.key0, g.key1);
+        d[0] = Work<S>::in(own[k]);
+        d[1] = Work<S>::in(mid[0][c - 1]);
+        d[2] = Work<S>::in(mid[1][c - RW]);
+        d[3] = Work<S>::in(mid[2][c + 1]);
+        d[4] = Work<S>::in(mid[3][c + RW]);
+        d[5] = Work<S>::in(mid[4][c - RW - 1]);
+        d[6] = Work<S>::in(mid[5][c - RW + 1]);
+        d[7] = Work<S>::in(mid[6][c + RW + 1]);
+        d[8] = Work<S>::in(mid[7][c + RW - 1]);
+        update_site<NOISE, S>(d, P, (uint32_t)(y * nx + x), t + 1, g.key0, g.key1);
         const uint32_t off = ((uint32_t)y * px + (uint32_t)x) * E;
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            gstore<NT>(reinterpret_cast<T *>(dp[i] + off), Codec<S>::encode(d[i], P, i));
+            gstore<NT>(reinterpret_cast<T *>(dp[i] + off), Work<S>::out(d[i]));
     }
 }
 
