@@ -275,6 +275,40 @@ def cpu_baseline(workloads, name, side=1024):
             "host": host}
 
 
+def sample_only(torch, flb, workloads, names, n=32, warm=16):
+    """Correlator samples of a fixed (thermal) state enqueued back to back,
+    nothing beside them: ms per sample for each named workload (c5_4096,
+    batched_gi_96x512, batched_uneven_64), the sums' read-modify-writes
+    included (a whole number of accumulation cycles, then a flush)."""
+    c = workloads.CONFIGS["c5_4096"]
+    specs = {"c5_4096": [dict(nx=c["nx"], ny=c["ny"], tau=c["tau"], theta=c["theta"],
+                              u0=c["u0"])],
+             "batched_gi_96x512": workloads.gi_sweep_specs(),
+             "batched_uneven_64": workloads.uneven_batch_specs()}
+    out = {}
+    stream = torch.cuda.Stream()
+    for name in names:
+        b = flb.Lattice.batch(specs[name], seed=3)
+        b.set_sample_overlap(False)
+        b.set_stream(stream)
+        b.thermalize()
+        for _ in range(warm):
+            b.accumulate()
+        b.flush_correlators()
+        b.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            b.accumulate()
+        b.flush_correlators()
+        e1.record(stream)
+        e1.synchronize()
+        out[name] = {"sample_ms": e0.elapsed_time(e1) / n, "samples": n}
+        print(f"sample-only: {name} {out[name]}", flush=True)
+        b.close()
+    return out
+
+
 def host_cpu():
     """The host's CPU model and the number of CPUs this process may use."""
     model = platform.processor() or ""
@@ -307,6 +341,10 @@ def main():
     ap.add_argument("--velocity-sets", action="store_true",
                     help="only time the other velocity sets (D3Q15 at 256^3 with its "
                          "correlators, D1Q3 at 2^26 sites) and print their figures")
+    ap.add_argument("--sample-only", nargs="*", default=None, metavar="WORKLOAD",
+                    help="only time correlator samples alone (no steps beside them) on the "
+                         "named workloads (default: c5_4096 batched_gi_96x512 "
+                         "batched_uneven_64) and print their figures")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 603,979,776 bytes device to device three times "
                          "(the known-size reference for HBM byte counters)")
@@ -344,6 +382,10 @@ def main():
         return 0
     if args.sweep_shapes:
         sweep_shapes(flb, workloads, args.workload, args.storage)
+        return 0
+    if args.sample_only is not None:
+        names = args.sample_only or ["c5_4096", "batched_gi_96x512", "batched_uneven_64"]
+        print(json.dumps(sample_only(torch, flb, workloads, names)), flush=True)
         return 0
     if args.velocity_sets:
         stream = torch.cuda.Stream()
