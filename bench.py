@@ -159,6 +159,29 @@ def steady_step_ms(torch, g, stream, n=50, warm=100, reps=3):
     return min(time_step_kernel(torch, g, stream, n) for _ in range(reps))
 
 
+def plain_path_ms(torch, g, stream, n=32, warm=16):
+    """Whole-path time (ms) per benchmark step of one handle with the timed
+    region's calls (SAMPLE_EVERY steps and a sample, plain calls): `warm`
+    untimed benchmark steps and a flush, then n timed ones ending with the
+    flush of their stashed samples."""
+    with torch.cuda.stream(stream):
+        for _ in range(warm):
+            g.step(SAMPLE_EVERY)
+            g.accumulate()
+        g.flush_correlators()
+        g.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            g.step(SAMPLE_EVERY)
+            g.accumulate()
+        g.flush_correlators()
+        g.synchronize()
+        e1.record(stream)
+        e1.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
 def batched_form(torch, flb, stream, specs, storage, periods=16):
     """Whole path (graph-replayed periods of SAMPLE_EVERY steps + a sample)
     and step-only rates of one batched handle."""
@@ -515,7 +538,10 @@ def main():
                 shape, _ = h.autotune(50)
                 ms = steady_step_ms(torch, h, stream)
                 lf = launch_figures(h, V, ms)
+                pms = plain_path_ms(torch, h, stream)
                 forms[st] = {"step_glups": V / (ms * 1e-3) / 1e9,
+                             "path_glups": SAMPLE_EVERY * V / (pms * 1e-3) / 1e9,
+                             "sample_ms": max(pms - SAMPLE_EVERY * ms, 0.0),
                              "steps_per_launch": lf["steps_per_launch"],
                              "achieved_GBs": lf["achieved_GBs"],
                              "launch_shape": list(shape) + [list(h.time_blocking())]}

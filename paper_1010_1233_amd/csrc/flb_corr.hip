@@ -243,6 +243,193 @@ __global__ __launch_bounds__(kFftThreads, 6) void corr_rows_kernel(CorrArgs g)
     }
 }
 
+// store_row_spectra for the blocks of corr_rows_p2_kernel, sizes fixed at
+// compile time: the columns kx < 2^LG/2 of all lines four per thread (a
+// line's half spans whole waves), then the Nyquist column and the padding
+// columns up to k_xp = 2^LG/2 + 16.  The spectra of one lattice stay below
+// 2^31 elements, so offsets from the field's base are 32-bit.
+template <int LG>
+__device__ __forceinline__ void store_row_spectra_p2(const float2 *lds, float2 *sa, float2 *sb,
+                                                     int y0, int nl, bool pair, int tid)
+{
+    constexpr int M = 1 << LG, HALF = M / 2, KXP = HALF + 16, NL = 4096 >> LG;
+    auto put = [&](int l, int k) {
+        const uint32_t o = (uint32_t)((y0 + l) * KXP + k);
+        const float2 zk = lds[lds_slot<true>(l * M + k)];
+        if (!pair) {
+            sa[o] = zk;
+        } else {
+            const float2 zm = lds[lds_slot<true>(l * M + ((M - k) & (M - 1)))];
+            sa[o] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+            sb[o] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+        }
+    };
+#pragma unroll
+    for (int q = 0; q < (NL * HALF) / kFftThreads; ++q) {
+        const int e = tid + q * kFftThreads, l = e >> (LG - 1);
+        if (l < nl) put(l, e & (HALF - 1));
+    }
+    if (tid < 16 * NL) {
+        const int l = tid >> 4, k = HALF + (tid & 15);
+        if (l < nl) {
+            if (k == HALF) {
+                put(l, k);
+            } else {  // padding columns: keep them finite
+                const uint32_t o = (uint32_t)((y0 + l) * KXP + k);
+                sa[o] = make_float2(0.f, 0.f);
+                if (pair) sb[o] = make_float2(0.f, 0.f);
+            }
+        }
+    }
+}
+
+// One decimation-in-time pass (stages S0 .. S0+R-1, as fused_pass) over the
+// 4096 >> LG lines of 2^LG elements in a row block's LDS, every size fixed
+// at compile time.
+template <int LG, int S0, int R>
+__device__ __forceinline__ void row_dit_pass(float2 *buf, const float2 *tw, int tid)
+{
+    constexpr int M = 1 << LG, G = 1 << R, H = 1 << (S0 - 1);
+    constexpr int PER = (4096 >> R) / kFftThreads;  // groups per thread
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * kFftThreads;
+        const int l = idx >> (LG - R), gi = idx & ((1 << (LG - R)) - 1);
+        const int k = gi & (H - 1);
+        const int e0 = l * M + ((gi >> (S0 - 1)) << (S0 - 1 + R)) + k;
+        float2 v[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) v[j] = buf[lds_slot<true>(e0 + j * H)];
+        group_butterflies<R, false, false>(v, tw[k << (kTwLog - (S0 + R - 1))]);
+#pragma unroll
+        for (int j = 0; j < G; ++j) buf[lds_slot<true>(e0 + j * H)] = v[j];
+    }
+}
+
+// Field set 0 for lattices whose rows are powers of two of 2^LG = 512 ..
+// 4096 points: what corr_rows_kernel computes, with the line length fixed at
+// compile time.  Thread t takes the eight sites x = c + j 2^LG/8 (j < 8) of
+// line t / (2^LG/8) of the block, c = t mod 2^LG/8.  In bit-reversed order
+// these sites are the eight consecutive elements 8 rev(c) .. 8 rev(c) + 7 of
+// a line, one group of the first decimation-in-time pass (stages 1..3, no
+// twiddles), so that pass runs on the gathered values in registers and
+// writes eight consecutive LDS slots; stages 4..LG follow in LDS.  A line
+// spans whole waves, so the rows a wave reads are wave-uniform and the
+// gather addresses are scalar bases plus 32-bit offsets; the periodic wrap
+// along x is a mask.
+template <int S, int LG>
+__global__ __launch_bounds__(kFftThreads, 6) void corr_rows_p2_kernel(CorrArgs g)
+{
+    using T = typename Codec<S>::T;
+    constexpr int M = 1 << LG, H = M >> 3;
+    static_assert(LG >= 9 && LG <= 12, "a line spans whole waves; a block holds 4096 elements");
+    extern __shared__ float2 lds[];
+    const CorrItem it = g.items[blockIdx.x];
+    if (it.lattice < 0) return;
+    const LatticeParams &P = g.params[it.lattice];
+    const int y0 = it.a, nl = min(it.b, P.ny - y0);
+    const int t = (int)threadIdx.x, c = t & (H - 1);
+    const int l = __builtin_amdgcn_readfirstlane(t >> (LG - 3));
+    const T *p = (const T *)g.pops + P.base;
+
+    float r[8], jx[8], jy[8];
+    double acc[5] = {0, 0, 0, 0, 0};
+    if (l < nl) {
+        // wave-uniform plane rows: scalar bases, 32-bit offsets
+        const int ny = P.ny, y = y0 + l;
+        const int ym = __builtin_amdgcn_readfirstlane(y == 0 ? ny - 1 : y - 1);
+        const int yp = __builtin_amdgcn_readfirstlane(y == ny - 1 ? 0 : y + 1);
+        const int64_t px = P.px, pl = P.plane;
+        const T *rc = p + y * px, *rm = p + ym * px, *rp = p + yp * px;
+        const T *__restrict__ q0 = rc, *__restrict__ q1 = rc + pl, *__restrict__ q2 = rm + 2 * pl;
+        const T *__restrict__ q3 = rc + 3 * pl, *__restrict__ q4 = rp + 4 * pl;
+        const T *__restrict__ q5 = rm + 5 * pl, *__restrict__ q6 = rm + 6 * pl;
+        const T *__restrict__ q7 = rp + 7 * pl, *__restrict__ q8 = rp + 8 * pl;
+        double sx = 0, sy = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t x = (uint32_t)(c + j * H), xm = (x - 1) & (M - 1), xp = (x + 1) & (M - 1);
+            float d[9];
+            d[0] = Codec<S>::decode(q0[x], P, 0);
+            d[1] = Codec<S>::decode(q1[xm], P, 1);
+            d[2] = Codec<S>::decode(q2[x], P, 2);
+            d[3] = Codec<S>::decode(q3[xp], P, 3);
+            d[4] = Codec<S>::decode(q4[x], P, 4);
+            d[5] = Codec<S>::decode(q5[xm], P, 5);
+            d[6] = Codec<S>::decode(q6[xp], P, 6);
+            d[7] = Codec<S>::decode(q7[xp], P, 7);
+            d[8] = Codec<S>::decode(q8[xm], P, 8);
+            r[j] = d[0] + (d[1] + d[3]) + (d[2] + d[4]) + (d[5] + d[7]) + (d[6] + d[8]);
+            jx[j] = (d[1] - d[3]) + (d[5] - d[7]) - (d[6] - d[8]);
+            jy[j] = (d[2] - d[4]) + (d[5] - d[7]) + (d[6] - d[8]);
+            acc[0] += r[j];
+            sx += jx[j];
+            sy += jy[j];
+        }
+        // the thread's sites share the parity of x (c) and of y
+        acc[1] = sx;
+        acc[2] = sy;
+        acc[3] = (c & 1) ? -sx : sx;
+        acc[4] = (y & 1) ? -sy : sy;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r[j] = jx[j] = jy[j] = 0.f;
+    }
+    block_sum5<kFftThreads>(acc, g.csum_part + 5 * (int64_t)it.c);
+
+    const float2 *tw = g.tables;
+    float2 *spec = g.spec + P.spec_base;
+    const int64_t fstride = (int64_t)P.ny * P.kxp;
+    const float rho0 = P.rho0, u0x = P.u0x, u0y = P.u0y;
+    const float jx0 = rho0 * u0x, jy0 = rho0 * u0y;
+#pragma unroll 1
+    for (int sig = 0; sig < 3; ++sig) {
+        // LDS addresses are recomputed for every signal rather than kept in
+        // registers through the loop
+        int tid = t;
+        asm volatile("" : "+v"(tid));
+        // first slot of the thread's group: eight consecutive slots (a pad
+        // slot falls only at multiples of 16)
+        const int base = lds_slot<true>(l * M + 8 * bitrev(tid & (H - 1), LG - 3));
+        float2 v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (sig == 0) {
+                v[j] = make_float2(jx[j] - jx0, jy[j] - jy0);
+            } else if (sig == 1) {
+                const float ir = __builtin_amdgcn_rcpf(rho0 + r[j]);
+                v[j] = make_float2(fmaf(jx[j], ir, -u0x), fmaf(jy[j], ir, -u0y));
+            } else {
+                v[j] = make_float2(r[j], 0.f);
+            }
+            if (l >= nl) v[j] = make_float2(0.f, 0.f);
+        }
+        // element 8 rev(c) + i of the line is site x = c + rev3(i) H
+        float2 u[8] = {v[0], v[4], v[2], v[6], v[1], v[5], v[3], v[7]};
+        group_butterflies<3, false, false, true>(u, make_float2(1.f, 0.f));
+        // (the block sum and the previous signal's reads of LDS are behind
+        // this barrier)
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lds[base + i] = u[i];
+        __syncthreads();
+        row_dit_pass<LG, 4, 3>(lds, tw, tid);
+        __syncthreads();
+        if constexpr (LG >= 10) {
+            row_dit_pass<LG, 7, 3>(lds, tw, tid);
+            __syncthreads();
+            row_dit_pass<LG, 10, LG - 9>(lds, tw, tid);
+        } else {
+            row_dit_pass<LG, 7, 3>(lds, tw, tid);
+        }
+        __syncthreads();
+        // spectra: 1, 2 = jx, jy; 3, 4 = ux, uy; 0 = rho
+        float2 *sa = spec + (sig == 0 ? 1 : sig == 1 ? 3 : 0) * fstride;
+        store_row_spectra_p2<LG>(lds, sa, sa + fstride, y0, nl, sig != 2, tid);
+    }
+}
+
+
 // Sums each lattice's row-kernel partials into its five conservation sums.
 __global__ __launch_bounds__(kThreads) void corr_csum_kernel(CorrArgs g, int nlat)
 {
@@ -744,11 +931,39 @@ static void rows_for(const DeviceView &v, const CorrArgs &g, int nitems, int lds
         hipLaunchKernelGGL((corr_rows_kernel<kF16, BLUE>), grid, block, lds_bytes, s, g);
 }
 
+template <int LG>
+static void rows_p2_for(const DeviceView &v, const CorrArgs &g, int nitems, int lds_bytes,
+                        hipStream_t s)
+{
+    const dim3 grid(nitems), block(kFftThreads);
+    if (v.storage == kF32)
+        hipLaunchKernelGGL((corr_rows_p2_kernel<kF32, LG>), grid, block, lds_bytes, s, g);
+    else if (v.storage == kBF16)
+        hipLaunchKernelGGL((corr_rows_p2_kernel<kBF16, LG>), grid, block, lds_bytes, s, g);
+    else
+        hipLaunchKernelGGL((corr_rows_p2_kernel<kF16, LG>), grid, block, lds_bytes, s, g);
+}
+
+bool corr_rows_p2_supported(int lg) { return lg >= 9 && lg <= 12; }
+
 hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems,
-                            const CorrItem *blue_items, int nblue, int lds_bytes, hipStream_t s)
+                            const RowLaunch *p2, int np2, const CorrItem *blue_items, int nblue,
+                            int lds_bytes, hipStream_t s)
 {
     if (nitems) {
         rows_for<false>(v, make_args(v, items, 0), nitems, lds_bytes, s);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    for (int q = 0; q < np2; ++q) {
+        const CorrArgs g = make_args(v, items + p2[q].off, 0);
+        switch (p2[q].lg) {
+        case 9: rows_p2_for<9>(v, g, p2[q].n, lds_bytes, s); break;
+        case 10: rows_p2_for<10>(v, g, p2[q].n, lds_bytes, s); break;
+        case 11: rows_p2_for<11>(v, g, p2[q].n, lds_bytes, s); break;
+        case 12: rows_p2_for<12>(v, g, p2[q].n, lds_bytes, s); break;
+        default: return hipErrorInvalidValue;
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

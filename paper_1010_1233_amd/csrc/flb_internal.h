@@ -151,9 +151,17 @@ hipError_t launch_debug_noise(uint64_t seed, uint32_t stream_id, uint32_t t, int
                               int64_t n, uint32_t *words_dev, float *z_dev, hipStream_t s);
 // Field set 0 (rho, j, u; kKinds kinds): fused fields + row transforms
 // (items of power-of-two rows and of Bluestein rows), then the conservation
-// sums of the sampled state.
+// sums of the sampled state.  Rows of 2^lg points, 9 <= lg <= 12
+// (corr_rows_p2_supported), go to a kernel specialised per length: launch q
+// takes items[p2[q].off .. p2[q].off + p2[q].n), all of lattices with rows of
+// 2^p2[q].lg points; the generic kernel takes items[0 .. nitems).
+struct RowLaunch {
+    int lg, off, n;
+};
+bool corr_rows_p2_supported(int lg);
 hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems,
-                            const CorrItem *blue_items, int nblue, int lds_bytes, hipStream_t s);
+                            const RowLaunch *p2, int np2, const CorrItem *blue_items, int nblue,
+                            int lds_bytes, hipStream_t s);
 // Field set 1 (the six non-conserved moments, kinds kKinds .. kKinds + 5):
 // FP32 field planes, then row transforms.
 hipError_t launch_corr_moment_fields(const DeviceView &v, const CorrItem *items, int nitems,
