@@ -199,11 +199,12 @@ int flb_accumulate_correlators(flb_t *h);
 /* Copies lattice `lattice`'s raw FP64 sums to out[kind][ky][kx] (host), with
  * kind < flb_num_kinds(h), ky < ny, kx < nx/2+1, and writes the number of
  * samples taken to *nsamples (may be NULL).  n_doubles must be at least
- * flb_num_kinds(h)*ny*(nx/2+1), else FLB_ESIZE.  Synchronises.  The library
- * adds the FP64 products of sixteen samples in one pass over the sums and
- * keeps the FP32 spectra of up to fifteen samples until then; a read adds those
- * first, so the sums are those of adding every sample, up to FP64 rounding
- * order. */
+ * flb_num_kinds(h)*ny*(nx/2+1), else FLB_ESIZE.  Synchronises, and takes
+ * host memory for one more copy of the lattice's sums (the device keeps them
+ * in another order).  The library adds the FP64 products of sixteen samples
+ * in one pass over the sums and keeps the FP32 spectra of up to sixteen
+ * samples until then; a read adds those first, so the sums are those of
+ * adding every sample, up to FP64 rounding order. */
 int flb_read_correlators(flb_t *h, int lattice, double *out, size_t n_doubles,
                          int64_t *nsamples);
 

@@ -15,11 +15,13 @@
 //          fields and the FP64 conservation partials of its rows.  (The
 //          optional moment set goes through FP32 field planes and a separate
 //          row kernel.)
-//   columns: one kernel transforms whole columns in LDS (Bluestein's
-//          convolution for lengths that are not powers of two) and keeps
-//          the spectra in a stash slot; with every kDeferK-th (sixteenth)
-//          sample a second kernel adds the fifteen products of that sample
-//          and of the stashed ones to the FP64 sums, one thread per k.
+//   columns: whole columns are transformed in LDS (Bluestein's convolution
+//          for lengths that are not powers of two; power-of-two columns of
+//          512 to 4096 points in a persistent, pipelined kernel) and the
+//          spectra go to one of sixteen stash slots, column-tiled; with
+//          every kDeferK-th (sixteenth) sample a second kernel adds the
+//          products of the sixteen stashed samples to the FP64 sums, one
+//          thread per k.
 // The line transforms themselves are in flb_fft.h.
 #include <algorithm>
 #include <type_traits>
@@ -558,25 +560,20 @@ __device__ __forceinline__ void accumulate_k(double *a, int64_t kstride, const f
     add_to_sums(a, kstride, val);
 }
 
-// Stash slots read per batch: fifteen slots (a cycle of sixteen samples) are
-// three batches, each with all its reads in flight at once.
-constexpr int kSlotBatch = 5;
+// Stash slots read per batch: the sixteen slots of a cycle are four
+// batches, each with all its reads in flight at once.
+constexpr int kSlotBatch = 4;
+static_assert(kDeferK % kSlotBatch == 0, "whole batches per cycle");
 
-// The products of X (when WITH_X) and of the n >= 1 stashed samples at st
-// (slot j at st + j * sstride, field f at + f * kstride), summed in that
-// order and added to the sums in one read-modify-write.
-template <bool WITH_X>
-__device__ __forceinline__ void accumulate_stashed_k(double *a, int64_t kstride,
-                                                     const float2 (&X)[5], const float2 *st,
+// The products of the n >= 1 stashed samples at st (slot j at st + j *
+// sstride, field f at + f * kstride), summed in slot order and added to the
+// sums in one read-modify-write.
+__device__ __forceinline__ void accumulate_stashed_k(double *a, int64_t kstride, const float2 *st,
                                                      int64_t sstride, int n)
 {
     double u[kKinds];
-    if constexpr (WITH_X) {
-        products_k(u, X);
-    } else {
 #pragma unroll
-        for (int q = 0; q < kKinds; ++q) u[q] = 0.0;
-    }
+    for (int q = 0; q < kKinds; ++q) u[q] = 0.0;
     for (int j0 = 0; j0 < n; j0 += kSlotBatch) {
         // slots past the last are read again (in bounds) and not added
         float2 Y[kSlotBatch][5];
@@ -648,11 +645,12 @@ __global__ __launch_bounds__(NT) void corr_cols_kernel(CorrArgs g)
     const int ny = P.ny, nkx = P.nkx, kxp = P.kxp;
     const int f = it.a, c0 = it.b, lgc = it.c, cb = 1 << lgc;
     const int ncol = min(cb, nkx - c0);
-    float2 *col = g.spec + P.spec_base + (int64_t)f * ny * kxp + c0;
-    // the transformed column goes back in place, or to stash slot g.arg >= 0
-    float2 *out = g.arg < 0 ? col
-                            : g.stash + (int64_t)g.arg * g.stash_stride + P.spec_base +
-                                  (int64_t)f * ny * kxp + c0;
+    const float2 *col = g.spec + P.spec_base + (int64_t)f * ny * kxp;
+    // the transformed column goes back in place (row order), or to stash
+    // slot g.arg >= 0 (column-tiled)
+    const bool tiled = g.arg >= 0;
+    float2 *out = (tiled ? g.stash + (int64_t)g.arg * g.stash_stride : g.spec) + P.spec_base +
+                  (int64_t)f * ny * kxp;
     const float2 *chirp = g.tables + L.chirp_off;
     const bool blue = L.bluestein != 0;
     // a Bluestein work length's zero padding, rows ny .. m-1
@@ -665,7 +663,7 @@ __global__ __launch_bounds__(NT) void corr_cols_kernel(CorrArgs g)
         for (int b = 0; b < kBatch; ++b) {
             const int idx = i0 + b * NT, j = idx >> lgc, c = idx & (cb - 1);
             v[b] = make_float2(0.f, 0.f);
-            if (idx < ne && c < ncol) v[b] = col[(int64_t)j * kxp + c];
+            if (idx < ne && c < ncol) v[b] = col[(int64_t)j * kxp + c0 + c];
         }
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
@@ -682,7 +680,8 @@ __global__ __launch_bounds__(NT) void corr_cols_kernel(CorrArgs g)
         const int j = idx >> lgc, c = idx & (cb - 1);
         if (c >= ncol) continue;
         const float2 x = lds[lds_slot<true>(idx)];
-        out[(int64_t)j * kxp + c] = blue ? cmul(x, chirp[j]) : x;
+        out[tiled ? spec_offset(j, c0 + c, ny) : (int64_t)j * kxp + c0 + c] =
+            blue ? cmul(x, chirp[j]) : x;
     }
 }
 
@@ -826,8 +825,14 @@ __global__ __launch_bounds__(cols_pipe_threads(LG)) void corr_cols_pipe_kernel(
         // last pass: stages LG - R3 + 1 .. LG, groups k < H3 of elements
         // k + j H3, which are in natural order when they leave it
         {
-            float2 *out = (g.arg < 0 ? g.spec : g.stash + (int64_t)g.arg * g.stash_stride) + cur.off;
-            const uint32_t kxp = (uint32_t)cur.kxp;
+            // in place (row order), or to a stash slot (column-tiled: rows
+            // of a tile kTileCols apart)
+            static_assert(kTileCols == 4, "tile offsets below");
+            const bool tiled = g.arg >= 0;
+            float2 *out = tiled ? g.stash + (int64_t)g.arg * g.stash_stride + cur.toff
+                                : g.spec + cur.off;
+            const uint32_t rs = tiled ? 4u : (uint32_t)cur.kxp;
+            const uint32_t ts = (uint32_t)cur.ts;
 #pragma unroll 1
             for (int i = 0; i < NG3; ++i) {
                 const int idx = tid + i * NT, k = idx >> LGC, cc = idx & (CB - 1);
@@ -837,9 +842,10 @@ __global__ __launch_bounds__(cols_pipe_threads(LG)) void corr_cols_pipe_kernel(
                 group_butterflies<R3, false, false>(x, tw3[0]);
                 rotate_left(tw3);
                 if (cc < cur.ncol) {
-                    const uint32_t o0 = (uint32_t)k * kxp + (uint32_t)cc;
+                    const uint32_t o0 = (uint32_t)k * rs + (tiled ? ((uint32_t)cc >> 2) * ts + (cc & 3)
+                                                                   : (uint32_t)cc);
 #pragma unroll
-                    for (int j = 0; j < G3; ++j) out[o0 + (uint32_t)(j * H3) * kxp] = x[j];
+                    for (int j = 0; j < G3; ++j) out[o0 + (uint32_t)(j * H3) * rs] = x[j];
                 }
             }
         }
@@ -849,6 +855,18 @@ __global__ __launch_bounds__(cols_pipe_threads(LG)) void corr_cols_pipe_kernel(
 }
 
 // Accumulation.  item: lattice, first k of the (ny, nkx) plane.
+// Row and column (ky, kx) of position o of a column-tiled plane; whether it
+// holds a k that is accumulated: not a padding column (kx >= nkx), not k = 0
+// (which carries no fluctuation).
+__device__ __forceinline__ bool tiled_k(const LatticeParams &P, uint32_t o, uint32_t &ky,
+                                        uint32_t &kx)
+{
+    const uint32_t q = o / kTileCols, tile = q / (uint32_t)P.ny;
+    ky = q - tile * (uint32_t)P.ny;
+    kx = tile * kTileCols + o % kTileCols;
+    return kx < (uint32_t)P.nkx && (kx | ky) != 0;
+}
+
 template <int SET>
 __global__ __launch_bounds__(kThreads) void corr_accum_kernel(CorrArgs g)
 {
@@ -856,25 +874,15 @@ __global__ __launch_bounds__(kThreads) void corr_accum_kernel(CorrArgs g)
     const CorrItem it = g.items[blockIdx.x];
     if (it.lattice < 0) return;
     const LatticeParams &P = g.params[it.lattice];
-    const int nkx = P.nkx, kxp = P.kxp;
-    const int64_t nk = (int64_t)P.ny * nkx;
-    const int64_t k = (int64_t)it.a + threadIdx.x;
-    if (k >= nk || k == 0) return;  // k = 0 carries no fluctuation
-    const int ky = (int)(k / nkx), kx = (int)(k - (int64_t)ky * nkx);
-    const int64_t o = (int64_t)ky * kxp + kx;
-    const int64_t fstride = (int64_t)P.ny * kxp;
-    const float2 *sp = g.spec + P.spec_base;
+    const int64_t fstride = (int64_t)P.ny * P.kxp;
+    const int64_t o = (int64_t)it.a + threadIdx.x;  // position in a tiled sum plane
+    uint32_t ky, kx;
+    if (o >= fstride || !tiled_k(P, (uint32_t)o, ky, kx)) return;
+    // this sample's spectra, in place in row order
+    const float2 *sp = g.spec + P.spec_base + (int64_t)ky * P.kxp + kx;
     float2 X[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) X[f] = sp[f * fstride + o];
-    if constexpr (SET == 0) {
-        // g.arg > 0: with the products of that many stashed samples
-        if (g.arg > 0) {
-            accumulate_stashed_k<true>(g.acc + P.acc_base + o, fstride, X,
-                                       g.stash + P.spec_base + o, g.stash_stride, g.arg);
-            return;
-        }
-    }
+    for (int f = 0; f < NF; ++f) X[f] = sp[f * fstride];
     accumulate_set<SET, NF>(g.acc + P.acc_base + o, fstride, X);
 }
 
@@ -886,16 +894,12 @@ __global__ __launch_bounds__(kThreads) void corr_flush_kernel(CorrArgs g)
     const CorrItem it = g.items[blockIdx.x];
     if (it.lattice < 0) return;
     const LatticeParams &P = g.params[it.lattice];
-    const int nkx = P.nkx, kxp = P.kxp;
-    const int64_t nk = (int64_t)P.ny * nkx;
-    const int64_t k = (int64_t)it.a + threadIdx.x;
-    if (k >= nk || k == 0) return;
-    const int ky = (int)(k / nkx), kx = (int)(k - (int64_t)ky * nkx);
-    const int64_t o = (int64_t)ky * kxp + kx;
-    const int64_t fstride = (int64_t)P.ny * kxp;
-    const float2 X[5] = {};
-    accumulate_stashed_k<false>(g.acc + P.acc_base + o, fstride, X,
-                                g.stash + P.spec_base + o, g.stash_stride, g.arg);
+    const int64_t fstride = (int64_t)P.ny * P.kxp;
+    const int64_t o = (int64_t)it.a + threadIdx.x;  // tiled stash and sum planes
+    uint32_t ky, kx;
+    if (o >= fstride || !tiled_k(P, (uint32_t)o, ky, kx)) return;
+    accumulate_stashed_k(g.acc + P.acc_base + o, fstride, g.stash + P.spec_base + o,
+                         g.stash_stride, g.arg);
 }
 
 static CorrArgs make_args(const DeviceView &v, const CorrItem *items, int set)
@@ -1058,10 +1062,9 @@ hipError_t launch_corr_cols_pipe(const DeviceView &v, const PipeItem *sched, int
 }
 
 hipError_t launch_corr_accum(const DeviceView &v, const CorrItem *items, int nitems, int set,
-                             int nslots, hipStream_t s)
+                             hipStream_t s)
 {
     CorrArgs g = make_args(v, items, set);
-    g.arg = nslots;
     if (set == 1)
         hipLaunchKernelGGL(corr_accum_kernel<1>, dim3(nitems), dim3(kThreads), 0, s, g);
     else

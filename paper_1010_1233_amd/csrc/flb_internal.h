@@ -12,9 +12,13 @@
 //   step     : one uint32 on the device, the time t of the next step, so
 //              that captured graphs replay with advancing noise counters.
 //   spec     : complex64 scratch for the correlator transforms, per lattice
-//              5 fields x ny x kxp (the half spectra of the real fields; kxp
-//              is nkx = nx/2+1 rounded up to 16 so column blocks are 128 B).
-//   acc      : FP64 correlator sums, per lattice FLB_NKINDS x ny x kxp.
+//              5 fields x ny x kxp in row order (the half spectra of the real
+//              fields after the row transforms; kxp is nkx = nx/2+1 rounded
+//              up to 16).
+//   stash    : kDeferK spectrum-sized slots: the column transforms' output,
+//              each field plane column-tiled (spec_offset below).
+//   acc      : FP64 correlator sums, per lattice FLB_NKINDS x ny x kxp, each
+//              kind's plane column-tiled.
 //   fields   : FP32 fluctuation fields of the sampled state, 5 x ny x nx
 //              per lattice, and the FP64 conservation sums of that state.
 #pragma once
@@ -63,7 +67,7 @@ struct alignas(16) LatticeParams {
     uint32_t stream_id;
     int32_t line_x;           // index of the x-direction line plan
     int32_t line_y;           // index of the y-direction line plan
-    int32_t kxp;              // row pitch of spectra and sums: nkx rounded up to 16
+    int32_t kxp;              // columns of the spectrum and sum planes: nkx rounded up to 16
     int32_t col_large;        // columns in the column kernel's large blocks
     int32_t col_lgcb;         // log2 of the columns per column-kernel block
     int32_t fld_tiles_x;      // field-kernel tiles (256 sites) per row band
@@ -82,6 +86,20 @@ struct alignas(16) LinePlan {
     int64_t chirp_off;        // float2 offset of exp(-i pi j^2 / n), j < n
     int64_t kernel_off;       // float2 offset of the length-m FFT of the chirp kernel
 };
+
+// The column transforms' output planes and the sums (ny rows of kxp
+// columns) are column-tiled: tiles of kTileCols adjacent columns, each tile
+// holding all ny rows contiguously, so that the output of a group of
+// kTileCols columns (what the column transforms take at 4096 points) is one
+// contiguous run of memory, as is every stretch of k the accumulation
+// takes.  (The row transforms' output stays in row order: their blocks hold
+// one row, and a tiled store from them would write 32-byte pieces.)  Column
+// kx of row y of a plane is at spec_offset.
+constexpr int kTileCols = 4;
+__host__ __device__ inline int64_t spec_offset(int y, int kx, int ny)
+{
+    return ((int64_t)(kx / kTileCols) * ny + y) * kTileCols + kx % kTileCols;
+}
 
 // Twiddle table: exp(-2 pi i k / kTwN), k < kTwN/2, for every power-of-two
 // work length up to kTwN.
@@ -182,28 +200,36 @@ hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nite
 // Column transforms of power-of-two lengths 2^lg, 9 <= lg <= 12, in
 // persistent blocks: sched holds niter x grid groups of columns (the group
 // of block b in round it at it * grid + b), each of 16384 / 2^lg (at most
-// 16) adjacent columns of one field: the complex offset of its first
-// column in the spectra (and in a stash slot), the row pitch kxp, and the
-// number of columns it has (0: no group).  `slot` as for launch_corr_cols.
+// 16) adjacent columns of one field, starting at a tile: the complex offset
+// of its first column in the spectra (row order, row pitch kxp), the offset
+// of its first tile in a stash slot (tile stride ts = kTileCols * ny), and
+// the number of columns it has (0: no group).  `slot` as for
+// launch_corr_cols.
 struct PipeItem {
     int64_t off;
+    int64_t toff;
     int32_t kxp;
+    int32_t ts;
     int32_t ncol;
+    int32_t pad;
 };
 bool corr_cols_pipe_supported(int lg);
 int corr_cols_pipe_lds_bytes(int lg);
 hipError_t launch_corr_cols_pipe(const DeviceView &v, const PipeItem *sched, int niter, int grid,
                                  int lg, int slot, hipStream_t s);
-// samples per read-modify-write of the FP64 sums (kDeferK - 1 stash slots,
-// each the size of the spectra: 5 GB at 4096^2).  4096^2 whole path: 87.5
+// samples per read-modify-write of the FP64 sums (kDeferK stash slots, each
+// the size of the spectra: 5.4 GB at 4096^2).  4096^2 whole path: 87.5
 // GLUPS with 16 against 86.4 with 8, the sums' read-modify-write being most
 // of the accumulation's bytes.
 constexpr int kDeferK = 16;
-// Adds the products of the first nslots stash slots to the sums (field set 0).
+// Adds the products of the first nslots stash slots to the sums (field set
+// 0): every kDeferK-th sample with nslots = kDeferK, and before a read.
 hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nitems, int nslots,
                              hipStream_t s);
+// Adds this sample's products to the sums at once (the column transforms'
+// output left in place, in row order).
 hipError_t launch_corr_accum(const DeviceView &v, const CorrItem *items, int nitems, int set,
-                             int nslots, hipStream_t s);
+                             hipStream_t s);
 hipError_t launch_fill(double *p, size_t n, hipStream_t s);
 
 // ---------------------------------------------------------------------

@@ -140,9 +140,9 @@ struct flb {
     };
     std::vector<PipeLaunch> pipe[2];
     // deferred accumulation: samples stash their spectra (the column
-    // transform's output) in kDeferK - 1 slots and every kDeferK-th one adds
-    // the products of all of them at once; `pending` counts the stashed
-    // samples
+    // transform's output) in kDeferK slots and every kDeferK-th one adds the
+    // products of all of them at once; `pending` counts the stashed samples
+    // whose products are not yet added
     bool defer = false;
     int pending = 0;
     float2 *d_stash = nullptr;
@@ -490,17 +490,21 @@ std::vector<CorrItem> persistent_schedule(const std::vector<CorrItem> &items, in
     return sched;
 }
 
-// The pipelined column kernel's form of scheduled column groups: offset of
-// the first column in the spectra, row pitch and number of columns.
+// The pipelined column kernel's form of scheduled column groups: offsets of
+// the first column in the spectra and of its tile in a stash slot, row
+// pitch, tile stride and number of columns.
 std::vector<PipeItem> pipe_items(const flb_t *h, const std::vector<CorrItem> &sched)
 {
-    std::vector<PipeItem> out(sched.size(), PipeItem{0, 0, 0});
+    std::vector<PipeItem> out(sched.size(), PipeItem{0, 0, 0, 0, 0, 0});
     for (size_t i = 0; i < sched.size(); ++i) {
         const CorrItem &it = sched[i];
         if (it.lattice < 0) continue;
         const LatticeParams &P = h->params[it.lattice];
-        out[i].off = P.spec_base + (int64_t)it.a * P.ny * P.kxp + it.b;
+        const int64_t plane = P.spec_base + (int64_t)it.a * P.ny * P.kxp;
+        out[i].off = plane + it.b;
+        out[i].toff = plane + spec_offset(0, it.b, P.ny);
         out[i].kxp = P.kxp;
+        out[i].ts = kTileCols * P.ny;
         out[i].ncol = std::min(1 << it.c, P.nkx - it.b);
     }
     return out;
@@ -607,7 +611,8 @@ int setup_correlators(flb_t *h)
                     (P.col_large ? cols_lm : cols_m).push_back({(int32_t)l, f, c0, P.col_lgcb});
                 }
         }
-        const int64_t nk = (int64_t)P.ny * P.nkx;
+        // the accumulation walks the tiled planes (padding columns skipped)
+        const int64_t nk = (int64_t)P.ny * P.kxp;
         for (int64_t k0 = 0; k0 < nk; k0 += kThreads) {
             accum.push_back({(int32_t)l, (int32_t)k0, 0, 0});
             flush.push_back({(int32_t)l, (int32_t)k0, 0, 0});
@@ -692,7 +697,7 @@ int setup_correlators(flb_t *h)
     FLB_HIP(hipMalloc((void **)&h->d_acc, acc * sizeof(double)));
     if (fld > 0) FLB_HIP(hipMalloc((void **)&h->d_fields, fld * sizeof(float)));
     if (h->defer)
-        FLB_HIP(hipMalloc((void **)&h->d_stash, (size_t)(kDeferK - 1) * spec * sizeof(float2)));
+        FLB_HIP(hipMalloc((void **)&h->d_stash, (size_t)kDeferK * spec * sizeof(float2)));
     FLB_HIP(hipMalloc((void **)&h->d_csum_part, (size_t)nparts * 5 * sizeof(double)));
     FLB_HIP(hipMalloc((void **)&h->d_csum, h->params.size() * 5 * sizeof(double)));
     FLB_HIP(launch_fill(h->d_csum, h->params.size() * 5, h->stream));
@@ -725,17 +730,19 @@ int enqueue_sample(flb_t *h, hipStream_t s, hipEvent_t ev_read = nullptr)
         } else {
             FLB_HIP(launch_corr_moment_rows(v, h->d_rows_m, h->n_rows_m, h->rows_lds, s));
         }
-        // field set 0: stash the column transform's output, or (every
-        // kDeferK-th sample) add this sample's products with the stashed ones
-        const bool stash = !set && h->defer && h->pending < kDeferK - 1;
+        // field set 0: the column transforms' output goes to stash slot
+        // `pending`, and every kDeferK-th sample adds the products of all
+        // the slots; otherwise it stays in place and is accumulated at once
+        const bool stash = !set && h->defer;
         const int slot = stash ? h->pending : -1;
         if (ng) FLB_HIP(launch_corr_cols(v, cg, ng, slot, false, h->cols_lds, s));
         if (nl) FLB_HIP(launch_corr_cols(v, cl, nl, slot, true, h->cols_l_lds, s));
         for (const auto &pl : h->pipe[set])
             FLB_HIP(launch_corr_cols_pipe(v, pl.d_sched, pl.niter, pl.grid, pl.lg, slot, s));
-        if (h->n_accum && !stash)
-            FLB_HIP(launch_corr_accum(v, h->d_accum, h->n_accum, set,
-                                      (!set && h->defer) ? h->pending : 0, s));
+        if (stash && h->pending == kDeferK - 1)
+            FLB_HIP(launch_corr_flush(v, h->d_flush, h->n_flush, kDeferK, s));
+        else if (h->n_accum && !stash)
+            FLB_HIP(launch_corr_accum(v, h->d_accum, h->n_accum, set, s));
     }
     if (h->defer) h->pending = (h->pending + 1) % kDeferK;
     return FLB_OK;
@@ -1224,10 +1231,23 @@ int flb_read_correlators(flb_t *h, int lattice, double *out, size_t n_doubles, i
     if (n_doubles < need) return fail(FLB_ESIZE, "output buffer too small for the correlators");
     if ((rc = settle_due(h)) || (rc = flush_pending(h))) return rc;
     FLB_HIP(hipStreamSynchronize(h->stream));
-    // device rows have pitch kxp >= nkx
-    FLB_HIP(hipMemcpy2D(out, (size_t)P.nkx * sizeof(double), h->d_acc + P.acc_base,
-                        (size_t)P.kxp * sizeof(double), (size_t)P.nkx * sizeof(double),
-                        (size_t)h->nkinds * P.ny, hipMemcpyDeviceToHost));
+    // the device planes are column-tiled with kxp >= nkx columns: copied
+    // whole, then put in row order
+    const int ny = P.ny, nkx = P.nkx;
+    const int64_t plane = (int64_t)ny * P.kxp;
+    std::vector<double> tiled((size_t)(h->nkinds * plane));
+    FLB_HIP(hipMemcpy(tiled.data(), h->d_acc + P.acc_base, tiled.size() * sizeof(double),
+                      hipMemcpyDeviceToHost));
+    for (int q = 0; q < h->nkinds; ++q) {
+        const double *src = tiled.data() + q * plane;
+        double *dst = out + (size_t)q * ny * nkx;
+        for (int x0 = 0; x0 < nkx; x0 += kTileCols) {
+            const int w = std::min(kTileCols, nkx - x0);
+            const double *t = src + spec_offset(0, x0, ny);
+            for (int y = 0; y < ny; ++y)
+                for (int c = 0; c < w; ++c) dst[(size_t)y * nkx + x0 + c] = t[y * kTileCols + c];
+        }
+    }
     if (nsamples) *nsamples = h->nsamples;
     return FLB_OK;
 }
