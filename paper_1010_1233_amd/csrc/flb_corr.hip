@@ -116,6 +116,8 @@ __device__ __forceinline__ void site_moments(const typename Codec<S>::T *p,
 // sequence (pair false) goes to field fa as is.  kx = 0..nx/2, padding
 // columns up to kxp zeroed.  With `chirp`, line element k is first
 // multiplied by chirp[k] (a Bluestein line left without its output chirp).
+// The spectra are streamed: the column transforms read them back only
+// after the whole launch has written them.
 __device__ __forceinline__ void store_row_spectra(const float2 *lds, const LatticeParams &P,
                                                   float2 *spec, int y0, int nl, int m, int fa,
                                                   bool pair, const float2 *chirp = nullptr)
@@ -138,13 +140,13 @@ __device__ __forceinline__ void store_row_spectra(const float2 *lds, const Latti
         float2 zk = lds[lds_slot<true>(l * m + k)];
         if (chirp) zk = cmul(zk, chirp[k]);
         if (!pair) {
-            sa[row] = zk;
+            stream_store(&sa[row], zk);
         } else {
             const int km = k == 0 ? 0 : nx - k;
             float2 zm = lds[lds_slot<true>(l * m + km)];
             if (chirp) zm = cmul(zm, chirp[km]);
-            sa[row] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-            sb[row] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+            stream_store(&sa[row], make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)));
+            stream_store(&sb[row], make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x)));
         }
     }
 }
@@ -259,11 +261,11 @@ __device__ __forceinline__ void store_row_spectra_p2(const float2 *lds, float2 *
         const uint32_t o = (uint32_t)((y0 + l) * KXP + k);
         const float2 zk = lds[lds_slot<true>(l * M + k)];
         if (!pair) {
-            sa[o] = zk;
+            stream_store(&sa[o], zk);
         } else {
             const float2 zm = lds[lds_slot<true>(l * M + ((M - k) & (M - 1)))];
-            sa[o] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-            sb[o] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+            stream_store(&sa[o], make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)));
+            stream_store(&sb[o], make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x)));
         }
     };
 #pragma unroll
@@ -542,14 +544,14 @@ __device__ __forceinline__ void products_k(double (&val)[kKinds], const float2 (
 // old value is read before any is written, so the reads are in flight
 // together (read and write addresses are the same, so the compiler may not
 // reorder a later read before an earlier write on its own).
-template <int NK>
+template <int NK, bool NT = false>
 __device__ __forceinline__ void add_to_sums(double *a, int64_t kstride, const double (&u)[NK])
 {
     double old[NK];
 #pragma unroll
-    for (int q = 0; q < NK; ++q) old[q] = a[q * kstride];
+    for (int q = 0; q < NK; ++q) old[q] = gload<NT>(&a[q * kstride]);
 #pragma unroll
-    for (int q = 0; q < NK; ++q) a[q * kstride] = old[q] + u[q];
+    for (int q = 0; q < NK; ++q) gstore<NT>(&a[q * kstride], old[q] + u[q]);
 }
 
 // Adds the products of one sample at one k to the sums.
@@ -567,7 +569,8 @@ static_assert(kDeferK % kSlotBatch == 0, "whole batches per cycle");
 
 // The products of the n >= 1 stashed samples at st (slot j at st + j *
 // sstride, field f at + f * kstride), summed in slot order and added to the
-// sums in one read-modify-write.
+// sums in one read-modify-write; stash and sums are streamed (each is read
+// once per cycle, far more than the L2 holds).
 __device__ __forceinline__ void accumulate_stashed_k(double *a, int64_t kstride, const float2 *st,
                                                      int64_t sstride, int n)
 {
@@ -581,7 +584,7 @@ __device__ __forceinline__ void accumulate_stashed_k(double *a, int64_t kstride,
         for (int b = 0; b < kSlotBatch; ++b) {
             const int j = min(j0 + b, n - 1);
 #pragma unroll
-            for (int f = 0; f < 5; ++f) Y[b][f] = st[j * sstride + f * kstride];
+            for (int f = 0; f < 5; ++f) Y[b][f] = stream_load(&st[j * sstride + f * kstride]);
         }
         // (a select, not a branch: the reads of a batch must not be sunk
         // into per-slot branches, which would serialise them again)
@@ -594,7 +597,7 @@ __device__ __forceinline__ void accumulate_stashed_k(double *a, int64_t kstride,
             for (int q = 0; q < kKinds; ++q) u[q] += on ? w[q] : 0.0;
         }
     }
-    add_to_sums(a, kstride, u);
+    add_to_sums<kKinds, true>(a, kstride, u);
 }
 
 // Squared moduli of the six moment spectra at one k, added to kinds
@@ -680,8 +683,9 @@ __global__ __launch_bounds__(NT) void corr_cols_kernel(CorrArgs g)
         const int j = idx >> lgc, c = idx & (cb - 1);
         if (c >= ncol) continue;
         const float2 x = lds[lds_slot<true>(idx)];
-        out[tiled ? spec_offset(j, c0 + c, ny) : (int64_t)j * kxp + c0 + c] =
-            blue ? cmul(x, chirp[j]) : x;
+        const float2 y = blue ? cmul(x, chirp[j]) : x;
+        if (tiled) stream_store(&out[spec_offset(j, c0 + c, ny)], y);
+        else out[(int64_t)j * kxp + c0 + c] = y;
     }
 }
 
@@ -845,7 +849,11 @@ __global__ __launch_bounds__(cols_pipe_threads(LG)) void corr_cols_pipe_kernel(
                     const uint32_t o0 = (uint32_t)k * rs + (tiled ? ((uint32_t)cc >> 2) * ts + (cc & 3)
                                                                    : (uint32_t)cc);
 #pragma unroll
-                    for (int j = 0; j < G3; ++j) out[o0 + (uint32_t)(j * H3) * rs] = x[j];
+                    for (int j = 0; j < G3; ++j) {
+                        float2 *p = &out[o0 + (uint32_t)(j * H3) * rs];
+                        if (tiled) stream_store(p, x[j]);
+                        else *p = x[j];
+                    }
                 }
             }
         }

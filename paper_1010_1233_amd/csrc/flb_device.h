@@ -118,6 +118,23 @@ template <bool NT, typename T> __device__ __forceinline__ T gload(const T *p)
         return *p;
 }
 
+// Streaming (non-temporal) access to a complex value: data written once and
+// read once much later (spectra on their way to the stash and the sums),
+// which would only displace other lines from the L2.
+typedef float flb_v2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void stream_store(float2 *p, float2 v)
+{
+    flb_v2f t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, (flb_v2f *)p);
+}
+__device__ __forceinline__ float2 stream_load(const float2 *p)
+{
+    const flb_v2f t = __builtin_nontemporal_load((const flb_v2f *)p);
+    return make_float2(t.x, t.y);
+}
+
 // D2Q9 velocities in the order of Sec. 3.
 __device__ constexpr int kVX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ constexpr int kVY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
