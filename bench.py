@@ -59,7 +59,7 @@ HBM_PEAK_GBS = 8000.0
 SAMPLE_EVERY = 10
 # samples per read-modify-write pass of the FP64 correlator sums in the
 # library (the others keep their spectra until then)
-ACCUMULATE_EVERY = 16
+ACCUMULATE_EVERY = 32
 STEP_KERNEL = "step_kernel"
 
 
@@ -159,7 +159,7 @@ def steady_step_ms(torch, g, stream, n=50, warm=100, reps=3):
     return min(time_step_kernel(torch, g, stream, n) for _ in range(reps))
 
 
-def plain_path_ms(torch, g, stream, n=32, warm=16):
+def plain_path_ms(torch, g, stream, n=ACCUMULATE_EVERY, warm=16):
     """Whole-path time (ms) per benchmark step of one handle with the timed
     region's calls (SAMPLE_EVERY steps and a sample, plain calls): `warm`
     untimed benchmark steps and a flush, then n timed ones ending with the
@@ -182,14 +182,14 @@ def plain_path_ms(torch, g, stream, n=32, warm=16):
     return e0.elapsed_time(e1) / n
 
 
-def batched_form(torch, flb, stream, specs, storage, periods=16):
+def batched_form(torch, flb, stream, specs, storage, periods=ACCUMULATE_EVERY):
     """Whole path (graph-replayed periods of SAMPLE_EVERY steps + a sample)
     and step-only rates of one batched handle."""
     # the captured periods depend on the buffer parity and on how many of the
-    # sixteen samples of an accumulation cycle are stashed: a multiple of 16
-    # periods starts the timed run where the warm-up started, so that it
-    # replays graphs the warm-up captured
-    assert periods % 16 == 0
+    # samples of an accumulation cycle are stashed: a whole number of cycles
+    # starts the timed run where the warm-up started, so that it replays
+    # graphs the warm-up captured
+    assert periods % ACCUMULATE_EVERY == 0
     b = flb.Lattice.batch(specs, seed=3, storage=storage)
     b.set_stream(stream)
     b.thermalize()
@@ -298,7 +298,7 @@ def cpu_baseline(workloads, name, side=1024):
             "host": host}
 
 
-def sample_only(torch, flb, workloads, names, n=32, warm=16):
+def sample_only(torch, flb, workloads, names, n=2 * ACCUMULATE_EVERY, warm=ACCUMULATE_EVERY):
     """Correlator samples of a fixed (thermal) state enqueued back to back,
     nothing beside them: ms per sample for each named workload (c5_4096,
     batched_gi_96x512, batched_uneven_64), the sums' read-modify-writes

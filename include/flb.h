@@ -201,9 +201,10 @@ int flb_accumulate_correlators(flb_t *h);
  * samples taken to *nsamples (may be NULL).  n_doubles must be at least
  * flb_num_kinds(h)*ny*(nx/2+1), else FLB_ESIZE.  Synchronises, and takes
  * host memory for one more copy of the lattice's sums (the device keeps them
- * in another order).  The library adds the FP64 products of sixteen samples
- * in one pass over the sums and keeps the FP32 spectra of up to sixteen
- * samples until then; a read adds those first, so the sums are those of
+ * in another order).  The library adds the FP64 products of 32 samples in
+ * one pass over the sums and keeps the FP32 spectra of up to 32 samples
+ * until then (32 spectrum-sized buffers of 5 x ny x (nx/2+16) complex
+ * values per lattice); a read adds those first, so the sums are those of
  * adding every sample, up to FP64 rounding order. */
 int flb_read_correlators(flb_t *h, int lattice, double *out, size_t n_doubles,
                          int64_t *nsamples);

@@ -18,10 +18,9 @@
 //   columns: whole columns are transformed in LDS (Bluestein's convolution
 //          for lengths that are not powers of two; power-of-two columns of
 //          512 to 4096 points in a persistent, pipelined kernel) and the
-//          spectra go to one of sixteen stash slots, column-tiled; with
-//          every kDeferK-th (sixteenth) sample a second kernel adds the
-//          products of the sixteen stashed samples to the FP64 sums, one
-//          thread per k.
+//          spectra go to one of kDeferK (32) stash slots, column-tiled;
+//          with every kDeferK-th sample a second kernel adds the products
+//          of all the stashed samples to the FP64 sums, one thread per k.
 // The line transforms themselves are in flb_fft.h.
 #include <algorithm>
 #include <type_traits>
@@ -562,8 +561,8 @@ __device__ __forceinline__ void accumulate_k(double *a, int64_t kstride, const f
     add_to_sums(a, kstride, val);
 }
 
-// Stash slots read per batch: the sixteen slots of a cycle are four
-// batches, each with all its reads in flight at once.
+// Stash slots read per batch: the slots of a cycle are whole batches, each
+// with all its reads in flight at once.
 constexpr int kSlotBatch = 4;
 static_assert(kDeferK % kSlotBatch == 0, "whole batches per cycle");
 

@@ -218,10 +218,10 @@ int corr_cols_pipe_lds_bytes(int lg);
 hipError_t launch_corr_cols_pipe(const DeviceView &v, const PipeItem *sched, int niter, int grid,
                                  int lg, int slot, hipStream_t s);
 // samples per read-modify-write of the FP64 sums (kDeferK stash slots, each
-// the size of the spectra: 5.4 GB at 4096^2).  4096^2 whole path: 87.5
-// GLUPS with 16 against 86.4 with 8, the sums' read-modify-write being most
-// of the accumulation's bytes.
-constexpr int kDeferK = 16;
+// the size of the spectra: 10.8 GB at 4096^2).  The sums' read-modify-write
+// is most of the accumulation's bytes: 4096^2 whole path 87.5 GLUPS with 16
+// against 86.4 with 8; a sample alone 0.504 ms with 32 against 0.520 with 16.
+constexpr int kDeferK = 32;
 // Adds the products of the first nslots stash slots to the sums (field set
 // 0): every kDeferK-th sample with nslots = kDeferK, and before a read.
 hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nitems, int nslots,

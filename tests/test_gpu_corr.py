@@ -246,8 +246,8 @@ def test_moment_spectra_paired_run_and_batch(flb, oracle_lib):
 
 
 def test_reads_between_paired_samples(flb, oracle_lib):
-    """Samples stash their spectra and every sixteenth adds the products of
-    all sixteen; a read with samples outstanding adds them first.  Reading after
+    """Samples stash their spectra and every 32nd adds the products of all
+    32; a read with samples outstanding adds them first.  Reading after
     every sample, twice in a row, or only at the end all give the oracle's
     sums."""
     kw = dict(u0=(0.02, 0.0), seed=12)
@@ -329,8 +329,8 @@ def test_storage_formats_against_oracle(flb, oracle_lib, side):
 
 def test_batch_of_column_block_widths_equals_separate_lattices(flb, oracle_lib):
     """Column work lengths 2048, 1024 and 256 (Bluestein, 4, 8 and 16
-    columns per block) and a power-of-two side in one batch: over twenty samples
-    (across a sixteen-sample accumulation cycle, with graph-replayed periods)
+    columns per block) and a power-of-two side in one batch: over forty samples
+    (across a 32-sample accumulation cycle, with graph-replayed periods)
     every lattice's sums are the bits of the same lattice run alone, and the
     longest columns' sums match the oracle."""
     specs = [dict(nx=40, ny=600, tau=TAU_C1, theta=1e-4, stream_id=0),
@@ -340,33 +340,32 @@ def test_batch_of_column_block_widths_equals_separate_lattices(flb, oracle_lib):
     note("column block widths batch")
     b = flb.Lattice.batch(specs, seed=8)
     b.thermalize()
-    b.run(80, 4)
+    b.run(160, 4)
     for i, s in enumerate(specs):
         one = flb.Lattice(s["nx"], s["ny"], s["tau"], s["theta"], u0=s.get("u0", (0, 0)),
                           seed=8, stream_id=s["stream_id"])
         one.thermalize()
-        one.run(80, 4)
+        one.run(160, 4)
         acc, ns = b.read_correlators(i)
         ref, nr = one.read_correlators()
-        assert ns == nr == 20
+        assert ns == nr == 40
         assert np.array_equal(acc, ref), i
         one.close()
     s = specs[0]
     o = oracle_lib.Lattice(s["nx"], s["ny"], s["tau"], s["theta"], seed=8,
                            stream_id=s["stream_id"])
     o.thermalize()
-    o.run(80, 4)
-    assert o.nsamples == 20
+    o.run(160, 4)
+    assert o.nsamples == 40
     _compare(b.read_correlators(0)[0], o.acc, 1e-3)
 
 
 def test_large_column_blocks_over_sample_cycles(flb, oracle_lib):
     """ny = 4096 takes the column kernel's large blocks (1024 threads, four
-    whole columns): twenty samples, which stash fifteen of sixteen and add
-    the sixteenth's products with them, overlapped beside the steps, with
-    reads after the third and seventeenth (a read adds the stashed samples
-    first), against samples enqueued at once (same bits) and against the
-    oracle."""
+    whole columns): forty samples, the 32nd of which adds the products of
+    the 32 stashed ones, overlapped beside the steps, with reads after the
+    third and the 33rd (a read adds the stashed samples first), against
+    samples enqueued at once (same bits) and against the oracle."""
     kw = dict(u0=(0.03, -0.01), seed=17)
     a = flb.Lattice(8, 4096, TAU_C1, 1e-4, **kw)
     b = flb.Lattice(8, 4096, TAU_C1, 1e-4, **kw)
@@ -374,19 +373,19 @@ def test_large_column_blocks_over_sample_cycles(flb, oracle_lib):
     b.set_sample_overlap(False)
     for L in (a, b, o):
         L.thermalize()
-    for i in range(20):
+    for i in range(40):
         for L in (a, b, o):
             L.step(3)
         a.accumulate()
         b.accumulate()
         o.sample()
-        if i in (2, 16):
+        if i in (2, 32):
             ra, na = a.read_correlators()
             assert na == i + 1
             assert np.array_equal(ra, b.read_correlators()[0])
             _compare(ra, o.acc, 2e-4)
     ra, na = a.read_correlators()
-    assert na == o.nsamples == 20
+    assert na == o.nsamples == 40
     assert np.array_equal(ra, b.read_correlators()[0])
     _compare(ra, o.acc, 2e-4)
 
@@ -395,23 +394,23 @@ def test_galilean_batch_shape_over_sample_cycles(flb, oracle_lib):
     """The Galilean-invariance sweep's shape: 512^2 lattices (512-point rows
     and 512-point columns in the small column blocks) at four of the sweep's
     mean velocities, batched, graph-replayed periods with the samples beside
-    the steps; twenty samples cross a sixteen-sample accumulation cycle.
+    the steps; forty samples cross a 32-sample accumulation cycle.
     Every lattice's sums match the oracle's run of the same trajectory
     element by element."""
     us = (0.0, 0.05, 0.1, 0.2)
     specs = [dict(nx=512, ny=512, tau=workloads.tau_vector(0.8, 1.0, 1.0), theta=1e-4,
                   rho0=1.0, u0=(u, 0.0), stream_id=16 * i) for i, u in enumerate(us)]
-    note("4 x 512^2 batch, 20 samples")
+    note("4 x 512^2 batch, 40 samples")
     b = flb.Lattice.batch(specs, seed=3)
     b.thermalize()
-    b.run(40, 2)
+    b.run(80, 2)
     for i, s in enumerate(specs):
         note("  oracle lattice", i)
         o = oracle_lib.Lattice(512, 512, s["tau"], s["theta"], u0=s["u0"], seed=3,
                                stream_id=s["stream_id"])
         o.thermalize()
-        o.run(40, 2)
+        o.run(80, 2)
         acc, ns = b.read_correlators(i)
-        assert ns == o.nsamples == 20
+        assert ns == o.nsamples == 40
         assert np.all(acc[:, 0, 0] == 0)
         _compare(acc, o.acc, 1e-3)
