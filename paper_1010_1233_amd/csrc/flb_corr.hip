@@ -286,11 +286,13 @@ __device__ __forceinline__ void store_row_spectra_p2(const float2 *lds, float2 *
     }
 }
 
-// One decimation-in-time pass (stages S0 .. S0+R-1, as fused_pass) over the
-// 4096 >> LG lines of 2^LG elements in a row block's LDS, every size fixed
-// at compile time.
-template <int LG, int S0, int R>
-__device__ __forceinline__ void row_dit_pass(float2 *buf, const float2 *tw, int tid)
+// One pass of R fused radix-2 stages S0 .. S0+R-1 (as fused_pass; inverse
+// and decimation in frequency as there) over the 4096 >> LG lines of 2^LG
+// elements in a row block's LDS, every size fixed at compile time.  The
+// first decimation-in-time pass and the last decimation-in-frequency pass
+// (S0 = 1) have fixed roots of unity only.
+template <int LG, int S0, int R, bool INV = false, bool DIF = false>
+__device__ __forceinline__ void row_fft_pass(float2 *buf, const float2 *tw, int tid)
 {
     constexpr int M = 1 << LG, G = 1 << R, H = 1 << (S0 - 1);
     constexpr int PER = (4096 >> R) / kFftThreads;  // groups per thread
@@ -303,15 +305,26 @@ __device__ __forceinline__ void row_dit_pass(float2 *buf, const float2 *tw, int 
         float2 v[G];
 #pragma unroll
         for (int j = 0; j < G; ++j) v[j] = buf[lds_slot<true>(e0 + j * H)];
-        group_butterflies<R, false, false>(v, tw[k << (kTwLog - (S0 + R - 1))]);
+        if constexpr (S0 == 1) {
+            group_butterflies<R, INV, DIF, true>(v, make_float2(1.f, 0.f));
+        } else {
+            float2 w = tw[k << (kTwLog - (S0 + R - 1))];
+            if (INV) w.y = -w.y;
+            group_butterflies<R, INV, DIF>(v, w);
+        }
 #pragma unroll
         for (int j = 0; j < G; ++j) buf[lds_slot<true>(e0 + j * H)] = v[j];
     }
 }
+template <int LG, int S0, int R>
+__device__ __forceinline__ void row_dit_pass(float2 *buf, const float2 *tw, int tid)
+{
+    row_fft_pass<LG, S0, R>(buf, tw, tid);
+}
 
-// Field set 0 for lattices whose rows are powers of two of 2^LG = 512 ..
-// 4096 points: what corr_rows_kernel computes, with the line length fixed at
-// compile time.  Thread t takes the eight sites x = c + j 2^LG/8 (j < 8) of
+// A block of corr_rows_p2_kernel for lattices whose rows are powers of
+// two of 2^LG = 512 .. 4096 points: what corr_rows_kernel computes, with the
+// line length fixed at compile time.  Thread t takes the eight sites x = c + j 2^LG/8 (j < 8) of
 // line t / (2^LG/8) of the block, c = t mod 2^LG/8.  In bit-reversed order
 // these sites are the eight consecutive elements 8 rev(c) .. 8 rev(c) + 7 of
 // a line, one group of the first decimation-in-time pass (stages 1..3, no
@@ -321,14 +334,12 @@ __device__ __forceinline__ void row_dit_pass(float2 *buf, const float2 *tw, int 
 // gather addresses are scalar bases plus 32-bit offsets; the periodic wrap
 // along x is a mask.
 template <int S, int LG>
-__global__ __launch_bounds__(kFftThreads, 6) void corr_rows_p2_kernel(CorrArgs g)
+__device__ __forceinline__ void rows_p2_block(const CorrArgs &g, const CorrItem &it)
 {
     using T = typename Codec<S>::T;
     constexpr int M = 1 << LG, H = M >> 3;
     static_assert(LG >= 9 && LG <= 12, "a line spans whole waves; a block holds 4096 elements");
     extern __shared__ float2 lds[];
-    const CorrItem it = g.items[blockIdx.x];
-    if (it.lattice < 0) return;
     const LatticeParams &P = g.params[it.lattice];
     const int y0 = it.a, nl = min(it.b, P.ny - y0);
     const int t = (int)threadIdx.x, c = t & (H - 1);
@@ -433,7 +444,209 @@ __global__ __launch_bounds__(kFftThreads, 6) void corr_rows_p2_kernel(CorrArgs g
 }
 
 
-// Sums each lattice's row-kernel partials into its five conservation sums.
+// The middle of a Bluestein convolution in a row block, on groups of 2^R
+// consecutive elements: the last stages of the forward decimation in
+// frequency (stages R .. 1, fixed roots), the product with the transformed
+// chirp kernel (bit-reversed order, as the forward transform leaves it) and
+// the first stages of the inverse decimation in time (1 .. R) in registers,
+// one LDS round trip for the three.
+template <int LG, int R>
+__device__ __forceinline__ void row_blue_middle(float2 *buf, const float2 *kern, int tid)
+{
+    constexpr int G = 1 << R, PER = (4096 >> R) / kFftThreads;
+    constexpr int M = 1 << LG;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e0 = (tid + q * kFftThreads) << R;  // line l = e0 / M, element e0 % M
+        const int s0 = lds_slot<true>(e0);            // G <= 8 consecutive slots
+        float2 v[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) v[j] = buf[s0 + j];
+        group_butterflies<R, false, true, true>(v, make_float2(1.f, 0.f));
+#pragma unroll
+        for (int j = 0; j < G; ++j) v[j] = cmul(v[j], kern[(e0 & (M - 1)) + j]);
+        group_butterflies<R, true, false, true>(v, make_float2(1.f, 0.f));
+#pragma unroll
+        for (int j = 0; j < G; ++j) buf[s0 + j] = v[j];
+    }
+}
+
+// A block of corr_rows_blue_kernel for lattices whose rows take
+// Bluestein's transform with a work length of 2^LG = 256 .. 2048 (rows of n
+// points, 2n - 1 <= 2^LG, n not a power of two): what corr_rows_kernel<S,
+// true> computes, with the work length fixed at compile time.  A block holds 4096 >> LG lines; thread t
+// takes the elements x = c + j 2^LG/8 (j < 8) of line t / (2^LG/8),
+// c = t mod 2^LG/8, which are one group of the forward transform's first
+// radix-8 pass (decimation in frequency, natural order); as 2^LG >= 2n - 1,
+// only j < 4 can hold sites, the rest are the convolution's zero padding.
+// That pass runs on the gathered, chirp-multiplied values in registers; the
+// forward transform's last pass, the product with the chirp kernel's
+// transform and the inverse transform's first pass share one LDS round
+// trip.  Passes per field pair: 6 (2^11), 6 (2^10), 4 (2^9), 4 (2^8), and
+// one store.
+template <int S, int LG>
+__device__ __forceinline__ void rows_blue_block(const CorrArgs &g, const CorrItem &it)
+{
+    using T = typename Codec<S>::T;
+    constexpr int M = 1 << LG, H = M >> 3;
+    static_assert(LG >= 8 && LG <= 11, "work lengths 256 .. 2048");
+    extern __shared__ float2 lds[];
+    const LatticeParams &P = g.params[it.lattice];
+    const LinePlan &L = g.plans[P.line_x];
+    const int nx = P.nx;
+    const int y0 = it.a, nl = min(it.b, P.ny - y0);
+    const int t = (int)threadIdx.x, c = t & (H - 1);
+    // a line spans whole waves from 2^9 on
+    const int l = LG >= 9 ? __builtin_amdgcn_readfirstlane(t >> (LG - 3)) : t >> (LG - 3);
+    const T *p = (const T *)g.pops + P.base;
+    const float2 *chirp = g.tables + L.chirp_off;
+
+    float r[4], jx[4], jy[4];
+    double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r[j] = jx[j] = jy[j] = 0.f;
+    if (l < nl) {
+        const int y = y0 + l;
+        double sx = 0, sy = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int x = c + j * H;
+            if (x < nx) {
+                float d[9];
+                pull_site<S>(p, P, x, y, d);
+                r[j] = d[0] + (d[1] + d[3]) + (d[2] + d[4]) + (d[5] + d[7]) + (d[6] + d[8]);
+                jx[j] = (d[1] - d[3]) + (d[5] - d[7]) - (d[6] - d[8]);
+                jy[j] = (d[2] - d[4]) + (d[5] - d[7]) + (d[6] - d[8]);
+                acc[0] += r[j];
+                sx += jx[j];
+                sy += jy[j];
+            }
+        }
+        // the thread's sites share the parity of x (c) and of y
+        acc[1] = sx;
+        acc[2] = sy;
+        acc[3] = (c & 1) ? -sx : sx;
+        acc[4] = (y & 1) ? -sy : sy;
+    }
+    block_sum5<kFftThreads>(acc, g.csum_part + 5 * (int64_t)it.c);
+
+    const float2 *tw = g.tables;
+    const float2 *kern = g.tables + L.kernel_off;
+    float2 *spec = g.spec + P.spec_base;
+    const float rho0 = P.rho0, u0x = P.u0x, u0y = P.u0y;
+    const float jx0 = rho0 * u0x, jy0 = rho0 * u0y;
+#pragma unroll 1
+    for (int sig = 0; sig < 3; ++sig) {
+        int tid = t;
+        asm volatile("" : "+v"(tid));
+        const int cc = tid & (H - 1), base = (l * M) + cc;
+        float2 v[8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int x = cc + j * H;
+            float2 z;
+            if (sig == 0) {
+                z = make_float2(jx[j] - jx0, jy[j] - jy0);
+            } else if (sig == 1) {
+                const float ir = __builtin_amdgcn_rcpf(rho0 + r[j]);
+                z = make_float2(fmaf(jx[j], ir, -u0x), fmaf(jy[j], ir, -u0y));
+            } else {
+                z = make_float2(r[j], 0.f);
+            }
+            z = cmul(z, chirp[x < nx ? x : 0]);
+            v[j] = (x < nx && l < nl) ? z : make_float2(0.f, 0.f);
+            v[j + 4] = make_float2(0.f, 0.f);
+        }
+        // forward stages LG .. LG-2 (decimation in frequency), twiddle
+        // exp(-2 pi i c / 2^LG)
+        group_butterflies<3, false, true>(v, tw[cc << (kTwLog - LG)]);
+        // (the block sum and the previous signal's reads of LDS are behind
+        // this barrier)
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 8; ++j) lds[lds_slot<true>(base + j * H)] = v[j];
+        __syncthreads();
+        // the rest of the forward transform, the kernel product, the
+        // inverse transform (decimation in time) back to natural order
+        if constexpr (LG == 11) {
+            row_fft_pass<LG, 6, 3, false, true>(lds, tw, tid);
+            __syncthreads();
+            row_fft_pass<LG, 3, 3, false, true>(lds, tw, tid);
+            __syncthreads();
+            row_blue_middle<LG, 2>(lds, kern, tid);
+            __syncthreads();
+            row_fft_pass<LG, 3, 3, true>(lds, tw, tid);
+            __syncthreads();
+            row_fft_pass<LG, 6, 3, true>(lds, tw, tid);
+            __syncthreads();
+            row_fft_pass<LG, 9, 3, true>(lds, tw, tid);
+        } else if constexpr (LG == 10) {
+            row_fft_pass<LG, 5, 3, false, true>(lds, tw, tid);
+            __syncthreads();
+            row_fft_pass<LG, 2, 3, false, true>(lds, tw, tid);
+            __syncthreads();
+            row_blue_middle<LG, 1>(lds, kern, tid);
+            __syncthreads();
+            row_fft_pass<LG, 2, 3, true>(lds, tw, tid);
+            __syncthreads();
+            row_fft_pass<LG, 5, 3, true>(lds, tw, tid);
+            __syncthreads();
+            row_fft_pass<LG, 8, 3, true>(lds, tw, tid);
+        } else if constexpr (LG == 9) {
+            row_fft_pass<LG, 4, 3, false, true>(lds, tw, tid);
+            __syncthreads();
+            row_blue_middle<LG, 3>(lds, kern, tid);
+            __syncthreads();
+            row_fft_pass<LG, 4, 3, true>(lds, tw, tid);
+            __syncthreads();
+            row_fft_pass<LG, 7, 3, true>(lds, tw, tid);
+        } else {
+            row_fft_pass<LG, 3, 3, false, true>(lds, tw, tid);
+            __syncthreads();
+            row_blue_middle<LG, 2>(lds, kern, tid);
+            __syncthreads();
+            row_fft_pass<LG, 3, 3, true>(lds, tw, tid);
+            __syncthreads();
+            row_fft_pass<LG, 6, 3, true>(lds, tw, tid);
+        }
+        __syncthreads();
+        // spectra: 1, 2 = jx, jy; 3, 4 = ux, uy; 0 = rho (the output chirp
+        // applied as they are read)
+        store_row_spectra(lds, P, spec, y0, nl, M, sig == 0 ? 1 : sig == 1 ? 3 : 0, sig != 2,
+                          chirp);
+    }
+}
+
+
+// Field set 0 for lattices whose rows have a length-specialised block: one
+// kernel per power-of-two length (corr_rows_p2_kernel; the lattices of a
+// batch usually share one), one for every Bluestein work length together
+// (corr_rows_blue_kernel: each block takes the code of its lattice's plan,
+// so that the lengths of an uneven batch share the device instead of
+// queueing as launches of their own; a kernel holding the power-of-two
+// blocks too took their registers and was slower for them).
+template <int S, int LG>
+__global__ __launch_bounds__(kFftThreads, 6) void corr_rows_p2_kernel(CorrArgs g)
+{
+    const CorrItem it = g.items[blockIdx.x];
+    if (it.lattice < 0) return;
+    rows_p2_block<S, LG>(g, it);
+}
+
+template <int S>
+__global__ __launch_bounds__(kFftThreads, 6) void corr_rows_blue_kernel(CorrArgs g)
+{
+    const CorrItem it = g.items[blockIdx.x];
+    if (it.lattice < 0) return;
+    switch (g.plans[g.params[it.lattice].line_x].log2m) {
+    case 8: rows_blue_block<S, 8>(g, it); break;
+    case 9: rows_blue_block<S, 9>(g, it); break;
+    case 10: rows_blue_block<S, 10>(g, it); break;
+    case 11: rows_blue_block<S, 11>(g, it); break;
+    default: break;
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void corr_csum_kernel(CorrArgs g, int nlat)
 {
     const int l = blockIdx.x;
@@ -942,6 +1155,9 @@ static void rows_for(const DeviceView &v, const CorrArgs &g, int nitems, int lds
         hipLaunchKernelGGL((corr_rows_kernel<kF16, BLUE>), grid, block, lds_bytes, s, g);
 }
 
+bool corr_rows_p2_supported(int lg) { return lg >= 9 && lg <= 12; }
+bool corr_rows_blue_supported(int lg) { return lg >= 8 && lg <= 11; }
+
 template <int LG>
 static void rows_p2_for(const DeviceView &v, const CorrArgs &g, int nitems, int lds_bytes,
                         hipStream_t s)
@@ -955,26 +1171,35 @@ static void rows_p2_for(const DeviceView &v, const CorrArgs &g, int nitems, int 
         hipLaunchKernelGGL((corr_rows_p2_kernel<kF16, LG>), grid, block, lds_bytes, s, g);
 }
 
-bool corr_rows_p2_supported(int lg) { return lg >= 9 && lg <= 12; }
-
 hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems,
-                            const RowLaunch *p2, int np2, const CorrItem *blue_items, int nblue,
-                            int lds_bytes, hipStream_t s)
+                            const RowLaunch *fixed, int nfixed, const CorrItem *blue_items,
+                            int nblue, int lds_bytes, hipStream_t s)
 {
-    if (nitems) {
-        rows_for<false>(v, make_args(v, items, 0), nitems, lds_bytes, s);
+    // the length-specialised blocks first (Bluestein, the most expensive,
+    // ahead of the power-of-two lengths)
+    for (int q = 0; q < nfixed; ++q) {
+        const CorrArgs g = make_args(v, items + fixed[q].off, 0);
+        const dim3 grid(fixed[q].n), block(kFftThreads);
+        switch (fixed[q].lg) {
+        case 0:  // every Bluestein work length of corr_rows_blue_supported
+            if (v.storage == kF32)
+                hipLaunchKernelGGL(corr_rows_blue_kernel<kF32>, grid, block, lds_bytes, s, g);
+            else if (v.storage == kBF16)
+                hipLaunchKernelGGL(corr_rows_blue_kernel<kBF16>, grid, block, lds_bytes, s, g);
+            else
+                hipLaunchKernelGGL(corr_rows_blue_kernel<kF16>, grid, block, lds_bytes, s, g);
+            break;
+        case 9: rows_p2_for<9>(v, g, fixed[q].n, lds_bytes, s); break;
+        case 10: rows_p2_for<10>(v, g, fixed[q].n, lds_bytes, s); break;
+        case 11: rows_p2_for<11>(v, g, fixed[q].n, lds_bytes, s); break;
+        case 12: rows_p2_for<12>(v, g, fixed[q].n, lds_bytes, s); break;
+        default: return hipErrorInvalidValue;
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    for (int q = 0; q < np2; ++q) {
-        const CorrArgs g = make_args(v, items + p2[q].off, 0);
-        switch (p2[q].lg) {
-        case 9: rows_p2_for<9>(v, g, p2[q].n, lds_bytes, s); break;
-        case 10: rows_p2_for<10>(v, g, p2[q].n, lds_bytes, s); break;
-        case 11: rows_p2_for<11>(v, g, p2[q].n, lds_bytes, s); break;
-        case 12: rows_p2_for<12>(v, g, p2[q].n, lds_bytes, s); break;
-        default: return hipErrorInvalidValue;
-        }
+    if (nitems) {
+        rows_for<false>(v, make_args(v, items, 0), nitems, lds_bytes, s);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -170,16 +170,22 @@ hipError_t launch_debug_noise(uint64_t seed, uint32_t stream_id, uint32_t t, int
 // Field set 0 (rho, j, u; kKinds kinds): fused fields + row transforms
 // (items of power-of-two rows and of Bluestein rows), then the conservation
 // sums of the sampled state.  Rows of 2^lg points, 9 <= lg <= 12
-// (corr_rows_p2_supported), go to a kernel specialised per length: launch q
-// takes items[p2[q].off .. p2[q].off + p2[q].n), all of lattices with rows of
-// 2^p2[q].lg points; the generic kernel takes items[0 .. nitems).
+// (corr_rows_p2_supported), and Bluestein rows of work length 2^lg,
+// 8 <= lg <= 11 (corr_rows_blue_supported), take blocks specialised per
+// length: launch q of `fixed` takes items[fixed[q].off .. + fixed[q].n),
+// the power-of-two rows of length 2^lg (lg = fixed[q].lg) or, for lg = 0,
+// the Bluestein rows of every supported work length.  The generic kernels
+// take the other power-of-two rows, items[0 .. nitems), and the other
+// Bluestein rows, blue_items.  Every block of these kernels holds 4096
+// complex values of LDS (lds_bytes for the padded slots).
 struct RowLaunch {
     int lg, off, n;
 };
 bool corr_rows_p2_supported(int lg);
+bool corr_rows_blue_supported(int lg);
 hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems,
-                            const RowLaunch *p2, int np2, const CorrItem *blue_items, int nblue,
-                            int lds_bytes, hipStream_t s);
+                            const RowLaunch *fixed, int nfixed, const CorrItem *blue_items,
+                            int nblue, int lds_bytes, hipStream_t s);
 // Field set 1 (the six non-conserved moments, kinds kKinds .. kKinds + 5):
 // FP32 field planes, then row transforms.
 hipError_t launch_corr_moment_fields(const DeviceView &v, const CorrItem *items, int nitems,

@@ -128,9 +128,9 @@ struct flb {
     int n_cols_m = 0, n_cols_lm = 0, n_rows_m = 0;
     CorrItem *d_rows_blue = nullptr;  // rows of lattices with Bluestein row transforms
     int n_rows_blue = 0;
-    // rows of 512..4096 points: launches of the length-specialised row
-    // kernel over parts of d_rows (after its first n_rows items)
-    std::vector<RowLaunch> rows_p2;
+    // launches of the length-specialised row blocks over parts of d_rows
+    // (after its first n_rows items)
+    std::vector<RowLaunch> rows_fixed;
     // power-of-two columns of 512..4096 points: persistent launches of the
     // pipelined column kernel, one per work length and field set, each with
     // its host-made schedule
@@ -562,7 +562,10 @@ int setup_correlators(flb_t *h)
     h->plans = lt.plans;
     std::vector<CorrItem> rows, cols, cols_l, accum, flds, cols_m, cols_lm, rows_m;
     std::vector<CorrItem> rows_blue, flush;
-    std::map<int, std::vector<CorrItem>> rows_p2;  // per log2 of the row length
+    // rows with length-specialised blocks: Bluestein rows per work length
+    // (longest first, one launch for all), power-of-two rows per length
+    std::vector<CorrItem> rows_fixed_blue[4];
+    std::map<int, std::vector<CorrItem>> rows_fixed_p2;
     std::map<int, std::vector<CorrItem>> pipe_full[2], pipe_part[2];  // per field set and lg
     for (size_t l = 0; l < h->params.size(); ++l) {
         const LatticeParams &P = h->params[l];
@@ -578,17 +581,17 @@ int setup_correlators(flb_t *h)
         // the row kernels pad their LDS lines (one slot per 16 and per 256);
         // the length-specialised one always transforms 4096 elements (lines
         // past the lattice's last row hold zeros)
-        const bool p2 = !lt.plans[P.line_x].bluestein &&
-                        corr_rows_p2_supported(lt.plans[P.line_x].log2m) &&
-                        P.kxp == mx / 2 + 16;
-        const int ne = p2 ? 4096 : rb * mx;
+        const LinePlan &Lx = lt.plans[P.line_x];
+        const bool p2 = !Lx.bluestein && corr_rows_p2_supported(Lx.log2m) && P.kxp == mx / 2 + 16;
+        const bool blue = Lx.bluestein && corr_rows_blue_supported(Lx.log2m);
+        const int ne = (p2 || blue) ? 4096 : rb * mx;
         const int slots = ne + (ne >> 4) + (ne >> 8) + 1;
         h->rows_lds = std::max(h->rows_lds, slots * (int)sizeof(float2));
         for (int y = 0, part = P.fld_part0; y < P.ny; y += rb, ++part) {
-            const LinePlan &Lx = lt.plans[P.line_x];
             const CorrItem ri{(int32_t)l, y, rb, part};
-            if (Lx.bluestein) rows_blue.push_back(ri);
-            else if (p2) rows_p2[Lx.log2m].push_back(ri);
+            if (blue) rows_fixed_blue[11 - Lx.log2m].push_back(ri);
+            else if (Lx.bluestein) rows_blue.push_back(ri);
+            else if (p2) rows_fixed_p2[Lx.log2m].push_back(ri);
             else rows.push_back(ri);
             if (h->moments)
                 for (int sig = 0; sig < 3; ++sig) rows_m.push_back({(int32_t)l, y, rb, sig});
@@ -674,11 +677,22 @@ int setup_correlators(flb_t *h)
     h->defer = !cols.empty() || !cols_l.empty() || !h->pipe[0].empty();
     h->pending = 0;
     h->n_rows = (int)rows.size();
-    h->rows_p2.clear();
-    for (auto &kv : rows_p2) {
-        const std::vector<CorrItem> part = xcd_order(kv.second, idle);
-        h->rows_p2.push_back({kv.first, (int)rows.size(), (int)part.size()});
-        rows.insert(rows.end(), part.begin(), part.end());
+    h->rows_fixed.clear();
+    {
+        // Bluestein rows: each work length spread over the XCDs on its own,
+        // so that every XCD gets its share of the expensive blocks
+        const int off = (int)rows.size();
+        for (const auto &part : rows_fixed_blue) {
+            if (part.empty()) continue;
+            const std::vector<CorrItem> o = xcd_order(part, idle);
+            rows.insert(rows.end(), o.begin(), o.end());
+        }
+        if ((int)rows.size() > off) h->rows_fixed.push_back({0, off, (int)rows.size() - off});
+        for (const auto &kv : rows_fixed_p2) {
+            const std::vector<CorrItem> o = xcd_order(kv.second, idle);
+            h->rows_fixed.push_back({kv.first, (int)rows.size(), (int)o.size()});
+            rows.insert(rows.end(), o.begin(), o.end());
+        }
     }
     h->n_cols = (int)cols.size();
     h->n_cols_l = (int)cols_l.size();
@@ -723,8 +737,8 @@ int enqueue_sample(flb_t *h, hipStream_t s, hipEvent_t ev_read = nullptr)
         const int ng = set ? h->n_cols_m : h->n_cols;
         const int nl = set ? h->n_cols_lm : h->n_cols_l;
         if (set == 0) {
-            FLB_HIP(launch_corr_rows(v, h->d_rows, h->n_rows, h->rows_p2.data(),
-                                     (int)h->rows_p2.size(), h->d_rows_blue, h->n_rows_blue,
+            FLB_HIP(launch_corr_rows(v, h->d_rows, h->n_rows, h->rows_fixed.data(),
+                                     (int)h->rows_fixed.size(), h->d_rows_blue, h->n_rows_blue,
                                      h->rows_lds, s));
             if (ev_read) FLB_HIP(hipEventRecord(ev_read, s));
         } else {

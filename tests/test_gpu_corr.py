@@ -35,7 +35,7 @@ def _compare(acc_g, acc_o, rtol):
                                    (128, 96), (3, 256), (40, 600), (1000, 5), (300, 7),
                                    (1500, 3), (12, 1024), (10, 2048), (6, 4096),
                                    (512, 512), (512, 300), (300, 512),
-                                   (1024, 3), (2048, 5), (4096, 3)])
+                                   (1024, 3), (2048, 5), (4096, 3), (100, 40), (200, 12)])
 def test_single_sample_matches_oracle(flb, oracle_lib, nx, ny):
     note("sample", nx, ny)
     g = flb.Lattice(nx, ny, TAU_C1, 1e-4, u0=(0.04, -0.01), seed=3)
@@ -171,11 +171,12 @@ def test_structure_factors_are_one_on_gpu(flb):
         assert abs(mean[k][m].mean()) < 0.005
 
 
-@pytest.mark.parametrize("nx,ny", [(48, 36), (512, 12), (1024, 7)])
+@pytest.mark.parametrize("nx,ny", [(48, 36), (512, 12), (1024, 7), (300, 7)])
 def test_sample_records_conservation_sums(flb, oracle_lib, nx, ny):
     """Each sample also returns the FP64 mass/momentum/staggered sums of the
     sampled state: they match the dedicated conservation call and the oracle
-    (generic and length-specialised row kernels)."""
+    (generic and length-specialised row kernels, power-of-two and
+    Bluestein)."""
     g = flb.Lattice(nx, ny, TAU_C1, 1e-3, u0=(0.03, -0.01), seed=5)
     o = oracle_lib.Lattice(nx, ny, TAU_C1, 1e-3, u0=(0.03, -0.01), seed=5)
     with pytest.raises(flb.FlbError):
