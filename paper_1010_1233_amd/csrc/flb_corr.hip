@@ -1075,6 +1075,163 @@ __global__ __launch_bounds__(cols_pipe_threads(LG)) void corr_cols_pipe_kernel(
 }
 
 // Accumulation.  item: lattice, first k of the (ny, nkx) plane.
+// Bluestein column transforms with the work length 2^LG = 256 .. 2048 fixed
+// at compile time: a block takes CB = 8192 / 2^LG columns of one field
+// (8192 complex values of LDS, two blocks per compute unit), interleaved in
+// LDS as the generic column kernel has them (element e of column c at
+// e * CB + c).  One pass of R radix-2 stages S0 .. S0+R-1 over all of them:
+template <int LG, int S0, int R, bool INV = false, bool DIF = false>
+__device__ __forceinline__ void col_fft_pass(float2 *buf, const float2 *tw, int tid)
+{
+    constexpr int LGC = 13 - LG, G = 1 << R, H = 1 << (S0 - 1);
+    constexpr int PER = (8192 >> R) / kFftThreads;  // groups per thread
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * kFftThreads;
+        const int l = idx & ((1 << LGC) - 1), gg = idx >> LGC;
+        const int k = gg & (H - 1);
+        const int e0 = ((gg >> (S0 - 1)) << (S0 - 1 + R)) + k;
+        float2 v[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) v[j] = buf[lds_slot<true>(((e0 + j * H) << LGC) + l)];
+        if constexpr (S0 == 1) {
+            group_butterflies<R, INV, DIF, true>(v, make_float2(1.f, 0.f));
+        } else {
+            float2 w = tw[k << (kTwLog - (S0 + R - 1))];
+            if (INV) w.y = -w.y;
+            group_butterflies<R, INV, DIF>(v, w);
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) buf[lds_slot<true>(((e0 + j * H) << LGC) + l)] = v[j];
+    }
+}
+
+// ... the last forward stages R .. 1, the product with the chirp kernel's
+// transform (bit-reversed order) and the first inverse stages 1 .. R on
+// groups of 2^R consecutive elements of a column (as row_blue_middle):
+template <int LG, int R>
+__device__ __forceinline__ void col_blue_middle(float2 *buf, const float2 *kern, int tid)
+{
+    constexpr int LGC = 13 - LG, G = 1 << R, PER = (8192 >> R) / kFftThreads;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * kFftThreads;
+        const int l = idx & ((1 << LGC) - 1), e0 = (idx >> LGC) << R;
+        float2 v[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) v[j] = buf[lds_slot<true>(((e0 + j) << LGC) + l)];
+        group_butterflies<R, false, true, true>(v, make_float2(1.f, 0.f));
+#pragma unroll
+        for (int j = 0; j < G; ++j) v[j] = cmul(v[j], kern[e0 + j]);
+        group_butterflies<R, true, false, true>(v, make_float2(1.f, 0.f));
+#pragma unroll
+        for (int j = 0; j < G; ++j) buf[lds_slot<true>(((e0 + j) << LGC) + l)] = v[j];
+    }
+}
+
+// ... and the block: what corr_cols_kernel computes for such columns.  Each
+// thread reads the column elements e = k + j 2^LG/16 (j < 16) of its column,
+// one group of the forward transform's first radix-16 pass (decimation in
+// frequency, natural order); as 2^LG >= 2 ny - 1 only j < 8 can hold rows,
+// and that pass runs in registers on the loaded, chirp-multiplied values.
+// The inverse transform's last radix-16 pass leaves the elements in natural
+// order and stores them (times the output chirp) from registers.  LDS
+// round trips per block: 4 (2^11, 2^10, 2^9) or 2 (2^8).
+template <int LG>
+__device__ __forceinline__ void cols_blue_block(const CorrArgs &g, const CorrItem &it)
+{
+    constexpr int M = 1 << LG, LGC = 13 - LG, CB = 1 << LGC, H = M >> 4;
+    static_assert(LG >= 8 && LG <= 11, "work lengths 256 .. 2048");
+    extern __shared__ float2 lds[];
+    const LatticeParams &P = g.params[it.lattice];
+    const LinePlan &L = g.plans[P.line_y];
+    const int ny = P.ny, nkx = P.nkx, kxp = P.kxp;
+    const int f = it.a, c0 = it.b;
+    const int ncol = min(CB, nkx - c0);
+    const int tid = (int)threadIdx.x, c = tid & (CB - 1), k = tid >> LGC;
+    const float2 *chirp = g.tables + L.chirp_off;
+    const float2 *tw = g.tables;
+    const float2 *col = g.spec + P.spec_base + (int64_t)f * ny * kxp + c0 + min(c, ncol - 1);
+
+    float2 v[16];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int e = k + j * H;
+        v[j] = e < ny ? col[(int64_t)e * kxp] : make_float2(0.f, 0.f);
+        v[j + 8] = make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int e = k + j * H;
+        v[j] = cmul(v[j], chirp[e < ny ? e : 0]);
+    }
+    // forward stages LG .. LG-3 (decimation in frequency), twiddle
+    // exp(-2 pi i k / 2^LG)
+    group_butterflies<4, false, true>(v, tw[k << (kTwLog - LG)]);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) lds[lds_slot<true>(((k + j * H) << LGC) + c)] = v[j];
+    __syncthreads();
+    const float2 *kern = g.tables + L.kernel_off;
+    if constexpr (LG == 11) {
+        col_fft_pass<LG, 5, 3, false, true>(lds, tw, tid);
+        __syncthreads();
+        col_blue_middle<LG, 4>(lds, kern, tid);
+        __syncthreads();
+        col_fft_pass<LG, 5, 3, true>(lds, tw, tid);
+    } else if constexpr (LG == 10) {
+        col_fft_pass<LG, 4, 3, false, true>(lds, tw, tid);
+        __syncthreads();
+        col_blue_middle<LG, 3>(lds, kern, tid);
+        __syncthreads();
+        col_fft_pass<LG, 4, 3, true>(lds, tw, tid);
+    } else if constexpr (LG == 9) {
+        col_fft_pass<LG, 3, 3, false, true>(lds, tw, tid);
+        __syncthreads();
+        col_blue_middle<LG, 2>(lds, kern, tid);
+        __syncthreads();
+        col_fft_pass<LG, 3, 3, true>(lds, tw, tid);
+    } else {
+        col_blue_middle<LG, 4>(lds, kern, tid);
+    }
+    __syncthreads();
+    // inverse stages LG-3 .. LG: groups k of elements k + j 2^LG/16, natural
+    // order when they leave; rows e < ny are kept (e < 2^LG/2: j < 8)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = lds[lds_slot<true>(((k + j * H) << LGC) + c)];
+    float2 w = tw[k << (kTwLog - LG)];
+    w.y = -w.y;
+    group_butterflies<4, true, false>(v, w);
+    if (c >= ncol) return;
+    // the transformed column goes back in place, or to stash slot g.arg >= 0
+    // (column-tiled)
+    const bool tiled = g.arg >= 0;
+    float2 *out = (tiled ? g.stash + (int64_t)g.arg * g.stash_stride : g.spec) + P.spec_base +
+                  (int64_t)f * ny * kxp;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int e = k + j * H;
+        if (e >= ny) break;
+        const float2 y = cmul(v[j], chirp[e]);
+        if (tiled) stream_store(&out[spec_offset(e, c0 + c, ny)], y);
+        else out[(int64_t)e * kxp + c0 + c] = y;
+    }
+}
+
+// All Bluestein columns of work length 2^8 .. 2^11 (corr_cols_blue_supported)
+// in one launch, each block taking the code of its lattice's plan.
+__global__ __launch_bounds__(kFftThreads, 4) void corr_cols_blue_kernel(CorrArgs g)
+{
+    const CorrItem it = g.items[blockIdx.x];
+    if (it.lattice < 0) return;
+    switch (g.plans[g.params[it.lattice].line_y].log2m) {
+    case 8: cols_blue_block<8>(g, it); break;
+    case 9: cols_blue_block<9>(g, it); break;
+    case 10: cols_blue_block<10>(g, it); break;
+    case 11: cols_blue_block<11>(g, it); break;
+    default: break;
+    }
+}
+
 // Row and column (ky, kx) of position o of a column-tiled plane; whether it
 // holds a k that is accumulated: not a padding column (kx >= nkx), not k = 0
 // (which carries no fluctuation).
@@ -1242,6 +1399,19 @@ hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nit
     CorrArgs g = make_args(v, items, 0);
     g.arg = nslots;
     hipLaunchKernelGGL(corr_flush_kernel, dim3(nitems), dim3(kThreads), 0, s, g);
+    return hipGetLastError();
+}
+
+bool corr_cols_blue_supported(int lg) { return lg >= 8 && lg <= 11; }
+int corr_cols_blue_lds_bytes() { return lds_padded_elems(8192) * (int)sizeof(float2); }
+
+hipError_t launch_corr_cols_blue(const DeviceView &v, const CorrItem *items, int nitems, int slot,
+                                 hipStream_t s)
+{
+    CorrArgs g = make_args(v, items, 0);
+    g.arg = slot;
+    hipLaunchKernelGGL(corr_cols_blue_kernel, dim3(nitems), dim3(kFftThreads),
+                       corr_cols_blue_lds_bytes(), s, g);
     return hipGetLastError();
 }
 

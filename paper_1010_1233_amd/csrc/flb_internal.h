@@ -203,6 +203,13 @@ constexpr int kColsLargeElems = 16384;
 constexpr int kColsLargeThreads = 1024;
 hipError_t launch_corr_cols(const DeviceView &v, const CorrItem *items, int nitems, int slot,
                             bool large, int lds_bytes, hipStream_t s);
+// Column transforms of Bluestein work length 2^lg, 8 <= lg <= 11
+// (corr_cols_blue_supported), field set 0, in blocks specialised per work
+// length, all in one launch: items {lattice, field, first column, unused},
+// 8192 / 2^lg columns per item.  `slot` as for launch_corr_cols.
+bool corr_cols_blue_supported(int lg);
+hipError_t launch_corr_cols_blue(const DeviceView &v, const CorrItem *items, int nitems, int slot,
+                                 hipStream_t s);
 // Column transforms of power-of-two lengths 2^lg, 9 <= lg <= 12, in
 // persistent blocks: sched holds niter x grid groups of columns (the group
 // of block b in round it at it * grid + b), each of 16384 / 2^lg (at most

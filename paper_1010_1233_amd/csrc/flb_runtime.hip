@@ -128,6 +128,9 @@ struct flb {
     int n_cols_m = 0, n_cols_lm = 0, n_rows_m = 0;
     CorrItem *d_rows_blue = nullptr;  // rows of lattices with Bluestein row transforms
     int n_rows_blue = 0;
+    // field set 0's Bluestein columns with length-specialised blocks
+    CorrItem *d_cols_blue = nullptr;
+    int n_cols_blue = 0;
     // launches of the length-specialised row blocks over parts of d_rows
     // (after its first n_rows items)
     std::vector<RowLaunch> rows_fixed;
@@ -561,7 +564,7 @@ int setup_correlators(flb_t *h)
 
     h->plans = lt.plans;
     std::vector<CorrItem> rows, cols, cols_l, accum, flds, cols_m, cols_lm, rows_m;
-    std::vector<CorrItem> rows_blue, flush;
+    std::vector<CorrItem> rows_blue, flush, cols_blue[4];
     // rows with length-specialised blocks: Bluestein rows per work length
     // (longest first, one launch for all), power-of-two rows per length
     std::vector<CorrItem> rows_fixed_blue[4];
@@ -608,9 +611,17 @@ int setup_correlators(flb_t *h)
                     (whole ? pipe_full[1] : pipe_part[1])[Ly.log2m].push_back(it);
                 }
         } else {
+            // field set 0's Bluestein columns of the supported work lengths:
+            // 8192 / m columns per block (longest work lengths first)
+            const bool cblue = Ly.bluestein && corr_cols_blue_supported(Ly.log2m);
+            if (cblue)
+                for (int f = 0; f < kFields; ++f)
+                    for (int c0 = 0; c0 < P.nkx; c0 += 8192 / Ly.m)
+                        cols_blue[11 - Ly.log2m].push_back({(int32_t)l, f, c0, 0});
             for (int f = 0; f < h->nfld; ++f)
                 for (int c0 = 0; c0 < P.nkx; c0 += 1 << P.col_lgcb) {
-                    if (f < kFields) (P.col_large ? cols_l : cols).push_back({(int32_t)l, f, c0, P.col_lgcb});
+                    if (f < kFields && !cblue)
+                        (P.col_large ? cols_l : cols).push_back({(int32_t)l, f, c0, P.col_lgcb});
                     (P.col_large ? cols_lm : cols_m).push_back({(int32_t)l, f, c0, P.col_lgcb});
                 }
         }
@@ -674,7 +685,14 @@ int setup_correlators(flb_t *h)
                 h->pipe[set].push_back(pl);
             }
     }
-    h->defer = !cols.empty() || !cols_l.empty() || !h->pipe[0].empty();
+    std::vector<CorrItem> cblue_all;
+    for (const auto &part : cols_blue) {
+        if (part.empty()) continue;
+        const std::vector<CorrItem> o = xcd_order(part, idle);
+        cblue_all.insert(cblue_all.end(), o.begin(), o.end());
+    }
+    h->n_cols_blue = (int)cblue_all.size();
+    h->defer = !cols.empty() || !cols_l.empty() || !h->pipe[0].empty() || !cblue_all.empty();
     h->pending = 0;
     h->n_rows = (int)rows.size();
     h->rows_fixed.clear();
@@ -704,6 +722,7 @@ int setup_correlators(flb_t *h)
         (rc = upload(&h->d_accum, accum)) || (rc = upload(&h->d_cols_lm, cols_lm)) ||
         (rc = upload(&h->d_cols_m, cols_m)) || (rc = upload(&h->d_rows_m, rows_m)) ||
         (rc = upload(&h->d_rows_blue, rows_blue)) || (rc = upload(&h->d_flush, flush)) ||
+        (rc = upload(&h->d_cols_blue, cblue_all)) ||
         (rc = upload(&h->d_plans, h->plans)) ||
         (rc = upload(&h->d_tables, lt.tables)) || (rc = upload(&h->d_params, h->params)))
         return rc;
@@ -749,6 +768,8 @@ int enqueue_sample(flb_t *h, hipStream_t s, hipEvent_t ev_read = nullptr)
         // the slots; otherwise it stays in place and is accumulated at once
         const bool stash = !set && h->defer;
         const int slot = stash ? h->pending : -1;
+        if (!set && h->n_cols_blue)
+            FLB_HIP(launch_corr_cols_blue(v, h->d_cols_blue, h->n_cols_blue, slot, s));
         if (ng) FLB_HIP(launch_corr_cols(v, cg, ng, slot, false, h->cols_lds, s));
         if (nl) FLB_HIP(launch_corr_cols(v, cl, nl, slot, true, h->cols_l_lds, s));
         for (const auto &pl : h->pipe[set])
@@ -1049,7 +1070,7 @@ void flb_destroy(flb_t *h)
                     h->d_plans, h->d_tables, h->d_spec, h->d_acc, h->d_rows, h->d_cols,
                     h->d_accum, h->d_cols_l, h->d_fld, h->d_fields,
                     h->d_csum_part, h->d_csum, h->d_cols_lm, h->d_cols_m, h->d_rows_m,
-                    h->d_rows_blue, h->d_stash, h->d_flush, h->d_items2};
+                    h->d_rows_blue, h->d_stash, h->d_flush, h->d_items2, h->d_cols_blue};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &set : h->pipe)
