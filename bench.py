@@ -20,9 +20,10 @@ The JSON line also carries
                 (9 reads + 9 writes per site update, times the updates of
                 one launch: two per site for the time-blocked kernel, which
                 moves the state once for both) over its average duration,
-                measured with a HIP event pair around every launch on the
-                stream it runs on, within the timed region (so while the
-                sample shares the device; `isolated` repeats the figures
+                measured with a HIP event pair around each launch of every
+                fourth benchmark step on the stream it runs on, within the
+                timed region (so while the sample shares the device;
+                `launches_timed` counts them; `isolated` repeats the figures
                 for the kernel alone);
                 HBM traffic per launch from rocprofv3 counters when a
                 summary for the current kernel source is committed, and the
@@ -60,6 +61,7 @@ SAMPLE_EVERY = 10
 # samples per read-modify-write pass of the FP64 correlator sums in the
 # library (the others keep their spectra until then)
 ACCUMULATE_EVERY = 32
+LAUNCH_TIMING_EVERY = 4  # benchmark steps per step whose launches are timed
 STEP_KERNEL = "step_kernel"
 
 
@@ -444,21 +446,28 @@ def main():
         g.flush_correlators()
         g.synchronize()
         torch.cuda.synchronize()
-        # HIP event pairs around every step-kernel launch of the timed region
-        g.set_launch_timing(True)
+        # HIP event pairs around the step-kernel launches of every
+        # LAUNCH_TIMING_EVERY-th benchmark step of the timed region (an event
+        # pair around every launch cost about 20 us per benchmark step)
         t0 = time.perf_counter()
         for i in range(args.steps):
-            bench_step()
+            timed = i % LAUNCH_TIMING_EVERY == 0
+            if timed:
+                g.set_launch_timing(True)
+            g.step(SAMPLE_EVERY)
+            if timed:
+                g.set_launch_timing(False)
+            g.accumulate()
         # enqueues the last sample and the products of the stashed ones
         g.flush_correlators()
         g.synchronize()
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        g.set_launch_timing(False)
         n_launches, launch_total_ms = g.launch_timing()
 
     steps_per_launch = g.time_blocking()[0]
-    assert n_launches * steps_per_launch == args.steps * SAMPLE_EVERY, n_launches
+    steps_timed = -(-args.steps // LAUNCH_TIMING_EVERY)
+    assert n_launches * steps_per_launch == steps_timed * SAMPLE_EVERY, n_launches
     step_ms = launch_total_ms / n_launches / steps_per_launch
     ms_per_step = elapsed * 1e3 / args.steps
     value = args.steps * SAMPLE_EVERY * V / elapsed / 1e9
@@ -503,6 +512,7 @@ def main():
                      "steps_per_launch": launch["steps_per_launch"],
                      "algorithmic_bytes_per_launch": launch["algorithmic_bytes_per_launch"],
                      "avg_launch_ms": launch["avg_launch_ms"],
+                     "launches_timed": n_launches,
                      "launch_shape": list(tuned) + [list(blocking)],
                      "measured_GBs": (None if traffic is None else
                                       traffic / (launch["avg_launch_ms"] * 1e-3) / 1e9),
