@@ -396,7 +396,10 @@ __device__ __forceinline__ void rows_p2_block(const CorrArgs &g, const CorrItem 
     const int64_t fstride = (int64_t)P.ny * P.kxp;
     const float rho0 = P.rho0, u0x = P.u0x, u0y = P.u0y;
     const float jx0 = rho0 * u0x, jy0 = rho0 * u0y;
-#pragma unroll 1
+    // (unrolled, so that the sites' j die after the second field pair and
+    // the kernel keeps to 80 registers without spilling; rolled up, the
+    // loop held every site value to its end and spilled)
+#pragma unroll
     for (int sig = 0; sig < 3; ++sig) {
         // LDS addresses are recomputed for every signal rather than kept in
         // registers through the loop
@@ -535,7 +538,7 @@ __device__ __forceinline__ void rows_blue_block(const CorrArgs &g, const CorrIte
     float2 *spec = g.spec + P.spec_base;
     const float rho0 = P.rho0, u0x = P.u0x, u0y = P.u0y;
     const float jx0 = rho0 * u0x, jy0 = rho0 * u0y;
-#pragma unroll 1
+#pragma unroll
     for (int sig = 0; sig < 3; ++sig) {
         int tid = t;
         asm volatile("" : "+v"(tid));
@@ -633,8 +636,11 @@ __global__ __launch_bounds__(kFftThreads, 6) void corr_rows_p2_kernel(CorrArgs g
     rows_p2_block<S, LG>(g, it);
 }
 
+// (64 registers, four blocks per compute unit: 20 bytes of each thread
+// spill, and the uneven batch's sample is still 2 % faster than with three
+// blocks and no spill)
 template <int S>
-__global__ __launch_bounds__(kFftThreads, 6) void corr_rows_blue_kernel(CorrArgs g)
+__global__ __launch_bounds__(kFftThreads, 8) void corr_rows_blue_kernel(CorrArgs g)
 {
     const CorrItem it = g.items[blockIdx.x];
     if (it.lattice < 0) return;
