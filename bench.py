@@ -40,7 +40,9 @@ The JSON line also carries
                 and the other velocity sets (D3Q15 at 256^3 with its
                 correlators, D1Q3 at 2^26 sites).
 Every handle's step-kernel launch shape is chosen by the library's autotuner
-before timing.
+before timing: on whole sampling periods (flb_autotune_path) for the
+headline workload and the batched forms, on the step kernel alone
+(flb_autotune) for the storage forms' step rates.
 """
 from __future__ import annotations
 
@@ -195,7 +197,7 @@ def batched_form(torch, flb, stream, specs, storage, periods=ACCUMULATE_EVERY):
     b = flb.Lattice.batch(specs, seed=3, storage=storage)
     b.set_stream(stream)
     b.thermalize()
-    shape, _ = b.autotune(50)
+    shape, _ = b.autotune_path(50, SAMPLE_EVERY)
     sites = sum(s["nx"] * s["ny"] for s in specs)
     b.run(periods * SAMPLE_EVERY, SAMPLE_EVERY)  # capture the graphs
     b.synchronize()
@@ -428,7 +430,9 @@ def main():
     print(f"bench: {args.workload} {c['nx']}x{c['ny']} storage={args.storage} "
           f"step config={g.step_config()}", file=sys.stderr, flush=True)
     g.thermalize()
-    tuned, _ = g.autotune(50)
+    # the launch shape that makes the whole path fastest (the shapes nearly
+    # tied alone, timed on periods with the sample beside the steps)
+    tuned, _ = g.autotune_path(50, SAMPLE_EVERY)
     blocking = g.time_blocking()
     print(f"bench: autotuned step config {tuned}, steps per launch {blocking}", file=sys.stderr,
           flush=True)

@@ -345,9 +345,22 @@ int flb_get_time_blocking(flb_t *h, int *steps_per_launch, int *tile_w);
  * step counter are restored afterwards, so results are unchanged.  When the
  * environment variable FLB_AUTOTUNE_CACHE names a file, choices are read
  * from and appended to it, keyed by storage format, lattice count, total
- * sites and largest side.  Synchronises. *ms_out (may be NULL) receives the
- * chosen shape's time per step. */
+ * sites, largest side and noise.  Synchronises. *ms_out (may be NULL)
+ * receives the chosen shape's time per step. */
 int flb_autotune(flb_t *h, int nsteps, double *ms_out);
+
+/* As flb_autotune, then for the shapes within 4 % of the fastest alone (at
+ * most four) the whole path decides: each is timed on whole periods of
+ * sample_every >= 1 steps and a correlator sample (Eqs. 11-12), issued as
+ * flb_step and flb_accumulate_correlators issue them (with sample overlap,
+ * each sample runs beside the following steps, which a shape's time alone
+ * does not show), over a full accumulation cycle in two round-robin passes,
+ * and the fastest period is kept.  Only before the first sample (or after
+ * flb_reset_correlators): FLB_ESTATE otherwise.  Populations, step counter
+ * and correlator sums are as before the call.  Cached as flb_autotune under
+ * a key that includes sample_every.  *ms_out receives the chosen shape's
+ * whole-path time per step. */
+int flb_autotune_path(flb_t *h, int nsteps, int sample_every, double *ms_out);
 
 #ifdef __cplusplus
 }

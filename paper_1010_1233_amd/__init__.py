@@ -110,6 +110,7 @@ SIGNATURES = {
     "flb_set_time_blocking": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "flb_get_time_blocking": (ctypes.c_int, [ctypes.c_void_p, _intp, _intp]),
     "flb_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp]),
+    "flb_autotune_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp]),
     # other velocity sets (flb_dq.h)
     "flb_dq_tables": (ctypes.c_int, [ctypes.c_int, _i32p, _i32p, _i32p, _dp, _dp]),
     "flb_dq_create": (ctypes.c_void_p, [ctypes.c_int, _i32p, _dp, ctypes.c_double,
@@ -313,6 +314,14 @@ class Lattice:
         a, b = ctypes.c_int(), ctypes.c_int()
         _check(lib().flb_get_time_blocking(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def autotune_path(self, nsteps=10, sample_every=10):
+        """Tune the step launch shape on whole sampling periods (see
+        flb_autotune_path): returns the chosen (tile_w, sites, nontemporal)
+        and the whole path's ms per step."""
+        ms = ctypes.c_double()
+        _check(lib().flb_autotune_path(self._h, int(nsteps), int(sample_every), ctypes.byref(ms)))
+        return self.step_config(), ms.value
 
     def autotune(self, nsteps=10):
         """Time every step-kernel launch shape on this handle, the

@@ -1562,10 +1562,25 @@ int flb_get_step_config(flb_t *h, int *tile_w, int *sites, int *nontemporal)
     return FLB_OK;
 }
 
-int flb_autotune(flb_t *h, int nsteps, double *ms_out)
+}  // extern "C"
+
+// A step launch shape: one-step tile width, sites per thread, streaming
+// accesses, steps per launch (1 or 2), two-step tile width.
+struct StepShape {
+    int tw, sv, nt, tb, t2;
+};
+
+static void apply_shape(flb_t *h, const StepShape &c)
 {
-    if (check_handle(h)) return FLB_EINVAL;
-    if (nsteps < 1) return fail(FLB_EINVAL, "nsteps must be >= 1");
+    h->tile_w = c.tw;
+    h->sites = c.sv;
+    h->nontemporal = c.nt != 0;
+    h->tblock = c.tb;
+    h->tile2 = c.t2;
+}
+
+static std::string tune_key(const flb_t *h, const char *kind, int every)
+{
     int64_t total = 0;
     int maxside = 0;
     for (auto &P : h->params) {
@@ -1573,35 +1588,47 @@ int flb_autotune(flb_t *h, int nsteps, double *ms_out)
         maxside = std::max(maxside, std::max(P.nx, P.ny));
     }
     char key[160];
-    snprintf(key, sizeof key, "flb-step:%d:%zu:%lld:%d:%d", h->storage, h->params.size(),
-             (long long)total, maxside, h->noise ? 1 : 0);
-    const char *cache = getenv("FLB_AUTOTUNE_CACHE");
-    if (cache) {
-        if (FILE *fp = fopen(cache, "r")) {
-            char k[160];
-            int tw, sv, nt, tb, t2;
-            double ms;
-            int found = 0;
-            while (fscanf(fp, "%159s %d %d %d %d %d %lf", k, &tw, &sv, &nt, &tb, &t2, &ms) == 7)
-                if (strcmp(k, key) == 0 && step_tile_supported(tw, sv) && (tb == 1 || tb == 2) &&
-                    step2_tile_supported(t2)) {
-                    found = 1;
-                    h->tile_w = tw;
-                    h->sites = sv;
-                    h->nontemporal = nt != 0;
-                    h->tblock = tb;
-                    h->tile2 = t2;
-                    if (ms_out) *ms_out = ms;
-                }
-            fclose(fp);
-            if (found) {
-                clear_graphs(h);
-                return build_step_items(h);
-            }
-        }
-    }
+    snprintf(key, sizeof key, "%s:%d:%zu:%lld:%d:%d:%d", kind, h->storage, h->params.size(),
+             (long long)total, maxside, h->noise ? 1 : 0, every);
+    return key;
+}
 
-    // save the state: the candidates advance it (a due sample reads it first)
+// A shape from the FLB_AUTOTUNE_CACHE file, if it names one for this key.
+static bool cached_shape(const char *cache, const std::string &key, StepShape &c, double &ms)
+{
+    if (!cache) return false;
+    FILE *fp = fopen(cache, "r");
+    if (!fp) return false;
+    char k[160];
+    StepShape x{};
+    double t = 0;
+    bool found = false;
+    while (fscanf(fp, "%159s %d %d %d %d %d %lf", k, &x.tw, &x.sv, &x.nt, &x.tb, &x.t2, &t) == 7)
+        if (key == k && step_tile_supported(x.tw, x.sv) && (x.tb == 1 || x.tb == 2) &&
+            step2_tile_supported(x.t2)) {
+            found = true;
+            c = x;
+            ms = t;
+        }
+    fclose(fp);
+    return found;
+}
+
+static void cache_shape(const char *cache, const std::string &key, const StepShape &c, double ms)
+{
+    if (!cache) return;
+    if (FILE *fp = fopen(cache, "a")) {
+        fprintf(fp, "%s %d %d %d %d %d %.6f\n", key.c_str(), c.tw, c.sv, c.nt, c.tb, c.t2, ms);
+        fclose(fp);
+    }
+}
+
+// Runs body(h) between a saved and a restored state: the populations, the
+// device and host step counters and the buffer parity are put back
+// afterwards, and launch timing is off meanwhile (the candidates' launches
+// are not the caller's).
+template <typename F> static int with_saved_state(flb_t *h, F body)
+{
     if (int rc0 = settle_due(h)) return rc0;
     FLB_HIP(hipStreamSynchronize(h->stream));
     const size_t bytes = (size_t)h->total_elems * h->elem_bytes;
@@ -1609,105 +1636,179 @@ int flb_autotune(flb_t *h, int nsteps, double *ms_out)
     FLB_HIP(hipMalloc(&saved, bytes));
     uint32_t step0 = 0;
     const int cur0 = h->cur;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    int rc = FLB_OK;
+    const int64_t t0 = h->t;
+    const bool timing0 = h->timing;
+    const StepShape shape0{h->tile_w, h->sites, h->nontemporal ? 1 : 0, h->tblock, h->tile2};
+    h->timing = false;
     hipError_t e = hipMemcpyAsync(saved, h->pops[cur0], bytes, hipMemcpyDeviceToDevice, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&step0, h->d_step, sizeof step0, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e == hipSuccess) e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    // every shape is timed in each of kRounds round-robin passes and keeps its
-    // fastest pass, so that a slow moment of the device does not decide
-    constexpr int kRounds = 3;
-    const int tws[3] = {64, 128, 256}, svs[3] = {1, 2, 4};
-    float tbest[3][3][2];
-    for (auto &x : tbest)
-        for (auto &y : x) y[0] = y[1] = 1e30f;
-    // two-step candidates: tile widths 64, 128, streaming or not
-    const int t2s[2] = {64, 128};
-    float t2best[2][2] = {{1e30f, 1e30f}, {1e30f, 1e30f}};
-    const int n2 = nsteps + (nsteps & 1);  // whole pairs
-    auto time_steps = [&](int n, float &best_ms) {
-        if ((rc = build_step_items(h)) != FLB_OK) return;
-        if ((rc = enqueue_steps(h, 2, h->stream)) != FLB_OK) return;
-        e = hipEventRecord(e0, h->stream);
-        if (e == hipSuccess && (rc = enqueue_steps(h, n, h->stream)) != FLB_OK) return;
-        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e == hipSuccess) best_ms = std::min(best_ms, ms / n);
-    };
-    const int tb0 = h->tblock, t20 = h->tile2;
-    const bool timing0 = h->timing;  // the candidates' launches are not the caller's
-    h->timing = false;
-    for (int round = 0; round < kRounds && e == hipSuccess && rc == FLB_OK; ++round) {
-        h->tblock = 1;
-        for (int a = 0; a < 3 && e == hipSuccess && rc == FLB_OK; ++a)
-            for (int b = 0; b < 3 && e == hipSuccess && rc == FLB_OK; ++b)
-                for (int nt = 0; nt < 2 && e == hipSuccess && rc == FLB_OK; ++nt) {
-                    h->tile_w = tws[a];
-                    h->sites = svs[b];
-                    h->nontemporal = nt != 0;
-                    time_steps(nsteps, tbest[a][b][nt]);
-                }
-        h->tblock = 2;
-        for (int a = 0; a < 2 && e == hipSuccess && rc == FLB_OK; ++a)
-            for (int nt = 0; nt < 2 && e == hipSuccess && rc == FLB_OK; ++nt) {
-                h->tile2 = t2s[a];
-                h->nontemporal = nt != 0;
-                time_steps(n2, t2best[a][nt]);
-            }
-    }
-    h->tblock = tb0;
-    h->tile2 = t20;
+    int rc = e == hipSuccess ? body(h) : FLB_OK;
     h->timing = timing0;
-    int best_tw = h->tile_w, best_sv = h->sites;
-    bool best_nt = h->nontemporal;
-    float best = 1e30f;
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
-            for (int nt = 0; nt < 2; ++nt)
-                if (tbest[a][b][nt] < best) {
-                    best = tbest[a][b][nt];
-                    best_tw = tws[a];
-                    best_sv = svs[b];
-                    best_nt = nt != 0;
-                }
-    int best_tb = 1, best_t2 = h->tile2;
-    for (int a = 0; a < 2; ++a)
-        for (int nt = 0; nt < 2; ++nt)
-            if (t2best[a][nt] < best) {
-                best = t2best[a][nt];
-                best_tb = 2;
-                best_t2 = t2s[a];
-                best_nt = nt != 0;
-            }
-    // restore the state, the step counter and the buffer parity
+    apply_shape(h, shape0);
     h->cur = cur0;
+    h->t = t0;
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->pops[cur0], saved, bytes, hipMemcpyDeviceToDevice, h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->d_step, &step0, sizeof step0, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(saved);
+    clear_graphs(h);
     if (rc != FLB_OK) return rc;
     if (e != hipSuccess) return fail(FLB_EHIP, std::string("autotune: ") + hipGetErrorString(e));
-    h->tile_w = best_tw;
-    h->sites = best_sv;
-    h->nontemporal = best_nt;
-    h->tblock = best_tb;
-    h->tile2 = best_t2;
+    return build_step_items(h);
+}
+
+// Times every supported launch shape alone (nsteps steps each, whole pairs
+// for the two-step kernel) in kRounds round-robin passes, each shape keeping
+// its fastest pass, so that a slow moment of the device does not decide; ms
+// per step, fastest first.
+static int time_every_shape(flb_t *h, int nsteps, std::vector<std::pair<float, StepShape>> &out)
+{
+    constexpr int kRounds = 3;
+    std::vector<StepShape> shapes;
+    for (int tw : {64, 128, 256})
+        for (int sv : {1, 2, 4})
+            for (int nt = 0; nt < 2; ++nt) shapes.push_back({tw, sv, nt, 1, h->tile2});
+    for (int t2 : {64, 128})
+        for (int nt = 0; nt < 2; ++nt) shapes.push_back({h->tile_w, h->sites, nt, 2, t2});
+    std::vector<float> best(shapes.size(), 1e30f);
+    return with_saved_state(h, [&](flb_t *hh) -> int {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        int rc = FLB_OK;
+        for (int round = 0; round < kRounds && e == hipSuccess && rc == FLB_OK; ++round)
+            for (size_t i = 0; i < shapes.size() && e == hipSuccess && rc == FLB_OK; ++i) {
+                apply_shape(hh, shapes[i]);
+                const int n = shapes[i].tb == 2 ? nsteps + (nsteps & 1) : nsteps;
+                if ((rc = build_step_items(hh)) != FLB_OK) break;
+                if ((rc = enqueue_steps(hh, 2, hh->stream)) != FLB_OK) break;
+                e = hipEventRecord(e0, hh->stream);
+                if (e == hipSuccess && (rc = enqueue_steps(hh, n, hh->stream)) != FLB_OK) break;
+                if (e == hipSuccess) e = hipEventRecord(e1, hh->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e == hipSuccess) best[i] = std::min(best[i], ms / n);
+            }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (rc != FLB_OK) return rc;
+        if (e != hipSuccess) return fail(FLB_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+        out.clear();
+        for (size_t i = 0; i < shapes.size(); ++i) out.push_back({best[i], shapes[i]});
+        std::stable_sort(out.begin(), out.end(),
+                         [](const std::pair<float, StepShape> &a,
+                            const std::pair<float, StepShape> &b) { return a.first < b.first; });
+        return FLB_OK;
+    });
+}
+
+extern "C" {
+
+int flb_autotune(flb_t *h, int nsteps, double *ms_out)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (nsteps < 1) return fail(FLB_EINVAL, "nsteps must be >= 1");
+    const std::string key = tune_key(h, "flb-step", 0);
+    const char *cache = getenv("FLB_AUTOTUNE_CACHE");
+    StepShape c{};
+    double ms = 0;
+    if (cached_shape(cache, key, c, ms)) {
+        apply_shape(h, c);
+        if (ms_out) *ms_out = ms;
+        clear_graphs(h);
+        return build_step_items(h);
+    }
+    std::vector<std::pair<float, StepShape>> t;
+    if (int rc = time_every_shape(h, nsteps, t)) return rc;
+    apply_shape(h, t[0].second);
     clear_graphs(h);
-    if (ms_out) *ms_out = best;
-    if (cache)
-        if (FILE *fp = fopen(cache, "a")) {
-            fprintf(fp, "%s %d %d %d %d %d %.6f\n", key, best_tw, best_sv, best_nt ? 1 : 0,
-                    best_tb, best_t2, (double)best);
-            fclose(fp);
-        }
+    if (ms_out) *ms_out = t[0].first;
+    cache_shape(cache, key, t[0].second, t[0].first);
+    return build_step_items(h);
+}
+
+int flb_autotune_path(flb_t *h, int nsteps, int sample_every, double *ms_out)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (nsteps < 1 || sample_every < 1) return fail(FLB_EINVAL, "nsteps and sample_every must be >= 1");
+    if (h->nsamples != 0 || h->due || h->pending)
+        return fail(FLB_ESTATE, "tune the whole path before taking correlator samples");
+    const std::string key = tune_key(h, "flb-path", sample_every);
+    const char *cache = getenv("FLB_AUTOTUNE_CACHE");
+    StepShape c{};
+    double ms = 0;
+    if (cached_shape(cache, key, c, ms)) {
+        apply_shape(h, c);
+        if (ms_out) *ms_out = ms;
+        clear_graphs(h);
+        return build_step_items(h);
+    }
+    int rc = setup_correlators(h);
+    if (rc) return rc;
+    std::vector<std::pair<float, StepShape>> t;
+    if ((rc = time_every_shape(h, nsteps, t))) return rc;
+    // the shapes within 4 % of the fastest alone (at most four) are timed
+    // on whole periods: sample_every steps and a sample, the sample beside
+    // the next period's steps as with the handle's own calls, in two
+    // round-robin passes of kDeferK periods (a whole accumulation cycle)
+    std::vector<StepShape> cand;
+    for (const auto &x : t)
+        if (x.first <= 1.04f * t[0].first && cand.size() < 4) cand.push_back(x.second);
+    std::vector<float> best(cand.size(), 1e30f);
+    if (cand.size() > 1) {
+        rc = with_saved_state(h, [&](flb_t *hh) -> int {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            hipError_t e = hipEventCreate(&e0);
+            if (e == hipSuccess) e = hipEventCreate(&e1);
+            int r = FLB_OK;
+            auto periods = [&](int n) -> int {
+                for (int p = 0; p < n; ++p) {
+                    if (int q = flb_step(hh, sample_every)) return q;
+                    if (int q = flb_accumulate_correlators(hh)) return q;
+                }
+                if (int q = settle_due(hh)) return q;
+                return flush_pending(hh);
+            };
+            for (int round = 0; round < 2 && e == hipSuccess && r == FLB_OK; ++round)
+                for (size_t i = 0; i < cand.size() && e == hipSuccess && r == FLB_OK; ++i) {
+                    apply_shape(hh, cand[i]);
+                    clear_graphs(hh);
+                    if ((r = build_step_items(hh)) != FLB_OK) break;
+                    if ((r = periods(4)) != FLB_OK) break;
+                    e = hipEventRecord(e0, hh->stream);
+                    if (e == hipSuccess && (r = periods(kDeferK)) != FLB_OK) break;
+                    if (e == hipSuccess) e = hipEventRecord(e1, hh->stream);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    float t_ms = 0;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&t_ms, e0, e1);
+                    if (e == hipSuccess)
+                        best[i] = std::min(best[i], t_ms / ((float)kDeferK * sample_every));
+                }
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            // the tuning's samples leave nothing behind
+            const int rr = flb_reset_correlators(hh);
+            if (r == FLB_OK) r = rr;
+            if (r == FLB_OK && e != hipSuccess)
+                r = fail(FLB_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+            return r;
+        });
+        if (rc) return rc;
+    } else {
+        best[0] = t[0].first;
+    }
+    size_t k = 0;
+    for (size_t i = 1; i < cand.size(); ++i)
+        if (best[i] < best[k]) k = i;
+    apply_shape(h, cand[k]);
+    clear_graphs(h);
+    if (ms_out) *ms_out = best[k];
+    cache_shape(cache, key, cand[k], best[k]);
     return build_step_items(h);
 }
 

@@ -267,6 +267,41 @@ def test_autotune_keeps_state_and_caches(flb, tmp_path, monkeypatch):
     assert len((tmp_path / "tune.txt").read_text().splitlines()) == 1
 
 
+def test_autotune_path_keeps_state_and_sums(flb, tmp_path, monkeypatch):
+    """Tuning on whole sampling periods: the populations, the step counter
+    and the correlator sums are as before (the run after it has the bits of
+    an untuned handle set to the chosen shape); refused once a sample has
+    been taken; cached under its own key."""
+    monkeypatch.setenv("FLB_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    kw = dict(u0=(0.02, 0.0), seed=21)
+    ref = flb.Lattice(300, 128, TAU_C1, 1e-3, **kw)
+    g = flb.Lattice(300, 128, TAU_C1, 1e-3, **kw)
+    for h in (ref, g):
+        h.thermalize()
+        h.step(4)
+    cfg, ms = g.autotune_path(4, 5)
+    assert ms > 0 and cfg[0] in (64, 128, 256) and cfg[1] in (1, 2, 4)
+    assert g.t == 4
+    assert np.array_equal(g.get_populations(), ref.get_populations())
+    with pytest.raises(flb.FlbError):
+        g.sample_conservation()  # the tuning's samples were dropped
+    ref.set_step_config(*cfg)
+    ref.set_time_blocking(*g.time_blocking())
+    for h in (ref, g):
+        h.run(20, 5)
+    a, na = g.read_correlators()
+    b, nb = ref.read_correlators()
+    assert na == nb == 4 and np.array_equal(a, b)
+    assert np.array_equal(g.get_populations(), ref.get_populations())
+    with pytest.raises(flb.FlbError):
+        g.autotune_path(4, 5)  # samples taken
+    g.reset_correlators()
+    cfg2, ms2 = g.autotune_path(4, 5)  # from the cache file
+    assert cfg2 == cfg and abs(ms2 - ms) < 1e-5
+    lines = (tmp_path / "tune.txt").read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("flb-path:")
+
+
 def test_resume_from_saved_state_is_bit_identical(flb):
     """Checkpoint = populations + t (the noise is counter-based): a new handle
     given both continues exactly like the uninterrupted run."""
