@@ -282,17 +282,20 @@ def test_reads_between_paired_samples(flb, oracle_lib):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("side", [2048, 4096])
-def test_storage_formats_against_oracle(flb, oracle_lib, side):
+@pytest.mark.parametrize("nx,ny", [(2048, 2048), (4096, 4096), (600, 300), (200, 130)])
+def test_storage_formats_against_oracle(flb, oracle_lib, nx, ny):
     """The 4096^2 workload (u_x = 0.05, tau_s = 0.6, kT = 1e-4), at 4096^2
-    itself and at 2048^2: thermal start, ten steps and one sample in each
-    storage format against the oracle's FP64 run of the same trajectory
-    (one oracle run per side, about a minute at 4096^2).  Per kind, the error of the sums over k relative to their
-    size (cross kinds relative to the geometric mean of the two fields' auto
-    sums) measures what the storage format costs the correlators."""
+    itself and at 2048^2, and on sides whose transforms take Bluestein's
+    convolution (rows and columns of work lengths 2048 and 1024, 512 and
+    512): thermal start, ten steps and one sample in each storage format
+    against the oracle's FP64 run of the same trajectory (one oracle run per
+    shape, about a minute at 4096^2).  Per kind, the error of the sums over k
+    relative to their size (cross kinds relative to the geometric mean of the
+    two fields' auto sums) measures what the storage format costs the
+    correlators."""
     c = workloads.CONFIGS["c5_4096"]
-    nx = ny = side
-    note(f"{side}^2 oracle run")
+    side = f"{nx}x{ny}"
+    note(f"{side} oracle run")
     o = oracle_lib.Lattice(nx, ny, c["tau"], c["theta"], u0=c["u0"], seed=c["seed"])
     o.thermalize()
     o.step(10)
@@ -307,7 +310,7 @@ def test_storage_formats_against_oracle(flb, oracle_lib, side):
     # measured at 2048^2: worst kind 5e-7, 3.7e-4, 2.9e-3
     bounds = {"f32": 3e-6, "f16": 2e-3, "bf16": 1.5e-2}
     for storage, bound in bounds.items():
-        note(f"{side}^2", storage)
+        note(side, storage)
         g = flb.Lattice(nx, ny, c["tau"], c["theta"], u0=c["u0"], seed=c["seed"],
                         storage=storage)
         g.thermalize()
