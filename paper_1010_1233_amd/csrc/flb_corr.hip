@@ -36,8 +36,7 @@ struct CorrArgs {
     const float2 *tables;
     const CorrItem *items;
     float2 *spec;
-    float2 *stash;  // spectra of samples whose products are not yet added
-    int64_t stash_stride;  // elements per stash slot
+    float2 *stash;  // spectra of samples whose products are not yet added (stash_offset)
     int arg;        // stash slot (stash mode) or number of slots (pair mode, flush)
     double *acc;
     float *fields;
@@ -785,12 +784,12 @@ __device__ __forceinline__ void accumulate_k(double *a, int64_t kstride, const f
 constexpr int kSlotBatch = 4;
 static_assert(kDeferK % kSlotBatch == 0, "whole batches per cycle");
 
-// The products of the n >= 1 stashed samples at st (slot j at st + j *
-// sstride, field f at + f * kstride), summed in slot order and added to the
-// sums in one read-modify-write; stash and sums are streamed (each is read
-// once per cycle, far more than the L2 holds).
+// The products of the n >= 1 stashed samples at st (field f of slot j at
+// st + (5 j + f) * fs), summed in slot order and added to the sums (kind q
+// at a + q * kstride) in one read-modify-write; stash and sums are streamed
+// (each is read once per cycle, far more than the L2 holds).
 __device__ __forceinline__ void accumulate_stashed_k(double *a, int64_t kstride, const float2 *st,
-                                                     int64_t sstride, int n)
+                                                     int64_t fs, int n)
 {
     double u[kKinds];
 #pragma unroll
@@ -802,7 +801,7 @@ __device__ __forceinline__ void accumulate_stashed_k(double *a, int64_t kstride,
         for (int b = 0; b < kSlotBatch; ++b) {
             const int j = min(j0 + b, n - 1);
 #pragma unroll
-            for (int f = 0; f < 5; ++f) Y[b][f] = stream_load(&st[j * sstride + f * kstride]);
+            for (int f = 0; f < 5; ++f) Y[b][f] = stream_load(&st[(j * 5 + f) * fs]);
         }
         // (a select, not a branch: the reads of a batch must not be sunk
         // into per-slot branches, which would serialise them again)
@@ -868,10 +867,10 @@ __global__ __launch_bounds__(NT) void corr_cols_kernel(CorrArgs g)
     const int ncol = min(cb, nkx - c0);
     const float2 *col = g.spec + P.spec_base + (int64_t)f * ny * kxp;
     // the transformed column goes back in place (row order), or to stash
-    // slot g.arg >= 0 (column-tiled)
+    // slot g.arg >= 0
     const bool tiled = g.arg >= 0;
-    float2 *out = (tiled ? g.stash + (int64_t)g.arg * g.stash_stride : g.spec) + P.spec_base +
-                  (int64_t)f * ny * kxp;
+    float2 *out = g.spec + P.spec_base + (int64_t)f * ny * kxp;
+    const int64_t plane = (int64_t)ny * kxp;
     const float2 *chirp = g.tables + L.chirp_off;
     const bool blue = L.bluestein != 0;
     // a Bluestein work length's zero padding, rows ny .. m-1
@@ -902,8 +901,11 @@ __global__ __launch_bounds__(NT) void corr_cols_kernel(CorrArgs g)
         if (c >= ncol) continue;
         const float2 x = lds[lds_slot<true>(idx)];
         const float2 y = blue ? cmul(x, chirp[j]) : x;
-        if (tiled) stream_store(&out[spec_offset(j, c0 + c, ny)], y);
-        else out[(int64_t)j * kxp + c0 + c] = y;
+        if (tiled)
+            stream_store(&g.stash[stash_offset(P.spec_base, plane, spec_offset(j, c0 + c, ny),
+                                               g.arg, f)], y);
+        else
+            out[(int64_t)j * kxp + c0 + c] = y;
     }
 }
 
@@ -1048,11 +1050,10 @@ __global__ __launch_bounds__(cols_pipe_threads(LG)) void corr_cols_pipe_kernel(
         // k + j H3, which are in natural order when they leave it
         {
             // in place (row order), or to a stash slot (column-tiled: rows
-            // of a tile kTileCols apart)
+            // of a tile kTileCols apart, positions placed by stash_offset)
             static_assert(kTileCols == 4, "tile offsets below");
             const bool tiled = g.arg >= 0;
-            float2 *out = tiled ? g.stash + (int64_t)g.arg * g.stash_stride + cur.toff
-                                : g.spec + cur.off;
+            float2 *out = g.spec + cur.off;
             const uint32_t rs = tiled ? 4u : (uint32_t)cur.kxp;
             const uint32_t ts = (uint32_t)cur.ts;
 #pragma unroll 1
@@ -1068,9 +1069,13 @@ __global__ __launch_bounds__(cols_pipe_threads(LG)) void corr_cols_pipe_kernel(
                                                                    : (uint32_t)cc);
 #pragma unroll
                     for (int j = 0; j < G3; ++j) {
-                        float2 *p = &out[o0 + (uint32_t)(j * H3) * rs];
-                        if (tiled) stream_store(p, x[j]);
-                        else *p = x[j];
+                        const uint32_t o = o0 + (uint32_t)(j * H3) * rs;
+                        if (tiled)
+                            stream_store(&g.stash[stash_offset(cur.sbase, cur.plane,
+                                                               (int64_t)cur.o0 + o, g.arg, cur.f)],
+                                         x[j]);
+                        else
+                            out[o] = x[j];
                     }
                 }
             }
@@ -1209,17 +1214,19 @@ __device__ __forceinline__ void cols_blue_block(const CorrArgs &g, const CorrIte
     group_butterflies<4, true, false>(v, w);
     if (c >= ncol) return;
     // the transformed column goes back in place, or to stash slot g.arg >= 0
-    // (column-tiled)
     const bool tiled = g.arg >= 0;
-    float2 *out = (tiled ? g.stash + (int64_t)g.arg * g.stash_stride : g.spec) + P.spec_base +
-                  (int64_t)f * ny * kxp;
+    float2 *out = g.spec + P.spec_base + (int64_t)f * ny * kxp;
+    const int64_t plane = (int64_t)ny * kxp;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int e = k + j * H;
         if (e >= ny) break;
         const float2 y = cmul(v[j], chirp[e]);
-        if (tiled) stream_store(&out[spec_offset(e, c0 + c, ny)], y);
-        else out[(int64_t)e * kxp + c0 + c] = y;
+        if (tiled)
+            stream_store(&g.stash[stash_offset(P.spec_base, plane, spec_offset(e, c0 + c, ny),
+                                               g.arg, f)], y);
+        else
+            out[(int64_t)e * kxp + c0 + c] = y;
     }
 }
 
@@ -1281,8 +1288,12 @@ __global__ __launch_bounds__(kThreads) void corr_flush_kernel(CorrArgs g)
     const int64_t o = (int64_t)it.a + threadIdx.x;  // tiled stash and sum planes
     uint32_t ky, kx;
     if (o >= fstride || !tiled_k(P, (uint32_t)o, ky, kx)) return;
-    accumulate_stashed_k(g.acc + P.acc_base + o, fstride, g.stash + P.spec_base + o,
-                         g.stash_stride, g.arg);
+    // this position's chunk of the stash: every slot and field in turn,
+    // chunk-wide apart
+    const int64_t c = o / kStashChunk, left = fstride - c * kStashChunk;
+    const int64_t w = left < kStashChunk ? left : kStashChunk;
+    accumulate_stashed_k(g.acc + P.acc_base + o, fstride,
+                         g.stash + stash_offset(P.spec_base, fstride, o, 0, 0), w, g.arg);
 }
 
 static CorrArgs make_args(const DeviceView &v, const CorrItem *items, int set)
@@ -1295,7 +1306,6 @@ static CorrArgs make_args(const DeviceView &v, const CorrItem *items, int set)
     g.items = items;
     g.spec = v.spec;
     g.stash = v.stash;
-    g.stash_stride = v.stash_stride;
     g.arg = 0;
     g.acc = v.acc;
     g.fields = v.fields;

@@ -16,7 +16,9 @@
 //              fields after the row transforms; kxp is nkx = nx/2+1 rounded
 //              up to 16).
 //   stash    : kDeferK spectrum-sized slots: the column transforms' output,
-//              each field plane column-tiled (spec_offset below).
+//              each field plane column-tiled (spec_offset below), stored by
+//              chunks of plane positions across slots and fields
+//              (stash_offset below).
 //   acc      : FP64 correlator sums, per lattice FLB_NKINDS x ny x kxp, each
 //              kind's plane column-tiled.
 //   fields   : FP32 fluctuation fields of the sampled state, 5 x ny x nx
@@ -133,8 +135,7 @@ struct DeviceView {
     const uint32_t *step;             // device step counter
     uint32_t *step_rw;
     float2 *spec;
-    float2 *stash;                    // slots of spectra awaiting accumulation (layout of spec)
-    int64_t stash_stride;             // elements per stash slot
+    float2 *stash;                    // spectra awaiting accumulation (stash_offset)
     double *acc;
     float *fields;                    // [6][ny][nx] FP32 moment planes per lattice
     double *csum_part;                // field-kernel partial sums
@@ -219,12 +220,14 @@ hipError_t launch_corr_cols_blue(const DeviceView &v, const CorrItem *items, int
 // the number of columns it has (0: no group).  `slot` as for
 // launch_corr_cols.
 struct PipeItem {
-    int64_t off;
-    int64_t toff;
-    int32_t kxp;
-    int32_t ts;
-    int32_t ncol;
-    int32_t pad;
+    int64_t off;     // first column in the spectra (row order)
+    int64_t sbase;   // the lattice's spec_base, for stash_offset
+    int32_t kxp;     // row pitch of the spectra
+    int32_t ts;      // column-tile stride of a stash plane, kTileCols * ny
+    int32_t ncol;    // columns in the group (0: no group)
+    int32_t o0;      // plane position of the group's first column in a stash plane
+    int32_t f;       // field
+    int32_t plane;   // positions per stash plane, ny * kxp
 };
 bool corr_cols_pipe_supported(int lg);
 int corr_cols_pipe_lds_bytes(int lg);
@@ -235,6 +238,26 @@ hipError_t launch_corr_cols_pipe(const DeviceView &v, const PipeItem *sched, int
 // is most of the accumulation's bytes: 4096^2 whole path 87.5 GLUPS with 16
 // against 86.4 with 8; a sample alone 0.504 ms with 32 against 0.520 with 16.
 constexpr int kDeferK = 32;
+
+// Stash layout: per lattice, kDeferK x 5 planes of ny * kxp values (each
+// column-tiled as spec_offset has it) in a region of kDeferK times the
+// lattice's spectra, by chunks of kStashChunk consecutive plane positions:
+// chunk c holds its positions of plane (slot j, field f) for every j and f
+// in turn, so that an accumulation block (one chunk) reads its kDeferK x 5
+// planes as one contiguous run instead of 5 kDeferK streams.  The last
+// chunk of a plane may be narrower.  Offset (complex values) of position o
+// of plane (j, f) for the lattice whose spectra start at spec_base:
+constexpr int kStashLog = 8, kStashChunk = 1 << kStashLog;
+__host__ __device__ inline int64_t stash_offset(int64_t spec_base, int64_t plane, int64_t o,
+                                                int j, int f)
+{
+    // (o, plane < 2^31)
+    const uint32_t c = (uint32_t)o >> kStashLog, r = (uint32_t)o & (kStashChunk - 1);
+    const uint32_t left = (uint32_t)plane - (c << kStashLog);
+    const uint32_t w = left < (uint32_t)kStashChunk ? left : (uint32_t)kStashChunk;
+    return kDeferK * spec_base + (int64_t)c * (kStashChunk * 5 * kDeferK) +
+           (int64_t)((uint32_t)(j * 5 + f) * w + r);
+}
 // Adds the products of the first nslots stash slots to the sums (field set
 // 0): every kDeferK-th sample with nslots = kDeferK, and before a read.
 hipError_t launch_corr_flush(const DeviceView &v, const CorrItem *items, int nitems, int nslots,

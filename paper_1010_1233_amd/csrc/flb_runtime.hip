@@ -189,7 +189,6 @@ struct flb {
         v.step_rw = d_step;
         v.spec = d_spec;
         v.stash = d_stash;
-        v.stash_stride = spec_elems;
         v.acc = d_acc;
         v.fields = d_fields;
         v.csum_part = d_csum_part;
@@ -498,16 +497,18 @@ std::vector<CorrItem> persistent_schedule(const std::vector<CorrItem> &items, in
 // pitch, tile stride and number of columns.
 std::vector<PipeItem> pipe_items(const flb_t *h, const std::vector<CorrItem> &sched)
 {
-    std::vector<PipeItem> out(sched.size(), PipeItem{0, 0, 0, 0, 0, 0});
+    std::vector<PipeItem> out(sched.size(), PipeItem{0, 0, 0, 0, 0, 0, 0, 0});
     for (size_t i = 0; i < sched.size(); ++i) {
         const CorrItem &it = sched[i];
         if (it.lattice < 0) continue;
         const LatticeParams &P = h->params[it.lattice];
-        const int64_t plane = P.spec_base + (int64_t)it.a * P.ny * P.kxp;
-        out[i].off = plane + it.b;
-        out[i].toff = plane + spec_offset(0, it.b, P.ny);
+        out[i].off = P.spec_base + (int64_t)it.a * P.ny * P.kxp + it.b;
+        out[i].sbase = P.spec_base;
         out[i].kxp = P.kxp;
         out[i].ts = kTileCols * P.ny;
+        out[i].o0 = (int32_t)spec_offset(0, it.b, P.ny);
+        out[i].f = it.a;
+        out[i].plane = P.ny * P.kxp;
         out[i].ncol = std::min(1 << it.c, P.nkx - it.b);
     }
     return out;
