@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "flb_corr_internal.h"
 #include "flb_fft.h"
 
 namespace flbdev {

@@ -21,7 +21,7 @@
 #include <vector>
 
 #include "../../include/flb.h"
-#include "flb_internal.h"
+#include "flb_corr_internal.h"
 
 using namespace flbdev;
 
