@@ -220,6 +220,28 @@ def batched_form(torch, flb, stream, specs, storage, periods=ACCUMULATE_EVERY):
             "sample_ms": max(ms_period - SAMPLE_EVERY * step_ms, 0.0)}
 
 
+def shard_form(torch, flb, workloads, stream, name, storage, strips=8):
+    """One GPU's share of the workload's lattice split into `strips` x-strips
+    (nx / strips x ny sites, the workload's parameters, periodic): step rate
+    and whole-path rate with the strip's own sample."""
+    c = workloads.CONFIGS[name]
+    nx, ny = c["nx"] // strips, c["ny"]
+    g = flb.Lattice(nx, ny, c["tau"], c["theta"], rho0=c["rho0"], u0=c["u0"], seed=c["seed"],
+                    storage=storage)
+    g.set_stream(stream)
+    g.thermalize()
+    shape, _ = g.autotune_path(50, SAMPLE_EVERY)
+    step_ms = steady_step_ms(torch, g, stream)
+    pms = plain_path_ms(torch, g, stream)
+    out = {"sites": nx * ny, "sides": [nx, ny],
+           "launch_shape": list(shape) + [list(g.time_blocking())],
+           "step_glups": nx * ny / (step_ms * 1e-3) / 1e9,
+           "path_glups": SAMPLE_EVERY * nx * ny / (pms * 1e-3) / 1e9,
+           "sample_ms": max(pms - SAMPLE_EVERY * step_ms, 0.0)}
+    g.close()
+    return out
+
+
 def velocity_set_form(torch, flb, stream, model, sides, sample=True, periods=5):
     """Step (and, where the sides allow correlators, whole-path) rates of one
     lattice of another velocity set: FP32 deviations, Q loads + Q stores per
@@ -573,6 +595,13 @@ def main():
                                 ("batched_uneven_64", workloads.uneven_batch_specs())):
                 forms[name] = batched_form(torch, flb, stream, specs, args.storage)
                 print(f"bench: {name} {forms[name]}", file=sys.stderr, flush=True)
+            # one GPU's share of the 4096^2 lattice split into eight x-strips
+            # (the halo and all-to-all exchanges are not built: the strip is
+            # periodic here); its step rate, and its sample, whose row
+            # transforms are the strip's own part of the distributed one
+            forms["shard_512x4096"] = shard_form(torch, flb, workloads, stream, args.workload,
+                                                 args.storage)
+            print(f"bench: shard {forms['shard_512x4096']}", file=sys.stderr, flush=True)
             # the other velocity sets the paper tested (Sec. 3)
             forms["d3q15_256x256x256"] = velocity_set_form(torch, flb, stream, "D3Q15",
                                                            (256, 256, 256))

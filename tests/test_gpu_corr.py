@@ -36,7 +36,7 @@ def _compare(acc_g, acc_o, rtol):
                                    (1500, 3), (12, 1024), (10, 2048), (6, 4096),
                                    (512, 512), (512, 300), (300, 512),
                                    (1024, 3), (2048, 5), (4096, 3), (100, 40), (200, 12),
-                                   (64, 200), (20, 1000)])
+                                   (64, 200), (20, 1000), (512, 4096)])
 def test_single_sample_matches_oracle(flb, oracle_lib, nx, ny):
     note("sample", nx, ny)
     g = flb.Lattice(nx, ny, TAU_C1, 1e-4, u0=(0.04, -0.01), seed=3)
