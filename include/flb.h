@@ -269,9 +269,10 @@ int flb_set_populations(flb_t *h, int lattice, const double *in, size_t n);
 int flb_conservation(flb_t *h, int lattice, double out[5]);
 
 /* The same five sums, for the state of the most recent correlator sample:
- * every sample computes them from its fluctuation fields at no extra pass
- * over the populations (FP32 per site, FP64 sums).  FLB_ESTATE if no sample
- * was taken since creation or the last reset.  Synchronises. */
+ * every sample's row transforms leave FP64 partial sums of its fluctuation
+ * fields (FP32 per site) at no extra pass over the populations, and this
+ * call adds them up.  FLB_ESTATE if no sample was taken since creation or
+ * the last reset.  Synchronises. */
 int flb_sample_conservation(flb_t *h, int lattice, double out[5]);
 
 /* As flb_conservation, but enqueue-only: the five sums are written to

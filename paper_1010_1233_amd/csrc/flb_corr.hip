@@ -1382,7 +1382,12 @@ hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nite
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const CorrArgs g = make_args(v, items, 0);
+    return hipSuccess;
+}
+
+hipError_t launch_corr_csum(const DeviceView &v, hipStream_t s)
+{
+    const CorrArgs g = make_args(v, nullptr, 0);
     hipLaunchKernelGGL(corr_csum_kernel, dim3(v.nlat), dim3(kThreads), 0, s, g, v.nlat);
     return hipGetLastError();
 }

@@ -22,8 +22,8 @@ __host__ __device__ inline int64_t spec_offset(int y, int kx, int ny)
 }
 
 // Field set 0 (rho, j, u; kKinds kinds): fused fields + row transforms
-// (items of power-of-two rows and of Bluestein rows), then the conservation
-// sums of the sampled state.  Rows of 2^lg points, 9 <= lg <= 12
+// (items of power-of-two rows and of Bluestein rows), each block leaving
+// its partial conservation sums of the sampled state.  Rows of 2^lg points, 9 <= lg <= 12
 // (corr_rows_p2_supported), and Bluestein rows of work length 2^lg,
 // 8 <= lg <= 11 (corr_rows_blue_supported), take blocks specialised per
 // length: launch q of `fixed` takes items[fixed[q].off .. + fixed[q].n),
@@ -40,6 +40,10 @@ bool corr_rows_blue_supported(int lg);
 hipError_t launch_corr_rows(const DeviceView &v, const CorrItem *items, int nitems,
                             const RowLaunch *fixed, int nfixed, const CorrItem *blue_items,
                             int nblue, int lds_bytes, hipStream_t s);
+// The five conservation sums of the last sample per lattice, from the row
+// blocks' partials in a fixed order (taken when they are read: the partials
+// stay until the next sample's row transforms).
+hipError_t launch_corr_csum(const DeviceView &v, hipStream_t s);
 // Field set 1 (the six non-conserved moments, kinds kKinds .. kKinds + 5):
 // FP32 field planes, then row transforms.
 hipError_t launch_corr_moment_fields(const DeviceView &v, const CorrItem *items, int nitems,

@@ -1416,6 +1416,9 @@ int flb_sample_conservation(flb_t *h, int lattice, double out[5])
         return fail(FLB_ESTATE, "no correlator sample taken since the last reset");
     int rc = settle_due(h);
     if (rc) return rc;
+    // the stream is ordered after the last sample's row transforms (a sample
+    // beside the steps joins it at their end)
+    FLB_HIP(launch_corr_csum(h->view(), h->stream));
     FLB_HIP(hipStreamSynchronize(h->stream));
     FLB_HIP(hipMemcpy(out, h->d_csum + 5 * (size_t)lattice, 5 * sizeof(double),
                       hipMemcpyDeviceToHost));
