@@ -127,7 +127,7 @@ def sweep_shapes(flb, workloads, name, storage, steps=5):
             for nt in (0, 1):
                 g.set_step_config(tw, sites, nt)
                 g.step(steps)
-    for tile2 in (64, 128):
+    for tile2 in (32, 64, 128):
         for nt in (0, 1):
             g.set_step_config(256, 1, nt)
             g.set_time_blocking(2, tile2)
@@ -135,7 +135,7 @@ def sweep_shapes(flb, workloads, name, storage, steps=5):
     g.set_time_blocking(1, 64)
     g.synchronize()
     print(f"sweep-shapes: {name} {storage}: 18 one-step shapes x {steps} steps, "
-          f"4 two-step shapes x {steps} launches", flush=True)
+          f"6 two-step shapes x {steps} launches", flush=True)
 
 
 def make_lattice(flb, workloads, name, storage):
@@ -211,8 +211,11 @@ def batched_form(torch, flb, stream, specs, storage, periods=ACCUMULATE_EVERY):
     step_ms = steady_step_ms(torch, b, stream)
     lf = launch_figures(b, sites, step_ms)
     shape = list(shape) + [list(b.time_blocking())]
+    tiles = b.lattice_tiles()
     b.close()
     return {"lattices": len(specs), "sites": sites, "launch_shape": shape,
+            # lattices per two-step tile width (the tuner's choice per size class)
+            "lattice_tiles": {str(w): tiles.count(w) for w in sorted(set(tiles))},
             "path_glups": SAMPLE_EVERY * sites / (ms_period * 1e-3) / 1e9,
             "step_glups": sites / (step_ms * 1e-3) / 1e9,
             "steps_per_launch": lf["steps_per_launch"],

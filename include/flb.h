@@ -328,21 +328,38 @@ int flb_set_step_config(flb_t *h, int tile_w, int sites, int nontemporal);
 int flb_get_step_config(flb_t *h, int *tile_w, int *sites, int *nontemporal);
 
 /* Time blocking: steps_per_launch = 2 runs pairs of steps in one kernel
- * launch (tiles of tile_w x 1024/tile_w sites, tile_w 64 or 128; each block
- * collides its tile and a one-site halo at t, keeps them on chip and
+ * launch (tiles of tile_w x 1024/tile_w sites, tile_w 32, 64 or 128; each
+ * block collides its tile and a one-site halo at t, keeps them on chip and
  * collides the tile again at t+1), so the populations cross HBM once per two
  * steps; an odd last step uses the one-step kernel.  Every site sees the
  * same arithmetic, noise counters and storage rounding as with one step per
  * launch: results do not depend on it.  steps_per_launch = 1 (default) turns
- * it off.  FLB_EINVAL for other values. */
+ * it off.  FLB_EINVAL for other values.  flb_get_time_blocking reports
+ * tile_w = 0 while each lattice has its own tile (flb_set_lattice_tiles). */
 int flb_set_time_blocking(flb_t *h, int steps_per_launch, int tile_w);
 int flb_get_time_blocking(flb_t *h, int *steps_per_launch, int *tile_w);
+
+/* Time blocking with a tile shape per lattice: tile_w[l] (32 or 64, one
+ * entry per lattice of the handle, host memory, read during the call) gives
+ * lattice l tiles of tile_w[l] x 1024/tile_w[l] sites; all lattices still
+ * step in one launch.  Sets steps_per_launch = 2.  Results do not depend on
+ * it.  FLB_EINVAL for a NULL array or another width.
+ * flb_get_lattice_tiles writes each lattice's two-step tile width in
+ * effect (the handle's one width, or its own) to tile_w[0 .. lattices-1]. */
+int flb_set_lattice_tiles(flb_t *h, const int *tile_w);
+int flb_get_lattice_tiles(flb_t *h, int *tile_w);
 
 /* Chooses the step kernel's launch shape by timing every supported shape
  * (nsteps >= 1 steps each, HIP events on the handle's stream, in three
  * round-robin passes of which each shape keeps its fastest) on this
  * handle's own lattices, the time-blocked shapes included (per step), and
- * keeps the fastest.  The populations and the
+ * keeps the fastest.  For a batch whose fastest shape is time-blocked, the
+ * two-step tile is then chosen per size class (the lattices whose sides
+ * round up to the same powers of two): each class takes the faster of
+ * 32 x 32 and 64 x 16 tiles, timed on its own lattices' tiles (the one with
+ * fewer halo collisions where they are within 1 %), and these per-class tiles
+ * (flb_set_lattice_tiles) replace the fastest shape if the whole batch then
+ * steps faster.  The populations and the
  * step counter are restored afterwards, so results are unchanged.  When the
  * environment variable FLB_AUTOTUNE_CACHE names a file, choices are read
  * from and appended to it, keyed by storage format, lattice count, total
@@ -351,7 +368,8 @@ int flb_get_time_blocking(flb_t *h, int *steps_per_launch, int *tile_w);
 int flb_autotune(flb_t *h, int nsteps, double *ms_out);
 
 /* As flb_autotune, then for the shapes within 4 % of the fastest alone (at
- * most four) the whole path decides: each is timed on whole periods of
+ * most four), and for a batch the tile per size class as above, the whole
+ * path decides: each is timed on whole periods of
  * sample_every >= 1 steps and a correlator sample (Eqs. 11-12), issued as
  * flb_step and flb_accumulate_correlators issue them (with sample overlap,
  * each sample runs beside the following steps, which a shape's time alone

@@ -109,6 +109,8 @@ SIGNATURES = {
     "flb_get_step_config": (ctypes.c_int, [ctypes.c_void_p, _intp, _intp, _intp]),
     "flb_set_time_blocking": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "flb_get_time_blocking": (ctypes.c_int, [ctypes.c_void_p, _intp, _intp]),
+    "flb_set_lattice_tiles": (ctypes.c_int, [ctypes.c_void_p, _i32p]),
+    "flb_get_lattice_tiles": (ctypes.c_int, [ctypes.c_void_p, _i32p]),
     "flb_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp]),
     "flb_autotune_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp]),
     # other velocity sets (flb_dq.h)
@@ -307,13 +309,29 @@ class Lattice:
     def set_time_blocking(self, steps_per_launch, tile_w=64):
         """1: one step per kernel launch; 2: pairs of steps per launch (the
         populations cross HBM once per two steps), tiles of tile_w x
-        1024/tile_w sites (tile_w 64 or 128)."""
+        1024/tile_w sites (tile_w 32, 64 or 128)."""
         _check(lib().flb_set_time_blocking(self._h, int(steps_per_launch), int(tile_w)))
 
     def time_blocking(self):
+        """(steps per launch, two-step tile width); the width is 0 while
+        each lattice has its own (lattice_tiles())."""
         a, b = ctypes.c_int(), ctypes.c_int()
         _check(lib().flb_get_time_blocking(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def set_lattice_tiles(self, tile_w):
+        """Pairs of steps per launch with each lattice's own tile width (32
+        or 64), one entry per lattice."""
+        a = np.ascontiguousarray(tile_w, dtype=np.int32)
+        if a.shape != (self.nlattices,):
+            raise ValueError(f"need {self.nlattices} tile widths, got shape {a.shape}")
+        _check(lib().flb_set_lattice_tiles(self._h, a.ctypes.data_as(_i32p)))
+
+    def lattice_tiles(self):
+        """Each lattice's two-step tile width in effect."""
+        a = np.zeros(self.nlattices, dtype=np.int32)
+        _check(lib().flb_get_lattice_tiles(self._h, a.ctypes.data_as(_i32p)))
+        return a.tolist()
 
     def autotune_path(self, nsteps=10, sample_every=10):
         """Tune the step launch shape on whole sampling periods (see

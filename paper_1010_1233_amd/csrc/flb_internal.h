@@ -137,8 +137,11 @@ hipError_t launch_step(const DeviceView &v, const StepItem *items, int nitems, i
                        int sites, uint32_t step_add, bool nontemporal, bool noise,
                        hipStream_t s);
 bool step_tile_supported(int tw, int r);
-// Two steps per launch: tiles of tile_w x (1024 / tile_w) sites, tile_w 64
-// or 128; items enumerate each lattice's tiles of that shape.
+// Two steps per launch: tiles of tile_w x (1024 / tile_w) sites, tile_w 32,
+// 64 or 128; items enumerate each lattice's tiles of that shape.  tile_w 0:
+// each lattice has its own shape, 32 x 32 or 64 x 16, and the tile index of
+// an item of a 32 x 32 lattice carries kStep2Square.
+constexpr int32_t kStep2Square = 1 << 30;
 hipError_t launch_step2(const DeviceView &v, const StepItem *items, int nitems, int tile_w,
                         uint32_t step_add, bool nontemporal, bool noise, hipStream_t s);
 bool step2_tile_supported(int tw);

@@ -14,8 +14,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <utility>
 #include <vector>
@@ -102,7 +104,9 @@ struct flb {
     StepItem *d_items = nullptr;
     int nitems = 0;
     // time blocking: steps per launch (1 or 2) and the two-step kernel's tile
+    // width; tile2 = 0: each lattice has its own, log2 of it in ltile (5 or 6)
     int tblock = 1, tile2 = 64;
+    std::vector<int8_t> ltile;
     StepItem *d_items2 = nullptr;
     int nitems2 = 0;
     int64_t t = 0;
@@ -329,6 +333,24 @@ int upload(T **dptr, const std::vector<T> &v)
     return FLB_OK;
 }
 
+// The two-step kernel's work items, in XCD order: every lattice's tiles of
+// width tw, or with lt, of width 2^lt[l] (the mixed kernel's items, the
+// 32 x 32 ones flagged); only the lattices `only` marks, if given.
+std::vector<StepItem> step2_items(const flb_t *h, const std::vector<int8_t> *lt, int tw,
+                                  const std::vector<char> *only)
+{
+    std::vector<StepItem> items;
+    for (size_t l = 0; l < h->params.size(); ++l) {
+        if (only && !(*only)[l]) continue;
+        const LatticeParams &P = h->params[l];
+        const int w = lt ? 1 << (*lt)[l] : tw, th = 1024 / w;
+        const int32_t flag = lt && w == 32 ? kStep2Square : 0;
+        const int n2 = ((P.nx + w - 1) / w) * ((P.ny + th - 1) / th);
+        for (int t = 0; t < n2; ++t) items.push_back({(int32_t)l, t | flag});
+    }
+    return xcd_order(items, StepItem{-1, 0});
+}
+
 int build_step_items(flb_t *h)
 {
     const int TH = kThreads / h->tile_w;
@@ -344,15 +366,12 @@ int build_step_items(flb_t *h)
     h->nitems = (int)items.size();
     int rc = upload(&h->d_items, items);
     if (rc) return rc;
-    // the two-step kernel's tiles: tile2 x (1024 / tile2) sites
-    std::vector<StepItem> items2;
-    const int TH2 = 1024 / h->tile2;
-    for (size_t l = 0; l < h->params.size(); ++l) {
-        const LatticeParams &P = h->params[l];
-        const int n2 = ((P.nx + h->tile2 - 1) / h->tile2) * ((P.ny + TH2 - 1) / TH2);
-        for (int t = 0; t < n2; ++t) items2.push_back({(int32_t)l, t});
-    }
-    items2 = xcd_order(items2, StepItem{-1, 0});
+    // the two-step kernel's tiles: tile2 x (1024 / tile2) sites, or each
+    // lattice's own shape
+    if (h->tile2 == 0 && h->ltile.size() != h->params.size())
+        return fail(FLB_ESTATE, "per-lattice two-step tiles do not match the lattices");
+    std::vector<StepItem> items2 =
+        step2_items(h, h->tile2 == 0 ? &h->ltile : nullptr, h->tile2, nullptr);
     h->nitems2 = (int)items2.size();
     if ((rc = upload(&h->d_items2, items2))) return rc;
     return upload(&h->d_params, h->params);
@@ -1557,6 +1576,33 @@ int flb_get_time_blocking(flb_t *h, int *steps_per_launch, int *tile_w)
     return FLB_OK;
 }
 
+int flb_set_lattice_tiles(flb_t *h, const int *tile_w)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (!tile_w) return fail(FLB_EINVAL, "tile_w must not be NULL");
+    std::vector<int8_t> lt(h->params.size());
+    for (size_t l = 0; l < lt.size(); ++l) {
+        if (tile_w[l] != 32 && tile_w[l] != 64)
+            return fail(FLB_EINVAL, "per-lattice two-step tiles are 32 or 64 sites wide");
+        lt[l] = tile_w[l] == 32 ? 5 : 6;
+    }
+    FLB_HIP(hipStreamSynchronize(h->stream));
+    h->tblock = 2;
+    h->tile2 = 0;
+    h->ltile = lt;
+    clear_graphs(h);
+    return build_step_items(h);
+}
+
+int flb_get_lattice_tiles(flb_t *h, int *tile_w)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (!tile_w) return fail(FLB_EINVAL, "tile_w must not be NULL");
+    for (size_t l = 0; l < h->params.size(); ++l)
+        tile_w[l] = h->tile2 ? h->tile2 : 1 << h->ltile[l];
+    return FLB_OK;
+}
+
 int flb_get_step_config(flb_t *h, int *tile_w, int *sites, int *nontemporal)
 {
     if (check_handle(h)) return FLB_EINVAL;
@@ -1569,9 +1615,11 @@ int flb_get_step_config(flb_t *h, int *tile_w, int *sites, int *nontemporal)
 }  // extern "C"
 
 // A step launch shape: one-step tile width, sites per thread, streaming
-// accesses, steps per launch (1 or 2), two-step tile width.
+// accesses, steps per launch (1 or 2), two-step tile width (0: per lattice,
+// log2 of each lattice's in lt).
 struct StepShape {
     int tw, sv, nt, tb, t2;
+    std::vector<int8_t> lt;
 };
 
 static void apply_shape(flb_t *h, const StepShape &c)
@@ -1581,6 +1629,7 @@ static void apply_shape(flb_t *h, const StepShape &c)
     h->nontemporal = c.nt != 0;
     h->tblock = c.tb;
     h->tile2 = c.t2;
+    h->ltile = c.t2 == 0 ? c.lt : std::vector<int8_t>();
 }
 
 static std::string tune_key(const flb_t *h, const char *kind, int every)
@@ -1597,32 +1646,56 @@ static std::string tune_key(const flb_t *h, const char *kind, int every)
     return key;
 }
 
-// A shape from the FLB_AUTOTUNE_CACHE file, if it names one for this key.
-static bool cached_shape(const char *cache, const std::string &key, StepShape &c, double &ms)
+// A shape from the FLB_AUTOTUNE_CACHE file, if it names one for this key
+// (the last such line).  Lines: key tw sv nt tb t2 ms, where t2 is a width
+// or "L" followed by each lattice's log2 width (per-lattice tiles).
+static bool cached_shape(const char *cache, const std::string &key, size_t nlat, StepShape &c,
+                         double &ms)
 {
     if (!cache) return false;
-    FILE *fp = fopen(cache, "r");
-    if (!fp) return false;
-    char k[160];
-    StepShape x{};
-    double t = 0;
+    std::ifstream in(cache);
+    if (!in) return false;
+    std::string line;
     bool found = false;
-    while (fscanf(fp, "%159s %d %d %d %d %d %lf", k, &x.tw, &x.sv, &x.nt, &x.tb, &x.t2, &t) == 7)
-        if (key == k && step_tile_supported(x.tw, x.sv) && (x.tb == 1 || x.tb == 2) &&
-            step2_tile_supported(x.t2)) {
+    while (std::getline(in, line)) {
+        std::istringstream ls(line);
+        std::string k, t2s;
+        StepShape x{};
+        double t = 0;
+        if (!(ls >> k >> x.tw >> x.sv >> x.nt >> x.tb >> t2s >> t) || k != key) continue;
+        if (!t2s.empty() && t2s[0] == 'L') {
+            if (t2s.size() != nlat + 1) continue;
+            bool ok = true;
+            for (size_t l = 0; l < nlat; ++l) {
+                const char ch = t2s[l + 1];
+                ok = ok && (ch == '5' || ch == '6');
+                x.lt.push_back((int8_t)(ch - '0'));
+            }
+            if (!ok || x.tb != 2) continue;
+            x.t2 = 0;
+        } else {
+            x.t2 = atoi(t2s.c_str());
+            if (!step2_tile_supported(x.t2)) continue;
+        }
+        if (step_tile_supported(x.tw, x.sv) && (x.tb == 1 || x.tb == 2)) {
             found = true;
             c = x;
             ms = t;
         }
-    fclose(fp);
+    }
     return found;
 }
 
 static void cache_shape(const char *cache, const std::string &key, const StepShape &c, double ms)
 {
     if (!cache) return;
+    std::string t2s = std::to_string(c.t2);
+    if (c.t2 == 0) {
+        t2s = "L";
+        for (int8_t v : c.lt) t2s += (char)('0' + v);
+    }
     if (FILE *fp = fopen(cache, "a")) {
-        fprintf(fp, "%s %d %d %d %d %d %.6f\n", key.c_str(), c.tw, c.sv, c.nt, c.tb, c.t2, ms);
+        fprintf(fp, "%s %d %d %d %d %s %.6f\n", key.c_str(), c.tw, c.sv, c.nt, c.tb, t2s.c_str(), ms);
         fclose(fp);
     }
 }
@@ -1642,7 +1715,8 @@ template <typename F> static int with_saved_state(flb_t *h, F body)
     const int cur0 = h->cur;
     const int64_t t0 = h->t;
     const bool timing0 = h->timing;
-    const StepShape shape0{h->tile_w, h->sites, h->nontemporal ? 1 : 0, h->tblock, h->tile2};
+    const StepShape shape0{h->tile_w, h->sites, h->nontemporal ? 1 : 0, h->tblock, h->tile2,
+                           h->ltile};
     h->timing = false;
     hipError_t e = hipMemcpyAsync(saved, h->pops[cur0], bytes, hipMemcpyDeviceToDevice, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&step0, h->d_step, sizeof step0, hipMemcpyDeviceToHost, h->stream);
@@ -1665,20 +1739,15 @@ template <typename F> static int with_saved_state(flb_t *h, F body)
     return build_step_items(h);
 }
 
-// Times every supported launch shape alone (nsteps steps each, whole pairs
-// for the two-step kernel) in kRounds round-robin passes, each shape keeping
+// Times the given launch shapes alone (nsteps steps each, whole pairs for
+// the two-step kernel) in kRounds round-robin passes, each shape keeping
 // its fastest pass, so that a slow moment of the device does not decide; ms
-// per step, fastest first.
-static int time_every_shape(flb_t *h, int nsteps, std::vector<std::pair<float, StepShape>> &out)
+// per step into best.
+static int time_shapes(flb_t *h, int nsteps, const std::vector<StepShape> &shapes,
+                       std::vector<float> &best)
 {
     constexpr int kRounds = 3;
-    std::vector<StepShape> shapes;
-    for (int tw : {64, 128, 256})
-        for (int sv : {1, 2, 4})
-            for (int nt = 0; nt < 2; ++nt) shapes.push_back({tw, sv, nt, 1, h->tile2});
-    for (int t2 : {64, 128})
-        for (int nt = 0; nt < 2; ++nt) shapes.push_back({h->tile_w, h->sites, nt, 2, t2});
-    std::vector<float> best(shapes.size(), 1e30f);
+    best.assign(shapes.size(), 1e30f);
     return with_saved_state(h, [&](flb_t *hh) -> int {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         hipError_t e = hipEventCreate(&e0);
@@ -1702,13 +1771,129 @@ static int time_every_shape(flb_t *h, int nsteps, std::vector<std::pair<float, S
         if (e1) (void)hipEventDestroy(e1);
         if (rc != FLB_OK) return rc;
         if (e != hipSuccess) return fail(FLB_EHIP, std::string("autotune: ") + hipGetErrorString(e));
-        out.clear();
-        for (size_t i = 0; i < shapes.size(); ++i) out.push_back({best[i], shapes[i]});
-        std::stable_sort(out.begin(), out.end(),
-                         [](const std::pair<float, StepShape> &a,
-                            const std::pair<float, StepShape> &b) { return a.first < b.first; });
         return FLB_OK;
     });
+}
+
+// Every supported launch shape timed alone, fastest first.
+static int time_every_shape(flb_t *h, int nsteps, std::vector<std::pair<float, StepShape>> &out)
+{
+    std::vector<StepShape> shapes;
+    for (int tw : {64, 128, 256})
+        for (int sv : {1, 2, 4})
+            for (int nt = 0; nt < 2; ++nt) shapes.push_back({tw, sv, nt, 1, 64, {}});
+    for (int t2 : {32, 64, 128})
+        for (int nt = 0; nt < 2; ++nt) shapes.push_back({h->tile_w, h->sites, nt, 2, t2, {}});
+    std::vector<float> best;
+    if (int rc = time_shapes(h, nsteps, shapes, best)) return rc;
+    out.clear();
+    for (size_t i = 0; i < shapes.size(); ++i) out.push_back({best[i], shapes[i]});
+    std::stable_sort(out.begin(), out.end(),
+                     [](const std::pair<float, StepShape> &a, const std::pair<float, StepShape> &b) {
+                         return a.first < b.first;
+                     });
+    return FLB_OK;
+}
+
+// Collisions of the two-step kernel's phase 1 on lattice P with tiles of
+// width 2^lg: tiles x (tile + ring).
+static int64_t step2_collisions(const LatticeParams &P, int lg)
+{
+    const int w = 1 << lg, th = 1024 / w;
+    return (int64_t)((P.nx + w - 1) / w) * ((P.ny + th - 1) / th) * (w + 2) * (th + 2);
+}
+
+// The two-step tile per size class of a batch: lattices whose sides round
+// up to the same powers of two form a class, and each class takes the
+// faster of 32 x 32 and 64 x 16 tiles, timed on its own lattices (nsteps
+// steps, launches of the per-lattice kernel over that class's tiles only,
+// three round-robin passes, fastest pass kept).  Where the two are within
+// 1 %, the shape with fewer phase-1 collisions is kept.  Streaming accesses
+// as nt says.  lt receives log2 of each lattice's tile width.
+static int tune_lattice_tiles(flb_t *h, int nsteps, int nt, std::vector<int8_t> &lt)
+{
+    constexpr int kRounds = 3;
+    const size_t nlat = h->params.size();
+    std::map<std::pair<int, int>, std::vector<int>> classes;
+    for (size_t l = 0; l < nlat; ++l)
+        classes[{log2i(h->params[l].nx), log2i(h->params[l].ny)}].push_back((int)l);
+    lt.assign(nlat, 6);
+    const int launches = std::max(1, (nsteps + 1) / 2);
+    return with_saved_state(h, [&](flb_t *hh) -> int {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        StepItem *d_it[2] = {nullptr, nullptr};
+        hipError_t e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        int rc = FLB_OK;
+        for (auto cit = classes.begin(); cit != classes.end() && e == hipSuccess && rc == FLB_OK;
+             ++cit) {
+            std::vector<char> only(nlat, 0);
+            for (int l : cit->second) only[l] = 1;
+            int n[2];
+            for (int o = 0; o < 2 && rc == FLB_OK; ++o) {
+                const std::vector<int8_t> cand(nlat, (int8_t)(5 + o));
+                const std::vector<StepItem> items = step2_items(hh, &cand, 0, &only);
+                n[o] = (int)items.size();
+                rc = upload(&d_it[o], items);
+            }
+            float best[2] = {1e30f, 1e30f};
+            for (int round = 0; round < kRounds && e == hipSuccess && rc == FLB_OK; ++round)
+                for (int o = 0; o < 2 && e == hipSuccess; ++o) {
+                    // the same launch repeated on the same buffers: the
+                    // state is put back afterwards
+                    e = launch_step2(hh->view(), d_it[o], n[o], 0, 0, nt != 0, hh->noise, hh->stream);
+                    if (e == hipSuccess) e = hipEventRecord(e0, hh->stream);
+                    for (int k = 0; k < launches && e == hipSuccess; ++k)
+                        e = launch_step2(hh->view(), d_it[o], n[o], 0, 0, nt != 0, hh->noise,
+                                         hh->stream);
+                    if (e == hipSuccess) e = hipEventRecord(e1, hh->stream);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    float ms = 0;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    if (e == hipSuccess) best[o] = std::min(best[o], ms);
+                }
+            int8_t pick;
+            if (best[0] < 0.99f * best[1]) pick = 5;
+            else if (best[1] < 0.99f * best[0]) pick = 6;
+            else {
+                int64_t c5 = 0, c6 = 0;
+                for (int l : cit->second) {
+                    c5 += step2_collisions(hh->params[l], 5);
+                    c6 += step2_collisions(hh->params[l], 6);
+                }
+                pick = c5 < c6 ? 5 : 6;
+            }
+            for (int l : cit->second) lt[l] = pick;
+        }
+        for (StepItem *p : d_it)
+            if (p) (void)hipFree(p);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (rc != FLB_OK) return rc;
+        if (e != hipSuccess) return fail(FLB_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+        return FLB_OK;
+    });
+}
+
+// For a batch whose chosen shape is two-step: the per-class tiles as a
+// further candidate shape (none if every class kept the chosen width).
+static int lattice_tile_candidate(flb_t *h, int nsteps, const StepShape &chosen,
+                                  std::vector<StepShape> &extra)
+{
+    extra.clear();
+    if (h->params.size() < 2 || chosen.tb != 2) return FLB_OK;
+    std::vector<int8_t> lt;
+    if (int rc = tune_lattice_tiles(h, nsteps, chosen.nt, lt)) return rc;
+    bool same = chosen.t2 == 32 || chosen.t2 == 64;
+    for (int8_t v : lt) same = same && (1 << v) == chosen.t2;
+    if (same) return FLB_OK;
+    StepShape m = chosen;
+    bool uniform = true;
+    for (int8_t v : lt) uniform = uniform && v == lt[0];
+    m.t2 = uniform ? 1 << lt[0] : 0;
+    m.lt = uniform ? std::vector<int8_t>() : lt;
+    extra.push_back(m);
+    return FLB_OK;
 }
 
 extern "C" {
@@ -1721,7 +1906,7 @@ int flb_autotune(flb_t *h, int nsteps, double *ms_out)
     const char *cache = getenv("FLB_AUTOTUNE_CACHE");
     StepShape c{};
     double ms = 0;
-    if (cached_shape(cache, key, c, ms)) {
+    if (cached_shape(cache, key, h->params.size(), c, ms)) {
         apply_shape(h, c);
         if (ms_out) *ms_out = ms;
         clear_graphs(h);
@@ -1729,10 +1914,24 @@ int flb_autotune(flb_t *h, int nsteps, double *ms_out)
     }
     std::vector<std::pair<float, StepShape>> t;
     if (int rc = time_every_shape(h, nsteps, t)) return rc;
-    apply_shape(h, t[0].second);
+    StepShape pick = t[0].second;
+    float pick_ms = t[0].first;
+    // a batch: the per-class tiles against the fastest shape, timed together
+    std::vector<StepShape> extra;
+    if (int rc = lattice_tile_candidate(h, nsteps, pick, extra)) return rc;
+    if (!extra.empty()) {
+        std::vector<StepShape> two{pick, extra[0]};
+        std::vector<float> best;
+        if (int rc = time_shapes(h, nsteps, two, best)) return rc;
+        if (best[1] < best[0]) {
+            pick = extra[0];
+            pick_ms = best[1];
+        }
+    }
+    apply_shape(h, pick);
     clear_graphs(h);
-    if (ms_out) *ms_out = t[0].first;
-    cache_shape(cache, key, t[0].second, t[0].first);
+    if (ms_out) *ms_out = pick_ms;
+    cache_shape(cache, key, pick, pick_ms);
     return build_step_items(h);
 }
 
@@ -1746,7 +1945,7 @@ int flb_autotune_path(flb_t *h, int nsteps, int sample_every, double *ms_out)
     const char *cache = getenv("FLB_AUTOTUNE_CACHE");
     StepShape c{};
     double ms = 0;
-    if (cached_shape(cache, key, c, ms)) {
+    if (cached_shape(cache, key, h->params.size(), c, ms)) {
         apply_shape(h, c);
         if (ms_out) *ms_out = ms;
         clear_graphs(h);
@@ -1756,13 +1955,17 @@ int flb_autotune_path(flb_t *h, int nsteps, int sample_every, double *ms_out)
     if (rc) return rc;
     std::vector<std::pair<float, StepShape>> t;
     if ((rc = time_every_shape(h, nsteps, t))) return rc;
-    // the shapes within 4 % of the fastest alone (at most four) are timed
-    // on whole periods: sample_every steps and a sample, the sample beside
-    // the next period's steps as with the handle's own calls, in two
-    // round-robin passes of kDeferK periods (a whole accumulation cycle)
+    // the shapes within 4 % of the fastest alone (at most four), and for a
+    // batch the per-class tiles, are timed on whole periods: sample_every
+    // steps and a sample, the sample beside the next period's steps as with
+    // the handle's own calls, in two round-robin passes of kDeferK periods
+    // (a whole accumulation cycle)
     std::vector<StepShape> cand;
     for (const auto &x : t)
         if (x.first <= 1.04f * t[0].first && cand.size() < 4) cand.push_back(x.second);
+    std::vector<StepShape> extra;
+    if ((rc = lattice_tile_candidate(h, nsteps, cand[0], extra))) return rc;
+    cand.insert(cand.end(), extra.begin(), extra.end());
     std::vector<float> best(cand.size(), 1e30f);
     if (cand.size() > 1) {
         rc = with_saved_state(h, [&](flb_t *hh) -> int {

@@ -383,11 +383,26 @@ hipError_t launch_step(const DeviceView &v, const StepItem *items, int nitems, i
 // ---------------------------------------------------------------------
 constexpr int kStep2Threads = 512;
 
+// Tile shapes of the two-step kernel: TW x TH = 1024 sites, TW a power of
+// two.  Fixed carries the shape at compile time; Dyn at run time, so that
+// one kernel body serves tiles of several shapes (the kernel's registers
+// stay those of one shape).
+template <int TW_, int TH_> struct Fixed {
+    static_assert(TW_ * TH_ == 1024 && (TW_ & (TW_ - 1)) == 0, "tile shape");
+    static constexpr int tw = TW_, th = TH_, rw = TW_ + 2, rn = (TW_ + 2) * (TH_ + 2);
+    static constexpr int lg = TW_ == 32 ? 5 : TW_ == 64 ? 6 : TW_ == 128 ? 7 : 8;
+};
+struct Dyn {
+    int tw, th, rw, rn, lg;
+    __device__ explicit Dyn(int lg_) : tw(1 << lg_), th(1024 >> lg_), rw(tw + 2),
+                                       rn((tw + 2) * (th + 2)), lg(lg_) {}
+};
+
 // region coordinates of the h-th site of the one-site ring around a tile
-template <int TW, int TH>
-__device__ __forceinline__ void ring_site(int h, int &rx, int &ry)
+template <class SH>
+__device__ __forceinline__ void ring_site(const SH &sh, int h, int &rx, int &ry)
 {
-    constexpr int RW = TW + 2;
+    const int RW = sh.rw, TH = sh.th;
     if (h < RW) {
         ry = 0;
         rx = h;
@@ -403,21 +418,22 @@ __device__ __forceinline__ void ring_site(int h, int &rx, int &ry)
     }
 }
 
-template <int S, bool NT, bool NOISE, int TW, int TH>
-__global__ __launch_bounds__(kStep2Threads) void step2_kernel(StepArgs g)
+// One tile's two steps; mid holds 8 x sh.rn values of LDS (planes 1..8
+// after phase 1, plane-major).
+template <int S, bool NT, bool NOISE, class SH>
+__device__ __forceinline__ void step2_tile(const StepArgs &g, StepItem it, const SH sh,
+                                           typename Codec<S>::T *__restrict__ mid)
 {
     using T = typename Codec<S>::T;
-    constexpr int RW = TW + 2, RN = RW * (TH + 2);
-    constexpr int NTILE = TW * TH, NRING = RN - NTILE;
+    const int TW = sh.tw, TH = sh.th, RW = sh.rw, RN = sh.rn;
+    constexpr int NTILE = 1024;
+    const int NRING = RN - NTILE;              // at most 276 (128 x 8), below the thread count
     constexpr int KT = NTILE / kStep2Threads;  // tile sites per thread
     constexpr int K = KT + 1;                  // phase-1 sites per thread: tile sites, then a ring site
-    static_assert(NTILE % kStep2Threads == 0 && NRING <= kStep2Threads, "tile shape");
-    __shared__ T mid[8][RN];  // planes 1..8 after phase 1
-    const StepItem it = g.items[blockIdx.x];
-    if (it.lattice < 0) return;
+    static_assert(NTILE % kStep2Threads == 0, "tile shape");
     const LatticeParams &P = g.params[it.lattice];
     const int nx = P.nx, ny = P.ny;
-    const int tiles_x = (nx + TW - 1) / TW;
+    const int tiles_x = (nx + TW - 1) >> sh.lg;
     const int x0 = (it.tile % tiles_x) * TW, y0 = (it.tile / tiles_x) * TH;
     const T *__restrict__ src = (const T *)g.src + P.base;
     T *__restrict__ dst = (T *)g.dst + P.base;
@@ -432,10 +448,10 @@ __global__ __launch_bounds__(kStep2Threads) void step2_kernel(StepArgs g)
         int rx, ry;
         if (k < KT) {
             const int o = tid + k * kStep2Threads;
-            ry = o / TW + 1;
-            rx = o % TW + 1;
+            ry = (o >> sh.lg) + 1;
+            rx = (o & (TW - 1)) + 1;
         } else {
-            ring_site<TW, TH>(tid < NRING ? tid : 0, rx, ry);
+            ring_site(sh, tid < NRING ? tid : 0, rx, ry);
         }
         rs[k] = ry * RW + rx;
         // wrap (x >= -1): at most one subtraction unless the lattice is
@@ -487,32 +503,66 @@ __global__ __launch_bounds__(kStep2Threads) void step2_kernel(StepArgs g)
         update_site<NOISE, S>(d, P, (uint32_t)(ys[k] * nx + xs[k]), t, g.key0, g.key1);
         if (k < KT) own[k] = Work<S>::out(d[0]);
 #pragma unroll
-        for (int i = 1; i < 9; ++i) mid[i - 1][rs[k]] = Work<S>::out(d[i]);
+        for (int i = 1; i < 9; ++i) mid[(i - 1) * RN + rs[k]] = Work<S>::out(d[i]);
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
         const int o = tid + k * kStep2Threads;
-        const int oy = o / TW, ox = o % TW;
+        const int oy = o >> sh.lg, ox = o & (TW - 1);
         const int x = x0 + ox, y = y0 + oy;
         if (x >= nx || y >= ny) continue;
         const int c = rs[k];
         float d[9];
         d[0] = Work<S>::in(own[k]);
-        d[1] = Work<S>::in(mid[0][c - 1]);
-        d[2] = Work<S>::in(mid[1][c - RW]);
-        d[3] = Work<S>::in(mid[2][c + 1]);
-        d[4] = Work<S>::in(mid[3][c + RW]);
-        d[5] = Work<S>::in(mid[4][c - RW - 1]);
-        d[6] = Work<S>::in(mid[5][c - RW + 1]);
-        d[7] = Work<S>::in(mid[6][c + RW + 1]);
-        d[8] = Work<S>::in(mid[7][c + RW - 1]);
+        d[1] = Work<S>::in(mid[0 * RN + c - 1]);
+        d[2] = Work<S>::in(mid[1 * RN + c - RW]);
+        d[3] = Work<S>::in(mid[2 * RN + c + 1]);
+        d[4] = Work<S>::in(mid[3 * RN + c + RW]);
+        d[5] = Work<S>::in(mid[4 * RN + c - RW - 1]);
+        d[6] = Work<S>::in(mid[5 * RN + c - RW + 1]);
+        d[7] = Work<S>::in(mid[6 * RN + c + RW + 1]);
+        d[8] = Work<S>::in(mid[7 * RN + c + RW - 1]);
         update_site<NOISE, S>(d, P, (uint32_t)(y * nx + x), t + 1, g.key0, g.key1);
         const uint32_t off = ((uint32_t)y * px + (uint32_t)x) * E;
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             gstore<NT>(reinterpret_cast<T *>(dp[i] + off), Work<S>::out(d[i]));
     }
+}
+
+// Every tile of the launch has the shape TW x TH.
+template <int S, bool NT, bool NOISE, int TW, int TH>
+__global__ __launch_bounds__(kStep2Threads) void step2_kernel(StepArgs g)
+{
+    using T = typename Codec<S>::T;
+    using SH = Fixed<TW, TH>;
+    __shared__ T mid[8 * SH::rn];
+    const StepItem it = g.items[blockIdx.x];
+    if (it.lattice < 0) return;
+    step2_tile<S, NT, NOISE>(g, it, SH{}, mid);
+}
+
+// Each work item has its own tile shape: 32 x 32 when the tile index
+// carries kStep2Square, else 64 x 16 (a lattice's items all have the same
+// shape).  The two shapes need about the same LDS (37 and 38 KB in FP32,
+// four blocks per CU), so a batch can give each lattice the shape that fits
+// its sides in one launch.
+// (In FP32 the run-time shape would take a 65th register and leave three
+// blocks per CU instead of four: the register budget of eight waves per SIMD
+// is asked for.)
+template <int S, bool NT, bool NOISE>
+__global__ __launch_bounds__(kStep2Threads)
+__attribute__((amdgpu_waves_per_eu(S == kF32 ? 8 : 7))) void step2_mixed_kernel(StepArgs g)
+{
+    using T = typename Codec<S>::T;
+    constexpr int RN = Fixed<32, 32>::rn > Fixed<64, 16>::rn ? Fixed<32, 32>::rn : Fixed<64, 16>::rn;
+    __shared__ T mid[8 * RN];
+    StepItem it = g.items[blockIdx.x];
+    if (it.lattice < 0) return;
+    const bool square = (it.tile & kStep2Square) != 0;
+    it.tile &= ~kStep2Square;
+    step2_tile<S, NT, NOISE>(g, it, Dyn(square ? 5 : 6), mid);
 }
 
 template <int S, bool NT, bool NOISE>
@@ -523,12 +573,16 @@ static hipError_t launch_step2_tiles(const StepArgs &a, int nitems, int tw, hipS
         hipLaunchKernelGGL((step2_kernel<S, NT, NOISE, 64, 16>), grid, block, 0, s, a);
     else if (tw == 128)
         hipLaunchKernelGGL((step2_kernel<S, NT, NOISE, 128, 8>), grid, block, 0, s, a);
+    else if (tw == 32)
+        hipLaunchKernelGGL((step2_kernel<S, NT, NOISE, 32, 32>), grid, block, 0, s, a);
+    else if (tw == 0)
+        hipLaunchKernelGGL((step2_mixed_kernel<S, NT, NOISE>), grid, block, 0, s, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-bool step2_tile_supported(int tw) { return tw == 64 || tw == 128; }
+bool step2_tile_supported(int tw) { return tw == 32 || tw == 64 || tw == 128; }
 
 hipError_t launch_step2(const DeviceView &v, const StepItem *items, int nitems, int tile_w,
                         uint32_t step_add, bool nontemporal, bool noise, hipStream_t s)

@@ -324,11 +324,11 @@ def test_resume_from_saved_state_is_bit_identical(flb):
 def test_time_blocking_equals_one_step_launches(flb, storage):
     """Pairs of steps per launch (halo recomputed on chip) give exactly the
     populations of one step per launch: tiny, ragged and tile-sized shapes,
-    both tile widths, an odd number of steps."""
-    for nx, ny in [(2, 2), (3, 5), (37, 23), (64, 16), (130, 17), (257, 3), (5, 300),
+    every tile width, an odd number of steps."""
+    for nx, ny in [(2, 2), (3, 5), (37, 23), (64, 16), (32, 32), (130, 17), (257, 3), (5, 300),
                    (1000, 7)]:
         note("time blocking", storage, nx, ny)
-        for tile in (64, 128):
+        for tile in (32, 64, 128):
             a = flb.Lattice(nx, ny, TAU_C1, 1e-3, u0=(0.03, -0.02), seed=4, storage=storage)
             b = flb.Lattice(nx, ny, TAU_C1, 1e-3, u0=(0.03, -0.02), seed=4, storage=storage)
             b.set_time_blocking(2, tile)
@@ -348,17 +348,91 @@ def test_time_blocking_batch_and_graph_periods(flb):
     a = flb.Lattice.batch(specs, seed=6)
     b = flb.Lattice.batch(specs, seed=6)
     b.set_time_blocking(2, 128)
-    for h in (a, b):
+    # each lattice its own tile in one launch (the size-class form)
+    c = flb.Lattice.batch(specs, seed=6)
+    c.set_lattice_tiles([32, 64, 32])
+    assert c.time_blocking() == (2, 0) and c.lattice_tiles() == [32, 64, 32]
+    assert b.lattice_tiles() == [128, 128, 128]
+    for h in (a, b, c):
         h.thermalize()
         h.run(103, 10)  # graph periods of ten steps plus a ragged tail
         h.run(37, 3)    # odd periods started off-phase
     for i in range(len(specs)):
-        assert np.array_equal(a.get_populations(i), b.get_populations(i))
-        assert np.array_equal(a.read_correlators(i)[0], b.read_correlators(i)[0])
+        for h in (b, c):
+            assert np.array_equal(a.get_populations(i), h.get_populations(i))
+            assert np.array_equal(a.read_correlators(i)[0], h.read_correlators(i)[0])
     with pytest.raises(flb.FlbError):
         b.set_time_blocking(3, 64)
     with pytest.raises(flb.FlbError):
         b.set_time_blocking(2, 256)
+    with pytest.raises(flb.FlbError):
+        c.set_lattice_tiles([32, 128, 64])
+    with pytest.raises(ValueError):
+        c.set_lattice_tiles([32, 64])
+    assert c.lattice_tiles() == [32, 64, 32]
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_lattice_tiles_equal_one_step_launches(flb, storage):
+    """Per-lattice tile shapes on ragged and tiny lattices of one batch give
+    the populations of one step per launch, every assignment of the two
+    widths to the lattices."""
+    sides = [(2, 2), (37, 23), (130, 17), (33, 65), (5, 300)]
+    specs = [dict(nx=nx, ny=ny, tau=TAU_C1, theta=1e-3, u0=(0.03, -0.01), stream_id=i)
+             for i, (nx, ny) in enumerate(sides)]
+    ref = flb.Lattice.batch(specs, seed=9, storage=storage)
+    ref.thermalize()
+    ref.step(9)
+    want = [ref.get_populations(i) for i in range(len(sides))]
+    for mask in range(1 << len(sides)):
+        tiles = [32 if mask >> i & 1 else 64 for i in range(len(sides))]
+        g = flb.Lattice.batch(specs, seed=9, storage=storage)
+        g.set_lattice_tiles(tiles)
+        g.thermalize()
+        g.step(9)
+        for i in range(len(sides)):
+            assert np.array_equal(g.get_populations(i), want[i]), (tiles, i)
+        g.close()
+
+
+def test_autotune_tiles_per_size_class(flb, tmp_path, monkeypatch):
+    """A batch of lattices of several size classes: the whole-path tuner
+    (per-class tiles among its candidates) leaves populations, step counter
+    and sums unchanged, the run after it has the bits of an untuned handle
+    set to the chosen tiles, and a second handle of the same batch takes the
+    choice from the cache file."""
+    monkeypatch.setenv("FLB_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    sides = [(64, 64), (70, 200), (100, 100), (130, 300), (300, 130), (257, 257), (90, 40),
+             (40, 90)]
+    specs = [dict(nx=nx, ny=ny, tau=TAU_C1, theta=1e-3, u0=(0.02, 0.0), stream_id=i)
+             for i, (nx, ny) in enumerate(sides)]
+    ref = flb.Lattice.batch(specs, seed=31)
+    g = flb.Lattice.batch(specs, seed=31)
+    for h in (ref, g):
+        h.thermalize()
+        h.step(4)
+    cfg, ms = g.autotune_path(4, 5)
+    tiles = g.lattice_tiles()
+    note("size-class tiles", g.time_blocking(), tiles, ms)
+    assert ms > 0 and g.t == 4
+    assert all(w in (32, 64, 128) for w in tiles)
+    for i in range(len(sides)):
+        assert np.array_equal(g.get_populations(i), ref.get_populations(i))
+    ref.set_step_config(*cfg)
+    if g.time_blocking()[1] == 0:
+        ref.set_lattice_tiles(tiles)
+    else:
+        ref.set_time_blocking(*g.time_blocking())
+    for h in (ref, g):
+        h.run(20, 5)
+    for i in range(len(sides)):
+        assert np.array_equal(g.get_populations(i), ref.get_populations(i))
+        assert np.array_equal(g.read_correlators(i)[0], ref.read_correlators(i)[0])
+    h = flb.Lattice.batch(specs, seed=2)
+    cfg2, ms2 = h.autotune_path(4, 5)  # from the cache file
+    assert cfg2 == cfg and abs(ms2 - ms) < 1e-5
+    assert h.time_blocking() == g.time_blocking() and h.lattice_tiles() == tiles
+    assert len((tmp_path / "tune.txt").read_text().splitlines()) == 1
 
 
 VX = (0, 1, 0, -1, 0, 1, -1, -1, 1)
