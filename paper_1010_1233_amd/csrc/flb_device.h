@@ -38,6 +38,7 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 // revolutions, so 2 pi a needs no range reduction.
 __device__ __forceinline__ void normals6(uint4 w, float z[6])
 {
+#pragma clang fp contract(off)  // the same bits in every kernel that inlines this
     const uint32_t wv[3] = {w.x, w.y, w.z};
 #pragma unroll
     for (int p = 0; p < 3; ++p) {

@@ -25,6 +25,10 @@ namespace flbdev {
 template <bool NOISE>
 __device__ __forceinline__ void collide(float (&d)[9], const LatticeParams &P, const float (&z)[6])
 {
+    // only the written fmaf calls fuse: a multiply and an add are never
+    // contracted by the compiler, whose choice could differ between the
+    // kernels that inline this (their results must be the same bits)
+#pragma clang fp contract(off)
     const float a = d[1] + d[3], b = d[2] + d[4];
     const float c = d[5] + d[7], e = d[6] + d[8];
     const float ab = a + b, ce = c + e;
@@ -34,8 +38,8 @@ __device__ __forceinline__ void collide(float (&d)[9], const LatticeParams &P, c
     const float jx = x13 + p57 - p68;
     const float jy = y24 + p57 + p68;
 
-    const float s3 = 2.25f * (a - b);
-    const float s4 = 9.0f * (c - e);
+    // s3 = 9/4 (a - b) and s4 = 9 (c - e) enter only through e3 - s3 and
+    // e4 - s4 below
     const float s5 = fmaf(0.5f, ab, fmaf(2.0f, ce, -d[0]));
     const float s6 = 1.5f * fmaf(2.0f, p57 - p68, -x13);
     const float s7 = 1.5f * fmaf(2.0f, p57 + p68, -y24);
@@ -43,14 +47,14 @@ __device__ __forceinline__ void collide(float (&d)[9], const LatticeParams &P, c
 
     // Eq. (10) in the scaled basis: 3/2 rho (ux^2 - uy^2) -> 9/4 (jx^2 - jy^2)/rho, ...
     const float ir = __builtin_amdgcn_rcpf(P.rho0 + drho);
-    const float jxx = jx * jx, jyy = jy * jy;
-    const float e3 = 2.25f * (jxx - jyy) * ir;
+    const float jyy = jy * jy;
+    const float e3 = 2.25f * fmaf(jx, jx, -jyy) * ir;
     const float e4 = 9.0f * (jx * jy) * ir;
-    const float e5 = 1.5f * (jxx + jyy) * ir;
+    const float e5 = 1.5f * fmaf(jx, jx, jyy) * ir;
 
     // change of each scaled moment, Eq. (5) and Eq. (8)
-    float t3 = P.omega[0] * (e3 - s3);
-    float t4 = P.omega[1] * (e4 - s4);
+    float t3 = P.omega[0] * fmaf(-2.25f, a - b, e3);
+    float t4 = P.omega[1] * fmaf(-9.0f, c - e, e4);
     float t5 = P.omega[2] * (e5 - s5);
     float t6 = -P.omega[3] * s6;
     float t7 = -P.omega[4] * s7;
@@ -67,17 +71,18 @@ __device__ __forceinline__ void collide(float (&d)[9], const LatticeParams &P, c
     // d*_i = d_i + w_i sum_{a>=3} m_i^a dM^a
     const float A = fmaf(0.5f, t5, -t8);
     const float B = 2.0f * (t5 + t8);
-    const float P6 = 2.0f * t6, Q7 = 2.0f * t7;
+    const float Q7 = 2.0f * t7;
+    const float PpQ = fmaf(2.0f, t6, Q7), PmQ = fmaf(2.0f, t6, -Q7);  // 2 t6 +- 2 t7
     constexpr float w0 = 4.0f / 9.0f, w1 = 1.0f / 9.0f, w5 = 1.0f / 36.0f;
     d[0] = fmaf(w0, fmaf(0.5f, t8, -t5), d[0]);
     d[1] = fmaf(w1, (A + t3) - t6, d[1]);
     d[3] = fmaf(w1, (A + t3) + t6, d[3]);
     d[2] = fmaf(w1, (A - t3) - t7, d[2]);
     d[4] = fmaf(w1, (A - t3) + t7, d[4]);
-    d[5] = fmaf(w5, (B + t4) + (P6 + Q7), d[5]);
-    d[6] = fmaf(w5, (B - t4) - (P6 - Q7), d[6]);
-    d[7] = fmaf(w5, (B + t4) - (P6 + Q7), d[7]);
-    d[8] = fmaf(w5, (B - t4) + (P6 - Q7), d[8]);
+    d[5] = fmaf(w5, (B + t4) + PpQ, d[5]);
+    d[6] = fmaf(w5, (B - t4) - PmQ, d[6]);
+    d[7] = fmaf(w5, (B + t4) - PpQ, d[7]);
+    d[8] = fmaf(w5, (B - t4) + PmQ, d[8]);
 }
 
 // The same collision for the 16-bit formats, on the stored scaled
@@ -91,6 +96,7 @@ template <bool NOISE>
 __device__ __forceinline__ void collide_q(float (&q)[9], const LatticeParams &P,
                                           const float (&z)[6])
 {
+#pragma clang fp contract(off)  // as in collide
     const float *C = P.qcoef, *K = P.qoff;
     const float qa = q[1] + q[3], qb = q[2] + q[4];
     const float qc = q[5] + q[7], qe = q[6] + q[8];
@@ -441,6 +447,11 @@ __device__ __forceinline__ void step2_tile(const StepArgs &g, StepItem it, const
     const uint32_t t = *g.step + g.step_add;
     const int tid = threadIdx.x;
 
+    // An interior tile: the region and every site it pulls from lie inside
+    // the lattice, so no coordinate wraps and each plane's pull is one
+    // fixed shift of the site's own offset (block-uniform test).
+    const bool interior = x0 >= 2 && y0 >= 2 && x0 + TW + 2 <= nx && y0 + TH + 2 <= ny;
+
     // phase-1 sites: region index and (wrapped) lattice coordinates
     int xs[K], ys[K], rs[K];
 #pragma unroll
@@ -454,15 +465,22 @@ __device__ __forceinline__ void step2_tile(const StepArgs &g, StepItem it, const
             ring_site(sh, tid < NRING ? tid : 0, rx, ry);
         }
         rs[k] = ry * RW + rx;
+        xs[k] = x0 - 1 + rx;
+        ys[k] = y0 - 1 + ry;
+    }
+    if (!interior) {
         // wrap (x >= -1): at most one subtraction unless the lattice is
         // smaller than a tile
-        int x = x0 - 1 + rx, y = y0 - 1 + ry;
-        x = x < 0 ? x + nx : x;
-        y = y < 0 ? y + ny : y;
-        while (x >= nx) x -= nx;
-        while (y >= ny) y -= ny;
-        xs[k] = x;
-        ys[k] = y;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            int x = xs[k], y = ys[k];
+            x = x < 0 ? x + nx : x;
+            y = y < 0 ? y + ny : y;
+            while (x >= nx) x -= nx;
+            while (y >= ny) y -= ny;
+            xs[k] = x;
+            ys[k] = y;
+        }
     }
     // per-plane bases (wave-uniform) and byte offsets within a plane
     const char *sp[9];
@@ -474,6 +492,34 @@ __device__ __forceinline__ void step2_tile(const StepArgs &g, StepItem it, const
     }
     constexpr uint32_t E = sizeof(T);
     T raw[K][9];
+    if (interior) {
+        // plane i pulls from x - v_i: its base shifted by -(v_iy px + v_ix)
+        // values, so one vector offset serves all nine loads of a site
+        const int64_t row = (int64_t)px * E;
+        const char *const sh0 = sp[0];
+        const char *const sh1 = sp[1] - (int64_t)E;
+        const char *const sh2 = sp[2] - row;
+        const char *const sh3 = sp[3] + (int64_t)E;
+        const char *const sh4 = sp[4] + row;
+        const char *const sh5 = sp[5] - row - (int64_t)E;
+        const char *const sh6 = sp[6] - row + (int64_t)E;
+        const char *const sh7 = sp[7] + row + (int64_t)E;
+        const char *const sh8 = sp[8] + row - (int64_t)E;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (k == KT && tid >= NRING) break;
+            const uint32_t o = ((uint32_t)ys[k] * px + (uint32_t)xs[k]) * E;
+            raw[k][0] = *reinterpret_cast<const T *>(sh0 + o);
+            raw[k][1] = *reinterpret_cast<const T *>(sh1 + o);
+            raw[k][2] = *reinterpret_cast<const T *>(sh2 + o);
+            raw[k][3] = *reinterpret_cast<const T *>(sh3 + o);
+            raw[k][4] = *reinterpret_cast<const T *>(sh4 + o);
+            raw[k][5] = *reinterpret_cast<const T *>(sh5 + o);
+            raw[k][6] = *reinterpret_cast<const T *>(sh6 + o);
+            raw[k][7] = *reinterpret_cast<const T *>(sh7 + o);
+            raw[k][8] = *reinterpret_cast<const T *>(sh8 + o);
+        }
+    } else {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (k == KT && tid >= NRING) break;
@@ -492,6 +538,7 @@ __device__ __forceinline__ void step2_tile(const StepArgs &g, StepItem it, const
         raw[k][6] = *reinterpret_cast<const T *>(sp[6] + (rm + xr));
         raw[k][7] = *reinterpret_cast<const T *>(sp[7] + (rp + xr));
         raw[k][8] = *reinterpret_cast<const T *>(sp[8] + (rp + xm));
+    }
     }
     T own[KT];  // plane 0 of the tile sites after phase 1, in the storage format
 #pragma unroll
@@ -531,9 +578,16 @@ __device__ __forceinline__ void step2_tile(const StepArgs &g, StepItem it, const
     }
 }
 
+// Waves per SIMD a kernel's register budget is set for: in FP32 the 32 x 32
+// and 64 x 16 tiles take 37-38 KB of LDS, so a CU holds four blocks (eight
+// waves per SIMD) if each thread keeps to 64 registers; the 128 x 8 tile's
+// 42 KB leave three, as do the 16-bit kernels' registers.
+template <int S, int TW> constexpr int step2_waves() { return S == kF32 && TW != 128 ? 8 : 6; }
+
 // Every tile of the launch has the shape TW x TH.
 template <int S, bool NT, bool NOISE, int TW, int TH>
-__global__ __launch_bounds__(kStep2Threads) void step2_kernel(StepArgs g)
+__global__ __launch_bounds__(kStep2Threads)
+__attribute__((amdgpu_waves_per_eu(step2_waves<S, TW>()))) void step2_kernel(StepArgs g)
 {
     using T = typename Codec<S>::T;
     using SH = Fixed<TW, TH>;
@@ -548,12 +602,9 @@ __global__ __launch_bounds__(kStep2Threads) void step2_kernel(StepArgs g)
 // shape).  The two shapes need about the same LDS (37 and 38 KB in FP32,
 // four blocks per CU), so a batch can give each lattice the shape that fits
 // its sides in one launch.
-// (In FP32 the run-time shape would take a 65th register and leave three
-// blocks per CU instead of four: the register budget of eight waves per SIMD
-// is asked for.)
 template <int S, bool NT, bool NOISE>
 __global__ __launch_bounds__(kStep2Threads)
-__attribute__((amdgpu_waves_per_eu(S == kF32 ? 8 : 7))) void step2_mixed_kernel(StepArgs g)
+__attribute__((amdgpu_waves_per_eu(step2_waves<S, 64>()))) void step2_mixed_kernel(StepArgs g)
 {
     using T = typename Codec<S>::T;
     constexpr int RN = Fixed<32, 32>::rn > Fixed<64, 16>::rn ? Fixed<32, 32>::rn : Fixed<64, 16>::rn;
