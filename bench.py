@@ -101,20 +101,26 @@ def launch_figures(g, sites, step_ms):
             "achieved_GBs": algo / (launch_ms * 1e-3) / 1e9}
 
 
-def measured_traffic(workload, storage, shape, blocking=(1, 64)):
-    """HBM bytes per step-kernel launch of this launch shape from the
-    committed counter summary, or None when it is missing or was taken on a
-    different kernel source."""
+def counter_entry(workload, storage, shape, blocking=(1, 64)):
+    """This launch shape's entry of the committed counter summary (HBM bytes
+    per step-kernel launch, VALU instructions per site update), or {}
+    when it is missing or was taken on a different kernel source."""
     path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
-        return None
+        return {}
     e = d.get(shape_key(workload, storage, shape, blocking))
     if not e or e.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    return e.get("bytes_per_launch")
+        return {}
+    return e
+
+
+def measured_traffic(workload, storage, shape, blocking=(1, 64)):
+    """HBM bytes per step-kernel launch of this launch shape from the
+    committed counter summary, or None (see counter_entry)."""
+    return counter_entry(workload, storage, shape, blocking).get("bytes_per_launch")
 
 
 def sweep_shapes(flb, workloads, name, storage, steps=5):
@@ -161,6 +167,27 @@ def steady_step_ms(torch, g, stream, n=50, warm=100, reps=3):
     `reps` runs of n steps."""
     time_step_kernel(torch, g, stream, warm)
     return min(time_step_kernel(torch, g, stream, n) for _ in range(reps))
+
+
+def copy_GBs(torch, stream, nbytes, n=20, reps=3):
+    """The device copy's practical rate (read + write bytes per second) over
+    nbytes each way, on `stream`: the fastest of `reps` runs of n copies."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    best = 1e30
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            b.copy_(a)
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(n):
+                b.copy_(a)
+            e1.record(stream)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) / n)
+    del a, b
+    return 2 * nbytes / (best * 1e-3) / 1e9
 
 
 def plain_path_ms(torch, g, stream, n=ACCUMULATE_EVERY, warm=16):
@@ -515,6 +542,9 @@ def main():
     with torch.cuda.stream(stream):
         iso_ms = steady_step_ms(torch, g, stream, n=10 * SAMPLE_EVERY, warm=20 * SAMPLE_EVERY)
     iso = launch_figures(g, V, iso_ms)
+    # the device copy of one population buffer (the bytes one step moves at
+    # the algorithmic count): the practical ceiling next to 8 TB/s
+    copy_rate = copy_GBs(torch, stream, 9 * V * g.storage_info()[1])
 
     out = {
         "metric": METRIC,
@@ -548,6 +578,15 @@ def main():
                      "measured_frac": (None if traffic is None else
                                        traffic / (launch["avg_launch_ms"] * 1e-3) / 1e9
                                        / HBM_PEAK_GBS),
+                     # VALU instructions (per lane) per site update, from
+                     # the counters (SQ_INSTS_VALU x 64 / updates per launch)
+                     "valu_insts_per_update": counter_entry(args.workload, args.storage, tuned,
+                                                            blocking).get("valu_insts_per_update"),
+                     "copy": {"bytes_each_way": 9 * V * g.storage_info()[1],
+                              "GBs": copy_rate, "achieved_over_copy": achieved / copy_rate,
+                              "measured_over_copy": (None if traffic is None else
+                                                     traffic / (launch["avg_launch_ms"] * 1e-3)
+                                                     / 1e9 / copy_rate)},
                      "isolated": {"avg_launch_ms": iso["avg_launch_ms"],
                                   "achieved": iso["achieved_GBs"],
                                   "frac": iso["achieved_GBs"] / HBM_PEAK_GBS,

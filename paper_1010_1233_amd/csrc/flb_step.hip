@@ -384,7 +384,7 @@ hipError_t launch_step(const DeviceView &v, const StepItem *items, int nitems, i
 // Each thread collides the same tile sites in both phases (and one ring
 // site in phase 1), so the rest population, which streams from the site
 // itself, stays in a register: LDS holds planes 1..8 only (38 KB for a
-// 64 x 16 tile, four blocks per CU).  All of a thread's phase-1 loads are
+// 64 x 16 tile in FP32).  All of a thread's phase-1 loads are
 // issued before its first collision.
 // ---------------------------------------------------------------------
 constexpr int kStep2Threads = 512;
@@ -578,16 +578,12 @@ __device__ __forceinline__ void step2_tile(const StepArgs &g, StepItem it, const
     }
 }
 
-// Waves per SIMD a kernel's register budget is set for: in FP32 the 32 x 32
-// and 64 x 16 tiles take 37-38 KB of LDS, so a CU holds four blocks (eight
-// waves per SIMD) if each thread keeps to 64 registers; the 128 x 8 tile's
-// 42 KB leave three, as do the 16-bit kernels' registers.
-template <int S, int TW> constexpr int step2_waves() { return S == kF32 && TW != 128 ? 8 : 6; }
-
-// Every tile of the launch has the shape TW x TH.
+// Every tile of the launch has the shape TW x TH.  (A CU holds three
+// blocks: 65-71 registers a thread; a budget of 64 for four blocks of the
+// 38 KB FP32 tiles made the compiler spill, and the spills cost 5 % more
+// HBM bytes than the fourth block gained.)
 template <int S, bool NT, bool NOISE, int TW, int TH>
-__global__ __launch_bounds__(kStep2Threads)
-__attribute__((amdgpu_waves_per_eu(step2_waves<S, TW>()))) void step2_kernel(StepArgs g)
+__global__ __launch_bounds__(kStep2Threads) void step2_kernel(StepArgs g)
 {
     using T = typename Codec<S>::T;
     using SH = Fixed<TW, TH>;
@@ -599,12 +595,11 @@ __attribute__((amdgpu_waves_per_eu(step2_waves<S, TW>()))) void step2_kernel(Ste
 
 // Each work item has its own tile shape: 32 x 32 when the tile index
 // carries kStep2Square, else 64 x 16 (a lattice's items all have the same
-// shape).  The two shapes need about the same LDS (37 and 38 KB in FP32,
-// four blocks per CU), so a batch can give each lattice the shape that fits
-// its sides in one launch.
+// shape).  The two shapes need about the same LDS (37 and 38 KB in FP32),
+// so a batch can give each lattice the shape that fits its sides in one
+// launch.
 template <int S, bool NT, bool NOISE>
-__global__ __launch_bounds__(kStep2Threads)
-__attribute__((amdgpu_waves_per_eu(step2_waves<S, 64>()))) void step2_mixed_kernel(StepArgs g)
+__global__ __launch_bounds__(kStep2Threads) void step2_mixed_kernel(StepArgs g)
 {
     using T = typename Codec<S>::T;
     constexpr int RN = Fixed<32, 32>::rn > Fixed<64, 16>::rn ? Fixed<32, 32>::rn : Fixed<64, 16>::rn;
