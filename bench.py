@@ -79,23 +79,27 @@ def shape_key(workload, storage, shape, blocking=(1, 64)):
     """Key of a launch shape: one-step kernels by threads x sites, the
     two-step kernel by its tile width."""
     tw, sites, nt = shape
-    if blocking[0] == 2:
-        return f"{workload}/{storage}/step2_{blocking[1]}/nt{int(bool(nt))}"
+    if blocking[0] >= 2:
+        return f"{workload}/{storage}/step{blocking[0]}_{blocking[1]}/nt{int(bool(nt))}"
     return f"{workload}/{storage}/{tw}x{sites}/nt{int(bool(nt))}"
 
 
-def launch_figures(g, sites, step_ms):
+KERNEL_OF_STEPS = {1: STEP_KERNEL, 2: "step2_kernel", 3: "step3_kernel"}
+
+
+def launch_figures(g, sites, step_ms, steps=None):
     """The dominant kernel's launch: which kernel, steps per launch, its
     duration and its algorithmic bytes = 18 values per site update (9 loads
-    + 9 stores) x the site updates of one launch.  The two-step kernel does
-    two updates per site and launch on one read and one write of the state,
-    so its algorithmic rate can exceed what HBM moves (see the measured
-    traffic)."""
-    steps, tile2 = g.time_blocking()
+    + 9 stores) x the site updates of one launch.  The two- and three-step
+    kernels do two or three updates per site and launch on one read and one
+    write of the state, so their algorithmic rate can exceed what HBM moves
+    (see the measured traffic)."""
+    if steps is None:
+        steps = g.time_blocking()[0]
     bpv = g.storage_info()[1]
     launch_ms = steps * step_ms
     algo = 18 * bpv * sites * steps
-    return {"kernel": "step2_kernel" if steps == 2 else STEP_KERNEL,
+    return {"kernel": KERNEL_OF_STEPS[steps],
             "steps_per_launch": steps, "avg_launch_ms": launch_ms,
             "algorithmic_bytes_per_launch": algo,
             "achieved_GBs": algo / (launch_ms * 1e-3) / 1e9}
@@ -133,15 +137,16 @@ def sweep_shapes(flb, workloads, name, storage, steps=5):
             for nt in (0, 1):
                 g.set_step_config(tw, sites, nt)
                 g.step(steps)
-    for tile2 in (32, 64, 128):
-        for nt in (0, 1):
-            g.set_step_config(256, 1, nt)
-            g.set_time_blocking(2, tile2)
-            g.step(2 * steps)
+    for blocking in (2, 3):
+        for tile2 in (32, 64, 128):
+            for nt in (0, 1):
+                g.set_step_config(256, 1, nt)
+                g.set_time_blocking(blocking, tile2)
+                g.step(blocking * steps)
     g.set_time_blocking(1, 64)
     g.synchronize()
     print(f"sweep-shapes: {name} {storage}: 18 one-step shapes x {steps} steps, "
-          f"6 two-step shapes x {steps} launches", flush=True)
+          f"6 two-step and 6 three-step shapes x {steps} launches", flush=True)
 
 
 def make_lattice(flb, workloads, name, storage):
@@ -161,7 +166,7 @@ def time_step_kernel(torch, g, stream, n):
     return e0.elapsed_time(e1) / n
 
 
-def steady_step_ms(torch, g, stream, n=50, warm=100, reps=3):
+def steady_step_ms(torch, g, stream, n=60, warm=120, reps=3):
     """Step time (ms) of a handle alone: `warm` untimed steps (the device
     leaves the power state of whatever ran before), then the fastest of
     `reps` runs of n steps."""
@@ -519,15 +524,19 @@ def main():
         g.synchronize()
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        n_launches, launch_total_ms = g.launch_timing()
+        kinds = g.launch_timing_kinds()
 
-    steps_per_launch = g.time_blocking()[0]
+    # launches of 1, 2 and 3 steps (with three steps per launch a period of
+    # ten steps is 3 + 3 + 2 + 2); the roofline takes the kind that took the
+    # most time
     steps_timed = -(-args.steps // LAUNCH_TIMING_EVERY)
-    assert n_launches * steps_per_launch == steps_timed * SAMPLE_EVERY, n_launches
-    step_ms = launch_total_ms / n_launches / steps_per_launch
+    assert sum((q + 1) * n for q, (n, _) in enumerate(kinds)) == steps_timed * SAMPLE_EVERY, kinds
+    n_launches = sum(n for n, _ in kinds)
+    step_ms = sum(ms for _, ms in kinds) / (steps_timed * SAMPLE_EVERY)
+    qd = max(range(3), key=lambda q: kinds[q][1])
     ms_per_step = elapsed * 1e3 / args.steps
     value = args.steps * SAMPLE_EVERY * V / elapsed / 1e9
-    launch = launch_figures(g, V, step_ms)
+    launch = launch_figures(g, V, kinds[qd][1] / kinds[qd][0] / (qd + 1), steps=qd + 1)
     achieved = launch["achieved_GBs"]
     traffic = measured_traffic(args.workload, args.storage, tuned, blocking)
     drift = float(abs(g.sample_conservation()[0] - cons0[0]))
@@ -540,7 +549,8 @@ def main():
     # untimed steps that the device has left the power state of the idle
     # host-side read above
     with torch.cuda.stream(stream):
-        iso_ms = steady_step_ms(torch, g, stream, n=10 * SAMPLE_EVERY, warm=20 * SAMPLE_EVERY)
+        # 120 steps: whole launches of the dominant kind
+        iso_ms = steady_step_ms(torch, g, stream, n=120, warm=240)
     iso = launch_figures(g, V, iso_ms)
     # the device copy of one population buffer (the bytes one step moves at
     # the algorithmic count): the practical ceiling next to 8 TB/s
@@ -572,6 +582,7 @@ def main():
                      "algorithmic_bytes_per_launch": launch["algorithmic_bytes_per_launch"],
                      "avg_launch_ms": launch["avg_launch_ms"],
                      "launches_timed": n_launches,
+                     "launches_of_kernel": kinds[qd][0],
                      "launch_shape": list(tuned) + [list(blocking)],
                      "measured_GBs": (None if traffic is None else
                                       traffic / (launch["avg_launch_ms"] * 1e-3) / 1e9),

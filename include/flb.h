@@ -170,9 +170,13 @@ int flb_get_sample_overlap(flb_t *h);
  * synchronises the work stream and writes the number of timed launches and
  * the sum of their durations (ms) since the previous call, then starts a new
  * count.  Graph-replayed periods and flb_autotune's candidates are not
- * timed; each timed launch keeps its event pair until it is read. */
+ * timed; each timed launch keeps its event pair until it is read.
+ * flb_get_launch_timing_kinds reads the same records split by the steps a
+ * launch took: launches[q] and total_ms[q] (caller arrays of three) for the
+ * launches of q + 1 steps. */
 int flb_set_launch_timing(flb_t *h, int on);
 int flb_get_launch_timing(flb_t *h, int64_t *launches, double *total_ms);
+int flb_get_launch_timing_kinds(flb_t *h, int64_t launches[3], double total_ms[3]);
 
 /* Advances every lattice of the handle by nsteps >= 0 steps of Eq. (5) with
  * streaming (Eq. 1).  Enqueues only. */
@@ -331,11 +335,16 @@ int flb_get_step_config(flb_t *h, int *tile_w, int *sites, int *nontemporal);
  * launch (tiles of tile_w x 1024/tile_w sites, tile_w 32, 64 or 128; each
  * block collides its tile and a one-site halo at t, keeps them on chip and
  * collides the tile again at t+1), so the populations cross HBM once per two
- * steps; an odd last step uses the one-step kernel.  Every site sees the
- * same arithmetic, noise counters and storage rounding as with one step per
- * launch: results do not depend on it.  steps_per_launch = 1 (default) turns
- * it off.  FLB_EINVAL for other values.  flb_get_time_blocking reports
- * tile_w = 0 while each lattice has its own tile (flb_set_lattice_tiles). */
+ * steps; an odd last step uses the one-step kernel.  steps_per_launch = 3
+ * runs three steps per launch on the same tiles with a two-site halo (the
+ * halo at t, the tile and the inner ring at t+1, the tile at t+2); a
+ * remainder of two steps takes the two-step kernel, and of one step the
+ * one-step kernel if fewer than four steps are enqueued, else the last
+ * three-step launch and it become two two-step launches.  Every site sees the same arithmetic, noise counters and storage
+ * rounding as with one step per launch: results do not depend on it.
+ * steps_per_launch = 1 (default) turns it off.  FLB_EINVAL for other values.
+ * flb_get_time_blocking reports tile_w = 0 while each lattice has its own
+ * tile (flb_set_lattice_tiles). */
 int flb_set_time_blocking(flb_t *h, int steps_per_launch, int tile_w);
 int flb_get_time_blocking(flb_t *h, int *steps_per_launch, int *tile_w);
 

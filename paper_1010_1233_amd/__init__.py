@@ -77,6 +77,8 @@ SIGNATURES = {
     "flb_set_sample_overlap": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "flb_get_sample_overlap": (ctypes.c_int, [ctypes.c_void_p]),
     "flb_set_launch_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "flb_get_launch_timing_kinds": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                                   _dp]),
     "flb_get_launch_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                              ctypes.POINTER(ctypes.c_double)]),
     "flb_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
@@ -283,6 +285,14 @@ class Lattice:
         _check(lib().flb_get_launch_timing(self._h, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
 
+    def launch_timing_kinds(self):
+        """As launch_timing, split by the steps a launch took: a list of
+        (launches, total ms) for one, two and three steps per launch."""
+        n = (ctypes.c_int64 * 3)()
+        ms = (ctypes.c_double * 3)()
+        _check(lib().flb_get_launch_timing_kinds(self._h, n, ms))
+        return [(n[q], ms[q]) for q in range(3)]
+
     def step(self, n=1):
         _check(lib().flb_step(self._h, int(n)))
 
@@ -307,8 +317,8 @@ class Lattice:
         return a.value, b.value, bool(c.value)
 
     def set_time_blocking(self, steps_per_launch, tile_w=64):
-        """1: one step per kernel launch; 2: pairs of steps per launch (the
-        populations cross HBM once per two steps), tiles of tile_w x
+        """1: one step per kernel launch; 2 or 3: that many steps per launch
+        (the populations cross HBM once per launch), tiles of tile_w x
         1024/tile_w sites (tile_w 32, 64 or 128)."""
         _check(lib().flb_set_time_blocking(self._h, int(steps_per_launch), int(tile_w)))
 

@@ -145,6 +145,10 @@ constexpr int32_t kStep2Square = 1 << 30;
 hipError_t launch_step2(const DeviceView &v, const StepItem *items, int nitems, int tile_w,
                         uint32_t step_add, bool nontemporal, bool noise, hipStream_t s);
 bool step2_tile_supported(int tw);
+// Three steps per launch on the two-step kernel's tiles (tile_w 32, 64 or
+// 128, the same items).
+hipError_t launch_step3(const DeviceView &v, const StepItem *items, int nitems, int tile_w,
+                        uint32_t step_add, bool nontemporal, bool noise, hipStream_t s);
 hipError_t launch_advance_step(uint32_t *step, uint32_t n, hipStream_t s);
 hipError_t launch_init(const DeviceView &v, int lattice, int64_t plane, hipStream_t s);
 hipError_t launch_get(const DeviceView &v, int lattice, int nx, int ny, double *out_dev,

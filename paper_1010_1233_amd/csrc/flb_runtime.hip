@@ -175,6 +175,7 @@ struct flb {
     // that it brackets the kernel alone
     bool timing = false, capturing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare_events;
+    std::vector<int> timed_steps;  // steps of each timed launch
 
     // streams and graphs
     hipStream_t own = nullptr;
@@ -378,7 +379,11 @@ int build_step_items(flb_t *h)
 }
 
 // Kernel launches for n steps (the buffer parity flips once per launch).
-int64_t step_launches(const flb_t *h, int64_t n) { return h->tblock == 2 ? n / 2 + n % 2 : n; }
+int64_t step_launches(const flb_t *h, int64_t n)
+{
+    if (h->tblock == 3) return n / 3 + (n % 3 ? 1 : 0);  // a remainder of 2 takes one launch
+    return h->tblock == 2 ? n / 2 + n % 2 : n;
+}
 
 void clear_graphs(flb_t *h)
 {
@@ -823,7 +828,7 @@ int enqueue_steps(flb_t *h, int64_t n, hipStream_t s, hipEvent_t wait_before_sec
     int launches = 0;
     const bool timing = h->timing && !h->capturing;
     hipEvent_t stop = nullptr;
-    auto before_launch = [&]() -> int {
+    auto before_launch = [&](int steps) -> int {
         if (launches++ == 1 && wait_before_second)
             FLB_HIP(hipStreamWaitEvent(s, wait_before_second, 0));
         if (timing) {
@@ -839,6 +844,7 @@ int enqueue_steps(flb_t *h, int64_t n, hipStream_t s, hipEvent_t wait_before_sec
                 }
             }
             h->timed.push_back(ev);
+            h->timed_steps.push_back(steps);
             FLB_HIP(hipEventRecord(ev.first, s));
             stop = ev.second;
         }
@@ -849,16 +855,27 @@ int enqueue_steps(flb_t *h, int64_t n, hipStream_t s, hipEvent_t wait_before_sec
         return FLB_OK;
     };
     int rc;
-    if (h->tblock == 2)
+    // three steps per launch: a remainder of one step after at least three
+    // goes as two launches of two steps (3 + 1 -> 2 + 2), as one step per
+    // launch costs a whole HBM round trip
+    const int64_t n3 = h->tblock == 3 ? (n % 3 == 1 && n >= 4 ? n / 3 - 1 : n / 3) : 0;
+    for (; k < 3 * n3; k += 3) {
+        if ((rc = before_launch(3))) return rc;
+        FLB_HIP(launch_step3(h->view(), h->d_items2, h->nitems2, h->tile2, (uint32_t)k,
+                             h->nontemporal, h->noise, s));
+        if ((rc = after_launch())) return rc;
+        h->cur ^= 1;
+    }
+    if (h->tblock >= 2)
         for (; k + 2 <= n; k += 2) {
-            if ((rc = before_launch())) return rc;
+            if ((rc = before_launch(2))) return rc;
             FLB_HIP(launch_step2(h->view(), h->d_items2, h->nitems2, h->tile2, (uint32_t)k,
                                  h->nontemporal, h->noise, s));
             if ((rc = after_launch())) return rc;
             h->cur ^= 1;
         }
     for (; k < n; ++k) {
-        if ((rc = before_launch())) return rc;
+        if ((rc = before_launch(1))) return rc;
         FLB_HIP(launch_step(h->view(), h->d_items, h->nitems, h->tile_w, h->sites, (uint32_t)k,
                             h->nontemporal, h->noise, s));
         if ((rc = after_launch())) return rc;
@@ -1181,21 +1198,37 @@ int flb_set_launch_timing(flb_t *h, int on)
     return FLB_OK;
 }
 
-int flb_get_launch_timing(flb_t *h, int64_t *launches, double *total_ms)
+int flb_get_launch_timing_kinds(flb_t *h, int64_t launches[3], double total_ms[3])
 {
     if (check_handle(h)) return FLB_EINVAL;
     if (!launches || !total_ms) return fail(FLB_EINVAL, "launches and total_ms must not be NULL");
     FLB_HIP(hipStreamSynchronize(h->stream));
-    double sum = 0.0;
-    for (auto &pr : h->timed) {
-        float ms = 0.0f;
-        FLB_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
-        sum += ms;
+    for (int q = 0; q < 3; ++q) {
+        launches[q] = 0;
+        total_ms[q] = 0.0;
     }
-    *launches = (int64_t)h->timed.size();
-    *total_ms = sum;
+    for (size_t i = 0; i < h->timed.size(); ++i) {
+        float ms = 0.0f;
+        FLB_HIP(hipEventElapsedTime(&ms, h->timed[i].first, h->timed[i].second));
+        const int q = h->timed_steps[i] - 1;
+        launches[q] += 1;
+        total_ms[q] += ms;
+    }
     h->spare_events.insert(h->spare_events.end(), h->timed.begin(), h->timed.end());
     h->timed.clear();
+    h->timed_steps.clear();
+    return FLB_OK;
+}
+
+int flb_get_launch_timing(flb_t *h, int64_t *launches, double *total_ms)
+{
+    if (check_handle(h)) return FLB_EINVAL;
+    if (!launches || !total_ms) return fail(FLB_EINVAL, "launches and total_ms must not be NULL");
+    int64_t n[3];
+    double ms[3];
+    if (int rc = flb_get_launch_timing_kinds(h, n, ms)) return rc;
+    *launches = n[0] + n[1] + n[2];
+    *total_ms = ms[0] + ms[1] + ms[2];
     return FLB_OK;
 }
 
@@ -1558,8 +1591,8 @@ int flb_set_step_config(flb_t *h, int tile_w, int sites, int nontemporal)
 int flb_set_time_blocking(flb_t *h, int steps_per_launch, int tile_w)
 {
     if (check_handle(h)) return FLB_EINVAL;
-    if (steps_per_launch != 1 && steps_per_launch != 2)
-        return fail(FLB_EINVAL, "steps_per_launch must be 1 or 2");
+    if (steps_per_launch < 1 || steps_per_launch > 3)
+        return fail(FLB_EINVAL, "steps_per_launch must be 1, 2 or 3");
     if (!step2_tile_supported(tile_w)) return fail(FLB_EINVAL, "unsupported two-step tile");
     FLB_HIP(hipStreamSynchronize(h->stream));
     h->tblock = steps_per_launch;
@@ -1677,7 +1710,7 @@ static bool cached_shape(const char *cache, const std::string &key, size_t nlat,
             x.t2 = atoi(t2s.c_str());
             if (!step2_tile_supported(x.t2)) continue;
         }
-        if (step_tile_supported(x.tw, x.sv) && (x.tb == 1 || x.tb == 2)) {
+        if (step_tile_supported(x.tw, x.sv) && x.tb >= 1 && x.tb <= 3) {
             found = true;
             c = x;
             ms = t;
@@ -1756,7 +1789,8 @@ static int time_shapes(flb_t *h, int nsteps, const std::vector<StepShape> &shape
         for (int round = 0; round < kRounds && e == hipSuccess && rc == FLB_OK; ++round)
             for (size_t i = 0; i < shapes.size() && e == hipSuccess && rc == FLB_OK; ++i) {
                 apply_shape(hh, shapes[i]);
-                const int n = shapes[i].tb == 2 ? nsteps + (nsteps & 1) : nsteps;
+                const int tb = shapes[i].tb;  // whole launches
+                const int n = (nsteps + tb - 1) / tb * tb;
                 if ((rc = build_step_items(hh)) != FLB_OK) break;
                 if ((rc = enqueue_steps(hh, 2, hh->stream)) != FLB_OK) break;
                 e = hipEventRecord(e0, hh->stream);
@@ -1782,8 +1816,9 @@ static int time_every_shape(flb_t *h, int nsteps, std::vector<std::pair<float, S
     for (int tw : {64, 128, 256})
         for (int sv : {1, 2, 4})
             for (int nt = 0; nt < 2; ++nt) shapes.push_back({tw, sv, nt, 1, 64, {}});
-    for (int t2 : {32, 64, 128})
-        for (int nt = 0; nt < 2; ++nt) shapes.push_back({h->tile_w, h->sites, nt, 2, t2, {}});
+    for (int tb : {2, 3})
+        for (int t2 : {32, 64, 128})
+            for (int nt = 0; nt < 2; ++nt) shapes.push_back({h->tile_w, h->sites, nt, tb, t2, {}});
     std::vector<float> best;
     if (int rc = time_shapes(h, nsteps, shapes, best)) return rc;
     out.clear();
@@ -1881,7 +1916,7 @@ static int lattice_tile_candidate(flb_t *h, int nsteps, const StepShape &chosen,
                                   std::vector<StepShape> &extra)
 {
     extra.clear();
-    if (h->params.size() < 2 || chosen.tb != 2) return FLB_OK;
+    if (h->params.size() < 2 || chosen.tb < 2) return FLB_OK;
     std::vector<int8_t> lt;
     if (int rc = tune_lattice_tiles(h, nsteps, chosen.nt, lt)) return rc;
     bool same = chosen.t2 == 32 || chosen.t2 == 64;
@@ -1892,6 +1927,7 @@ static int lattice_tile_candidate(flb_t *h, int nsteps, const StepShape &chosen,
     for (int8_t v : lt) uniform = uniform && v == lt[0];
     m.t2 = uniform ? 1 << lt[0] : 0;
     m.lt = uniform ? std::vector<int8_t>() : lt;
+    if (!uniform) m.tb = 2;  // per-lattice tiles: the two-step kernel
     extra.push_back(m);
     return FLB_OK;
 }

@@ -658,6 +658,276 @@ hipError_t launch_step2(const DeviceView &v, const StepItem *items, int nitems, 
 }
 
 // ---------------------------------------------------------------------
+// Three steps per launch.  A block owns a TW x TH tile; its region adds two
+// rings of sites.  Phase 1 collides the whole region at t (each site pulled
+// from HBM), phase 2 the tile and the inner ring at t + 1 (pulled from
+// phase 1's values in LDS), phase 3 the tile at t + 2, which it stores.
+// Every intermediate value is rounded to the storage format, so the
+// results are the bits of three one-step launches; the populations cross
+// HBM once per three steps.  A thread keeps its sites across the phases
+// (its two tile sites in all three, its inner-ring site in the first two,
+// its outer-ring site in the first), so a site's rest population stays in a
+// register and LDS holds planes 1..8 of the region.  Phase 2 reads all its
+// inputs before a barrier and then overwrites them in place.
+// ---------------------------------------------------------------------
+
+// region coordinates of the h-th site of the one-site ring around a w x hh
+// box whose top-left site is at region (1, 1); the ring spans [0, w + 2) x
+// [0, hh + 2)
+__device__ __forceinline__ void ring_box(int w, int hh, int h, int &rx, int &ry)
+{
+    const int RW = w + 2;
+    if (h < RW) {
+        ry = 0;
+        rx = h;
+    } else if (h < 2 * RW) {
+        ry = hh + 1;
+        rx = h - RW;
+    } else if (h < 2 * RW + hh) {
+        ry = h - 2 * RW + 1;
+        rx = 0;
+    } else {
+        ry = h - 2 * RW - hh + 1;
+        rx = RW - 1;
+    }
+}
+
+// (FP32: the register budget of six waves per SIMD, three blocks per CU as
+// the 51 KB of LDS of a 128 x 8 region allow.)
+template <int S, bool NT, bool NOISE, int TW, int TH>
+__global__ __launch_bounds__(kStep2Threads)
+__attribute__((amdgpu_waves_per_eu(S == kF32 ? 6 : 4))) void step3_kernel(StepArgs g)
+{
+    using T = typename Codec<S>::T;
+    static_assert(TW * TH == 1024 && (TW & (TW - 1)) == 0, "tile shape");
+    constexpr int RW = TW + 4, RN = RW * (TH + 4);
+    constexpr int N1 = 2 * (TW + 2) + 2 * TH;        // inner ring
+    constexpr int N2 = 2 * (TW + 4) + 2 * (TH + 2);  // outer ring
+    constexpr int KT = 1024 / kStep2Threads;        // tile sites per thread
+    constexpr int K = KT + 2;                       // phase-1 slots: tile, inner, outer
+    static_assert(N1 <= kStep2Threads && N2 <= kStep2Threads, "tile shape");
+    constexpr int LG = TW == 32 ? 5 : TW == 64 ? 6 : 7;
+    __shared__ T mid[8 * RN];  // planes 1..8 of the region
+    const StepItem it = g.items[blockIdx.x];
+    if (it.lattice < 0) return;
+    const LatticeParams &P = g.params[it.lattice];
+    const int nx = P.nx, ny = P.ny;
+    const int tiles_x = (nx + TW - 1) >> LG;
+    const int x0 = (it.tile % tiles_x) * TW, y0 = (it.tile / tiles_x) * TH;
+    const T *__restrict__ src = (const T *)g.src + P.base;
+    T *__restrict__ dst = (T *)g.dst + P.base;
+    const uint32_t plane = (uint32_t)P.plane, px = (uint32_t)P.px;
+    const uint32_t t = *g.step + g.step_add;
+    const int tid = threadIdx.x;
+    const bool has1 = tid < N1, has2 = tid >= kStep2Threads - N2;
+    const bool interior = x0 >= 3 && y0 >= 3 && x0 + TW + 3 <= nx && y0 + TH + 3 <= ny;
+
+    // slots: 0 .. KT-1 tile sites, KT the inner-ring site, KT+1 the outer
+    int xs[K], ys[K], rs[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        int rx, ry;
+        if (k < KT) {
+            const int o = tid + k * kStep2Threads;
+            ry = (o >> LG) + 2;
+            rx = (o & (TW - 1)) + 2;
+        } else if (k == KT) {
+            ring_box(TW, TH, has1 ? tid : 0, rx, ry);
+            rx += 1;
+            ry += 1;
+        } else {
+            ring_box(TW + 2, TH + 2, has2 ? tid - (kStep2Threads - N2) : 0, rx, ry);
+        }
+        rs[k] = ry * RW + rx;
+        xs[k] = x0 - 2 + rx;
+        ys[k] = y0 - 2 + ry;
+    }
+    if (!interior) {
+        // wrap (x >= -2, nx >= 2): at most one subtraction unless the
+        // lattice is smaller than a tile
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            int x = xs[k], y = ys[k];
+            x = x < 0 ? x + nx : x;
+            y = y < 0 ? y + ny : y;
+            while (x >= nx) x -= nx;
+            while (y >= ny) y -= ny;
+            xs[k] = x;
+            ys[k] = y;
+        }
+    }
+    const char *sp[9];
+    char *dp[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        sp[i] = reinterpret_cast<const char *>(src) + (size_t)i * plane * sizeof(T);
+        dp[i] = reinterpret_cast<char *>(dst) + (size_t)i * plane * sizeof(T);
+    }
+    constexpr uint32_t E = sizeof(T);
+    auto active = [&](int k) { return k < KT || (k == KT ? has1 : has2); };
+
+    // phase 1 (t): every region site, pulled from HBM
+    T raw[K][9];
+    if (interior) {
+        const int64_t row = (int64_t)px * E;
+        const char *const sh0 = sp[0];
+        const char *const sh1 = sp[1] - (int64_t)E;
+        const char *const sh2 = sp[2] - row;
+        const char *const sh3 = sp[3] + (int64_t)E;
+        const char *const sh4 = sp[4] + row;
+        const char *const sh5 = sp[5] - row - (int64_t)E;
+        const char *const sh6 = sp[6] - row + (int64_t)E;
+        const char *const sh7 = sp[7] + row + (int64_t)E;
+        const char *const sh8 = sp[8] + row - (int64_t)E;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!active(k)) continue;
+            const uint32_t o = ((uint32_t)ys[k] * px + (uint32_t)xs[k]) * E;
+            raw[k][0] = *reinterpret_cast<const T *>(sh0 + o);
+            raw[k][1] = *reinterpret_cast<const T *>(sh1 + o);
+            raw[k][2] = *reinterpret_cast<const T *>(sh2 + o);
+            raw[k][3] = *reinterpret_cast<const T *>(sh3 + o);
+            raw[k][4] = *reinterpret_cast<const T *>(sh4 + o);
+            raw[k][5] = *reinterpret_cast<const T *>(sh5 + o);
+            raw[k][6] = *reinterpret_cast<const T *>(sh6 + o);
+            raw[k][7] = *reinterpret_cast<const T *>(sh7 + o);
+            raw[k][8] = *reinterpret_cast<const T *>(sh8 + o);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!active(k)) continue;
+            const int x = xs[k], y = ys[k];
+            const uint32_t ux = (uint32_t)x * E;
+            const uint32_t xm = (uint32_t)(x == 0 ? nx - 1 : x - 1) * E;
+            const uint32_t xr = (uint32_t)(x == nx - 1 ? 0 : x + 1) * E;
+            const uint32_t rc = (uint32_t)y * px * E;
+            const uint32_t rm = (uint32_t)(y == 0 ? ny - 1 : y - 1) * px * E;
+            const uint32_t rp = (uint32_t)(y == ny - 1 ? 0 : y + 1) * px * E;
+            raw[k][0] = *reinterpret_cast<const T *>(sp[0] + (rc + ux));
+            raw[k][1] = *reinterpret_cast<const T *>(sp[1] + (rc + xm));
+            raw[k][2] = *reinterpret_cast<const T *>(sp[2] + (rm + ux));
+            raw[k][3] = *reinterpret_cast<const T *>(sp[3] + (rc + xr));
+            raw[k][4] = *reinterpret_cast<const T *>(sp[4] + (rp + ux));
+            raw[k][5] = *reinterpret_cast<const T *>(sp[5] + (rm + xm));
+            raw[k][6] = *reinterpret_cast<const T *>(sp[6] + (rm + xr));
+            raw[k][7] = *reinterpret_cast<const T *>(sp[7] + (rp + xr));
+            raw[k][8] = *reinterpret_cast<const T *>(sp[8] + (rp + xm));
+        }
+    }
+    T own[KT + 1];  // plane 0 of the tile and inner-ring sites, storage format
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (!active(k)) continue;
+        float d[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] = Work<S>::in(raw[k][i]);
+        update_site<NOISE, S>(d, P, (uint32_t)(ys[k] * nx + xs[k]), t, g.key0, g.key1);
+        if (k <= KT) own[k] = Work<S>::out(d[0]);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) mid[(i - 1) * RN + rs[k]] = Work<S>::out(d[i]);
+    }
+    __syncthreads();
+
+    // phase 2 (t + 1): tile and inner ring, pulled from LDS; every read
+    // before the barrier, every write after it
+    T nxt[KT + 1][8];
+#pragma unroll
+    for (int k = 0; k <= KT; ++k) {
+        if (!active(k)) continue;
+        const int c = rs[k];
+        float d[9];
+        d[0] = Work<S>::in(own[k]);
+        d[1] = Work<S>::in(mid[0 * RN + c - 1]);
+        d[2] = Work<S>::in(mid[1 * RN + c - RW]);
+        d[3] = Work<S>::in(mid[2 * RN + c + 1]);
+        d[4] = Work<S>::in(mid[3 * RN + c + RW]);
+        d[5] = Work<S>::in(mid[4 * RN + c - RW - 1]);
+        d[6] = Work<S>::in(mid[5 * RN + c - RW + 1]);
+        d[7] = Work<S>::in(mid[6 * RN + c + RW + 1]);
+        d[8] = Work<S>::in(mid[7 * RN + c + RW - 1]);
+        update_site<NOISE, S>(d, P, (uint32_t)(ys[k] * nx + xs[k]), t + 1, g.key0, g.key1);
+        own[k] = Work<S>::out(d[0]);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) nxt[k][i - 1] = Work<S>::out(d[i]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k <= KT; ++k) {
+        if (!active(k)) continue;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) mid[(i - 1) * RN + rs[k]] = nxt[k][i - 1];
+    }
+    __syncthreads();
+
+    // phase 3 (t + 2): the tile, stored
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+        const int o = tid + k * kStep2Threads;
+        const int x = x0 + (o & (TW - 1)), y = y0 + (o >> LG);
+        if (x >= nx || y >= ny) continue;
+        const int c = rs[k];
+        float d[9];
+        d[0] = Work<S>::in(own[k]);
+        d[1] = Work<S>::in(mid[0 * RN + c - 1]);
+        d[2] = Work<S>::in(mid[1 * RN + c - RW]);
+        d[3] = Work<S>::in(mid[2 * RN + c + 1]);
+        d[4] = Work<S>::in(mid[3 * RN + c + RW]);
+        d[5] = Work<S>::in(mid[4 * RN + c - RW - 1]);
+        d[6] = Work<S>::in(mid[5 * RN + c - RW + 1]);
+        d[7] = Work<S>::in(mid[6 * RN + c + RW + 1]);
+        d[8] = Work<S>::in(mid[7 * RN + c + RW - 1]);
+        update_site<NOISE, S>(d, P, (uint32_t)(y * nx + x), t + 2, g.key0, g.key1);
+        const uint32_t off = ((uint32_t)y * px + (uint32_t)x) * E;
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            gstore<NT>(reinterpret_cast<T *>(dp[i] + off), Work<S>::out(d[i]));
+    }
+}
+
+template <int S, bool NT, bool NOISE>
+static hipError_t launch_step3_tiles(const StepArgs &a, int nitems, int tw, hipStream_t s)
+{
+    const dim3 grid(nitems), block(kStep2Threads);
+    if (tw == 64)
+        hipLaunchKernelGGL((step3_kernel<S, NT, NOISE, 64, 16>), grid, block, 0, s, a);
+    else if (tw == 128)
+        hipLaunchKernelGGL((step3_kernel<S, NT, NOISE, 128, 8>), grid, block, 0, s, a);
+    else if (tw == 32)
+        hipLaunchKernelGGL((step3_kernel<S, NT, NOISE, 32, 32>), grid, block, 0, s, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_step3(const DeviceView &v, const StepItem *items, int nitems, int tile_w,
+                        uint32_t step_add, bool nontemporal, bool noise, hipStream_t s)
+{
+    StepArgs a;
+    a.src = v.pops[v.cur];
+    a.dst = v.pops[v.cur ^ 1];
+    a.params = v.params;
+    a.items = items;
+    a.step = v.step;
+    a.step_add = step_add;
+    a.key0 = (uint32_t)(v.seed & 0xFFFFFFFFu);
+    a.key1 = (uint32_t)(v.seed >> 32);
+#define FLB_SEL(S_)                                                                              \
+    if (v.storage == S_) {                                                                       \
+        if (nontemporal)                                                                         \
+            return noise ? launch_step3_tiles<S_, true, true>(a, nitems, tile_w, s)              \
+                         : launch_step3_tiles<S_, true, false>(a, nitems, tile_w, s);            \
+        return noise ? launch_step3_tiles<S_, false, true>(a, nitems, tile_w, s)                 \
+                     : launch_step3_tiles<S_, false, false>(a, nitems, tile_w, s);               \
+    }
+    FLB_SEL(kF32)
+    FLB_SEL(kBF16)
+    FLB_SEL(kF16)
+#undef FLB_SEL
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------
 // Step counter
 // ---------------------------------------------------------------------
 __global__ void advance_step_kernel(uint32_t *step, uint32_t n)

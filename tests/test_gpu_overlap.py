@@ -38,7 +38,7 @@ def _pair(flb, nx, ny, storage="f32", moments=False, blocking=1):
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
-@pytest.mark.parametrize("blocking", [1, 2])
+@pytest.mark.parametrize("blocking", [1, 2, 3])
 def test_overlapped_samples_equal_immediate(flb, storage, blocking):
     """1024 x 512: the sample outlasts a step launch, so the overwriting
     launch really waits; step counts 1..10 move it from absent to late."""

@@ -322,23 +322,26 @@ def test_resume_from_saved_state_is_bit_identical(flb):
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 def test_time_blocking_equals_one_step_launches(flb, storage):
-    """Pairs of steps per launch (halo recomputed on chip) give exactly the
-    populations of one step per launch: tiny, ragged and tile-sized shapes,
-    every tile width, an odd number of steps."""
+    """Two and three steps per launch (halo recomputed on chip) give exactly
+    the populations of one step per launch: tiny, ragged and tile-sized
+    shapes, every tile width, step counts that leave each remainder."""
     for nx, ny in [(2, 2), (3, 5), (37, 23), (64, 16), (32, 32), (130, 17), (257, 3), (5, 300),
-                   (1000, 7)]:
+                   (1000, 7), (300, 140)]:
         note("time blocking", storage, nx, ny)
-        for tile in (32, 64, 128):
-            a = flb.Lattice(nx, ny, TAU_C1, 1e-3, u0=(0.03, -0.02), seed=4, storage=storage)
-            b = flb.Lattice(nx, ny, TAU_C1, 1e-3, u0=(0.03, -0.02), seed=4, storage=storage)
-            b.set_time_blocking(2, tile)
-            assert b.time_blocking() == (2, tile)
-            a.thermalize()
-            b.thermalize()
-            a.step(7)
-            b.step(7)
-            assert a.t == b.t == 7
-            assert np.array_equal(a.get_populations(), b.get_populations()), (nx, ny, tile)
+        for blocking in (2, 3):
+            for tile in (32, 64, 128):
+                a = flb.Lattice(nx, ny, TAU_C1, 1e-3, u0=(0.03, -0.02), seed=4, storage=storage)
+                b = flb.Lattice(nx, ny, TAU_C1, 1e-3, u0=(0.03, -0.02), seed=4, storage=storage)
+                b.set_time_blocking(blocking, tile)
+                assert b.time_blocking() == (blocking, tile)
+                a.thermalize()
+                b.thermalize()
+                for n, t in ((7, 7), (8, 15), (3, 18)):
+                    a.step(n)
+                    b.step(n)
+                    assert a.t == b.t == t
+                    assert np.array_equal(a.get_populations(), b.get_populations()), \
+                        (nx, ny, blocking, tile, t)
 
 
 def test_time_blocking_batch_and_graph_periods(flb):
@@ -348,21 +351,23 @@ def test_time_blocking_batch_and_graph_periods(flb):
     a = flb.Lattice.batch(specs, seed=6)
     b = flb.Lattice.batch(specs, seed=6)
     b.set_time_blocking(2, 128)
+    d = flb.Lattice.batch(specs, seed=6)
+    d.set_time_blocking(3, 64)
     # each lattice its own tile in one launch (the size-class form)
     c = flb.Lattice.batch(specs, seed=6)
     c.set_lattice_tiles([32, 64, 32])
     assert c.time_blocking() == (2, 0) and c.lattice_tiles() == [32, 64, 32]
     assert b.lattice_tiles() == [128, 128, 128]
-    for h in (a, b, c):
+    for h in (a, b, c, d):
         h.thermalize()
         h.run(103, 10)  # graph periods of ten steps plus a ragged tail
         h.run(37, 3)    # odd periods started off-phase
     for i in range(len(specs)):
-        for h in (b, c):
+        for h in (b, c, d):
             assert np.array_equal(a.get_populations(i), h.get_populations(i))
             assert np.array_equal(a.read_correlators(i)[0], h.read_correlators(i)[0])
     with pytest.raises(flb.FlbError):
-        b.set_time_blocking(3, 64)
+        b.set_time_blocking(4, 64)
     with pytest.raises(flb.FlbError):
         b.set_time_blocking(2, 256)
     with pytest.raises(flb.FlbError):
@@ -455,7 +460,9 @@ def test_sampled_sites_at_full_and_maximum_size(flb, oracle_lib, nx, ny):
     after one step of the one-step kernel and after two steps of the
     two-step kernel, each against the oracle's collision of that site (for
     two steps, of its nine upstream neighbours at t, then of the site at
-    t + 1); the two kernels' states after two steps are the same bits."""
+    t + 1); the two kernels' states after two steps are the same bits, and
+    one launch of the three-step kernel gives the bits of three one-step
+    launches."""
     c = workloads.CONFIGS["c5_4096"]
     tau, theta, seed = c["tau"], c["theta"], c["seed"]
     sigma = oracle_lib.noise_amplitudes(tau, theta, 1.0)
@@ -502,6 +509,18 @@ def test_sampled_sites_at_full_and_maximum_size(flb, oracle_lib, nx, ny):
     assert err2 < 2e-6
     b.step(1)  # second step through the one-step kernel
     assert np.array_equal(b.get_populations(), f2)
+    del f2
+    # three steps in one launch of the three-step kernel (the shape the
+    # benchmark times at 4096^2) against a third one-step launch
+    c = flb.Lattice(nx, ny, tau, theta, **kw)
+    c.set_step_config(256, 1, 1)
+    c.set_populations(f0)
+    c.t = t
+    c.set_time_blocking(3, 64)
+    c.step(3)
+    b.step(1)
+    assert c.t == b.t == t + 3
+    assert np.array_equal(c.get_populations(), b.get_populations())
 
 
 def test_empty_calls_change_nothing(flb):
