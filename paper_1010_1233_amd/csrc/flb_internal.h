@@ -53,6 +53,9 @@ struct alignas(16) LatticeParams {
     int64_t acc_base;         // double offset of kind 0 in acc
     float omega[6];           // 1/tau^a, a = 3..8
     float amp[6];             // noise amplitude per scaled moment, a = 3..8
+    // the FP32 collision's folded coefficients: 9/4 omega[0], 9 omega[1],
+    // -3 omega[3], -3 omega[4], 2 amp[3], 2 amp[4] (see collide)
+    float fcoef[6];
     float rho0, u0x, u0y;
     float feq[9];             // f_i^0(rho0,u0) - w_i rho0 (16-bit reference state)
     float scale[9];           // sqrt(mu rho0 w_i) (16-bit storage scale)

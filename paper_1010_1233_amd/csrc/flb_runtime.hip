@@ -260,6 +260,12 @@ LatticeParams make_params(const flb_lattice_spec &s, uint32_t flags)
         if ((flags & FLB_FLAG_NO_GHOST_NOISE) && a >= 6) sigma = 0.0;
         P.amp[a - 3] = (float)(mscale[a - 3] * sigma);
     }
+    P.fcoef[0] = (float)(2.25 / s.tau[3]);
+    P.fcoef[1] = (float)(9.0 / s.tau[4]);
+    P.fcoef[2] = (float)(-3.0 / s.tau[6]);
+    P.fcoef[3] = (float)(-3.0 / s.tau[7]);
+    P.fcoef[4] = 2.0f * P.amp[3];
+    P.fcoef[5] = 2.0f * P.amp[4];
     P.rho0 = (float)s.rho0;
     P.u0x = (float)s.u0[0];
     P.u0y = (float)s.u0[1];

@@ -38,47 +38,47 @@ __device__ __forceinline__ void collide(float (&d)[9], const LatticeParams &P, c
     const float jx = x13 + p57 - p68;
     const float jy = y24 + p57 + p68;
 
-    // s3 = 9/4 (a - b) and s4 = 9 (c - e) enter only through e3 - s3 and
-    // e4 - s4 below
+    // In the scaled basis s3 = 9/4 (a - b), s4 = 9 (c - e), s5, s6 = 3/2 g6,
+    // s7 = 3/2 g7, s8, and Eq. (10): e3 = 9/4 (jx^2 - jy^2)/rho,
+    // e4 = 9 jx jy/rho, e5 = 3/2 (jx^2 + jy^2)/rho, the others 0.  The
+    // constant factors ride in per-lattice coefficients (fcoef): t3 =
+    // 9/4 omega3 ((jx^2 - jy^2)/rho - (a - b)), t4 = 9 omega4 (jx jy/rho -
+    // (c - e)), and the ghost changes are kept doubled, u6 = 2 t6 =
+    // -3 omega6 g6 (+ 2 amp z), u7 = 2 t7 likewise.
     const float s5 = fmaf(0.5f, ab, fmaf(2.0f, ce, -d[0]));
-    const float s6 = 1.5f * fmaf(2.0f, p57 - p68, -x13);
-    const float s7 = 1.5f * fmaf(2.0f, p57 + p68, -y24);
+    const float g6 = fmaf(2.0f, p57 - p68, -x13);
+    const float g7 = fmaf(2.0f, p57 + p68, -y24);
     const float s8 = fmaf(0.5f, d[0], fmaf(2.0f, ce, -ab));
-
-    // Eq. (10) in the scaled basis: 3/2 rho (ux^2 - uy^2) -> 9/4 (jx^2 - jy^2)/rho, ...
     const float ir = __builtin_amdgcn_rcpf(P.rho0 + drho);
     const float jyy = jy * jy;
-    const float e3 = 2.25f * fmaf(jx, jx, -jyy) * ir;
-    const float e4 = 9.0f * (jx * jy) * ir;
-    const float e5 = 1.5f * fmaf(jx, jx, jyy) * ir;
 
     // change of each scaled moment, Eq. (5) and Eq. (8)
-    float t3 = P.omega[0] * fmaf(-2.25f, a - b, e3);
-    float t4 = P.omega[1] * fmaf(-9.0f, c - e, e4);
-    float t5 = P.omega[2] * (e5 - s5);
-    float t6 = -P.omega[3] * s6;
-    float t7 = -P.omega[4] * s7;
+    float t3 = P.fcoef[0] * fmaf(fmaf(jx, jx, -jyy), ir, -(a - b));
+    float t4 = P.fcoef[1] * fmaf(jx * jy, ir, -(c - e));
+    float t5 = P.omega[2] * fmaf(1.5f * fmaf(jx, jx, jyy), ir, -s5);
+    float u6 = P.fcoef[2] * g6;
+    float u7 = P.fcoef[3] * g7;
     float t8 = -P.omega[5] * s8;
     if constexpr (NOISE) {
         t3 = fmaf(P.amp[0], z[0], t3);
         t4 = fmaf(P.amp[1], z[1], t4);
         t5 = fmaf(P.amp[2], z[2], t5);
-        t6 = fmaf(P.amp[3], z[3], t6);
-        t7 = fmaf(P.amp[4], z[4], t7);
+        u6 = fmaf(P.fcoef[4], z[3], u6);
+        u7 = fmaf(P.fcoef[5], z[4], u7);
         t8 = fmaf(P.amp[5], z[5], t8);
     }
 
     // d*_i = d_i + w_i sum_{a>=3} m_i^a dM^a
     const float A = fmaf(0.5f, t5, -t8);
     const float B = 2.0f * (t5 + t8);
-    const float Q7 = 2.0f * t7;
-    const float PpQ = fmaf(2.0f, t6, Q7), PmQ = fmaf(2.0f, t6, -Q7);  // 2 t6 +- 2 t7
+    const float PpQ = u6 + u7, PmQ = u6 - u7;  // 2 t6 +- 2 t7
+    const float Ap = A + t3, Am = A - t3;
     constexpr float w0 = 4.0f / 9.0f, w1 = 1.0f / 9.0f, w5 = 1.0f / 36.0f;
     d[0] = fmaf(w0, fmaf(0.5f, t8, -t5), d[0]);
-    d[1] = fmaf(w1, (A + t3) - t6, d[1]);
-    d[3] = fmaf(w1, (A + t3) + t6, d[3]);
-    d[2] = fmaf(w1, (A - t3) - t7, d[2]);
-    d[4] = fmaf(w1, (A - t3) + t7, d[4]);
+    d[1] = fmaf(w1, fmaf(-0.5f, u6, Ap), d[1]);
+    d[3] = fmaf(w1, fmaf(0.5f, u6, Ap), d[3]);
+    d[2] = fmaf(w1, fmaf(-0.5f, u7, Am), d[2]);
+    d[4] = fmaf(w1, fmaf(0.5f, u7, Am), d[4]);
     d[5] = fmaf(w5, (B + t4) + PpQ, d[5]);
     d[6] = fmaf(w5, (B - t4) - PmQ, d[6]);
     d[7] = fmaf(w5, (B + t4) - PpQ, d[7]);
