@@ -42,7 +42,9 @@ __device__ __forceinline__ void normals6(uint4 w, float z[6])
     const uint32_t wv[3] = {w.x, w.y, w.z};
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-        const float r = fmaf((float)(wv[p] >> 9), 0x1p-23f, 0x1p-24f);
+        // r = (2 (w >> 9) + 1) 2^-24: 1 + (w >> 9) 2^-23 built from its bits,
+        // less 1 - 2^-24 (exact: the operands are within a factor 2)
+        const float r = __uint_as_float(0x3F800000u | (wv[p] >> 9)) - 0x1.fffffep-1f;
         const uint32_t al = ((wv[p] & 0x1FFu) << 10) | ((w.w >> (10 * p)) & 0x3FFu);
         const float a = fmaf((float)al, 0x1p-19f, 0x1p-20f);
         // r >= 2^-24 is never denormal: the hardware log2 needs no range

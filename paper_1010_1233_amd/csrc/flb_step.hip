@@ -35,8 +35,9 @@ __device__ __forceinline__ void collide(float (&d)[9], const LatticeParams &P, c
     const float drho = d[0] + ab + ce;
     const float x13 = d[1] - d[3], y24 = d[2] - d[4];
     const float p57 = d[5] - d[7], p68 = d[6] - d[8];
-    const float jx = x13 + p57 - p68;
-    const float jy = y24 + p57 + p68;
+    const float q68 = p57 - p68, r68 = p57 + p68;  // shared with g6, g7
+    const float jx = x13 + q68;
+    const float jy = y24 + r68;
 
     // In the scaled basis s3 = 9/4 (a - b), s4 = 9 (c - e), s5, s6 = 3/2 g6,
     // s7 = 3/2 g7, s8, and Eq. (10): e3 = 9/4 (jx^2 - jy^2)/rho,
@@ -46,8 +47,8 @@ __device__ __forceinline__ void collide(float (&d)[9], const LatticeParams &P, c
     // (c - e)), and the ghost changes are kept doubled, u6 = 2 t6 =
     // -3 omega6 g6 (+ 2 amp z), u7 = 2 t7 likewise.
     const float s5 = fmaf(0.5f, ab, fmaf(2.0f, ce, -d[0]));
-    const float g6 = fmaf(2.0f, p57 - p68, -x13);
-    const float g7 = fmaf(2.0f, p57 + p68, -y24);
+    const float g6 = fmaf(2.0f, q68, -x13);
+    const float g7 = fmaf(2.0f, r68, -y24);
     const float s8 = fmaf(0.5f, d[0], fmaf(2.0f, ce, -ab));
     const float ir = __builtin_amdgcn_rcpf(P.rho0 + drho);
     const float jyy = jy * jy;
