@@ -103,8 +103,9 @@ struct flb {
     bool nontemporal = false;
     StepItem *d_items = nullptr;
     int nitems = 0;
-    // time blocking: steps per launch (1 or 2) and the two-step kernel's tile
-    // width; tile2 = 0: each lattice has its own, log2 of it in ltile (5 or 6)
+    // time blocking: steps per launch (1, 2 or 3) and the two- and
+    // three-step kernels' tile width; tile2 = 0: each lattice has its own,
+    // log2 of it in ltile (5 or 6)
     int tblock = 1, tile2 = 64;
     std::vector<int8_t> ltile;
     StepItem *d_items2 = nullptr;
@@ -1654,8 +1655,8 @@ int flb_get_step_config(flb_t *h, int *tile_w, int *sites, int *nontemporal)
 }  // extern "C"
 
 // A step launch shape: one-step tile width, sites per thread, streaming
-// accesses, steps per launch (1 or 2), two-step tile width (0: per lattice,
-// log2 of each lattice's in lt).
+// accesses, steps per launch (1, 2 or 3), two- and three-step tile width
+// (0: per lattice, log2 of each lattice's in lt).
 struct StepShape {
     int tw, sv, nt, tb, t2;
     std::vector<int8_t> lt;
