@@ -111,6 +111,10 @@ def test_null_handle_calls_fail_cleanly(flb):
     assert L.flb_set_launch_timing(None, 1) == flb.EINVAL
     n, ms = ctypes.c_int64(), ctypes.c_double()
     assert L.flb_get_launch_timing(None, ctypes.byref(n), ctypes.byref(ms)) == flb.EINVAL
+    n3, ms3 = (ctypes.c_int64 * 3)(), (ctypes.c_double * 3)()
+    assert L.flb_get_launch_timing_kinds(None, n3, ms3) == flb.EINVAL
+    assert L.flb_set_lattice_tiles(None, None) == flb.EINVAL
+    assert L.flb_get_lattice_tiles(None, None) == flb.EINVAL
     assert "NULL" in flb.last_error()
     L.flb_destroy(None)
 

@@ -192,3 +192,15 @@ def test_overlap_switch_and_launch_timing(flb):
     a.set_launch_timing(False)
     a.step(2)
     assert a.launch_timing() == (0, 0.0)
+    # three steps per launch: ten steps are 3 + 3 + 2 + 2, seven 3 + 2 + 2,
+    # two one launch of two and one a one-step launch; the records split
+    # by the steps a launch took
+    a.set_time_blocking(3, 64)
+    a.set_launch_timing(True)
+    for n, want in ((10, (0, 2, 2)), (7, (0, 2, 1)), (2, (0, 1, 0)), (1, (1, 0, 0)),
+                    (9, (0, 0, 3))):
+        a.step(n)
+        kinds = a.launch_timing_kinds()
+        assert tuple(k[0] for k in kinds) == want, (n, kinds)
+        assert all((c == 0) == (ms == 0.0) for c, ms in kinds)
+    a.set_launch_timing(False)
