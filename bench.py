@@ -174,6 +174,19 @@ def steady_step_ms(torch, g, stream, n=60, warm=120, reps=3):
     return min(time_step_kernel(torch, g, stream, n) for _ in range(reps))
 
 
+# VALU issue: 256 CUs x 2.4 GHz, one wave-level (64-lane) VALU instruction
+# per CU and cycle (four SIMDs of 16 lanes)
+VALU_ISSUE_PER_S = 256 * 2.4e9
+
+
+def valu_issue_frac(valu_per_update, updates_per_launch, launch_ms):
+    """Time the launch's VALU instructions need at the issue rate over its
+    duration (None without the counters' figure)."""
+    if valu_per_update is None:
+        return None
+    return valu_per_update * updates_per_launch / 64 / VALU_ISSUE_PER_S / (launch_ms * 1e-3)
+
+
 def copy_GBs(torch, stream, nbytes, n=20, reps=3):
     """The device copy's practical rate (read + write bytes per second) over
     nbytes each way, on `stream`: the fastest of `reps` runs of n copies."""
@@ -539,6 +552,7 @@ def main():
     launch = launch_figures(g, V, kinds[qd][1] / kinds[qd][0] / (qd + 1), steps=qd + 1)
     achieved = launch["achieved_GBs"]
     traffic = measured_traffic(args.workload, args.storage, tuned, blocking)
+    valu = counter_entry(args.workload, args.storage, tuned, blocking).get("valu_insts_per_update")
     drift = float(abs(g.sample_conservation()[0] - cons0[0]))
 
     # correlator sanity (matched S(k)): k-averaged S(rho) over the run
@@ -591,8 +605,11 @@ def main():
                                        / HBM_PEAK_GBS),
                      # VALU instructions (per lane) per site update, from
                      # the counters (SQ_INSTS_VALU x 64 / updates per launch)
-                     "valu_insts_per_update": counter_entry(args.workload, args.storage, tuned,
-                                                            blocking).get("valu_insts_per_update"),
+                     "valu_insts_per_update": valu,
+                     # the same instructions at the VALU issue rate over the
+                     # launch's duration: the kernel's other bound
+                     "valu_issue_frac": valu_issue_frac(valu, V * launch["steps_per_launch"],
+                                                        launch["avg_launch_ms"]),
                      "copy": {"bytes_each_way": 9 * V * g.storage_info()[1],
                               "GBs": copy_rate, "achieved_over_copy": achieved / copy_rate,
                               "measured_over_copy": (None if traffic is None else
@@ -602,7 +619,9 @@ def main():
                                   "achieved": iso["achieved_GBs"],
                                   "frac": iso["achieved_GBs"] / HBM_PEAK_GBS,
                                   "measured_GBs": (None if traffic is None else
-                                                   traffic / (iso["avg_launch_ms"] * 1e-3) / 1e9)}},
+                                                   traffic / (iso["avg_launch_ms"] * 1e-3) / 1e9),
+                                  "valu_issue_frac": valu_issue_frac(
+                                      valu, V * iso["steps_per_launch"], iso["avg_launch_ms"])}},
         "step_kernel_glups": V / (step_ms * 1e-3) / 1e9,
         "step_kernel_glups_isolated": V / (iso_ms * 1e-3) / 1e9,
         "sample_ms": max(ms_per_step - SAMPLE_EVERY * iso_ms, 0.0),
