@@ -302,6 +302,35 @@ def test_autotune_path_keeps_state_and_sums(flb, tmp_path, monkeypatch):
     assert len(lines) == 1 and lines[0].startswith("flb-path:")
 
 
+def test_autotune_cache_with_lattice_tiles(flb, tmp_path, monkeypatch):
+    """A cache line naming per-lattice tiles ("L" and each lattice's log2
+    width) is taken as it stands: the handle steps with those tiles and
+    gives the bits of an untuned handle set to them; a line whose lattice
+    count does not match, or whose widths are not 32 or 64, is skipped."""
+    sides = [(70, 40), (33, 129), (8, 8)]
+    specs = [dict(nx=nx, ny=ny, tau=TAU_C1, theta=1e-3, stream_id=i)
+             for i, (nx, ny) in enumerate(sides)]
+    total = sum(nx * ny for nx, ny in sides)
+    key = f"flb-path:0:{len(sides)}:{total}:{max(max(x) for x in sides)}:1:5"
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{key} 128 1 1 2 L565 0.5\n"
+                     f"{key} 128 1 1 2 L56 0.25\n"     # wrong lattice count
+                     f"{key} 128 1 1 2 L575 0.125\n")  # width 2^7 not offered
+    monkeypatch.setenv("FLB_AUTOTUNE_CACHE", str(cache))
+    g = flb.Lattice.batch(specs, seed=8)
+    cfg, ms = g.autotune_path(4, 5)
+    assert cfg == (128, 1, True) and ms == 0.5
+    assert g.time_blocking() == (2, 0) and g.lattice_tiles() == [32, 64, 32]
+    ref = flb.Lattice.batch(specs, seed=8)
+    ref.set_step_config(128, 1, 1)
+    ref.set_lattice_tiles([32, 64, 32])
+    for h in (g, ref):
+        h.thermalize()
+        h.run(23, 5)
+    for i in range(len(sides)):
+        assert np.array_equal(g.get_populations(i), ref.get_populations(i))
+
+
 def test_resume_from_saved_state_is_bit_identical(flb):
     """Checkpoint = populations + t (the noise is counter-based): a new handle
     given both continues exactly like the uninterrupted run."""
